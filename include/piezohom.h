@@ -1,0 +1,219 @@
+/*
+ * piezohom — periodic piezoelectric homogenisation on one AMD MI355X (gfx950).
+ *
+ * The library computes the effective (homogenised) tensors of a periodic
+ * piezoelectric unit cell, following Wegert, Roberts & Challis, "Level
+ * set-based inverse homogenisation of three-dimensional piezoelectric
+ * materials":
+ *
+ *   Sec. 2.1   the cell geometry is a level set phi (phi < 0 solid, phi > 0
+ *              void) or a per-element density rho in [0, 1];
+ *   Sec. 2.2   the nine cell problems (six unit macroscopic strains, three
+ *              unit macroscopic electric fields) of linear piezoelectricity
+ *              are solved on a periodic N^3 mesh of trilinear hexahedra with
+ *              4 dofs per node (u_x, u_y, u_z, phi); the effective C^H, e^H,
+ *              kappa^H are the cell averages of stress and electric
+ *              displacement (the paper's homogenisation formulas);
+ *   Sec. 2.5   the saddle-point system [[A, B^T], [B, -C]] is solved by
+ *              right-preconditioned GMRES with the block lower-triangular
+ *              approximate-Schur preconditioner of Sec. 2.5.3, whose Schur
+ *              block is the element-wise S_bar = sum_e C_e + B_e A_e^-1 B_e^T;
+ *              the inner maps v -> A\v and u -> S_bar\u are geometric
+ *              multigrid V-cycles with Chebyshev-Jacobi smoothing;
+ *   Sec. 2.3   figures of merit d_h, g_h, B_Voigt, B_Reuss, k_h;
+ *   Sec. 2.1   one Hamilton-Jacobi upwind step of the level set.
+ *
+ * Material interpolation: every element carries the ersatz scale
+ * s_e = eps_v + (1 - eps_v) rho_e applied to C, e and kappa alike, with
+ * rho_e = 1 - H_eta(mean of the element's 8 nodal phi), H_eta the sinusoidal
+ * smoothed Heaviside of half-width eta = smooth_width * h (Sec. 2.6: the
+ * interface is smoothed over about two elements).
+ *
+ * Grid and layouts (all arrays are C order, float64 unless stated):
+ *   node n = i + N*(j + N*k), x fastest, coordinates (i, j, k)/N, periodic;
+ *   element (i, j, k) has corner nodes ((i+a)%N, (j+b)%N, (k+c)%N) and shares
+ *   the node numbering (element e "starts" at node e);
+ *   solution X: [node][field 0..3][load 0..8], fields (u_x, u_y, u_z, phi),
+ *   loads in Voigt order (xx, yy, zz, yz, xz, xy) then (E_x, E_y, E_z);
+ *   tensors are SI, Voigt order (xx, yy, zz, yz, xz, xy), engineering shear:
+ *   C[6*6] Pa, e[3*6] C/m^2, kappa[3*3] F/m, all row-major.
+ *
+ * Ownership: the caller owns every buffer it passes.  Host pointers are
+ * read or written before the call returns.  Device pointers (on_device = 1)
+ * must be device memory of the context's device; the library reads and
+ * writes them on the context's stream, and the caller orders later work on
+ * that stream.  The library owns its workspaces until phz_destroy.
+ *
+ * Errors: every call returns an int status.  PHZ_OK = 0;
+ * PHZ_NOT_CONVERGED = 1 is a warning (outputs and histories are written);
+ * negative values are errors, after which phz_last_error(ctx) describes the
+ * cause.  Nothing throws, aborts or exits across this interface.  A context
+ * is used by one host thread at a time.
+ */
+#ifndef PIEZOHOM_H
+#define PIEZOHOM_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PHZ_OK 0
+#define PHZ_NOT_CONVERGED 1
+#define PHZ_E_INVALID (-1)
+#define PHZ_E_NAN (-2)
+#define PHZ_E_HIP (-3)
+#define PHZ_E_OOM (-4)
+#define PHZ_E_STATE (-5)
+#define PHZ_E_INTERNAL (-6)
+
+/* precision forms of phz_options.precision */
+#define PHZ_FP64 0       /* every kernel and vector in float64 */
+#define PHZ_FP32_IR 1    /* float32 operator, smoothers and Krylov basis inside
+                            float64 iterative refinement; float64 residuals,
+                            Hessenberg/Givens, coarse solve and reductions */
+
+/* operator blocks for phz_apply (Sec. 2.5 block structure) */
+#define PHZ_OP_FULL 0    /* calA = [[A, B^T], [B, -C]] on [n][4][k]        */
+#define PHZ_OP_A 1       /* A (elasticity) on [n][3][k]                    */
+#define PHZ_OP_B 2       /* B (coupling) [n][3][k] -> [n][1][k]            */
+#define PHZ_OP_SBAR 3    /* element-wise approximate Schur S_bar on [n][1][k] */
+
+typedef struct phz_ctx phz_ctx;
+
+/* Base material, SI units (Sec. 2.3 layout).  void_scale = eps_v. */
+typedef struct {
+    double C[36];
+    double e[18];
+    double kappa[9];
+    double void_scale;
+} phz_material;
+
+typedef struct {
+    int precision;          /* PHZ_FP64 or PHZ_FP32_IR                          */
+    int batched;            /* 1: the nine loads as one 9-column block;
+                               0: one load at a time                            */
+    int restart;            /* GMRES restart length m (default 30)              */
+    int max_iters;          /* cap on GMRES iterations per load (default 2000)  */
+    double rtol;            /* true relative residual target (default 1e-10)    */
+    int cheby_degree;       /* Chebyshev smoothing degree per sweep (default 2) */
+    int mg_levels;          /* 0 = coarsen while N even and N > 4               */
+    double smooth_width;    /* eta / h of the smoothed Heaviside (default 2)    */
+    int vcycles_a;          /* V-cycles per application of A^-1 (default 1)     */
+    int vcycles_s;          /* V-cycles per application of S_bar^-1 (default 1) */
+    double inner_rtol;      /* FP32_IR: relative residual reduction at which one
+                               float GMRES cycle stops early (default 1e-5)     */
+    int max_refine;         /* FP32_IR: cap on refinement steps, each one float
+                               GMRES cycle of at most `restart` steps (default 50) */
+    int verbose;            /* 0 silent; 1 per-solve summary on stderr          */
+} phz_options;
+
+typedef struct {
+    int iterations[9];      /* total GMRES iterations per load (inner, for IR) */
+    int restarts[9];        /* restart cycles per load                          */
+    int refinements;        /* FP64 refinement steps (FP32_IR), else 0          */
+    double true_residual[9];/* final ||b - calA x|| / ||b|| in float64          */
+    double flux_energy_defect; /* max |MH_flux - MH_energy| / max |MH|          */
+    double setup_ms;        /* preconditioner setup (last phz_solve)            */
+    double solve_ms;        /* whole phz_solve wall time                        */
+    int mg_levels;          /* levels used                                      */
+    double cheb_lambda[16]; /* lambda_max estimates, A then S_bar per level     */
+} phz_stats;
+
+typedef struct {
+    double d_h, g_h, B_voigt, B_reuss, k_h;
+} phz_foms_t;
+
+/* Fill *o with the defaults documented in phz_options. */
+void phz_default_options(phz_options* o);
+
+/* Create a context for an N x N x N periodic cell.  N must be even and
+ * >= 2 (multigrid halves N).  stream is a hipStream_t (NULL: the library
+ * creates its own).  On success *out owns device workspaces sized for N,
+ * nine loads and the chosen restart length. */
+int phz_create(int n, const phz_material* mat, const phz_options* opt,
+               void* stream, phz_ctx** out);
+void phz_destroy(phz_ctx* ctx);
+const char* phz_last_error(const phz_ctx* ctx);
+const char* phz_strerror(int status);
+/* Replace the options of an existing context (workspaces are re-sized). */
+int phz_set_options(phz_ctx* ctx, const phz_options* opt);
+
+/* Geometry.  phi: [N^3] nodal level set (Sec. 2.1 sign convention).
+ * rho: [N^3] per-element density in [0, 1].  NaN/Inf -> PHZ_E_NAN. */
+int phz_set_levelset(phz_ctx* ctx, const double* phi, int on_device);
+int phz_set_density(phz_ctx* ctx, const double* rho, int on_device);
+/* Per-element ersatz scale s_e currently in use, [N^3]. */
+int phz_get_scale(phz_ctx* ctx, double* s, int on_device);
+
+/* Solve the nine cell problems and reduce to the effective tensors. */
+int phz_solve(phz_ctx* ctx);
+
+/* Effective tensors of the last solve (SI, host). Any pointer may be NULL. */
+int phz_get_effective(phz_ctx* ctx, double CH[36], double eH[18], double kH[9]);
+/* Non-dimensional 9x9 effective matrices (flux and energy forms, host). */
+int phz_get_effective_nd(phz_ctx* ctx, double MH[81], double MH_energy[81]);
+/* Per-load residual history (relative GMRES estimates, then true
+ * residuals at restarts).  Writes min(cap, available) values to buf and the
+ * available count to *len. */
+int phz_get_history(phz_ctx* ctx, int load, double* buf, int cap, int* len);
+int phz_get_stats(phz_ctx* ctx, phz_stats* st);
+/* Fluctuation solution X, [N^3][4][9] non-dimensional (zero mean per field). */
+int phz_get_solution(phz_ctx* ctx, double* X, int on_device);
+/* Warm start for the next solve, same layout; NULL clears it. */
+int phz_set_initial_guess(phz_ctx* ctx, const double* X, int on_device);
+/* Load vectors b = -sum_e s_e F0 e_L, [N^3][4][9] non-dimensional. */
+int phz_get_rhs(phz_ctx* ctx, double* b, int on_device);
+
+/* Figures of merit (Sec. 2.3) of SI tensors and their gradients with respect
+ * to every entry of C (36), e (18), kappa (9).  Gradient pointers may be
+ * NULL.  Pure function: no context. */
+int phz_foms(const double CH[36], const double eH[18], const double kH[9],
+             phz_foms_t* out, const char* grad_of,
+             double gC[36], double ge[18], double gk[9]);
+
+/* Sensitivities of J with respect to the per-element density, given
+ * gC = dJ/dC^H, ge = dJ/de^H, gk = dJ/dkappa^H (SI).  Uses the last solve:
+ * dJ/drho_e = (1 - eps_v) <W, G_e>, G_e[K, L] = element energy of the
+ * fields e_K + B x^K and e_L + B x^L.  grad_rho: [N^3].  grad_phi (may be
+ * NULL): [N^3] chain rule through the smoothed Heaviside (requires a level
+ * set given by phz_set_levelset). */
+int phz_backward(phz_ctx* ctx, const double gC[36], const double ge[18],
+                 const double gk[9], double* grad_rho, double* grad_phi,
+                 int on_device);
+
+/* One first-order Godunov step of phi_t + v |grad phi| = 0 (Sec. 2.1) on
+ * the context's level set, dt = cfl * h.  velocity: [N^3] nodal values, or
+ * NULL to use the nodal mean of the last phz_backward's dJ/drho normalised
+ * to max |v| = 1.  The stepped level set becomes the context's geometry and
+ * is written to phi_out ([N^3], may be NULL). */
+int phz_hj_step(phz_ctx* ctx, const double* velocity, double cfl,
+                double* phi_out, int on_device);
+
+/* Low-level operator apply on the current geometry: y = calA_block x for
+ * nrhs in {1, 9} columns, device pointers, layouts [n][fields][nrhs].
+ * precision PHZ_FP64 (double buffers) or PHZ_FP32_IR (float buffers). */
+int phz_apply(phz_ctx* ctx, int op, int nrhs, int precision,
+              const void* x, void* y);
+/* Apply the SCP preconditioner z = P^-1 r (device, [n][4][nrhs], float64),
+ * building it for the current geometry if needed. */
+int phz_precondition(phz_ctx* ctx, int nrhs, const double* r, double* z);
+/* Galerkin coarse operator of multigrid level >= 1 applied to x (device,
+ * float64): block PHZ_OP_A ([nc][3][nrhs]) or PHZ_OP_SBAR ([nc][1][nrhs]). */
+int phz_coarse_apply(phz_ctx* ctx, int level, int op, int nrhs,
+                     const double* x, double* y);
+
+/* Per-kernel timing.  With timing enabled, every operator launch (fine
+ * blocks, coarse levels), every SCP preconditioner application and every
+ * Arnoldi orthogonalisation of later calls is bracketed by HIP events on the
+ * context's stream.  Enabling (or disabling) clears the totals.
+ * phz_get_kernel_timing writes one line "name count total_ms" per kernel
+ * class into buf (NUL-terminated, truncated to cap) and the full length to
+ * *len.  Names: fine_{full,A,B,S}_k{1,9}_f{64,32}, coarse_{A,S}_f{64,32},
+ * precond_f{64,32}, arnoldi_cgs2_f{64,32}. */
+int phz_kernel_timing(phz_ctx* ctx, int enable);
+int phz_get_kernel_timing(phz_ctx* ctx, char* buf, int cap, int* len);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PIEZOHOM_H */

@@ -1,0 +1,373 @@
+"""piezohom: periodic piezoelectric homogenisation on AMD MI355X.
+
+Thin ctypes binding over libpiezohom.so (the C ABI in include/piezohom.h).
+Every step of the computation runs in the library's HIP kernels; this
+module only marshals arguments.  PyTorch is used, when present, for device
+memory and streams (device tensors are passed by pointer).
+
+The library must be built (``python -m paper_2410_03148_amd.build``);
+importing the package without it raises ImportError.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpiezohom.so")
+
+PHZ_OK = 0
+PHZ_NOT_CONVERGED = 1
+PHZ_FP64 = 0
+PHZ_FP32_IR = 1
+OP_FULL, OP_A, OP_B, OP_SBAR = 0, 1, 2, 3
+
+
+class phz_material(C.Structure):
+    _fields_ = [("C", C.c_double * 36), ("e", C.c_double * 18), ("kappa", C.c_double * 9),
+                ("void_scale", C.c_double)]
+
+
+class phz_options(C.Structure):
+    _fields_ = [("precision", C.c_int), ("batched", C.c_int), ("restart", C.c_int),
+                ("max_iters", C.c_int), ("rtol", C.c_double), ("cheby_degree", C.c_int),
+                ("mg_levels", C.c_int), ("smooth_width", C.c_double), ("vcycles_a", C.c_int),
+                ("vcycles_s", C.c_int), ("inner_rtol", C.c_double), ("max_refine", C.c_int),
+                ("verbose", C.c_int)]
+
+
+class phz_stats(C.Structure):
+    _fields_ = [("iterations", C.c_int * 9), ("restarts", C.c_int * 9), ("refinements", C.c_int),
+                ("true_residual", C.c_double * 9), ("flux_energy_defect", C.c_double),
+                ("setup_ms", C.c_double), ("solve_ms", C.c_double), ("mg_levels", C.c_int),
+                ("cheb_lambda", C.c_double * 16)]
+
+
+class phz_foms_t(C.Structure):
+    _fields_ = [("d_h", C.c_double), ("g_h", C.c_double), ("B_voigt", C.c_double),
+                ("B_reuss", C.c_double), ("k_h", C.c_double)]
+
+
+EXPORTS = [
+    "phz_default_options", "phz_create", "phz_destroy", "phz_last_error", "phz_strerror",
+    "phz_set_options", "phz_set_levelset", "phz_set_density", "phz_get_scale", "phz_solve",
+    "phz_get_effective", "phz_get_effective_nd", "phz_get_history", "phz_get_stats",
+    "phz_get_solution", "phz_set_initial_guess", "phz_get_rhs", "phz_foms", "phz_backward",
+    "phz_hj_step", "phz_apply", "phz_precondition", "phz_coarse_apply",
+    "phz_kernel_timing", "phz_get_kernel_timing",
+]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2410_03148_amd.build`")
+    lib = C.CDLL(LIB_PATH)
+    vp, dp, ip = C.c_void_p, C.POINTER(C.c_double), C.c_int
+    sig = {
+        "phz_default_options": (None, [C.POINTER(phz_options)]),
+        "phz_create": (ip, [ip, C.POINTER(phz_material), C.POINTER(phz_options), vp, C.POINTER(vp)]),
+        "phz_destroy": (None, [vp]),
+        "phz_last_error": (C.c_char_p, [vp]),
+        "phz_strerror": (C.c_char_p, [ip]),
+        "phz_set_options": (ip, [vp, C.POINTER(phz_options)]),
+        "phz_set_levelset": (ip, [vp, vp, ip]),
+        "phz_set_density": (ip, [vp, vp, ip]),
+        "phz_get_scale": (ip, [vp, vp, ip]),
+        "phz_solve": (ip, [vp]),
+        "phz_get_effective": (ip, [vp, dp, dp, dp]),
+        "phz_get_effective_nd": (ip, [vp, dp, dp]),
+        "phz_get_history": (ip, [vp, ip, dp, ip, C.POINTER(ip)]),
+        "phz_get_stats": (ip, [vp, C.POINTER(phz_stats)]),
+        "phz_get_solution": (ip, [vp, vp, ip]),
+        "phz_set_initial_guess": (ip, [vp, vp, ip]),
+        "phz_get_rhs": (ip, [vp, vp, ip]),
+        "phz_foms": (ip, [dp, dp, dp, C.POINTER(phz_foms_t), C.c_char_p, dp, dp, dp]),
+        "phz_backward": (ip, [vp, dp, dp, dp, vp, vp, ip]),
+        "phz_hj_step": (ip, [vp, vp, C.c_double, vp, ip]),
+        "phz_apply": (ip, [vp, ip, ip, ip, vp, vp]),
+        "phz_precondition": (ip, [vp, ip, vp, vp]),
+        "phz_coarse_apply": (ip, [vp, ip, ip, ip, vp, vp]),
+        "phz_kernel_timing": (ip, [vp, ip]),
+        "phz_get_kernel_timing": (ip, [vp, C.c_char_p, ip, C.POINTER(ip)]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    return lib
+
+
+_lib = _load()
+
+
+class PiezoError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{_lib.phz_strerror(status).decode()} ({status}): {msg}")
+        self.status = status
+
+
+def default_options(**overrides):
+    o = phz_options()
+    _lib.phz_default_options(C.byref(o))
+    for k, v in overrides.items():
+        if not hasattr(o, k):
+            raise TypeError(f"unknown option {k!r}")
+        setattr(o, k, v)
+    return o
+
+
+def make_material(mat):
+    """phz_material from an object with C, e, kappa, void_scale (SI)."""
+    m = phz_material()
+    m.C[:] = [float(v) for v in np.asarray(mat.C, dtype=np.float64).ravel()]
+    m.e[:] = [float(v) for v in np.asarray(mat.e, dtype=np.float64).ravel()]
+    m.kappa[:] = [float(v) for v in np.asarray(mat.kappa, dtype=np.float64).ravel()]
+    m.void_scale = float(mat.void_scale)
+    return m
+
+
+def _dptr(a):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _arg(buf, n, dtype=np.float64):
+    """(pointer, on_device, keepalive) for a host numpy array or a device tensor."""
+    if hasattr(buf, "data_ptr"):  # torch tensor
+        if buf.is_cuda:
+            assert buf.is_contiguous() and buf.numel() == n
+            return C.c_void_p(buf.data_ptr()), 1, buf
+        buf = buf.detach().cpu().numpy()
+    a = np.ascontiguousarray(buf, dtype=dtype).ravel()
+    assert a.size == n, (a.size, n)
+    return C.c_void_p(a.ctypes.data), 0, a
+
+
+def foms(CH, eH, kH, grad_of=None):
+    """Figures of merit (d_h, g_h, B_voigt, B_reuss, k_h) and optional gradients."""
+    CH = np.ascontiguousarray(CH, dtype=np.float64).ravel()
+    eH = np.ascontiguousarray(eH, dtype=np.float64).ravel()
+    kH = np.ascontiguousarray(kH, dtype=np.float64).ravel()
+    out = phz_foms_t()
+    gC, ge, gk = np.zeros(36), np.zeros(18), np.zeros(9)
+    st = _lib.phz_foms(_dptr(CH), _dptr(eH), _dptr(kH), C.byref(out),
+                       grad_of.encode() if grad_of else None, _dptr(gC), _dptr(ge), _dptr(gk))
+    if st != PHZ_OK:
+        raise PiezoError(st, "phz_foms")
+    f = {k: getattr(out, k) for k in ("d_h", "g_h", "B_voigt", "B_reuss", "k_h")}
+    if grad_of:
+        return f, (gC.reshape(6, 6), ge.reshape(3, 6), gk.reshape(3, 3))
+    return f
+
+
+class Context:
+    """One periodic N^3 cell on the GPU (wraps phz_ctx)."""
+
+    def __init__(self, n, material, stream=None, **opts):
+        self.n = n
+        self.nn = n ** 3
+        self._mat = make_material(material)
+        self._opt = default_options(**opts)
+        h = C.c_void_p()
+        st = _lib.phz_create(n, C.byref(self._mat), C.byref(self._opt),
+                             C.c_void_p(stream) if stream else None, C.byref(h))
+        if st != PHZ_OK:
+            raise PiezoError(st, "phz_create")
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.phz_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def _check(self, st, what, allow_nc=False):
+        if st == PHZ_OK or (allow_nc and st == PHZ_NOT_CONVERGED):
+            return st
+        raise PiezoError(st, f"{what}: {_lib.phz_last_error(self._h).decode()}")
+
+    def set_options(self, **opts):
+        for k, v in opts.items():
+            setattr(self._opt, k, v)
+        self._check(_lib.phz_set_options(self._h, C.byref(self._opt)), "phz_set_options")
+
+    def set_levelset(self, phi):
+        p, dev, keep = _arg(phi, self.nn)
+        self._check(_lib.phz_set_levelset(self._h, p, dev), "phz_set_levelset")
+
+    def set_density(self, rho):
+        p, dev, keep = _arg(rho, self.nn)
+        self._check(_lib.phz_set_density(self._h, p, dev), "phz_set_density")
+
+    def scale(self):
+        out = np.zeros(self.nn)
+        self._check(_lib.phz_get_scale(self._h, C.c_void_p(out.ctypes.data), 0), "phz_get_scale")
+        return out
+
+    def solve(self):
+        """Solve the nine cell problems; returns PHZ_OK or PHZ_NOT_CONVERGED."""
+        return self._check(_lib.phz_solve(self._h), "phz_solve", allow_nc=True)
+
+    def effective(self):
+        Cm, e, k = np.zeros(36), np.zeros(18), np.zeros(9)
+        self._check(_lib.phz_get_effective(self._h, _dptr(Cm), _dptr(e), _dptr(k)), "phz_get_effective")
+        return Cm.reshape(6, 6), e.reshape(3, 6), k.reshape(3, 3)
+
+    def effective_nd(self):
+        a, b = np.zeros(81), np.zeros(81)
+        self._check(_lib.phz_get_effective_nd(self._h, _dptr(a), _dptr(b)), "phz_get_effective_nd")
+        return a.reshape(9, 9), b.reshape(9, 9)
+
+    def stats(self):
+        s = phz_stats()
+        self._check(_lib.phz_get_stats(self._h, C.byref(s)), "phz_get_stats")
+        return {
+            "iterations": list(s.iterations), "restarts": list(s.restarts),
+            "refinements": s.refinements, "true_residual": list(s.true_residual),
+            "flux_energy_defect": s.flux_energy_defect, "setup_ms": s.setup_ms,
+            "solve_ms": s.solve_ms, "mg_levels": s.mg_levels,
+            "cheb_lambda": list(s.cheb_lambda),
+        }
+
+    def history(self, load):
+        n = C.c_int()
+        self._check(_lib.phz_get_history(self._h, load, None, 0, C.byref(n)), "phz_get_history")
+        buf = np.zeros(max(n.value, 1))
+        self._check(_lib.phz_get_history(self._h, load, _dptr(buf), n.value, C.byref(n)), "phz_get_history")
+        return buf[: n.value]
+
+    def solution(self, out=None):
+        """X as [N^3, 4, 9] (host numpy, or into a device tensor `out`)."""
+        if out is not None:
+            p, dev, keep = _arg(out, self.nn * 36)
+            self._check(_lib.phz_get_solution(self._h, p, dev), "phz_get_solution")
+            return out
+        X = np.zeros(self.nn * 36)
+        self._check(_lib.phz_get_solution(self._h, C.c_void_p(X.ctypes.data), 0), "phz_get_solution")
+        return X.reshape(self.nn, 4, 9)
+
+    def set_initial_guess(self, X):
+        if X is None:
+            self._check(_lib.phz_set_initial_guess(self._h, None, 0), "phz_set_initial_guess")
+            return
+        p, dev, keep = _arg(X, self.nn * 36)
+        self._check(_lib.phz_set_initial_guess(self._h, p, dev), "phz_set_initial_guess")
+
+    def rhs(self):
+        b = np.zeros(self.nn * 36)
+        self._check(_lib.phz_get_rhs(self._h, C.c_void_p(b.ctypes.data), 0), "phz_get_rhs")
+        return b.reshape(self.nn, 4, 9)
+
+    def backward(self, gC=None, ge=None, gk=None, want_phi=False, out_rho=None, out_phi=None):
+        """dJ/drho (and dJ/dphi) for upstream gradients w.r.t. (C^H, e^H, kappa^H)."""
+        z = lambda a, n: np.ascontiguousarray(np.zeros(n) if a is None else a, dtype=np.float64).ravel()
+        gC, ge, gk = z(gC, 36), z(ge, 18), z(gk, 9)
+        dev = out_rho is not None and hasattr(out_rho, "is_cuda") and out_rho.is_cuda
+        if dev:
+            prho = C.c_void_p(out_rho.data_ptr())
+            pphi = C.c_void_p(out_phi.data_ptr()) if out_phi is not None else None
+            self._check(_lib.phz_backward(self._h, _dptr(gC), _dptr(ge), _dptr(gk), prho, pphi, 1), "phz_backward")
+            return out_rho, out_phi
+        grho = np.zeros(self.nn)
+        gphi = np.zeros(self.nn) if want_phi else None
+        self._check(_lib.phz_backward(self._h, _dptr(gC), _dptr(ge), _dptr(gk), C.c_void_p(grho.ctypes.data),
+                                      C.c_void_p(gphi.ctypes.data) if want_phi else None, 0), "phz_backward")
+        return (grho, gphi) if want_phi else grho
+
+    def hj_step(self, velocity=None, cfl=0.5, return_phi=True):
+        """One HJ step; velocity None uses the last backward's dJ/drho."""
+        out = np.zeros(self.nn) if return_phi else None
+        optr = C.c_void_p(out.ctypes.data) if return_phi else None
+        if velocity is None:
+            st = _lib.phz_hj_step(self._h, None, cfl, optr, 0)
+        else:
+            v = np.ascontiguousarray(velocity, dtype=np.float64).ravel()
+            st = _lib.phz_hj_step(self._h, C.c_void_p(v.ctypes.data), cfl, optr, 0)
+        self._check(st, "phz_hj_step")
+        return out
+
+    def kernel_timing(self, enable=True):
+        """Enable (or disable) per-kernel HIP-event timing; clears the totals."""
+        self._check(_lib.phz_kernel_timing(self._h, 1 if enable else 0), "phz_kernel_timing")
+
+    def kernel_times(self):
+        """{name: (launches, total_ms)} recorded since timing was enabled."""
+        n = C.c_int()
+        self._check(_lib.phz_get_kernel_timing(self._h, None, 0, C.byref(n)), "phz_get_kernel_timing")
+        buf = C.create_string_buffer(n.value + 1)
+        self._check(_lib.phz_get_kernel_timing(self._h, buf, n.value + 1, C.byref(n)), "phz_get_kernel_timing")
+        out = {}
+        for line in buf.value.decode().splitlines():
+            name, cnt, ms = line.split()
+            out[name] = (int(cnt), float(ms))
+        return out
+
+    # ---- low-level device entry points (pointers to device memory) ----
+    def apply(self, op, nrhs, precision, x_ptr, y_ptr):
+        self._check(_lib.phz_apply(self._h, op, nrhs, precision, C.c_void_p(x_ptr), C.c_void_p(y_ptr)),
+                    "phz_apply")
+
+    def precondition(self, nrhs, r_ptr, z_ptr):
+        self._check(_lib.phz_precondition(self._h, nrhs, C.c_void_p(r_ptr), C.c_void_p(z_ptr)),
+                    "phz_precondition")
+
+    def coarse_apply(self, level, op, nrhs, x_ptr, y_ptr):
+        self._check(_lib.phz_coarse_apply(self._h, level, op, nrhs, C.c_void_p(x_ptr), C.c_void_p(y_ptr)),
+                    "phz_coarse_apply")
+
+
+def homogenise(n, material, phi=None, rho=None, **opts):
+    """Solve one cell and return a dict of SI tensors, FOMs and solver stats."""
+    with Context(n, material, **opts) as ctx:
+        if phi is not None:
+            ctx.set_levelset(phi)
+        else:
+            ctx.set_density(rho)
+        status = ctx.solve()
+        Cm, e, k = ctx.effective()
+        return {"C": Cm, "e": e, "kappa": k, "foms": foms(Cm, e, k), "stats": ctx.stats(),
+                "status": status}
+
+
+def _autograd():
+    import torch
+
+    class Homogenise(torch.autograd.Function):
+        """(C^H, e^H, kappa^H) = F(rho) with a hand-written backward.
+
+        forward: rho (float64 tensor [N^3], any device) -> three float64 CPU
+        tensors; backward: phz_backward turns the upstream gradients into
+        dJ/drho on rho's device.
+        """
+
+        @staticmethod
+        def forward(ctx_, rho, context):
+            context.set_density(rho.detach().contiguous())
+            context.solve()
+            Cm, e, k = context.effective()
+            ctx_.context = context
+            ctx_.device = rho.device
+            return (torch.from_numpy(Cm.copy()), torch.from_numpy(e.copy()), torch.from_numpy(k.copy()))
+
+        @staticmethod
+        def backward(ctx_, gC, ge, gk):
+            cvt = lambda g: None if g is None else g.detach().cpu().double().numpy()
+            g = ctx_.context.backward(cvt(gC), cvt(ge), cvt(gk))
+            return torch.from_numpy(g).to(ctx_.device), None
+
+    return Homogenise
+
+
+def __getattr__(name):
+    if name == "Homogenise":
+        return _autograd()
+    raise AttributeError(name)

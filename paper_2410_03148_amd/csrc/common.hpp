@@ -1,0 +1,165 @@
+// Shared declarations of the HIP kernels' host launchers.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <stdexcept>
+#include <string>
+
+namespace phz {
+
+struct HipError : std::runtime_error {
+  using std::runtime_error::runtime_error;
+};
+
+#define PHZ_HIP(call)                                                              \
+  do {                                                                             \
+    hipError_t e_ = (call);                                                        \
+    if (e_ != hipSuccess)                                                          \
+      throw ::phz::HipError(std::string(#call) + ": " + hipGetErrorString(e_));    \
+  } while (0)
+
+#define PHZ_LAUNCH_CHECK() PHZ_HIP(hipGetLastError())
+
+// Maximum GMRES restart length supported by the fused Arnoldi kernels.
+constexpr int kMaxRestart = 32;
+
+// ---- operators (ops.hip) -----------------------------------------------------
+// Fine-level matrix-free block operator, y = beta*yin + alpha*(sum_e s_e Kref) x.
+// op: 0 full (4->4), 1 A (3->3), 2 B (3->1), 3 S_bar (1->1).  nrhs in {1, 9}.
+// kref is the op's reference block in (l*FO + fo, l'*FI + fi) layout.
+template <typename T>
+void fine_apply(int op, int nrhs, int N, const T* s, const T* kref, const T* x,
+                const T* yin, T* y, T alpha, T beta, hipStream_t st);
+
+// Coarse-level apply with stored Galerkin element matrices Ae laid out
+// [corner L][element][F][8F] (row (L, f) of each element matrix).
+template <typename T>
+void coarse_apply(int F, int nrhs, int N, const T* Ae, const T* x, const T* yin, T* y,
+                  T alpha, T beta, hipStream_t st);
+
+// Galerkin coarsening of element matrices: coarse element E gets
+// sum_children Q_c^T K_c Q_c with trilinear Q_c.  From the fine level
+// (s != nullptr: K_c = s_c kref) or from stored matrices Afine.
+void galerkin_build(int F, int Nf, const double* s, const double* kref, const double* Afine,
+                    double* Acoarse, hipStream_t st);
+
+// Inverse node-block diagonal (F x F per node), fine or coarse level.
+void diag_inv_fine(int F, int N, const double* s, const double* kref, double* Dinv,
+                   hipStream_t st);
+void diag_inv_coarse(int F, int N, const double* Ae, double* Dinv, hipStream_t st);
+
+// One Chebyshev-Jacobi step: d = a d + b Dinv r (a == 0 ignores old d);
+// x = d if xzero else x += d.
+template <typename T>
+void cheby_step(int F, int nrhs, long nn, const T* Dinv, const T* r, T* d, T* x, T a, T b,
+                bool xzero, hipStream_t st);
+
+// Full-weighting restriction rc = P^T rf and prolongation xf += P xc (periodic,
+// trilinear).  Nc = coarse N.
+template <typename T>
+void restrict_fw(int F, int nrhs, int Nc, const T* rf, T* rc, hipStream_t st);
+template <typename T>
+void prolong_add(int F, int nrhs, int Nc, const T* xc, T* xf, hipStream_t st);
+
+// z = Minv r on the coarsest level (dense, rows = F * nc^3, double matrix).
+template <typename T>
+void dense_apply(int rows, int nrhs, const double* Minv, const T* r, T* z, hipStream_t st);
+
+// ---- vectors / reductions / physics (vec.hip) --------------------------------
+template <typename Ts, typename Td>
+void convert(long count, const Ts* src, Td* dst, hipStream_t st);
+template <typename T>
+void fill(long count, T value, T* dst, hipStream_t st);
+
+// Per-column sums of squares of a [rows][nrhs] vector into out[nrhs] (double),
+// deterministic two-stage reduction; work must hold reduce_work_size() doubles.
+size_t reduce_work_size(int nvals);
+template <typename T>
+void col_norm2(long rows, int nrhs, const T* v, double* out, double* work, hipStream_t st);
+// Per-column (field, rhs) sums of a [nn][F][nrhs] vector into out[F*nrhs].
+template <typename T>
+void field_sums(long nn, int F, int nrhs, const T* v, double* out, double* work,
+                hipStream_t st);
+// v[n][f][k] -= sums[f*K+k] / nn
+template <typename T>
+void subtract_mean(long nn, int F, int nrhs, const double* sums, T* v, hipStream_t st);
+
+// Arnoldi passes on [rows][nrhs] vectors with the basis V (stride vstride
+// elements between vectors):
+//   dots:    hout[i][k] = <V_i, w>_k for i <= j
+//   update:  w -= sum_i V_i hin[i][k]; then (if hout) hout = V^T w_new and
+//            nrm2out = ||w_new||^2 (nrm2out may be null)
+template <typename T>
+void arnoldi_dots(long rows, int nrhs, int j, const T* V, long vstride, const T* w,
+                  double* hout, double* work, hipStream_t st);
+template <typename T>
+void arnoldi_update(long rows, int nrhs, int j, const T* V, long vstride, T* w,
+                    const double* hin, double* hout, double* nrm2out, double* work,
+                    hipStream_t st);
+// v = w * scale[k]
+template <typename T>
+void scale_cols(long rows, int nrhs, const T* w, const double* scale, T* v, hipStream_t st);
+// t = sum_{i < kused[k]} V_i y[i][k]
+template <typename T>
+void combine(long rows, int nrhs, int m, const T* V, long vstride, const double* y,
+             const int* kused, T* t, hipStream_t st);
+// x += a[k] * z (a may be null -> 1), mixed precision source allowed
+template <typename Tx, typename Tz>
+void axpy_cols(long rows, int nrhs, const double* a, const Tz* z, Tx* x, hipStream_t st);
+// full [nn][4][K] <-> u [nn][3][K] and p [nn][1][K]
+template <typename T>
+void split_fields(long nn, int nrhs, const T* full, T* u, T* p, hipStream_t st);
+template <typename T>
+void merge_fields(long nn, int nrhs, const T* u, const T* p, T* full, hipStream_t st);
+// strided column copies between a [nn][4][9] block and a [nn][4][1] vector
+void extract_column(long nn, int load, const double* block, double* col, hipStream_t st);
+void insert_column(long nn, int load, const double* col, double* block, hipStream_t st);
+
+// GMRES small-matrix kernels (one workgroup; state arrays in device memory).
+struct GmresState {
+  double* H;        // [(m+1)][m][K]
+  double* cs;       // [m][K]
+  double* sn;       // [m][K]
+  double* g;        // [(m+1)][K]
+  double* y;        // [m][K]
+  double* est;      // [m][K] relative residual estimates
+  double* bnorm;    // [K]
+  double* scale;    // [K] 1/h_{j+1,j} or 0
+  int* active;      // [K]
+  int* kused;       // [K]
+  int* nactive;     // [1]
+};
+// start of a cycle: beta = sqrt(nrm2); g[0] = beta; active if beta > tol*bnorm;
+// scale = 1/beta or 0.
+void gmres_start(int nrhs, const double* nrm2, double rtol, GmresState s, hipStream_t st);
+void gmres_givens(int nrhs, int m, int j, const double* h1, const double* h2,
+                  const double* nrm2, double rtol, GmresState s, hipStream_t st);
+void gmres_solve_y(int nrhs, int m, GmresState s, hipStream_t st);
+
+// physics
+void levelset_to_scale(int N, const double* phi, double eta, double void_scale, double* rho,
+                       double* s, float* s32, hipStream_t st);
+void density_to_scale(long nn, const double* rho, double void_scale, double* s, float* s32,
+                      hipStream_t st);
+// b = -sum_e s_e F0 e_L per node; absval: sum_e s_e |F0| (a magnitude reference)
+void build_rhs(int N, const double* s, const double* F0, double* b, hipStream_t st, bool absval = false);
+// partial sums for M^H: Y[(l,f),L] = sum_e s_e x_{node(e,l)}[f][L]; out[288] and
+// out[288] = sum_e s_e
+void reduce_effective(int N, const double* s, const double* X, double* out, double* work,
+                      hipStream_t st);
+void backward_elem(int N, const double* X, const double* K0, const double* FW, double cterm,
+                   double factor, double* grad, hipStream_t st);
+void grad_phi(int N, const double* phi, double eta, const double* grad_rho, double* out,
+              hipStream_t st);
+void nodal_mean_of_elements(int N, const double* ge, double* vn, hipStream_t st);
+void max_abs(long count, const double* v, double* out, double* work, hipStream_t st);
+void hj_step(int N, const double* phi, const double* v, const double* vmax, double dt,
+             double* out, hipStream_t st);
+int count_nonfinite(long count, const double* v, double* work, hipStream_t st);
+// power iteration helper: v = w / sqrt(nrm2[0])
+template <typename T>
+void normalize_by(long count, const double* nrm2, const T* w, T* v, hipStream_t st);
+void hash_fill(long count, unsigned seed, double* v, hipStream_t st);
+
+}  // namespace phz

@@ -1,0 +1,1431 @@
+// Host runtime and C ABI of the periodic piezoelectric homogenisation solver.
+//
+// Solve path (Sec. 2.5.3 of the paper, SCP-GMRES):
+//   calA = [[A, B^T], [B, -C]],  P = [[A, 0], [B, -S_bar]],
+//   right-preconditioned GMRES(m) on calA P^-1, with
+//   P^-1 (r_u, r_p) = (z_u, z_p):  z_u = A^-1 r_u,  z_p = S_bar^-1 (B z_u - r_p).
+// A^-1 and S_bar^-1 are geometric-multigrid V-cycles (Galerkin coarse
+// operators, Chebyshev-Jacobi smoothing, dense coarsest solve), a fixed
+// number per application so that P^-1 is a fixed linear operator.
+// The nine load columns run either as one 9-column block (one operator
+// apply serves all nine; nine independent Arnoldi processes in lockstep with
+// per-column convergence masks) or one at a time.
+// The FP32_IR form runs the same GMRES in float (operator, smoothers and
+// Krylov basis; float64 inner products, Hessenberg and Givens) as the inner
+// solver of float64 iterative refinement on the true residual.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "common.hpp"
+#include "piezohom.h"
+#include "refelem.hpp"
+
+namespace phz {
+
+template <typename T>
+struct DevBuf {
+  T* p = nullptr;
+  size_t n = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  ~DevBuf() { release(); }
+  void release() {
+    if (p) hipFree(p);
+    p = nullptr;
+    n = 0;
+  }
+  void alloc(size_t count) {
+    if (count == n && p) return;
+    release();
+    if (count == 0) return;
+    hipError_t e = hipMalloc(&p, count * sizeof(T));
+    if (e != hipSuccess) {
+      p = nullptr;
+      throw HipError(std::string("hipMalloc of ") + std::to_string(count * sizeof(T)) +
+                     " bytes: " + hipGetErrorString(e));
+    }
+    n = count;
+  }
+  void upload(const T* h, size_t count, hipStream_t st) {
+    alloc(count);
+    PHZ_HIP(hipMemcpyAsync(p, h, count * sizeof(T), hipMemcpyHostToDevice, st));
+  }
+};
+
+struct Level {
+  int N = 0;
+  long nn = 0;
+  DevBuf<double> Ae;      // Galerkin element matrices (levels >= 1)
+  DevBuf<float> Ae32;
+  DevBuf<double> Dinv;    // node-block diagonal inverse
+  DevBuf<float> Dinv32;
+  double lmax = 0.0;
+};
+
+struct Hierarchy {
+  int F = 0;              // 3 for A, 1 for S_bar
+  int op = 0;             // fine-level operator id
+  std::vector<std::unique_ptr<Level>> lv;
+  int rows = 0;           // coarsest dense size
+  DevBuf<double> Minv;
+};
+
+template <typename T>
+struct LevelWork {
+  DevBuf<T> b, x, r, d;
+};
+
+template <typename T>
+struct Work {
+  int cap_k = 0, cap_m = 0;
+  std::vector<std::unique_ptr<LevelWork<T>>> A, S;
+  DevBuf<T> ru, rp, zu, zp, t1u, t2u, t1p, t2p;   // preconditioner temporaries
+  DevBuf<T> V, w, z, t, r, b, x;                  // GMRES
+};
+
+}  // namespace phz
+
+struct phz_ctx {
+  int N = 0;
+  long nn = 0;
+  phz_material mat{};
+  phz_options opt{};
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  std::string err;
+
+  phz::RefElement ref;
+  phz::DevBuf<double> kref_full, kref_A, kref_B, kref_S, F0d;
+  phz::DevBuf<float> kref32_full, kref32_A, kref32_B, kref32_S;
+
+  phz::DevBuf<double> phi, rho, s, grad_rho, tmp_nodes;
+  phz::DevBuf<float> s32;
+  bool have_phi = false, have_s = false, have_solution = false, have_grad = false;
+  bool precond_ready = false;
+  bool have_guess = false;
+
+  phz::Hierarchy hA, hS;
+  phz::Work<double> w64;
+  phz::Work<float> w32;
+
+  phz::DevBuf<double> X, Bvec, R64, guess, col_b, col_x, col_r;  // [nn][4][9] and columns
+  phz::DevBuf<double> red_work, small;   // reduction scratch, small device values
+  phz::DevBuf<double> gm_H, gm_cs, gm_sn, gm_g, gm_y, gm_est, gm_bnorm, gm_scale, gm_h1, gm_h2, gm_nrm;
+  phz::DevBuf<int> gm_int;
+
+  // optional per-kernel timing with HIP events on the context stream
+  bool ktime = false;
+  std::vector<hipEvent_t> ev;           // start/stop pairs
+  std::vector<std::string> ev_name;
+  size_t ev_used = 0;
+  std::map<std::string, std::pair<long, double>> ktotals;
+
+  double MH[81] = {0}, MHe[81] = {0};
+  std::vector<double> hist[9];
+  phz_stats stats{};
+};
+
+namespace phz {
+
+static const char* kStatusNames[] = {"ok", "not converged", "invalid argument", "NaN or Inf",
+                                     "HIP runtime error", "out of memory", "invalid state",
+                                     "internal error"};
+
+using Clock = std::chrono::steady_clock;
+static double ms_since(Clock::time_point t0) {
+  return std::chrono::duration<double, std::milli>(Clock::now() - t0).count();
+}
+
+static void sync(phz_ctx* c) { PHZ_HIP(hipStreamSynchronize(c->stream)); }
+
+constexpr size_t kMaxTimedLaunches = 1 << 16;
+
+// Record a start event before a launch; returns the slot or -1.
+static long time_begin(phz_ctx* c, const char* name) {
+  if (!c->ktime || c->ev_used >= kMaxTimedLaunches) return -1;
+  const size_t i = c->ev_used++;
+  if (c->ev.size() < 2 * (i + 1)) {
+    hipEvent_t a, b;
+    PHZ_HIP(hipEventCreate(&a));
+    PHZ_HIP(hipEventCreate(&b));
+    c->ev.push_back(a);
+    c->ev.push_back(b);
+    c->ev_name.emplace_back();
+  }
+  c->ev_name[i] = name;
+  PHZ_HIP(hipEventRecord(c->ev[2 * i], c->stream));
+  return (long)i;
+}
+static void time_end(phz_ctx* c, long slot) {
+  if (slot < 0) return;
+  PHZ_HIP(hipEventRecord(c->ev[2 * slot + 1], c->stream));
+}
+// Fold recorded launch durations into the per-name totals (after a sync).
+static void collect_timing(phz_ctx* c) {
+  for (size_t i = 0; i < c->ev_used; ++i) {
+    float ms = 0.0f;
+    PHZ_HIP(hipEventElapsedTime(&ms, c->ev[2 * i], c->ev[2 * i + 1]));
+    auto& t = c->ktotals[c->ev_name[i]];
+    t.first += 1;
+    t.second += ms;
+  }
+  c->ev_used = 0;
+}
+
+// ------------------------------------------------------------------ setup
+static void upload_reference(phz_ctx* c) {
+  c->ref = build_ref_element(c->mat, 1.0 / c->N);
+  const RefElement& R = c->ref;
+  hipStream_t st = c->stream;
+  c->kref_full.upload(R.K0, 32 * 32, st);
+  c->kref_A.upload(R.A0, 24 * 24, st);
+  c->kref_B.upload(R.B0, 8 * 24, st);
+  c->kref_S.upload(R.S0, 8 * 8, st);
+  c->F0d.upload(R.F0, 32 * 9, st);
+  std::vector<float> f(32 * 32);
+  auto up32 = [&](DevBuf<float>& d, const double* h, int n) {
+    for (int i = 0; i < n; ++i) f[i] = (float)h[i];
+    d.upload(f.data(), n, st);
+    sync(c);
+  };
+  up32(c->kref32_full, R.K0, 32 * 32);
+  up32(c->kref32_A, R.A0, 24 * 24);
+  up32(c->kref32_B, R.B0, 8 * 24);
+  up32(c->kref32_S, R.S0, 8 * 8);
+}
+
+static void build_levels(phz_ctx* c, Hierarchy& H, int F, int op) {
+  H.F = F;
+  H.op = op;
+  H.lv.clear();
+  int N = c->N;
+  const int maxl = c->opt.mg_levels > 0 ? c->opt.mg_levels : 64;
+  for (int l = 0;; ++l) {
+    auto L = std::make_unique<Level>();
+    L->N = N;
+    L->nn = (long)N * N * N;
+    H.lv.push_back(std::move(L));
+    if (!(N % 2 == 0 && N > 4 && (int)H.lv.size() < maxl)) break;
+    N /= 2;
+  }
+}
+
+template <typename T>
+static void alloc_work(phz_ctx* c, Work<T>& W, int K, int m) {
+  if (W.cap_k >= K && W.cap_m >= m && !W.A.empty()) return;
+  const long nn = c->nn;
+  auto mk = [&](Hierarchy& H, std::vector<std::unique_ptr<LevelWork<T>>>& out) {
+    out.clear();
+    for (size_t l = 0; l < H.lv.size(); ++l) {
+      auto w = std::make_unique<LevelWork<T>>();
+      const size_t cnt = (size_t)H.lv[l]->nn * H.F * K;
+      w->r.alloc(cnt);
+      w->d.alloc(cnt);
+      if (l > 0) {
+        w->b.alloc(cnt);
+        w->x.alloc(cnt);
+      }
+      out.push_back(std::move(w));
+    }
+  };
+  mk(c->hA, W.A);
+  mk(c->hS, W.S);
+  const size_t u = (size_t)nn * 3 * K, p = (size_t)nn * K, full = (size_t)nn * 4 * K;
+  W.ru.alloc(u); W.zu.alloc(u); W.t1u.alloc(u); W.t2u.alloc(u);
+  W.rp.alloc(p); W.zp.alloc(p); W.t1p.alloc(p); W.t2p.alloc(p);
+  W.V.alloc(full * (m + 1));
+  W.w.alloc(full); W.z.alloc(full); W.t.alloc(full); W.r.alloc(full); W.b.alloc(full); W.x.alloc(full);
+  W.cap_k = K;
+  W.cap_m = m;
+}
+
+static void ensure_state_buffers(phz_ctx* c) {
+  const int m = c->opt.restart, K = 9;
+  c->gm_H.alloc((size_t)(m + 1) * m * K);
+  c->gm_cs.alloc((size_t)m * K);
+  c->gm_sn.alloc((size_t)m * K);
+  c->gm_g.alloc((size_t)(m + 1) * K);
+  c->gm_y.alloc((size_t)m * K);
+  c->gm_est.alloc((size_t)m * K);
+  c->gm_bnorm.alloc(K);
+  c->gm_scale.alloc(K);
+  c->gm_h1.alloc((size_t)(kMaxRestart + 1) * K);
+  c->gm_h2.alloc((size_t)(kMaxRestart + 1) * K);
+  c->gm_nrm.alloc(4 * K);
+  c->gm_int.alloc(3 * K + 1);
+  c->red_work.alloc(reduce_work_size(400));
+  c->small.alloc(512);
+}
+
+static GmresState gm_state(phz_ctx* c) {
+  GmresState s;
+  s.H = c->gm_H.p;
+  s.cs = c->gm_cs.p;
+  s.sn = c->gm_sn.p;
+  s.g = c->gm_g.p;
+  s.y = c->gm_y.p;
+  s.est = c->gm_est.p;
+  s.bnorm = c->gm_bnorm.p;
+  s.scale = c->gm_scale.p;
+  s.active = c->gm_int.p;
+  s.kused = c->gm_int.p + 9;
+  s.nactive = c->gm_int.p + 27;
+  return s;
+}
+
+// ---------------------------------------------------------- level operators
+template <typename T> static const T* kref_of(phz_ctx* c, int op);
+template <> const double* kref_of<double>(phz_ctx* c, int op) {
+  return op == 0 ? c->kref_full.p : op == 1 ? c->kref_A.p : op == 2 ? c->kref_B.p : c->kref_S.p;
+}
+template <> const float* kref_of<float>(phz_ctx* c, int op) {
+  return op == 0 ? c->kref32_full.p : op == 1 ? c->kref32_A.p : op == 2 ? c->kref32_B.p : c->kref32_S.p;
+}
+template <typename T> static const T* s_of(phz_ctx* c);
+template <> const double* s_of<double>(phz_ctx* c) { return c->s.p; }
+template <> const float* s_of<float>(phz_ctx* c) { return c->s32.p; }
+template <typename T> static const T* ae_of(Level& L);
+template <> const double* ae_of<double>(Level& L) { return L.Ae.p; }
+template <> const float* ae_of<float>(Level& L) { return L.Ae32.p; }
+template <typename T> static const T* dinv_of(Level& L);
+template <> const double* dinv_of<double>(Level& L) { return L.Dinv.p; }
+template <> const float* dinv_of<float>(Level& L) { return L.Dinv32.p; }
+template <typename T> static Work<T>& work_of(phz_ctx* c);
+template <> Work<double>& work_of<double>(phz_ctx* c) { return c->w64; }
+template <> Work<float>& work_of<float>(phz_ctx* c) { return c->w32; }
+
+// y = beta*yin + alpha*A_l x
+static const char* kOpNames[4][2][2] = {
+    {{"fine_full_k1_f64", "fine_full_k1_f32"}, {"fine_full_k9_f64", "fine_full_k9_f32"}},
+    {{"fine_A_k1_f64", "fine_A_k1_f32"}, {"fine_A_k9_f64", "fine_A_k9_f32"}},
+    {{"fine_B_k1_f64", "fine_B_k1_f32"}, {"fine_B_k9_f64", "fine_B_k9_f32"}},
+    {{"fine_S_k1_f64", "fine_S_k1_f32"}, {"fine_S_k9_f64", "fine_S_k9_f32"}}};
+
+// fine-level operator launch with optional timing
+template <typename T>
+static void op_apply(phz_ctx* c, int op, int K, const T* x, const T* yin, T* y, T alpha, T beta) {
+  const long slot = time_begin(c, kOpNames[op][K == 9][sizeof(T) == 4]);
+  fine_apply<T>(op, K, c->N, s_of<T>(c), kref_of<T>(c, op), x, yin, y, alpha, beta, c->stream);
+  time_end(c, slot);
+}
+
+template <typename T>
+static void level_apply(phz_ctx* c, Hierarchy& H, int l, int K, const T* x, const T* yin, T* y, T alpha,
+                        T beta) {
+  Level& L = *H.lv[l];
+  if (l == 0) {
+    op_apply<T>(c, H.op, K, x, yin, y, alpha, beta);
+  } else {
+    const long slot = time_begin(c, H.F == 3 ? (sizeof(T) == 4 ? "coarse_A_f32" : "coarse_A_f64")
+                                             : (sizeof(T) == 4 ? "coarse_S_f32" : "coarse_S_f64"));
+    coarse_apply<T>(H.F, K, L.N, ae_of<T>(L), x, yin, y, alpha, beta, c->stream);
+    time_end(c, slot);
+  }
+}
+
+// ------------------------------------------------------- multigrid set-up
+static void host_element_matrices(phz_ctx* c, Hierarchy& H, int l, std::vector<double>& Ae) {
+  Level& L = *H.lv[l];
+  const int F = H.F, S = 8 * F;
+  Ae.assign((size_t)8 * L.nn * F * S, 0.0);
+  if (l == 0) {
+    std::vector<double> sh(L.nn);
+    PHZ_HIP(hipMemcpyAsync(sh.data(), c->s.p, L.nn * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    sync(c);
+    const double* kref = F == 3 ? c->ref.A0 : c->ref.S0;
+    for (int Lc = 0; Lc < 8; ++Lc)
+      for (long e = 0; e < L.nn; ++e)
+        for (int f = 0; f < F; ++f)
+          for (int col = 0; col < S; ++col)
+            Ae[(((size_t)Lc * L.nn + e) * F + f) * S + col] = sh[e] * kref[(Lc * F + f) * S + col];
+  } else {
+    PHZ_HIP(hipMemcpyAsync(Ae.data(), L.Ae.p, Ae.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    sync(c);
+  }
+}
+
+static void build_coarsest(phz_ctx* c, Hierarchy& H) {
+  const int l = (int)H.lv.size() - 1;
+  Level& L = *H.lv[l];
+  const int F = H.F, S = 8 * F, N = L.N;
+  std::vector<double> Ae;
+  host_element_matrices(c, H, l, Ae);
+  const int rows = (int)(F * L.nn);
+  std::vector<double> M((size_t)rows * rows, 0.0);
+  for (long e = 0; e < L.nn; ++e) {
+    const int i = (int)(e % N), j = (int)((e / N) % N), k = (int)(e / ((long)N * N));
+    long node[8];
+    for (int q = 0; q < 8; ++q)
+      node[q] = ((i + (q & 1)) % N) + (long)N * (((j + ((q >> 1) & 1)) % N) + (long)N * ((k + ((q >> 2) & 1)) % N));
+    for (int Lc = 0; Lc < 8; ++Lc)
+      for (int f = 0; f < F; ++f)
+        for (int Lp = 0; Lp < 8; ++Lp)
+          for (int g = 0; g < F; ++g)
+            M[(size_t)(node[Lc] * F + f) * rows + node[Lp] * F + g] +=
+                Ae[(((size_t)Lc * L.nn + e) * F + f) * S + Lp * F + g];
+  }
+  // the periodic kernel is the constant field of each component; add
+  // alpha/nn * 1 1^T per component so the matrix is SPD and zero-mean
+  // right-hand sides give zero-mean solutions
+  double tr = 0.0;
+  for (int r = 0; r < rows; ++r) tr += M[(size_t)r * rows + r];
+  const double alpha = tr / rows / (double)L.nn;
+  for (long n = 0; n < L.nn; ++n)
+    for (long m2 = 0; m2 < L.nn; ++m2)
+      for (int f = 0; f < F; ++f) M[(size_t)(n * F + f) * rows + m2 * F + f] += alpha;
+  if (!spd_inverse(rows, M)) throw std::runtime_error("coarsest multigrid matrix is not positive definite");
+  H.rows = rows;
+  H.Minv.upload(M.data(), M.size(), c->stream);
+  sync(c);
+}
+
+static double power_lmax(phz_ctx* c, Hierarchy& H, int l) {
+  Level& L = *H.lv[l];
+  const long cnt = L.nn * H.F;
+  DevBuf<double> v, w;
+  v.alloc(cnt);
+  w.alloc(cnt);
+  double* nrm = c->small.p;
+  hash_fill(cnt, 12345u + 7u * l + 101u * H.F, v.p, c->stream);
+  col_norm2<double>(cnt, 1, v.p, nrm, c->red_work.p, c->stream);
+  normalize_by<double>(cnt, nrm, v.p, v.p, c->stream);
+  const int iters = 20;
+  for (int it = 0; it < iters; ++it) {
+    level_apply<double>(c, H, l, 1, v.p, nullptr, w.p, 1.0, 0.0);
+    cheby_step<double>(H.F, 1, L.nn, L.Dinv.p, w.p, w.p, w.p, 0.0, 1.0, true, c->stream);
+    col_norm2<double>(cnt, 1, w.p, nrm, c->red_work.p, c->stream);
+    normalize_by<double>(cnt, nrm, w.p, v.p, c->stream);
+  }
+  double h = 0.0;
+  PHZ_HIP(hipMemcpyAsync(&h, nrm, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  sync(c);
+  return std::sqrt(h);
+}
+
+static void setup_hierarchy(phz_ctx* c, Hierarchy& H) {
+  const int F = H.F;
+  const double* krefd = F == 3 ? c->kref_A.p : c->kref_S.p;
+  const int nl = (int)H.lv.size();
+  for (int l = 0; l < nl; ++l) {
+    Level& L = *H.lv[l];
+    if (l > 0) {
+      L.Ae.alloc((size_t)8 * L.nn * F * 8 * F);
+      if (l == 1)
+        galerkin_build(F, H.lv[0]->N, c->s.p, krefd, nullptr, L.Ae.p, c->stream);
+      else
+        galerkin_build(F, H.lv[l - 1]->N, nullptr, nullptr, H.lv[l - 1]->Ae.p, L.Ae.p, c->stream);
+    }
+    if (l < nl - 1) {
+      L.Dinv.alloc((size_t)L.nn * F * F);
+      if (l == 0) diag_inv_fine(F, L.N, c->s.p, krefd, L.Dinv.p, c->stream);
+      else diag_inv_coarse(F, L.N, L.Ae.p, L.Dinv.p, c->stream);
+    }
+  }
+  for (int l = 0; l < nl - 1; ++l) H.lv[l]->lmax = power_lmax(c, H, l);
+  build_coarsest(c, H);
+  if (c->opt.precision == PHZ_FP32_IR) {
+    for (int l = 0; l < nl; ++l) {
+      Level& L = *H.lv[l];
+      if (L.Ae.p) {
+        L.Ae32.alloc(L.Ae.n);
+        convert<double, float>((long)L.Ae.n, L.Ae.p, L.Ae32.p, c->stream);
+      }
+      if (L.Dinv.p) {
+        L.Dinv32.alloc(L.Dinv.n);
+        convert<double, float>((long)L.Dinv.n, L.Dinv.p, L.Dinv32.p, c->stream);
+      }
+    }
+  }
+}
+
+template <typename T>
+static void drop_level_work_if_changed(phz_ctx* c, Work<T>& W) {
+  if (W.A.size() != c->hA.lv.size() || W.S.size() != c->hS.lv.size()) {
+    W.A.clear();
+    W.S.clear();
+    W.cap_k = 0;
+  }
+}
+
+static void setup_preconditioner(phz_ctx* c) {
+  if (c->precond_ready) return;
+  build_levels(c, c->hA, 3, 1);
+  build_levels(c, c->hS, 1, 3);
+  drop_level_work_if_changed(c, c->w64);
+  drop_level_work_if_changed(c, c->w32);
+  setup_hierarchy(c, c->hA);
+  setup_hierarchy(c, c->hS);
+  sync(c);
+  c->precond_ready = true;
+  c->stats.mg_levels = (int)c->hA.lv.size();
+  int q = 0;
+  for (auto& L : c->hA.lv)
+    if (q < 16) c->stats.cheb_lambda[q++] = L->lmax;
+  for (auto& L : c->hS.lv)
+    if (q < 16) c->stats.cheb_lambda[q++] = L->lmax;
+}
+
+// ---------------------------------------------------------------- V-cycle
+template <typename T>
+static void cheby_smooth(phz_ctx* c, Hierarchy& H, int l, int K, const T* b, T* x, bool xzero,
+                         LevelWork<T>& W) {
+  Level& L = *H.lv[l];
+  const int deg = std::max(1, c->opt.cheby_degree);
+  const double hi = 1.1 * L.lmax, lo = 0.15 * L.lmax;
+  const double theta = 0.5 * (hi + lo), delta = 0.5 * (hi - lo), sigma = theta / delta;
+  double rho = 1.0 / sigma;
+  const T* r = b;
+  if (!xzero) {
+    level_apply<T>(c, H, l, K, x, b, W.r.p, T(-1), T(1));
+    r = W.r.p;
+  }
+  cheby_step<T>(H.F, K, L.nn, dinv_of<T>(L), r, W.d.p, x, T(0), T(1.0 / theta), xzero, c->stream);
+  for (int i = 1; i < deg; ++i) {
+    level_apply<T>(c, H, l, K, W.d.p, r, W.r.p, T(-1), T(1));
+    r = W.r.p;
+    const double rho_new = 1.0 / (2.0 * sigma - rho);
+    cheby_step<T>(H.F, K, L.nn, dinv_of<T>(L), r, W.d.p, x, T(rho_new * rho), T(2.0 * rho_new / delta), false,
+                  c->stream);
+    rho = rho_new;
+  }
+}
+
+// x = V-cycle approximation of A_l^-1 b (zero initial guess)
+template <typename T>
+static void vcycle(phz_ctx* c, Hierarchy& H, std::vector<std::unique_ptr<LevelWork<T>>>& WL, int l, int K,
+                   const T* b, T* x) {
+  const int nl = (int)H.lv.size();
+  if (l == nl - 1) {
+    dense_apply<T>(H.rows, K, H.Minv.p, b, x, c->stream);
+    return;
+  }
+  LevelWork<T>& W = *WL[l];
+  LevelWork<T>& Wc = *WL[l + 1];
+  cheby_smooth<T>(c, H, l, K, b, x, true, W);
+  level_apply<T>(c, H, l, K, x, b, W.r.p, T(-1), T(1));
+  restrict_fw<T>(H.F, K, H.lv[l + 1]->N, W.r.p, Wc.b.p, c->stream);
+  vcycle<T>(c, H, WL, l + 1, K, Wc.b.p, Wc.x.p);
+  prolong_add<T>(H.F, K, H.lv[l + 1]->N, Wc.x.p, x, c->stream);
+  cheby_smooth<T>(c, H, l, K, b, x, false, W);
+}
+
+// x = (ncycles V-cycles) A^-1 b
+template <typename T>
+static void block_solve(phz_ctx* c, Hierarchy& H, std::vector<std::unique_ptr<LevelWork<T>>>& WL, int K,
+                        int ncycles, const T* b, T* x, T* tmp_r, T* tmp_e) {
+  vcycle<T>(c, H, WL, 0, K, b, x);
+  const long cnt = H.lv[0]->nn * H.F;
+  for (int it = 1; it < ncycles; ++it) {
+    level_apply<T>(c, H, 0, K, x, b, tmp_r, T(-1), T(1));
+    vcycle<T>(c, H, WL, 0, K, tmp_r, tmp_e);
+    axpy_cols<T, T>(cnt, K, nullptr, tmp_e, x, c->stream);
+  }
+}
+
+// z = P^-1 r on [nn][4][K]
+template <typename T>
+static void precond_apply(phz_ctx* c, int K, const T* r, T* z) {
+  Work<T>& W = work_of<T>(c);
+  const long nn = c->nn;
+  split_fields<T>(nn, K, r, W.ru.p, W.rp.p, c->stream);
+  block_solve<T>(c, c->hA, W.A, K, std::max(1, c->opt.vcycles_a), W.ru.p, W.zu.p, W.t1u.p, W.t2u.p);
+  // t = B z_u - r_p
+  op_apply<T>(c, 2, K, W.zu.p, W.rp.p, W.t1p.p, T(1), T(-1));
+  block_solve<T>(c, c->hS, W.S, K, std::max(1, c->opt.vcycles_s), W.t1p.p, W.zp.p, W.t2p.p, W.rp.p);
+  merge_fields<T>(nn, K, W.zu.p, W.zp.p, z, c->stream);
+}
+
+// ------------------------------------------------------------------ GMRES
+struct GmresResult {
+  int iters[9] = {0};
+  int restarts[9] = {0};
+  double true_rel[9] = {0};
+  bool converged = false;
+};
+
+// Solve calA x = b (x holds the initial guess), K columns, storage T.
+// true residuals are evaluated in T (the caller refines in float64 if T is float).
+// x_is_zero: skip the first residual apply (r = b).  one_cycle: run one
+// restart cycle only and leave the true residual to the caller (float64
+// iterative refinement evaluates it in float64).
+template <typename T>
+static GmresResult gmres(phz_ctx* c, int K, const T* b, T* x, double rtol, int maxit, int hist_base,
+                         bool record_hist, bool x_is_zero = false, bool one_cycle = false) {
+  Work<T>& W = work_of<T>(c);
+  const long rows = c->nn * 4;
+  const long vs = rows * K;
+  const int m = c->opt.restart;
+  GmresState S = gm_state(c);
+  hipStream_t st = c->stream;
+  GmresResult res;
+  double* nrm = c->gm_nrm.p;
+  // ||b||
+  col_norm2<T>(rows, K, b, nrm, c->red_work.p, st);
+  {
+    std::vector<double> h(K);
+    PHZ_HIP(hipMemcpyAsync(h.data(), nrm, K * sizeof(double), hipMemcpyDeviceToHost, st));
+    sync(c);
+    for (int k = 0; k < K; ++k) h[k] = std::sqrt(h[k]);
+    PHZ_HIP(hipMemcpyAsync(S.bnorm, h.data(), K * sizeof(double), hipMemcpyHostToDevice, st));
+    sync(c);
+  }
+  int total = 0;
+  std::vector<double> estbuf((size_t)m * K), rn(K), bn(K);
+  std::vector<int> kused(K), act(K);
+  PHZ_HIP(hipMemcpyAsync(bn.data(), S.bnorm, K * sizeof(double), hipMemcpyDeviceToHost, st));
+  sync(c);
+  for (int cycle = 0;; ++cycle) {
+    // r = b - calA x
+    if (cycle == 0 && x_is_zero)
+      PHZ_HIP(hipMemcpyAsync(W.r.p, b, (size_t)vs * sizeof(T), hipMemcpyDeviceToDevice, st));
+    else
+      op_apply<T>(c, 0, K, x, b, W.r.p, T(-1), T(1));
+    col_norm2<T>(rows, K, W.r.p, nrm, c->red_work.p, st);
+    gmres_start(K, nrm, rtol, S, st);
+    PHZ_HIP(hipMemcpyAsync(rn.data(), nrm, K * sizeof(double), hipMemcpyDeviceToHost, st));
+    int nact = 0;
+    PHZ_HIP(hipMemcpyAsync(&nact, S.nactive, sizeof(int), hipMemcpyDeviceToHost, st));
+    sync(c);
+    for (int k = 0; k < K; ++k) {
+      res.true_rel[k] = bn[k] > 0 ? std::sqrt(rn[k]) / bn[k] : 0.0;
+      if (record_hist) c->hist[hist_base + k].push_back(res.true_rel[k]);
+    }
+    if (nact == 0) {
+      res.converged = true;
+      for (int k = 0; k < K; ++k)
+        if (!(res.true_rel[k] <= rtol) && bn[k] > 0) res.converged = false;
+      break;
+    }
+    if (total >= maxit) break;
+    for (int k = 0; k < K; ++k)
+      if (bn[k] > 0 && !(res.true_rel[k] <= rtol)) res.restarts[k] += 1;
+    // V_0 = r / beta
+    scale_cols<T>(rows, K, W.r.p, S.scale, W.V.p, st);
+    int j = 0;
+    for (; j < m; ++j) {
+      T* Vj = W.V.p + (size_t)j * vs;
+      const long tp = time_begin(c, sizeof(T) == 4 ? "precond_f32" : "precond_f64");
+      precond_apply<T>(c, K, Vj, W.z.p);
+      time_end(c, tp);
+      op_apply<T>(c, 0, K, W.z.p, (const T*)nullptr, W.w.p, T(1), T(0));
+      // classical Gram-Schmidt, twice
+      const long ts = time_begin(c, sizeof(T) == 4 ? "arnoldi_cgs2_f32" : "arnoldi_cgs2_f64");
+      arnoldi_dots<T>(rows, K, j, W.V.p, vs, W.w.p, c->gm_h1.p, c->red_work.p, st);
+      arnoldi_update<T>(rows, K, j, W.V.p, vs, W.w.p, c->gm_h1.p, c->gm_h2.p, nullptr, c->red_work.p, st);
+      arnoldi_update<T>(rows, K, j, W.V.p, vs, W.w.p, c->gm_h2.p, nullptr, nrm, c->red_work.p, st);
+      time_end(c, ts);
+      gmres_givens(K, m, j, c->gm_h1.p, c->gm_h2.p, nrm, rtol, S, st);
+      scale_cols<T>(rows, K, W.w.p, S.scale, W.V.p + (size_t)(j + 1) * vs, st);
+      ++total;
+      PHZ_HIP(hipMemcpyAsync(&nact, S.nactive, sizeof(int), hipMemcpyDeviceToHost, st));
+      sync(c);
+      if (nact == 0 || total >= maxit) {
+        ++j;
+        break;
+      }
+    }
+    // x += P^-1 (V y)
+    gmres_solve_y(K, m, S, st);
+    combine<T>(rows, K, m, W.V.p, vs, S.y, S.kused, W.t.p, st);
+    precond_apply<T>(c, K, W.t.p, W.z.p);
+    axpy_cols<T, T>(rows, K, nullptr, W.z.p, x, st);
+    PHZ_HIP(hipMemcpyAsync(kused.data(), S.kused, K * sizeof(int), hipMemcpyDeviceToHost, st));
+    PHZ_HIP(hipMemcpyAsync(estbuf.data(), S.est, (size_t)m * K * sizeof(double), hipMemcpyDeviceToHost, st));
+    sync(c);
+    for (int k = 0; k < K; ++k) {
+      res.iters[k] += kused[k];
+      if (record_hist)
+        for (int i = 0; i < kused[k]; ++i) c->hist[hist_base + k].push_back(estbuf[(size_t)i * K + k]);
+    }
+    if (one_cycle) {
+      res.converged = false;
+      for (int k = 0; k < K; ++k) {
+        res.true_rel[k] = kused[k] > 0 ? estbuf[(size_t)(kused[k] - 1) * K + k] : res.true_rel[k];
+        if (kused[k] > 0) res.restarts[k] = 1;
+      }
+      break;
+    }
+  }
+  return res;
+}
+
+// ------------------------------------------------------------ solve paths
+static void solve_fp64(phz_ctx* c, int K, const double* b, double* x, double rtol, int hist_base, GmresResult& out) {
+  alloc_work<double>(c, c->w64, K, c->opt.restart);
+  out = gmres<double>(c, K, b, x, rtol, c->opt.max_iters, hist_base, true);
+}
+
+// float64 iterative refinement around the float GMRES
+static int solve_ir(phz_ctx* c, int K, const double* b, double* x, double rtol, int hist_base, GmresResult& out) {
+  alloc_work<float>(c, c->w32, K, c->opt.restart);
+  Work<float>& W = c->w32;
+  const long rows = c->nn * 4;
+  hipStream_t st = c->stream;
+  double* nrm = c->gm_nrm.p + 9;
+  std::vector<double> bn(K), rn(K), scale(K), inv(K);
+  col_norm2<double>(rows, K, b, nrm, c->red_work.p, st);
+  PHZ_HIP(hipMemcpyAsync(bn.data(), nrm, K * sizeof(double), hipMemcpyDeviceToHost, st));
+  sync(c);
+  for (int k = 0; k < K; ++k) bn[k] = std::sqrt(bn[k]);
+  DevBuf<double>& r64 = c->R64;
+  double* scp = c->gm_nrm.p + 18;
+  int steps = 0;
+  int used = 0;
+  for (;;) {
+    // r = b - calA x in float64
+    op_apply<double>(c, 0, K, x, b, r64.p, -1.0, 1.0);
+    col_norm2<double>(rows, K, r64.p, nrm, c->red_work.p, st);
+    PHZ_HIP(hipMemcpyAsync(rn.data(), nrm, K * sizeof(double), hipMemcpyDeviceToHost, st));
+    sync(c);
+    bool done = true;
+    for (int k = 0; k < K; ++k) {
+      rn[k] = std::sqrt(rn[k]);
+      out.true_rel[k] = bn[k] > 0 ? rn[k] / bn[k] : 0.0;
+      c->hist[hist_base + k].push_back(out.true_rel[k]);
+      if (bn[k] > 0 && !(out.true_rel[k] <= rtol)) done = false;
+      if (!std::isfinite(rn[k])) throw std::runtime_error("non-finite residual in refinement");
+    }
+    if (done) {
+      out.converged = true;
+      break;
+    }
+    if (steps >= c->opt.max_refine || used >= c->opt.max_iters) break;
+    // solve calA d = r / ||r|| in float, x += ||r|| d
+    for (int k = 0; k < K; ++k) {
+      const bool act = bn[k] > 0 && !(out.true_rel[k] <= rtol);
+      scale[k] = act ? rn[k] : 0.0;
+      inv[k] = act ? 1.0 / rn[k] : 0.0;
+    }
+    PHZ_HIP(hipMemcpyAsync(scp, inv.data(), K * sizeof(double), hipMemcpyHostToDevice, st));
+    scale_cols<double>(rows, K, r64.p, scp, r64.p, st);
+    convert<double, float>(rows * K, r64.p, W.b.p, st);
+    fill<float>(rows * K, 0.0f, W.x.p, st);
+    GmresResult g = gmres<float>(c, K, W.b.p, W.x.p, c->opt.inner_rtol, c->opt.max_iters - used, hist_base, true,
+                                 true, true);
+    PHZ_HIP(hipMemcpyAsync(scp, scale.data(), K * sizeof(double), hipMemcpyHostToDevice, st));
+    axpy_cols<double, float>(rows, K, scp, W.x.p, x, st);
+    sync(c);
+    int mx = 0;
+    for (int k = 0; k < K; ++k) {
+      out.iters[k] += g.iters[k];
+      out.restarts[k] += g.restarts[k];
+      mx = std::max(mx, g.iters[k]);
+    }
+    used += std::max(mx, 1);
+    ++steps;
+  }
+  return steps;
+}
+
+static void compute_effective(phz_ctx* c) {
+  hipStream_t st = c->stream;
+  const long nn = c->nn;
+  // zero-mean fields (gauge); tensors do not depend on it
+  double* sums = c->small.p;
+  field_sums<double>(nn, 4, 9, c->X.p, sums, c->red_work.p, st);
+  subtract_mean<double>(nn, 4, 9, sums, c->X.p, st);
+  double* out = c->small.p + 64;
+  reduce_effective(c->N, c->s.p, c->X.p, out, c->red_work.p, st);
+  std::vector<double> red(289);
+  PHZ_HIP(hipMemcpyAsync(red.data(), out, 289 * sizeof(double), hipMemcpyDeviceToHost, st));
+  sync(c);
+  const double h3 = std::pow(1.0 / c->N, 3);
+  const double ssum = red[288];
+  const RefElement& R = c->ref;
+  double FY[81];
+  for (int K = 0; K < 9; ++K)
+    for (int L = 0; L < 9; ++L) {
+      double v = 0.0;
+      for (int l = 0; l < 8; ++l)
+        for (int f = 0; f < 4; ++f) v += R.F0[(4 * l + f) * 9 + K] * red[l * 36 + f * 9 + L];
+      FY[K * 9 + L] = v;
+    }
+  for (int K = 0; K < 9; ++K)
+    for (int L = 0; L < 9; ++L) c->MH[K * 9 + L] = h3 * ssum * R.M[K * 9 + L] + FY[K * 9 + L];
+  // energy form: <s>M + FY + FY^T + X^T calA X
+  fine_apply<double>(0, 9, c->N, c->s.p, c->kref_full.p, c->X.p, nullptr, c->R64.p, 1.0, 0.0, st);
+  // cross dots X[:,K] . (calA X)[:,L] through the Arnoldi dot kernel on
+  // single columns would need 81 passes; use a host-side 9x9 from column
+  // extractions instead
+  std::vector<double> XtAX(81, 0.0);
+  {
+    DevBuf<double> xc, ac;
+    xc.alloc(nn * 4);
+    ac.alloc(nn * 4);
+    for (int K = 0; K < 9; ++K) {
+      extract_column(nn, K, c->X.p, xc.p, st);
+      // V = xc (one basis vector), w = calA X column L: use arnoldi_dots with j = 0
+      for (int L = 0; L < 9; ++L) {
+        extract_column(nn, L, c->R64.p, ac.p, st);
+        arnoldi_dots<double>(nn * 4, 1, 0, xc.p, 0, ac.p, c->small.p + 400 + K * 9 + L, c->red_work.p, st);
+      }
+    }
+    PHZ_HIP(hipMemcpyAsync(XtAX.data(), c->small.p + 400, 81 * sizeof(double), hipMemcpyDeviceToHost, st));
+    sync(c);
+  }
+  double mx = 0.0, df = 0.0;
+  for (int K = 0; K < 9; ++K)
+    for (int L = 0; L < 9; ++L) {
+      c->MHe[K * 9 + L] = h3 * ssum * R.M[K * 9 + L] + FY[K * 9 + L] + FY[L * 9 + K] + XtAX[K * 9 + L];
+      mx = std::max(mx, std::fabs(c->MH[K * 9 + L]));
+      df = std::max(df, std::fabs(c->MH[K * 9 + L] - c->MHe[K * 9 + L]));
+    }
+  c->stats.flux_energy_defect = mx > 0 ? df / mx : 0.0;
+}
+
+// b = -sum_e s_e F0 e_L, projected to zero mean per field (the exact load is
+// compatible; rounding is not), and columns that vanish in exact arithmetic
+// (below 1e-12 of the magnitude of the terms they sum) set to exactly zero,
+// so such loads return X = 0 without iterating on rounding noise.
+static void prepare_rhs(phz_ctx* c) {
+  hipStream_t st = c->stream;
+  const long nn = c->nn;
+  build_rhs(c->N, c->s.p, c->F0d.p, c->R64.p, st, true);
+  double* nb = c->small.p;
+  double* nref = c->small.p + 16;
+  col_norm2<double>(nn * 4, 9, c->R64.p, nref, c->red_work.p, st);
+  build_rhs(c->N, c->s.p, c->F0d.p, c->Bvec.p, st, false);
+  field_sums<double>(nn, 4, 9, c->Bvec.p, c->small.p + 32, c->red_work.p, st);
+  subtract_mean<double>(nn, 4, 9, c->small.p + 32, c->Bvec.p, st);
+  col_norm2<double>(nn * 4, 9, c->Bvec.p, nb, c->red_work.p, st);
+  double h[32];
+  PHZ_HIP(hipMemcpyAsync(h, c->small.p, 32 * sizeof(double), hipMemcpyDeviceToHost, st));
+  sync(c);
+  double keep[9];
+  for (int L = 0; L < 9; ++L) keep[L] = std::sqrt(h[L]) <= 1e-12 * std::sqrt(h[16 + L]) ? 0.0 : 1.0;
+  PHZ_HIP(hipMemcpyAsync(c->small.p + 80, keep, 9 * sizeof(double), hipMemcpyHostToDevice, st));
+  scale_cols<double>(nn * 4, 9, c->Bvec.p, c->small.p + 80, c->Bvec.p, st);
+  sync(c);
+}
+
+static int do_solve(phz_ctx* c) {
+  if (!c->have_s) {
+    c->err = "no geometry: call phz_set_levelset or phz_set_density first";
+    return PHZ_E_STATE;
+  }
+  const auto t0 = Clock::now();
+  hipStream_t st = c->stream;
+  const long nn = c->nn;
+  std::memset(c->stats.iterations, 0, sizeof(c->stats.iterations));
+  std::memset(c->stats.restarts, 0, sizeof(c->stats.restarts));
+  c->stats.refinements = 0;
+  for (auto& h : c->hist) h.clear();
+  ensure_state_buffers(c);
+  c->X.alloc(nn * 36);
+  c->Bvec.alloc(nn * 36);
+  c->R64.alloc(nn * 36);
+  const auto ts = Clock::now();
+  setup_preconditioner(c);
+  c->stats.setup_ms = ms_since(ts);
+  prepare_rhs(c);
+  if (c->have_guess)
+    PHZ_HIP(hipMemcpyAsync(c->X.p, c->guess.p, nn * 36 * sizeof(double), hipMemcpyDeviceToDevice, st));
+  else
+    fill<double>(nn * 36, 0.0, c->X.p, st);
+  const double rtol = c->opt.rtol;
+  bool conv = true;
+  if (c->opt.batched) {
+    GmresResult g;
+    if (c->opt.precision == PHZ_FP32_IR) c->stats.refinements = solve_ir(c, 9, c->Bvec.p, c->X.p, rtol, 0, g);
+    else solve_fp64(c, 9, c->Bvec.p, c->X.p, rtol, 0, g);
+    for (int k = 0; k < 9; ++k) {
+      c->stats.iterations[k] = g.iters[k];
+      c->stats.restarts[k] = g.restarts[k];
+      c->stats.true_residual[k] = g.true_rel[k];
+    }
+    conv = g.converged;
+  } else {
+    c->col_b.alloc(nn * 4);
+    c->col_x.alloc(nn * 4);
+    for (int L = 0; L < 9; ++L) {
+      extract_column(nn, L, c->Bvec.p, c->col_b.p, st);
+      extract_column(nn, L, c->X.p, c->col_x.p, st);
+      GmresResult g;
+      if (c->opt.precision == PHZ_FP32_IR) c->stats.refinements += solve_ir(c, 1, c->col_b.p, c->col_x.p, rtol, L, g);
+      else solve_fp64(c, 1, c->col_b.p, c->col_x.p, rtol, L, g);
+      insert_column(nn, L, c->col_x.p, c->X.p, st);
+      c->stats.iterations[L] = g.iters[0];
+      c->stats.restarts[L] = g.restarts[0];
+      c->stats.true_residual[L] = g.true_rel[0];
+      conv = conv && g.converged;
+    }
+  }
+  for (int k = 0; k < 9; ++k)
+    if (!std::isfinite(c->stats.true_residual[k])) {
+      c->err = "non-finite residual";
+      return PHZ_E_NAN;
+    }
+  compute_effective(c);
+  sync(c);
+  collect_timing(c);
+  c->have_solution = true;
+  c->have_grad = false;
+  c->stats.solve_ms = ms_since(t0);
+  if (c->opt.verbose) {
+    int mx = 0;
+    for (int k = 0; k < 9; ++k) mx = std::max(mx, c->stats.iterations[k]);
+    std::fprintf(stderr, "[piezohom] N=%d %s %s: max iters %d, refinements %d, setup %.2f ms, solve %.2f ms\n",
+                 c->N, c->opt.precision == PHZ_FP32_IR ? "fp32-ir" : "fp64", c->opt.batched ? "batched" : "sequential",
+                 mx, c->stats.refinements, c->stats.setup_ms, c->stats.solve_ms);
+  }
+  if (!conv) {
+    c->err = "GMRES did not reach rtol within max_iters";
+    return PHZ_NOT_CONVERGED;
+  }
+  return PHZ_OK;
+}
+
+// ------------------------------------------------------------------ FOMs
+static bool inv_general(int n, const double* A, double* out) {
+  std::vector<long double> M((size_t)n * 2 * n);
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < 2 * n; ++j) M[(size_t)i * 2 * n + j] = j < n ? A[i * n + j] : (j - n == i ? 1.0L : 0.0L);
+  for (int col = 0; col < n; ++col) {
+    int piv = col;
+    for (int r = col + 1; r < n; ++r)
+      if (fabsl(M[(size_t)r * 2 * n + col]) > fabsl(M[(size_t)piv * 2 * n + col])) piv = r;
+    if (M[(size_t)piv * 2 * n + col] == 0.0L) return false;
+    if (piv != col)
+      for (int j = 0; j < 2 * n; ++j) std::swap(M[(size_t)piv * 2 * n + j], M[(size_t)col * 2 * n + j]);
+    const long double d = M[(size_t)col * 2 * n + col];
+    for (int j = 0; j < 2 * n; ++j) M[(size_t)col * 2 * n + j] /= d;
+    for (int r = 0; r < n; ++r) {
+      if (r == col) continue;
+      const long double f = M[(size_t)r * 2 * n + col];
+      if (f == 0.0L) continue;
+      for (int j = 0; j < 2 * n; ++j) M[(size_t)r * 2 * n + j] -= f * M[(size_t)col * 2 * n + j];
+    }
+  }
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) out[i * n + j] = (double)M[(size_t)i * 2 * n + n + j];
+  return true;
+}
+
+}  // namespace phz
+
+using namespace phz;
+
+#define PHZ_GUARD_BEGIN try {
+#define PHZ_GUARD_END(ctx)                                           \
+  }                                                                  \
+  catch (const HipError& ex) {                                       \
+    if (ctx) (ctx)->err = ex.what();                                 \
+    return std::strstr(ex.what(), "hipMalloc") ? PHZ_E_OOM : PHZ_E_HIP; \
+  }                                                                  \
+  catch (const std::exception& ex) {                                 \
+    if (ctx) (ctx)->err = ex.what();                                 \
+    return PHZ_E_INTERNAL;                                           \
+  }                                                                  \
+  catch (...) {                                                      \
+    if (ctx) (ctx)->err = "unknown exception";                       \
+    return PHZ_E_INTERNAL;                                           \
+  }
+
+extern "C" {
+
+void phz_default_options(phz_options* o) {
+  if (!o) return;
+  o->precision = PHZ_FP64;
+  o->batched = 1;
+  o->restart = 30;
+  o->max_iters = 2000;
+  o->rtol = 1e-10;
+  o->cheby_degree = 2;
+  o->mg_levels = 0;
+  o->smooth_width = 2.0;
+  o->vcycles_a = 1;
+  o->vcycles_s = 1;
+  o->inner_rtol = 1e-5;
+  o->max_refine = 50;
+  o->verbose = 0;
+}
+
+const char* phz_strerror(int status) {
+  if (status == PHZ_OK) return kStatusNames[0];
+  if (status == PHZ_NOT_CONVERGED) return kStatusNames[1];
+  if (status <= -1 && status >= -6) return kStatusNames[1 - status];
+  return "unknown status";
+}
+
+const char* phz_last_error(const phz_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+static int check_options(const phz_options* o, std::string& err) {
+  if (o->precision != PHZ_FP64 && o->precision != PHZ_FP32_IR) { err = "precision must be PHZ_FP64 or PHZ_FP32_IR"; return PHZ_E_INVALID; }
+  if (o->restart < 1 || o->restart > kMaxRestart) { err = "restart must be in [1, 32]"; return PHZ_E_INVALID; }
+  if (o->max_iters < 1) { err = "max_iters must be >= 1"; return PHZ_E_INVALID; }
+  if (!(o->rtol > 0 && o->rtol < 1)) { err = "rtol must be in (0, 1)"; return PHZ_E_INVALID; }
+  if (o->cheby_degree < 1 || o->cheby_degree > 16) { err = "cheby_degree must be in [1, 16]"; return PHZ_E_INVALID; }
+  if (o->mg_levels < 0) { err = "mg_levels must be >= 0"; return PHZ_E_INVALID; }
+  if (!(o->smooth_width > 0)) { err = "smooth_width must be > 0"; return PHZ_E_INVALID; }
+  if (o->vcycles_a < 1 || o->vcycles_s < 1) { err = "vcycles must be >= 1"; return PHZ_E_INVALID; }
+  if (!(o->inner_rtol > 0 && o->inner_rtol < 1)) { err = "inner_rtol must be in (0, 1)"; return PHZ_E_INVALID; }
+  if (o->max_refine < 1) { err = "max_refine must be >= 1"; return PHZ_E_INVALID; }
+  return PHZ_OK;
+}
+
+int phz_create(int n, const phz_material* mat, const phz_options* opt, void* stream, phz_ctx** out) {
+  if (!out) return PHZ_E_INVALID;
+  *out = nullptr;
+  if (!mat || n < 2 || n % 2 != 0 || n > 1024) return PHZ_E_INVALID;
+  for (int i = 0; i < 36; ++i) if (!std::isfinite(mat->C[i])) return PHZ_E_NAN;
+  for (int i = 0; i < 18; ++i) if (!std::isfinite(mat->e[i])) return PHZ_E_NAN;
+  for (int i = 0; i < 9; ++i) if (!std::isfinite(mat->kappa[i])) return PHZ_E_NAN;
+  if (!(mat->void_scale > 0.0 && mat->void_scale <= 1.0)) return PHZ_E_INVALID;
+  std::unique_ptr<phz_ctx> c(new phz_ctx());
+  PHZ_GUARD_BEGIN
+  c->N = n;
+  c->nn = (long)n * n * n;
+  c->mat = *mat;
+  if (opt) c->opt = *opt;
+  else phz_default_options(&c->opt);
+  std::string err;
+  int rc = check_options(&c->opt, err);
+  if (rc) return rc;
+  if (stream) {
+    c->stream = (hipStream_t)stream;
+  } else {
+    PHZ_HIP(hipStreamCreate(&c->stream));
+    c->own_stream = true;
+  }
+  upload_reference(c.get());
+  c->phi.alloc(c->nn);
+  c->rho.alloc(c->nn);
+  c->s.alloc(c->nn);
+  c->s32.alloc(c->nn);
+  ensure_state_buffers(c.get());
+  sync(c.get());
+  *out = c.release();
+  return PHZ_OK;
+  PHZ_GUARD_END(c.get())
+}
+
+void phz_destroy(phz_ctx* ctx) {
+  if (!ctx) return;
+  if (ctx->stream) hipStreamSynchronize(ctx->stream);
+  for (hipEvent_t e : ctx->ev) hipEventDestroy(e);
+  hipStream_t st = ctx->stream;
+  bool own = ctx->own_stream;
+  delete ctx;
+  if (own && st) hipStreamDestroy(st);
+}
+
+int phz_set_options(phz_ctx* c, const phz_options* opt) {
+  if (!c || !opt) return PHZ_E_INVALID;
+  int rc = check_options(opt, c->err);
+  if (rc) return rc;
+  PHZ_GUARD_BEGIN
+  const bool hier_change = opt->mg_levels != c->opt.mg_levels || opt->precision != c->opt.precision;
+  if (opt->restart != c->opt.restart) {
+    c->w64.cap_m = 0;
+    c->w32.cap_m = 0;
+  }
+  c->opt = *opt;
+  if (hier_change) c->precond_ready = false;
+  ensure_state_buffers(c);
+  return PHZ_OK;
+  PHZ_GUARD_END(c)
+}
+
+static int set_input(phz_ctx* c, const double* src, int on_device, DevBuf<double>& dst) {
+  if (on_device) PHZ_HIP(hipMemcpyAsync(dst.p, src, c->nn * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+  else PHZ_HIP(hipMemcpyAsync(dst.p, src, c->nn * sizeof(double), hipMemcpyHostToDevice, c->stream));
+  if (count_nonfinite(c->nn, dst.p, c->red_work.p, c->stream) > 0) {
+    c->err = "input holds NaN or Inf";
+    return PHZ_E_NAN;
+  }
+  return PHZ_OK;
+}
+
+int phz_set_levelset(phz_ctx* c, const double* phi, int on_device) {
+  if (!c || !phi) return PHZ_E_INVALID;
+  PHZ_GUARD_BEGIN
+  int rc = set_input(c, phi, on_device, c->phi);
+  if (rc) return rc;
+  levelset_to_scale(c->N, c->phi.p, c->opt.smooth_width / c->N, c->mat.void_scale, c->rho.p, c->s.p, c->s32.p,
+                    c->stream);
+  sync(c);
+  c->have_phi = true;
+  c->have_s = true;
+  c->precond_ready = false;
+  c->have_solution = false;
+  return PHZ_OK;
+  PHZ_GUARD_END(c)
+}
+
+int phz_set_density(phz_ctx* c, const double* rho, int on_device) {
+  if (!c || !rho) return PHZ_E_INVALID;
+  PHZ_GUARD_BEGIN
+  int rc = set_input(c, rho, on_device, c->rho);
+  if (rc) return rc;
+  density_to_scale(c->nn, c->rho.p, c->mat.void_scale, c->s.p, c->s32.p, c->stream);
+  sync(c);
+  c->have_phi = false;
+  c->have_s = true;
+  c->precond_ready = false;
+  c->have_solution = false;
+  return PHZ_OK;
+  PHZ_GUARD_END(c)
+}
+
+int phz_get_scale(phz_ctx* c, double* s, int on_device) {
+  if (!c || !s) return PHZ_E_INVALID;
+  if (!c->have_s) return PHZ_E_STATE;
+  PHZ_GUARD_BEGIN
+  PHZ_HIP(hipMemcpyAsync(s, c->s.p, c->nn * sizeof(double), on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                         c->stream));
+  sync(c);
+  return PHZ_OK;
+  PHZ_GUARD_END(c)
+}
+
+int phz_solve(phz_ctx* c) {
+  if (!c) return PHZ_E_INVALID;
+  PHZ_GUARD_BEGIN
+  return do_solve(c);
+  PHZ_GUARD_END(c)
+}
+
+int phz_get_effective(phz_ctx* c, double CH[36], double eH[18], double kH[9]) {
+  if (!c) return PHZ_E_INVALID;
+  if (!c->have_solution) { c->err = "no solution: call phz_solve first"; return PHZ_E_STATE; }
+  for (int i = 0; i < 6; ++i)
+    for (int j = 0; j < 6; ++j)
+      if (CH) CH[i * 6 + j] = kStress * c->MH[i * 9 + j];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 6; ++j)
+      if (eH) eH[i * 6 + j] = -kCharge * c->MH[(6 + i) * 9 + j];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j)
+      if (kH) kH[i * 3 + j] = -kPerm * c->MH[(6 + i) * 9 + 6 + j];
+  return PHZ_OK;
+}
+
+int phz_get_effective_nd(phz_ctx* c, double MH[81], double MHe[81]) {
+  if (!c) return PHZ_E_INVALID;
+  if (!c->have_solution) return PHZ_E_STATE;
+  if (MH) std::memcpy(MH, c->MH, sizeof(c->MH));
+  if (MHe) std::memcpy(MHe, c->MHe, sizeof(c->MHe));
+  return PHZ_OK;
+}
+
+int phz_get_history(phz_ctx* c, int load, double* buf, int cap, int* len) {
+  if (!c || load < 0 || load > 8 || cap < 0) return PHZ_E_INVALID;
+  const auto& h = c->hist[load];
+  const int n = (int)h.size();
+  if (buf)
+    for (int i = 0; i < std::min(n, cap); ++i) buf[i] = h[i];
+  if (len) *len = n;
+  return PHZ_OK;
+}
+
+int phz_get_stats(phz_ctx* c, phz_stats* st) {
+  if (!c || !st) return PHZ_E_INVALID;
+  *st = c->stats;
+  return PHZ_OK;
+}
+
+int phz_get_solution(phz_ctx* c, double* X, int on_device) {
+  if (!c || !X) return PHZ_E_INVALID;
+  if (!c->have_solution) return PHZ_E_STATE;
+  PHZ_GUARD_BEGIN
+  PHZ_HIP(hipMemcpyAsync(X, c->X.p, c->nn * 36 * sizeof(double),
+                         on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, c->stream));
+  sync(c);
+  return PHZ_OK;
+  PHZ_GUARD_END(c)
+}
+
+int phz_set_initial_guess(phz_ctx* c, const double* X, int on_device) {
+  if (!c) return PHZ_E_INVALID;
+  PHZ_GUARD_BEGIN
+  if (!X) {
+    c->have_guess = false;
+    return PHZ_OK;
+  }
+  c->guess.alloc(c->nn * 36);
+  PHZ_HIP(hipMemcpyAsync(c->guess.p, X, c->nn * 36 * sizeof(double),
+                         on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, c->stream));
+  if (count_nonfinite(c->nn * 36, c->guess.p, c->red_work.p, c->stream) > 0) {
+    c->err = "initial guess holds NaN or Inf";
+    return PHZ_E_NAN;
+  }
+  c->have_guess = true;
+  return PHZ_OK;
+  PHZ_GUARD_END(c)
+}
+
+int phz_get_rhs(phz_ctx* c, double* b, int on_device) {
+  if (!c || !b) return PHZ_E_INVALID;
+  if (!c->have_s) return PHZ_E_STATE;
+  PHZ_GUARD_BEGIN
+  c->Bvec.alloc(c->nn * 36);
+  c->R64.alloc(c->nn * 36);
+  prepare_rhs(c);
+  PHZ_HIP(hipMemcpyAsync(b, c->Bvec.p, c->nn * 36 * sizeof(double),
+                         on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, c->stream));
+  sync(c);
+  return PHZ_OK;
+  PHZ_GUARD_END(c)
+}
+
+int phz_foms(const double CH[36], const double eH[18], const double kH[9], phz_foms_t* out, const char* grad_of,
+             double gC[36], double ge[18], double gk[9]) {
+  if (!CH || !eH || !kH) return PHZ_E_INVALID;
+  double S[36];
+  if (!inv_general(6, CH, S)) return PHZ_E_INVALID;
+  double d[18];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 6; ++j) {
+      double v = 0.0;
+      for (int k = 0; k < 6; ++k) v += eH[i * 6 + k] * S[k * 6 + j];
+      d[i * 6 + j] = v;
+    }
+  const double dh = d[12] + d[13] + d[14];
+  double bv = 0.0, sr = 0.0;
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      bv += CH[i * 6 + j] / 9.0;
+      sr += S[i * 6 + j];
+    }
+  const double br = 1.0 / sr;
+  double de33 = 0.0;  // (d e^T)_33
+  for (int j = 0; j < 6; ++j) de33 += d[12 + j] * eH[12 + j];
+  const double kT = kH[8] + de33;
+  const double gh = dh / kT;
+  const double kh = std::sqrt(dh * gh * br);
+  if (out) {
+    out->d_h = dh;
+    out->g_h = gh;
+    out->B_voigt = bv;
+    out->B_reuss = br;
+    out->k_h = kh;
+  }
+  if (!grad_of) return PHZ_OK;
+  // a = S 1_3, b = S^T e_z, c = S^T 1_3, f = S e_z
+  double a[6], bb[6], cc[6], ff[6];
+  for (int i = 0; i < 6; ++i) {
+    a[i] = S[i * 6 + 0] + S[i * 6 + 1] + S[i * 6 + 2];
+    cc[i] = S[0 * 6 + i] + S[1 * 6 + i] + S[2 * 6 + i];
+    double v = 0.0, w = 0.0;
+    for (int k = 0; k < 6; ++k) {
+      v += S[k * 6 + i] * eH[12 + k];
+      w += S[i * 6 + k] * eH[12 + k];
+    }
+    bb[i] = v;
+    ff[i] = w;
+  }
+  double dC_dh[36], de_dh[18], dk_dh[9] = {0};
+  double dC_kT[36], de_kT[18], dk_kT[9] = {0};
+  double dC_br[36];
+  for (int i = 0; i < 18; ++i) de_dh[i] = de_kT[i] = 0.0;
+  for (int i = 0; i < 6; ++i)
+    for (int j = 0; j < 6; ++j) {
+      dC_dh[i * 6 + j] = -bb[i] * a[j];
+      dC_kT[i * 6 + j] = -bb[i] * ff[j];
+      dC_br[i * 6 + j] = br * br * cc[i] * a[j];
+    }
+  for (int j = 0; j < 6; ++j) {
+    de_dh[12 + j] = a[j];
+    de_kT[12 + j] = bb[j] + ff[j];
+  }
+  dk_kT[8] = 1.0;
+  const std::string which(grad_of);
+  double oc[36], oe[18], ok[9];
+  for (int i = 0; i < 36; ++i) oc[i] = 0.0;
+  for (int i = 0; i < 18; ++i) oe[i] = 0.0;
+  for (int i = 0; i < 9; ++i) ok[i] = 0.0;
+  if (which == "d_h") {
+    for (int i = 0; i < 36; ++i) oc[i] = dC_dh[i];
+    for (int i = 0; i < 18; ++i) oe[i] = de_dh[i];
+  } else if (which == "B_voigt") {
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) oc[i * 6 + j] = 1.0 / 9.0;
+  } else if (which == "B_reuss") {
+    for (int i = 0; i < 36; ++i) oc[i] = dC_br[i];
+  } else if (which == "g_h" || which == "k_h") {
+    double gC_[36], ge_[18], gk_[9];
+    for (int i = 0; i < 36; ++i) gC_[i] = dC_dh[i] / kT - dh / (kT * kT) * dC_kT[i];
+    for (int i = 0; i < 18; ++i) ge_[i] = de_dh[i] / kT - dh / (kT * kT) * de_kT[i];
+    for (int i = 0; i < 9; ++i) gk_[i] = dk_dh[i] / kT - dh / (kT * kT) * dk_kT[i];
+    if (which == "g_h") {
+      std::memcpy(oc, gC_, sizeof(oc));
+      std::memcpy(oe, ge_, sizeof(oe));
+      std::memcpy(ok, gk_, sizeof(ok));
+    } else {
+      const double f = 0.5 / kh;
+      for (int i = 0; i < 36; ++i) oc[i] = f * (dC_dh[i] * gh * br + dh * gC_[i] * br + dh * gh * dC_br[i]);
+      for (int i = 0; i < 18; ++i) oe[i] = f * (de_dh[i] * gh * br + dh * ge_[i] * br);
+      for (int i = 0; i < 9; ++i) ok[i] = f * (dh * gk_[i] * br);
+    }
+  } else {
+    return PHZ_E_INVALID;
+  }
+  if (gC) std::memcpy(gC, oc, sizeof(oc));
+  if (ge) std::memcpy(ge, oe, sizeof(oe));
+  if (gk) std::memcpy(gk, ok, sizeof(ok));
+  return PHZ_OK;
+}
+
+int phz_backward(phz_ctx* c, const double gC[36], const double ge[18], const double gk[9], double* grad_rho,
+                 double* grad_phi_out, int on_device) {
+  if (!c || !grad_rho) return PHZ_E_INVALID;
+  if (!c->have_solution) { c->err = "backward needs a solve"; return PHZ_E_STATE; }
+  if (grad_phi_out && !c->have_phi) { c->err = "grad_phi needs a level set"; return PHZ_E_STATE; }
+  PHZ_GUARD_BEGIN
+  double W[81] = {0};
+  for (int i = 0; i < 6; ++i)
+    for (int j = 0; j < 6; ++j) W[i * 9 + j] = gC ? kStress * gC[i * 6 + j] : 0.0;
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 6; ++j) W[(6 + i) * 9 + j] = ge ? -kCharge * ge[i * 6 + j] : 0.0;
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) W[(6 + i) * 9 + 6 + j] = gk ? -kPerm * gk[i * 3 + j] : 0.0;
+  for (int i = 0; i < 81; ++i)
+    if (!std::isfinite(W[i])) { c->err = "non-finite upstream gradient"; return PHZ_E_NAN; }
+  const RefElement& R = c->ref;
+  std::vector<double> buf(288 + 81);
+  for (int i = 0; i < 32; ++i)
+    for (int L = 0; L < 9; ++L) {
+      double v = 0.0;
+      for (int K = 0; K < 9; ++K) v += R.F0[i * 9 + K] * (W[K * 9 + L] + W[L * 9 + K]);
+      buf[i * 9 + L] = v;
+    }
+  for (int i = 0; i < 81; ++i) buf[288 + i] = W[i];
+  double cterm = 0.0;
+  for (int i = 0; i < 81; ++i) cterm += W[i] * R.M[i];
+  cterm *= std::pow(1.0 / c->N, 3);
+  DevBuf<double> dbuf;
+  dbuf.upload(buf.data(), buf.size(), c->stream);
+  c->grad_rho.alloc(c->nn);
+  backward_elem(c->N, c->X.p, c->kref_full.p, dbuf.p, cterm, 1.0 - c->mat.void_scale, c->grad_rho.p, c->stream);
+  const hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+  PHZ_HIP(hipMemcpyAsync(grad_rho, c->grad_rho.p, c->nn * sizeof(double), kind, c->stream));
+  if (grad_phi_out) {
+    c->tmp_nodes.alloc(c->nn);
+    grad_phi(c->N, c->phi.p, c->opt.smooth_width / c->N, c->grad_rho.p, c->tmp_nodes.p, c->stream);
+    PHZ_HIP(hipMemcpyAsync(grad_phi_out, c->tmp_nodes.p, c->nn * sizeof(double), kind, c->stream));
+  }
+  sync(c);
+  c->have_grad = true;
+  return PHZ_OK;
+  PHZ_GUARD_END(c)
+}
+
+int phz_hj_step(phz_ctx* c, const double* velocity, double cfl, double* phi_out, int on_device) {
+  if (!c || !(cfl > 0)) return PHZ_E_INVALID;
+  if (!c->have_phi) { c->err = "HJ step needs a level set"; return PHZ_E_STATE; }
+  if (!velocity && !c->have_grad) { c->err = "no velocity and no backward result"; return PHZ_E_STATE; }
+  PHZ_GUARD_BEGIN
+  DevBuf<double> v, out;
+  v.alloc(c->nn);
+  out.alloc(c->nn);
+  double* vmax = c->small.p + 500;
+  if (velocity) {
+    int rc = set_input(c, velocity, on_device, v);
+    if (rc) return rc;
+    hj_step(c->N, c->phi.p, v.p, nullptr, cfl / c->N, out.p, c->stream);
+  } else {
+    nodal_mean_of_elements(c->N, c->grad_rho.p, v.p, c->stream);
+    max_abs(c->nn, v.p, vmax, c->red_work.p, c->stream);
+    hj_step(c->N, c->phi.p, v.p, vmax, cfl / c->N, out.p, c->stream);
+  }
+  PHZ_HIP(hipMemcpyAsync(c->phi.p, out.p, c->nn * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+  levelset_to_scale(c->N, c->phi.p, c->opt.smooth_width / c->N, c->mat.void_scale, c->rho.p, c->s.p, c->s32.p,
+                    c->stream);
+  if (phi_out)
+    PHZ_HIP(hipMemcpyAsync(phi_out, c->phi.p, c->nn * sizeof(double),
+                           on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, c->stream));
+  sync(c);
+  c->precond_ready = false;
+  c->have_solution = false;
+  c->have_grad = false;
+  return PHZ_OK;
+  PHZ_GUARD_END(c)
+}
+
+int phz_kernel_timing(phz_ctx* c, int enable) {
+  if (!c) return PHZ_E_INVALID;
+  PHZ_GUARD_BEGIN
+  sync(c);
+  collect_timing(c);
+  c->ktime = enable != 0;
+  c->ktotals.clear();
+  return PHZ_OK;
+  PHZ_GUARD_END(c)
+}
+
+int phz_get_kernel_timing(phz_ctx* c, char* buf, int cap, int* len) {
+  if (!c || cap < 0) return PHZ_E_INVALID;
+  PHZ_GUARD_BEGIN
+  sync(c);
+  collect_timing(c);
+  std::string out;
+  char line[160];
+  for (auto& kv : c->ktotals) {
+    std::snprintf(line, sizeof(line), "%s %ld %.6f\n", kv.first.c_str(), kv.second.first, kv.second.second);
+    out += line;
+  }
+  if (len) *len = (int)out.size();
+  if (buf && cap > 0) {
+    const int n = std::min(cap - 1, (int)out.size());
+    std::memcpy(buf, out.data(), n);
+    buf[n] = 0;
+  }
+  return PHZ_OK;
+  PHZ_GUARD_END(c)
+}
+
+int phz_apply(phz_ctx* c, int op, int nrhs, int precision, const void* x, void* y) {
+  if (!c || !x || !y || op < 0 || op > 3 || (nrhs != 1 && nrhs != 9)) return PHZ_E_INVALID;
+  if (!c->have_s) return PHZ_E_STATE;
+  PHZ_GUARD_BEGIN
+  if (precision == PHZ_FP64)
+    op_apply<double>(c, op, nrhs, (const double*)x, (const double*)nullptr, (double*)y, 1.0, 0.0);
+  else if (precision == PHZ_FP32_IR)
+    op_apply<float>(c, op, nrhs, (const float*)x, (const float*)nullptr, (float*)y, 1.0f, 0.0f);
+  else
+    return PHZ_E_INVALID;
+  return PHZ_OK;
+  PHZ_GUARD_END(c)
+}
+
+int phz_precondition(phz_ctx* c, int nrhs, const double* r, double* z) {
+  if (!c || !r || !z || (nrhs != 1 && nrhs != 9)) return PHZ_E_INVALID;
+  if (!c->have_s) return PHZ_E_STATE;
+  PHZ_GUARD_BEGIN
+  ensure_state_buffers(c);
+  if (c->opt.precision != PHZ_FP64) { c->err = "phz_precondition runs the float64 preconditioner"; }
+  const int saved = c->opt.precision;
+  c->opt.precision = PHZ_FP64;
+  setup_preconditioner(c);
+  alloc_work<double>(c, c->w64, nrhs, c->opt.restart);
+  precond_apply<double>(c, nrhs, r, z);
+  c->opt.precision = saved;
+  if (saved != PHZ_FP64) c->precond_ready = false;
+  sync(c);
+  return PHZ_OK;
+  PHZ_GUARD_END(c)
+}
+
+int phz_coarse_apply(phz_ctx* c, int level, int op, int nrhs, const double* x, double* y) {
+  if (!c || !x || !y || (nrhs != 1 && nrhs != 9) || (op != PHZ_OP_A && op != PHZ_OP_SBAR)) return PHZ_E_INVALID;
+  if (!c->have_s) return PHZ_E_STATE;
+  PHZ_GUARD_BEGIN
+  ensure_state_buffers(c);
+  setup_preconditioner(c);
+  Hierarchy& H = op == PHZ_OP_A ? c->hA : c->hS;
+  if (level < 1 || level >= (int)H.lv.size()) { c->err = "level out of range"; return PHZ_E_INVALID; }
+  coarse_apply<double>(H.F, nrhs, H.lv[level]->N, H.lv[level]->Ae.p, x, nullptr, y, 1.0, 0.0, c->stream);
+  sync(c);
+  return PHZ_OK;
+  PHZ_GUARD_END(c)
+}
+
+}  // extern "C"
