@@ -190,15 +190,17 @@ int phz_hj_step(phz_ctx* ctx, const double* velocity, double cfl,
                 double* phi_out, int on_device);
 
 /* Low-level operator apply on the current geometry: y = calA_block x for
- * nrhs in {1, 9} columns, device pointers, layouts [n][fields][nrhs].
+ * nrhs in {1, 9} columns, device pointers.  These low-level entry points use
+ * the library's internal structure-of-arrays layout [field][load][N^3]
+ * (one contiguous column of node values per (field, load)).
  * precision PHZ_FP64 (double buffers) or PHZ_FP32_IR (float buffers). */
 int phz_apply(phz_ctx* ctx, int op, int nrhs, int precision,
               const void* x, void* y);
-/* Apply the SCP preconditioner z = P^-1 r (device, [n][4][nrhs], float64),
+/* Apply the SCP preconditioner z = P^-1 r (device, [4][nrhs][N^3], float64),
  * building it for the current geometry if needed. */
 int phz_precondition(phz_ctx* ctx, int nrhs, const double* r, double* z);
 /* Galerkin coarse operator of multigrid level >= 1 applied to x (device,
- * float64): block PHZ_OP_A ([nc][3][nrhs]) or PHZ_OP_SBAR ([nc][1][nrhs]). */
+ * float64): block PHZ_OP_A ([3][nrhs][nc]) or PHZ_OP_SBAR ([nrhs][nc]). */
 int phz_coarse_apply(phz_ctx* ctx, int level, int op, int nrhs,
                      const double* x, double* y);
 

@@ -25,18 +25,37 @@ struct HipError : std::runtime_error {
 constexpr int kMaxRestart = 32;
 
 // ---- operators (ops.hip) -----------------------------------------------------
-// Fine-level matrix-free block operator, y = beta*yin + alpha*(sum_e s_e Kref) x.
+// Output side of an operator launch: y = beta*yin + alpha*(A x), and with the
+// Chebyshev epilogue (square blocks only) also, per node and column,
+// dnew = ca*dold + cb*Dinv*y and x += dnew.  y may alias yin; dnew must not
+// alias the operator input.
+template <typename T>
+struct OpArgs {
+  const T* yin = nullptr;
+  T* y = nullptr;
+  T alpha = T(1), beta = T(0);
+  const T* dinv = nullptr;
+  const T* dold = nullptr;
+  T* dnew = nullptr;
+  T* x = nullptr;
+  T ca = T(0), cb = T(0);
+};
+
+// Fine-level matrix-free block operator on sum_e s_e Kref.
 // op: 0 full (4->4), 1 A (3->3), 2 B (3->1), 3 S_bar (1->1).  nrhs in {1, 9}.
 // kref is the op's reference block in (l*FO + fo, l'*FI + fi) layout.
 template <typename T>
-void fine_apply(int op, int nrhs, int N, const T* s, const T* kref, const T* x,
-                const T* yin, T* y, T alpha, T beta, hipStream_t st);
+void fine_apply(int op, int nrhs, int N, const T* s, const T* kref, const T* x, const OpArgs<T>& a,
+                bool cheby, hipStream_t st);
 
-// Coarse-level apply with stored Galerkin element matrices Ae laid out
-// [corner L][element][F][8F] (row (L, f) of each element matrix).
+// Coarse-level apply with assembled 27-point node stencils S laid out
+// structure-of-arrays [(d*F + fo)*F + fi][node].
 template <typename T>
-void coarse_apply(int F, int nrhs, int N, const T* Ae, const T* x, const T* yin, T* y,
-                  T alpha, T beta, hipStream_t st);
+void coarse_apply(int F, int nrhs, int N, const T* S, const T* x, const OpArgs<T>& a, bool cheby,
+                  hipStream_t st);
+// Node stencils of a coarse level from its Galerkin element matrices
+// (structure-of-arrays [corner L][row f][col][element]).
+void build_stencil(int F, int N, const double* Ae, double* S, hipStream_t st);
 
 // Galerkin coarsening of element matrices: coarse element E gets
 // sum_children Q_c^T K_c Q_c with trilinear Q_c.  From the fine level
@@ -49,11 +68,11 @@ void diag_inv_fine(int F, int N, const double* s, const double* kref, double* Di
                    hipStream_t st);
 void diag_inv_coarse(int F, int N, const double* Ae, double* Dinv, hipStream_t st);
 
-// One Chebyshev-Jacobi step: d = a d + b Dinv r (a == 0 ignores old d);
-// x = d if xzero else x += d.
+// First Chebyshev-Jacobi step: d = cf Dinv r; x = d if xzero else x += d.
+// r, d and x may alias (per-node in-place).
 template <typename T>
-void cheby_step(int F, int nrhs, long nn, const T* Dinv, const T* r, T* d, T* x, T a, T b,
-                bool xzero, hipStream_t st);
+void cheby_first(int F, int nrhs, long nn, const T* Dinv, const T* r, T* d, T* x, T cf, bool xzero,
+                 hipStream_t st);
 
 // Full-weighting restriction rc = P^T rf and prolongation xf += P xc (periodic,
 // trilinear).  Nc = coarse N.
@@ -62,59 +81,56 @@ void restrict_fw(int F, int nrhs, int Nc, const T* rf, T* rc, hipStream_t st);
 template <typename T>
 void prolong_add(int F, int nrhs, int Nc, const T* xc, T* xf, hipStream_t st);
 
-// z = Minv r on the coarsest level (dense, rows = F * nc^3, double matrix).
+// z = Minv r on the coarsest level: dense float64 matrix over rows (f*nc + n).
 template <typename T>
-void dense_apply(int rows, int nrhs, const double* Minv, const T* r, T* z, hipStream_t st);
+void dense_apply(int F, int nc, int nrhs, const double* Minv, const T* r, T* z, hipStream_t st);
 
 // ---- vectors / reductions / physics (vec.hip) --------------------------------
+// Vectors are structure of arrays: F*K columns (field f, load k -> column
+// f*K + k) of nn contiguous node values.
 template <typename Ts, typename Td>
 void convert(long count, const Ts* src, Td* dst, hipStream_t st);
 template <typename T>
 void fill(long count, T value, T* dst, hipStream_t st);
 
-// Per-column sums of squares of a [rows][nrhs] vector into out[nrhs] (double),
-// deterministic two-stage reduction; work must hold reduce_work_size() doubles.
-size_t reduce_work_size(int nvals);
+// scratch (doubles) needed by every reduction below
+size_t reduce_work_size();
+// out[k] = sum over fields and nodes of v^2, per load column k (double)
 template <typename T>
-void col_norm2(long rows, int nrhs, const T* v, double* out, double* work, hipStream_t st);
-// Per-column (field, rhs) sums of a [nn][F][nrhs] vector into out[F*nrhs].
+void col_norm2(long nn, int F, int K, const T* v, double* out, double* work, hipStream_t st);
+// out[f*K + k] = sum over nodes of column (f, k)
 template <typename T>
-void field_sums(long nn, int F, int nrhs, const T* v, double* out, double* work,
-                hipStream_t st);
-// v[n][f][k] -= sums[f*K+k] / nn
+void field_sums(long nn, int F, int K, const T* v, double* out, double* work, hipStream_t st);
+// v[(f, k)][n] -= sums[f*K + k] / nn
 template <typename T>
-void subtract_mean(long nn, int F, int nrhs, const double* sums, T* v, hipStream_t st);
+void subtract_mean(long nn, int F, int K, const double* sums, T* v, hipStream_t st);
 
-// Arnoldi passes on [rows][nrhs] vectors with the basis V (stride vstride
-// elements between vectors):
-//   dots:    hout[i][k] = <V_i, w>_k for i <= j
-//   update:  w -= sum_i V_i hin[i][k]; then (if hout) hout = V^T w_new and
-//            nrm2out = ||w_new||^2 (nrm2out may be null)
+// Arnoldi passes with the basis V_i = V + i*vstride:
+//   dots:    hout[i*K + k] = <V_i, w>_k for i <= j
+//   update:  w -= sum_i V_i hin[i*K + k]; then (if hout) hout = V^T w_new and
+//            (if nrm2out) nrm2out[k] = ||w_new||_k^2
 template <typename T>
-void arnoldi_dots(long rows, int nrhs, int j, const T* V, long vstride, const T* w,
-                  double* hout, double* work, hipStream_t st);
+void arnoldi_dots(long nn, int F, int K, int j, const T* V, long vstride, const T* w, double* hout,
+                  double* work, hipStream_t st);
 template <typename T>
-void arnoldi_update(long rows, int nrhs, int j, const T* V, long vstride, T* w,
-                    const double* hin, double* hout, double* nrm2out, double* work,
-                    hipStream_t st);
-// v = w * scale[k]
+void arnoldi_update(long nn, int F, int K, int j, const T* V, long vstride, T* w, const double* hin,
+                    double* hout, double* nrm2out, double* work, hipStream_t st);
+// v = w * scale[k] (in place allowed)
 template <typename T>
-void scale_cols(long rows, int nrhs, const T* w, const double* scale, T* v, hipStream_t st);
-// t = sum_{i < kused[k]} V_i y[i][k]
+void scale_cols(long nn, int F, int K, const T* w, const double* scale, T* v, hipStream_t st);
+// t = sum_{i < kused[k]} V_i y[i*K + k]
 template <typename T>
-void combine(long rows, int nrhs, int m, const T* V, long vstride, const double* y,
-             const int* kused, T* t, hipStream_t st);
+void combine(long nn, int F, int K, const T* V, long vstride, const double* y, const int* kused, T* t,
+             hipStream_t st);
 // x += a[k] * z (a may be null -> 1), mixed precision source allowed
 template <typename Tx, typename Tz>
-void axpy_cols(long rows, int nrhs, const double* a, const Tz* z, Tx* x, hipStream_t st);
-// full [nn][4][K] <-> u [nn][3][K] and p [nn][1][K]
-template <typename T>
-void split_fields(long nn, int nrhs, const T* full, T* u, T* p, hipStream_t st);
-template <typename T>
-void merge_fields(long nn, int nrhs, const T* u, const T* p, T* full, hipStream_t st);
-// strided column copies between a [nn][4][9] block and a [nn][4][1] vector
+void axpy_cols(long nn, int F, int K, const double* a, const Tz* z, Tx* x, hipStream_t st);
+// one load of a 9-load block <-> a single-load vector (4 fields)
 void extract_column(long nn, int load, const double* block, double* col, hipStream_t st);
 void insert_column(long nn, int load, const double* col, double* block, hipStream_t st);
+// structure of arrays [ncol][nn] <-> node-major [nn][ncol]
+void soa_to_aos(long nn, int ncol, const double* src, double* dst, hipStream_t st);
+void aos_to_soa(long nn, int ncol, const double* src, double* dst, hipStream_t st);
 
 // GMRES small-matrix kernels (one workgroup; state arrays in device memory).
 struct GmresState {
@@ -142,12 +158,13 @@ void levelset_to_scale(int N, const double* phi, double eta, double void_scale, 
                        double* s, float* s32, hipStream_t st);
 void density_to_scale(long nn, const double* rho, double void_scale, double* s, float* s32,
                       hipStream_t st);
-// b = -sum_e s_e F0 e_L per node; absval: sum_e s_e |F0| (a magnitude reference)
+// b[(f*9 + L)][n] = -sum_e s_e F0 e_L; absval: sum_e s_e |F0| (a magnitude reference)
 void build_rhs(int N, const double* s, const double* F0, double* b, hipStream_t st, bool absval = false);
-// partial sums for M^H: Y[(l,f),L] = sum_e s_e x_{node(e,l)}[f][L]; out[288] and
-// out[288] = sum_e s_e
+// out[l*36 + f*9 + L] = sum_e s_e x_{node(e,l)}[f][L]; out[288] = sum_e s_e
 void reduce_effective(int N, const double* s, const double* X, double* out, double* work,
                       hipStream_t st);
+// out[b*9 + a] = sum_{f, n} X[(f, a)][n] Y[(f, b)][n]  (9-load blocks)
+void cross_dots(long nn, const double* X, const double* Y, double* out, double* work, hipStream_t st);
 void backward_elem(int N, const double* X, const double* K0, const double* FW, double cterm,
                    double factor, double* grad, hipStream_t st);
 void grad_phi(int N, const double* phi, double eta, const double* grad_rho, double* out,

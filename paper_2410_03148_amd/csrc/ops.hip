@@ -1,20 +1,31 @@
 // Operator and multigrid kernels for the periodic hex8 cell (gfx950).
 //
+// Vector layout (device, internal): structure of arrays, one contiguous
+// column of nn node values per (field f, load column k), column index
+// f*K + k.  Consecutive threads own consecutive nodes, so every load and
+// store below is a unit-stride wavefront access.
+//
 // Fine level (matrix-free): the assembled operator of Sec. 2.5 is
 // sum_e s_e K0 with the reference element matrix K0.  One thread owns one
-// output node n and gathers its 27 neighbours m = n + d: the 4x4 (or
-// sub-block) coupling between n and m is
+// output node n and gathers its 27 neighbours m = n + d: the FO x FI coupling
+// between n and m is
 //     K_nm = sum_{elements e containing n and m} s_e K0[corner(n, e), corner(m, e)],
 // built in registers from the eight element scales around n and applied to
 // all load columns of x[m].  Every output is written by exactly one thread:
 // no scatter, no atomics, deterministic.  The block build costs 64*FO*FI
 // FMAs per node independent of the number of load columns, the apply
-// 27*FO*FI*K, so batching the nine loads halves the work of the element-wise
-// product (which would cost 64*FO*FI*K).
+// 27*FO*FI*K, so batching the nine loads roughly halves the work of the
+// element-wise product (64*FO*FI*K).
 //
 // Coarse levels: Galerkin element matrices (R A P assembled per coarse
-// element from its eight children) stored as [corner][element][F][8F] and
-// applied with the same owner-computes gather.
+// element from its eight children), stored structure-of-arrays as
+// [corner L][row f][col][element], applied with the same owner-computes
+// gather.
+//
+// Every square-block operator kernel takes an optional Chebyshev epilogue:
+// with r_new = yin - A d_old of a node in registers it also forms
+// d_new = ca d_old + cb Dinv r_new and x += d_new for that node, which saves
+// a separate pass over r, d and x per smoothing step.
 #include "common.hpp"
 
 namespace phz {
@@ -22,16 +33,15 @@ namespace phz {
 namespace {
 
 struct NodeIdx {
-  int i, j, k;
-  int im, ip, jm, jp, km, kp;
+  unsigned i, j, k, im, ip, jm, jp, km, kp;
 };
 
-__device__ __forceinline__ NodeIdx node_idx(long n, int N) {
+__device__ __forceinline__ NodeIdx node_idx(unsigned n, unsigned N) {
   NodeIdx r;
-  r.i = (int)(n % N);
-  long t = n / N;
-  r.j = (int)(t % N);
-  r.k = (int)(t / N);
+  const unsigned t = n / N;
+  r.i = n - t * N;
+  r.k = t / N;
+  r.j = t - r.k * N;
   r.im = r.i == 0 ? N - 1 : r.i - 1;
   r.ip = r.i + 1 == N ? 0 : r.i + 1;
   r.jm = r.j == 0 ? N - 1 : r.j - 1;
@@ -41,11 +51,12 @@ __device__ __forceinline__ NodeIdx node_idx(long n, int N) {
   return r;
 }
 
-__device__ __forceinline__ int pick(int d, int m, int c, int p) { return d < 0 ? m : (d > 0 ? p : c); }
+__device__ __forceinline__ unsigned pick(int d, unsigned m, unsigned c, unsigned p) {
+  return d < 0 ? m : (d > 0 ? p : c);
+}
 
-__device__ __forceinline__ long nb_node(const NodeIdx& q, int N, int dx, int dy, int dz) {
-  return (long)pick(dx, q.im, q.i, q.ip) +
-         (long)N * ((long)pick(dy, q.jm, q.j, q.jp) + (long)N * pick(dz, q.km, q.k, q.kp));
+__device__ __forceinline__ unsigned nb_node(const NodeIdx& q, unsigned N, int dx, int dy, int dz) {
+  return pick(dx, q.im, q.i, q.ip) + N * (pick(dy, q.jm, q.j, q.jp) + N * pick(dz, q.km, q.k, q.kp));
 }
 
 template <int OP> struct OpFields;
@@ -54,21 +65,91 @@ template <> struct OpFields<1> { static constexpr int FO = 3, FI = 3; };
 template <> struct OpFields<2> { static constexpr int FO = 1, FI = 3; };
 template <> struct OpFields<3> { static constexpr int FO = 1, FI = 1; };
 
-template <typename T, int FO, int FI, int K>
-__global__ __launch_bounds__(256) void k_fine_apply(int N, const T* __restrict__ s,
+// y = beta*yin + alpha*acc, optional Chebyshev epilogue (FO == FI), for the
+// KK load columns k0 .. k0+KK-1 of a node (column (f, k) at (f*K + k)*nn)
+template <typename T, int FO, int K, int KK, bool CHEBY>
+__device__ __forceinline__ void epilogue_cols(unsigned n, unsigned nn, int k0, const T* acc, const OpArgs<T>& a) {
+  T out[FO * KK];
+  if (a.beta == T(0)) {
+#pragma unroll
+    for (int f = 0; f < FO; ++f)
+#pragma unroll
+      for (int j = 0; j < KK; ++j) out[f * KK + j] = a.alpha * acc[f * KK + j];
+  } else {
+#pragma unroll
+    for (int f = 0; f < FO; ++f)
+#pragma unroll
+      for (int j = 0; j < KK; ++j)
+        out[f * KK + j] = a.beta * a.yin[(size_t)(f * K + k0 + j) * nn + n] + a.alpha * acc[f * KK + j];
+  }
+#pragma unroll
+  for (int f = 0; f < FO; ++f)
+#pragma unroll
+    for (int j = 0; j < KK; ++j) a.y[(size_t)(f * K + k0 + j) * nn + n] = out[f * KK + j];
+  if constexpr (CHEBY) {
+    T Di[FO * FO];
+#pragma unroll
+    for (int t = 0; t < FO * FO; ++t) Di[t] = a.dinv[(size_t)t * nn + n];
+#pragma unroll
+    for (int j = 0; j < KK; ++j)
+#pragma unroll
+      for (int f = 0; f < FO; ++f) {
+        T z = T(0);
+#pragma unroll
+        for (int g = 0; g < FO; ++g) z += Di[f * FO + g] * out[g * KK + j];
+        const size_t o = (size_t)(f * K + k0 + j) * nn + n;
+        const T dv = a.ca * a.dold[o] + a.cb * z;
+        a.dnew[o] = dv;
+        a.x[o] += dv;
+      }
+  }
+}
+
+template <typename T, int FO, int K, bool CHEBY>
+__device__ __forceinline__ void epilogue(unsigned n, unsigned nn, const T* acc, const OpArgs<T>& a) {
+  epilogue_cols<T, FO, K, K, CHEBY>(n, nn, 0, acc, a);
+}
+
+// Raw buffer loads: one scalar resource per array, the column offset in a
+// scalar register and the node offset in a 32-bit vector register (no
+// per-load 64-bit address arithmetic).  Arrays must span < 4 GiB.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* p, unsigned bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, 0x00020000);
+}
+template <typename T>
+__device__ __forceinline__ T buf_load(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff);
+template <>
+__device__ __forceinline__ float buf_load<float>(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, 0));
+}
+template <>
+__device__ __forceinline__ double buf_load<double>(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, 0));
+}
+
+// One thread per output node.  The reference block sits in LDS (a broadcast
+// read per coefficient, no scalar-register pressure); the 27 neighbour
+// records are read with buffer loads, all FI*K columns of a neighbour issued
+// before the block build so their latency overlaps it.
+template <typename T, int FO, int FI, int K, bool CHEBY, bool BUF>
+__global__ __launch_bounds__(128) void k_fine_apply(unsigned N, const T* __restrict__ s,
                                                     const T* __restrict__ kref,
-                                                    const T* __restrict__ x,
-                                                    const T* __restrict__ yin,
-                                                    T* __restrict__ y, T alpha, T beta) {
-  const long nn = (long)N * N * N;
-  const long n = (long)blockIdx.x * blockDim.x + threadIdx.x;
+                                                    const T* __restrict__ x, OpArgs<T> a) {
+  constexpr int NK = 64 * FO * FI;
+  __shared__ T kr[NK];
+  for (int t = threadIdx.x; t < NK; t += blockDim.x) kr[t] = kref[t];
+  __syncthreads();
+  const unsigned nn = N * N * N;
+  const unsigned n = blockIdx.x * blockDim.x + threadIdx.x;
   if (n >= nn) return;
   const NodeIdx q = node_idx(n, N);
   // scale of the element whose corner c is this node (origin n - c)
   T se[8];
 #pragma unroll
-  for (int c = 0; c < 8; ++c)
-    se[c] = s[nb_node(q, N, -(c & 1), -((c >> 1) & 1), -((c >> 2) & 1))];
+  for (int c = 0; c < 8; ++c) se[c] = s[nb_node(q, N, -(c & 1), -((c >> 1) & 1), -((c >> 2) & 1))];
+
+  __amdgpu_buffer_rsrc_t xr;
+  if constexpr (BUF) xr = make_rsrc(x, (unsigned)((size_t)FI * K * nn * sizeof(T)));
 
   T acc[FO * K];
 #pragma unroll
@@ -77,6 +158,15 @@ __global__ __launch_bounds__(256) void k_fine_apply(int N, const T* __restrict__
 #pragma unroll
   for (int d = 0; d < 27; ++d) {
     const int dx = d % 3 - 1, dy = (d / 3) % 3 - 1, dz = d / 9 - 1;
+    const unsigned m = nb_node(q, N, dx, dy, dz);
+    T xv[FI * K];
+#pragma unroll
+    for (int col = 0; col < FI * K; ++col) {
+      if constexpr (BUF)
+        xv[col] = buf_load<T>(xr, m * (unsigned)sizeof(T), (unsigned)(col * nn * sizeof(T)));
+      else
+        xv[col] = x[(size_t)col * nn + m];
+    }
     T blk[FO * FI];
 #pragma unroll
     for (int t = 0; t < FO * FI; ++t) blk[t] = T(0);
@@ -89,69 +179,89 @@ __global__ __launch_bounds__(256) void k_fine_apply(int N, const T* __restrict__
       for (int fo = 0; fo < FO; ++fo)
 #pragma unroll
         for (int fi = 0; fi < FI; ++fi)
-          blk[fo * FI + fi] += se[c] * kref[(c * FO + fo) * (8 * FI) + lm * FI + fi];
+          blk[fo * FI + fi] += se[c] * kr[(c * FO + fo) * (8 * FI) + lm * FI + fi];
     }
-    const T* xm = x + nb_node(q, N, dx, dy, dz) * (FI * K);
 #pragma unroll
     for (int fi = 0; fi < FI; ++fi)
 #pragma unroll
-      for (int kk = 0; kk < K; ++kk) {
-        const T xv = xm[fi * K + kk];
+      for (int kk = 0; kk < K; ++kk)
 #pragma unroll
-        for (int fo = 0; fo < FO; ++fo) acc[fo * K + kk] += blk[fo * FI + fi] * xv;
-      }
+        for (int fo = 0; fo < FO; ++fo) acc[fo * K + kk] += blk[fo * FI + fi] * xv[fi * K + kk];
   }
-  T* yo = y + n * (FO * K);
-  if (beta == T(0)) {
-#pragma unroll
-    for (int t = 0; t < FO * K; ++t) yo[t] = alpha * acc[t];
-  } else {
-    const T* yi = yin + n * (FO * K);
-#pragma unroll
-    for (int t = 0; t < FO * K; ++t) yo[t] = beta * yi[t] + alpha * acc[t];
-  }
+  epilogue<T, FO, K, CHEBY>(n, nn, acc, a);
 }
 
-template <typename T, int F, int K>
-__global__ __launch_bounds__(256) void k_coarse_apply(int N, const T* __restrict__ Ae,
-                                                      const T* __restrict__ x,
-                                                      const T* __restrict__ yin,
-                                                      T* __restrict__ y, T alpha, T beta) {
-  constexpr int S = 8 * F;
-  const long nn = (long)N * N * N;
-  const long n = (long)blockIdx.x * blockDim.x + threadIdx.x;
+// Coarse levels: assembled 27-point node stencils S[(d*F + fo)*F + fi][n]
+// (block coupling node n to neighbour d).  KK = K: one thread per node and
+// all load columns (large levels: each stencil coefficient read once);
+// KK = 1: one thread per (node, load column k = blockIdx.y) for small levels
+// where one thread per node would leave most of the chip idle.
+template <typename T, int F, int K, int KK, bool CHEBY, bool BUF>
+__global__ __launch_bounds__(256) void k_stencil_apply(unsigned N, const T* __restrict__ S,
+                                                       const T* __restrict__ x, OpArgs<T> a) {
+  const unsigned nn = N * N * N;
+  const unsigned n = blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= nn) return;
+  const int k0 = KK == K ? 0 : (int)blockIdx.y;
+  const NodeIdx q = node_idx(n, N);
+  __amdgpu_buffer_rsrc_t sr, xr;
+  if constexpr (BUF) {
+    sr = make_rsrc(S, (unsigned)((size_t)27 * F * F * nn * sizeof(T)));
+    xr = make_rsrc(x, (unsigned)((size_t)F * K * nn * sizeof(T)));
+  }
+  T acc[F * KK];
+#pragma unroll
+  for (int t = 0; t < F * KK; ++t) acc[t] = T(0);
+#pragma unroll
+  for (int d = 0; d < 27; ++d) {
+    const int dx = d % 3 - 1, dy = (d / 3) % 3 - 1, dz = d / 9 - 1;
+    const unsigned m = nb_node(q, N, dx, dy, dz);
+    T sv[F * F], xv[F * KK];
+#pragma unroll
+    for (int t = 0; t < F * F; ++t) {
+      if constexpr (BUF) sv[t] = buf_load<T>(sr, n * (unsigned)sizeof(T), (unsigned)((d * F * F + t) * nn * sizeof(T)));
+      else sv[t] = S[(size_t)(d * F * F + t) * nn + n];
+    }
+#pragma unroll
+    for (int fi = 0; fi < F; ++fi)
+#pragma unroll
+      for (int j = 0; j < KK; ++j) {
+        const unsigned col = fi * K + k0 + j;
+        if constexpr (BUF) xv[fi * KK + j] = buf_load<T>(xr, m * (unsigned)sizeof(T), col * nn * (unsigned)sizeof(T));
+        else xv[fi * KK + j] = x[(size_t)col * nn + m];
+      }
+#pragma unroll
+    for (int fi = 0; fi < F; ++fi)
+#pragma unroll
+      for (int j = 0; j < KK; ++j)
+#pragma unroll
+        for (int fo = 0; fo < F; ++fo) acc[fo * KK + j] += sv[fo * F + fi] * xv[fi * KK + j];
+  }
+  epilogue_cols<T, F, K, KK, CHEBY>(n, nn, k0, acc, a);
+}
+
+// S[(d*F + fo)*F + fi][n] = sum over elements e containing n and n + d of
+// the element block coupling them (element matrices Ae, structure of arrays)
+template <int F>
+__global__ void k_build_stencil(unsigned N, const double* __restrict__ Ae, double* __restrict__ S) {
+  constexpr int SZ = 8 * F;
+  const unsigned nn = N * N * N;
+  const unsigned n = blockIdx.x * blockDim.x + threadIdx.x;
   if (n >= nn) return;
   const NodeIdx q = node_idx(n, N);
-  T acc[F * K];
-#pragma unroll
-  for (int t = 0; t < F * K; ++t) acc[t] = T(0);
-#pragma unroll
-  for (int c = 0; c < 8; ++c) {
-    const int cx = c & 1, cy = (c >> 1) & 1, cz = (c >> 2) & 1;
-    const long e = nb_node(q, N, -cx, -cy, -cz);
-    const T* rows = Ae + ((long)c * nn + e) * (F * S);
-#pragma unroll
-    for (int lp = 0; lp < 8; ++lp) {
-      const int dx = (lp & 1) - cx, dy = ((lp >> 1) & 1) - cy, dz = ((lp >> 2) & 1) - cz;
-      const T* xm = x + nb_node(q, N, dx, dy, dz) * (F * K);
-#pragma unroll
-      for (int fi = 0; fi < F; ++fi)
-#pragma unroll
-        for (int kk = 0; kk < K; ++kk) {
-          const T xv = xm[fi * K + kk];
-#pragma unroll
-          for (int fo = 0; fo < F; ++fo) acc[fo * K + kk] += rows[fo * S + lp * F + fi] * xv;
-        }
+  for (int d = 0; d < 27; ++d) {
+    const int dx = d % 3 - 1, dy = (d / 3) % 3 - 1, dz = d / 9 - 1;
+    double blk[F * F];
+    for (int t = 0; t < F * F; ++t) blk[t] = 0.0;
+    for (int c = 0; c < 8; ++c) {
+      const int mx = (c & 1) + dx, my = ((c >> 1) & 1) + dy, mz = ((c >> 2) & 1) + dz;
+      if (mx < 0 || mx > 1 || my < 0 || my > 1 || mz < 0 || mz > 1) continue;
+      const int lm = mx + 2 * my + 4 * mz;
+      const unsigned e = nb_node(q, N, -(c & 1), -((c >> 1) & 1), -((c >> 2) & 1));
+      for (int fo = 0; fo < F; ++fo)
+        for (int fi = 0; fi < F; ++fi) blk[fo * F + fi] += Ae[((size_t)((c * F + fo) * SZ + lm * F + fi)) * nn + e];
     }
-  }
-  T* yo = y + n * (F * K);
-  if (beta == T(0)) {
-#pragma unroll
-    for (int t = 0; t < F * K; ++t) yo[t] = alpha * acc[t];
-  } else {
-    const T* yi = yin + n * (F * K);
-#pragma unroll
-    for (int t = 0; t < F * K; ++t) yo[t] = beta * yi[t] + alpha * acc[t];
+    for (int t = 0; t < F * F; ++t) S[(size_t)(d * F * F + t) * nn + n] = blk[t];
   }
 }
 
@@ -166,57 +276,48 @@ __device__ __forceinline__ double qweight(int cp, int l, int L) {
   return w;
 }
 
+// One workgroup per coarse element E: K_E = sum_children Q_c^T K_c Q_c.
 template <int F>
-__global__ void k_galerkin(int Nf, const double* __restrict__ s, const double* __restrict__ kref,
-                           const double* __restrict__ Afine, double* __restrict__ Acoarse) {
+__global__ __launch_bounds__(576) void k_galerkin(unsigned Nf, const double* __restrict__ s,
+                                                  const double* __restrict__ kref,
+                                                  const double* __restrict__ Afine, double* __restrict__ Acoarse) {
   constexpr int S = 8 * F;
   __shared__ double Kc[S * S];
   __shared__ double T1[S * S];
-  const int Nc = Nf / 2;
-  const long nec = (long)Nc * Nc * Nc;
-  const long nef = (long)Nf * Nf * Nf;
-  const long E = blockIdx.x;
-  const int I = (int)(E % Nc), J = (int)((E / Nc) % Nc), Kk = (int)(E / ((long)Nc * Nc));
-  double acc[(S * S + 63) / 64];
-  const int per = (S * S + blockDim.x - 1) / blockDim.x;
-  for (int u = 0; u < per; ++u) acc[u] = 0.0;
+  const unsigned Nc = Nf / 2;
+  const unsigned nec = Nc * Nc * Nc;
+  const unsigned nef = Nf * Nf * Nf;
+  const unsigned E = blockIdx.x;
+  const unsigned I = E % Nc, J = (E / Nc) % Nc, Kk = E / (Nc * Nc);
+  const int t = threadIdx.x;  // blockDim == S*S
+  const int r = t / S, col = t % S;
+  double acc = 0.0;
   for (int cp = 0; cp < 8; ++cp) {
-    const long ef = (long)(2 * I + (cp & 1)) +
-                    (long)Nf * ((2 * J + ((cp >> 1) & 1)) + (long)Nf * (2 * Kk + ((cp >> 2) & 1)));
-    for (int t = threadIdx.x; t < S * S; t += blockDim.x) {
-      const int r = t / S, col = t % S;
-      if (s) {
-        Kc[t] = s[ef] * kref[t];
-      } else {
-        const int l = r / F, f = r % F;
-        Kc[t] = Afine[(((long)l * nef + ef) * F + f) * S + col];
-      }
+    const unsigned ef = (2 * I + (cp & 1)) + Nf * ((2 * J + ((cp >> 1) & 1)) + Nf * (2 * Kk + ((cp >> 2) & 1)));
+    if (s) {
+      Kc[t] = s[ef] * kref[t];
+    } else {
+      const int l = r / F, f = r % F;
+      Kc[t] = Afine[((size_t)((l * F + f) * S + col)) * nef + ef];
     }
     __syncthreads();
-    for (int t = threadIdx.x; t < S * S; t += blockDim.x) {
-      const int r = t / S, col = t % S;
+    {
       const int Lp = col / F, g = col % F;
       double v = 0.0;
       for (int lp = 0; lp < 8; ++lp) v += Kc[r * S + lp * F + g] * qweight(cp, lp, Lp);
       T1[t] = v;
     }
     __syncthreads();
-    int u = 0;
-    for (int t = threadIdx.x; t < S * S; t += blockDim.x, ++u) {
-      const int r = t / S, col = t % S;
+    {
       const int L = r / F, f = r % F;
       double v = 0.0;
       for (int l = 0; l < 8; ++l) v += qweight(cp, l, L) * T1[(l * F + f) * S + col];
-      acc[u] += v;
+      acc += v;
     }
     __syncthreads();
   }
-  int u = 0;
-  for (int t = threadIdx.x; t < S * S; t += blockDim.x, ++u) {
-    const int r = t / S, col = t % S;
-    const int L = r / F, f = r % F;
-    Acoarse[(((long)L * nec + E) * F + f) * S + col] = acc[u];
-  }
+  const int L = r / F, f = r % F;
+  Acoarse[((size_t)((L * F + f) * S + col)) * nec + E] = acc;
 }
 
 __device__ __forceinline__ void inv3(const double* a, double* o) {
@@ -236,11 +337,23 @@ __device__ __forceinline__ void inv3(const double* a, double* o) {
   o[8] = (a[0] * a[4] - a[1] * a[3]) * id;
 }
 
+// Dinv stored [F*F][nn] (entry (f, g) of node n at (f*F + g)*nn + n)
 template <int F>
-__global__ void k_diag_fine(int N, const double* __restrict__ s, const double* __restrict__ kref,
+__device__ __forceinline__ void store_inv(unsigned n, unsigned nn, const double* D, double* Dinv) {
+  if (F == 1) {
+    Dinv[n] = 1.0 / D[0];
+  } else {
+    double o[9];
+    inv3(D, o);
+    for (int t = 0; t < 9; ++t) Dinv[(size_t)t * nn + n] = o[t];
+  }
+}
+
+template <int F>
+__global__ void k_diag_fine(unsigned N, const double* __restrict__ s, const double* __restrict__ kref,
                             double* __restrict__ Dinv) {
-  const long nn = (long)N * N * N;
-  const long n = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const unsigned nn = N * N * N;
+  const unsigned n = blockIdx.x * blockDim.x + threadIdx.x;
   if (n >= nn) return;
   const NodeIdx q = node_idx(n, N);
   double D[F * F];
@@ -250,153 +363,180 @@ __global__ void k_diag_fine(int N, const double* __restrict__ s, const double* _
     for (int f = 0; f < F; ++f)
       for (int g = 0; g < F; ++g) D[f * F + g] += sc * kref[(c * F + f) * (8 * F) + c * F + g];
   }
-  if (F == 1) {
-    Dinv[n] = 1.0 / D[0];
-  } else {
-    double o[9];
-    inv3(D, o);
-    for (int t = 0; t < 9; ++t) Dinv[n * 9 + t] = o[t];
-  }
+  store_inv<F>(n, nn, D, Dinv);
 }
 
 template <int F>
-__global__ void k_diag_coarse(int N, const double* __restrict__ Ae, double* __restrict__ Dinv) {
+__global__ void k_diag_coarse(unsigned N, const double* __restrict__ Ae, double* __restrict__ Dinv) {
   constexpr int S = 8 * F;
-  const long nn = (long)N * N * N;
-  const long n = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const unsigned nn = N * N * N;
+  const unsigned n = blockIdx.x * blockDim.x + threadIdx.x;
   if (n >= nn) return;
   const NodeIdx q = node_idx(n, N);
   double D[F * F];
   for (int t = 0; t < F * F; ++t) D[t] = 0.0;
   for (int c = 0; c < 8; ++c) {
-    const long e = nb_node(q, N, -(c & 1), -((c >> 1) & 1), -((c >> 2) & 1));
-    const double* rows = Ae + ((long)c * nn + e) * (F * S);
+    const unsigned e = nb_node(q, N, -(c & 1), -((c >> 1) & 1), -((c >> 2) & 1));
     for (int f = 0; f < F; ++f)
-      for (int g = 0; g < F; ++g) D[f * F + g] += rows[f * S + c * F + g];
+      for (int g = 0; g < F; ++g) D[f * F + g] += Ae[((size_t)((c * F + f) * S + c * F + g)) * nn + e];
   }
-  if (F == 1) {
-    Dinv[n] = 1.0 / D[0];
-  } else {
-    double o[9];
-    inv3(D, o);
-    for (int t = 0; t < 9; ++t) Dinv[n * 9 + t] = o[t];
-  }
+  store_inv<F>(n, nn, D, Dinv);
 }
 
-template <typename T, int F, int K>
-__global__ __launch_bounds__(256) void k_cheby(long nn, const T* __restrict__ Dinv,
-                                               const T* __restrict__ r, T* __restrict__ d,
-                                               T* __restrict__ x, T a, T b, int xzero) {
-  const long n = (long)blockIdx.x * blockDim.x + threadIdx.x;
+// First Chebyshev step for (node, column k = blockIdx.y): d = cf Dinv r; x = d or x += d
+template <typename T, int F>
+__global__ __launch_bounds__(256) void k_cheby_first(unsigned nn, int K, const T* __restrict__ Dinv,
+                                                     const T* r, T* d, T* x, T cf, int xzero) {
+  const unsigned n = blockIdx.x * blockDim.x + threadIdx.x;
   if (n >= nn) return;
-  const T* rn = r + n * (F * K);
-  T* dn = d + n * (F * K);
-  T* xn = x + n * (F * K);
-  T Di[F * F];
+  const int kk = blockIdx.y;
+  T rv[F];
 #pragma unroll
-  for (int t = 0; t < F * F; ++t) Di[t] = Dinv[n * (F * F) + t];
+  for (int f = 0; f < F; ++f) rv[f] = r[(size_t)(f * K + kk) * nn + n];
 #pragma unroll
-  for (int kk = 0; kk < K; ++kk) {
-    T rv[F];
+  for (int f = 0; f < F; ++f) {
+    T z = T(0);
 #pragma unroll
-    for (int f = 0; f < F; ++f) rv[f] = rn[f * K + kk];
-#pragma unroll
-    for (int f = 0; f < F; ++f) {
-      T z = T(0);
-#pragma unroll
-      for (int g = 0; g < F; ++g) z += Di[f * F + g] * rv[g];
-      T dv = b * z;
-      if (a != T(0)) dv += a * dn[f * K + kk];
-      dn[f * K + kk] = dv;
-      if (xzero) xn[f * K + kk] = dv;
-      else xn[f * K + kk] += dv;
-    }
+    for (int g = 0; g < F; ++g) z += Dinv[(size_t)(f * F + g) * nn + n] * rv[g];
+    const T dv = cf * z;
+    const size_t o = (size_t)(f * K + kk) * nn + n;
+    d[o] = dv;
+    if (xzero) x[o] = dv;
+    else x[o] += dv;
   }
 }
 
-// rc[I] = sum_{d in {-1,0,1}^3} prod(1 - |d|/2) rf[2I + d]
-template <typename T, int F, int K>
-__global__ void k_restrict(int Nc, const T* __restrict__ rf, T* __restrict__ rc) {
-  const int Nf = 2 * Nc;
-  const long nc = (long)Nc * Nc * Nc;
-  const long I = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (I >= nc) return;
-  const int ic = (int)(I % Nc), jc = (int)((I / Nc) % Nc), kc = (int)(I / ((long)Nc * Nc));
-  T acc[F * K];
-#pragma unroll
-  for (int t = 0; t < F * K; ++t) acc[t] = T(0);
-  for (int dz = -1; dz <= 1; ++dz)
-    for (int dy = -1; dy <= 1; ++dy)
-      for (int dx = -1; dx <= 1; ++dx) {
-        const T w = T((dx ? 0.5 : 1.0) * (dy ? 0.5 : 1.0) * (dz ? 0.5 : 1.0));
-        const int fi = (2 * ic + dx + Nf) % Nf, fj = (2 * jc + dy + Nf) % Nf,
-                  fk = (2 * kc + dz + Nf) % Nf;
-        const T* src = rf + ((long)fi + (long)Nf * (fj + (long)Nf * fk)) * (F * K);
-#pragma unroll
-        for (int t = 0; t < F * K; ++t) acc[t] += w * src[t];
-      }
-  T* dst = rc + I * (F * K);
-#pragma unroll
-  for (int t = 0; t < F * K; ++t) dst[t] = acc[t];
-}
-
-// xf[i] += sum_I P[i, I] xc[I], fine node i = 2I + c with c in {0,1}^3
-template <typename T, int F, int K>
-__global__ void k_prolong(int Nc, const T* __restrict__ xc, T* __restrict__ xf) {
-  const int Nf = 2 * Nc;
-  const long nf = (long)Nf * Nf * Nf;
-  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= nf) return;
-  const int fi = (int)(i % Nf), fj = (int)((i / Nf) % Nf), fk = (int)(i / ((long)Nf * Nf));
-  const int bi = fi >> 1, bj = fj >> 1, bk = fk >> 1;
-  const int oi = fi & 1, oj = fj & 1, ok = fk & 1;
-  T acc[F * K];
-#pragma unroll
-  for (int t = 0; t < F * K; ++t) acc[t] = T(0);
-  for (int c = 0; c < 8; ++c) {
-    const int ax = c & 1, ay = (c >> 1) & 1, az = (c >> 2) & 1;
-    if ((ax && !oi) || (ay && !oj) || (az && !ok)) continue;
-    const T w = T((oi ? 0.5 : 1.0) * (oj ? 0.5 : 1.0) * (ok ? 0.5 : 1.0));
-    const long I = (long)((bi + ax) % Nc) + (long)Nc * (((bj + ay) % Nc) + (long)Nc * ((bk + az) % Nc));
-    const T* src = xc + I * (F * K);
-#pragma unroll
-    for (int t = 0; t < F * K; ++t) acc[t] += w * src[t];
-  }
-  T* dst = xf + i * (F * K);
-#pragma unroll
-  for (int t = 0; t < F * K; ++t) dst[t] += acc[t];
-}
-
+// rc[I] = sum_{d in {-1,0,1}^3} prod(1 - |d|/2) rf[2I + d], all ncol columns
 template <typename T>
-__global__ void k_dense_apply(int rows, int K, const double* __restrict__ Minv,
-                              const T* __restrict__ r, T* __restrict__ z) {
-  const int row = blockIdx.x;
+__global__ __launch_bounds__(256) void k_restrict(unsigned Nc, int ncol, const T* __restrict__ rf, T* __restrict__ rc) {
+  const unsigned Nf = 2 * Nc;
+  const unsigned nc = Nc * Nc * Nc, nf = Nf * Nf * Nf;
+  const unsigned I = blockIdx.x * blockDim.x + threadIdx.x;
+  if (I >= nc) return;
+  const unsigned ic = I % Nc, jc = (I / Nc) % Nc, kc = I / (Nc * Nc);
+  const unsigned xs[3] = {(2 * ic + Nf - 1) % Nf, 2 * ic, 2 * ic + 1};
+  const unsigned ys[3] = {(2 * jc + Nf - 1) % Nf, 2 * jc, 2 * jc + 1};
+  const unsigned zs[3] = {(2 * kc + Nf - 1) % Nf, 2 * kc, 2 * kc + 1};
+  unsigned off[27];
+#pragma unroll
+  for (int t = 0; t < 27; ++t) off[t] = xs[t % 3] + Nf * (ys[(t / 3) % 3] + Nf * zs[t / 9]);
+  for (int col = 0; col < ncol; ++col) {
+    const T* src = rf + (size_t)col * nf;
+    T acc = T(0);
+#pragma unroll
+    for (int t = 0; t < 27; ++t) {
+      const int dx = t % 3, dy = (t / 3) % 3, dz = t / 9;
+      const T w = T((dx == 1 ? 1.0 : 0.5) * (dy == 1 ? 1.0 : 0.5) * (dz == 1 ? 1.0 : 0.5));
+      acc += w * src[off[t]];
+    }
+    rc[(size_t)col * nc + I] = acc;
+  }
+}
+
+// xf[i] += sum_I P[i, I] xc[I], fine node i = 2I + c, all ncol columns
+template <typename T>
+__global__ __launch_bounds__(256) void k_prolong(unsigned Nc, int ncol, const T* __restrict__ xc, T* __restrict__ xf) {
+  const unsigned Nf = 2 * Nc;
+  const unsigned nc = Nc * Nc * Nc, nf = Nf * Nf * Nf;
+  const unsigned i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nf) return;
+  const unsigned fi = i % Nf, fj = (i / Nf) % Nf, fk = i / (Nf * Nf);
+  const unsigned bi = fi >> 1, bj = fj >> 1, bk = fk >> 1;
+  const unsigned oi = fi & 1, oj = fj & 1, ok = fk & 1;
+  const unsigned bi1 = bi + 1 == Nc ? 0 : bi + 1, bj1 = bj + 1 == Nc ? 0 : bj + 1, bk1 = bk + 1 == Nc ? 0 : bk + 1;
+  const T w = T((oi ? 0.5 : 1.0) * (oj ? 0.5 : 1.0) * (ok ? 0.5 : 1.0));
+  unsigned src_idx[8];
+  int cnt = 0;
+#pragma unroll
+  for (int c = 0; c < 8; ++c) {
+    const unsigned ax = c & 1, ay = (c >> 1) & 1, az = (c >> 2) & 1;
+    const bool use = !((ax && !oi) || (ay && !oj) || (az && !ok));
+    src_idx[c] = (ax ? bi1 : bi) + Nc * ((ay ? bj1 : bj) + Nc * (az ? bk1 : bk));
+    if (use) ++cnt;
+    if (!use) src_idx[c] = 0xFFFFFFFFu;
+  }
+  for (int col = 0; col < ncol; ++col) {
+    const T* src = xc + (size_t)col * nc;
+    T acc = T(0);
+#pragma unroll
+    for (int c = 0; c < 8; ++c)
+      if (src_idx[c] != 0xFFFFFFFFu) acc += src[src_idx[c]];
+    xf[(size_t)col * nf + i] += w * acc;
+  }
+}
+
+// z[(f, k, n)] = sum_{(g, m)} Minv[(f*nc + n), (g*nc + m)] r[(g, k, m)]
+template <typename T>
+__global__ void k_dense_apply(int F, int nc, int K, const double* __restrict__ Minv, const T* __restrict__ r,
+                              T* __restrict__ z) {
+  const int row = blockIdx.x;  // f*nc + n
   const int kk = threadIdx.y;
+  const int rows = F * nc;
+  const int f = row / nc, n = row % nc;
   __shared__ double part[9][64];
   double v = 0.0;
-  for (int c = threadIdx.x; c < rows; c += 64) v += Minv[(long)row * rows + c] * (double)r[(long)c * K + kk];
+  for (int c = threadIdx.x; c < rows; c += 64) {
+    const int g = c / nc, m = c % nc;
+    v += Minv[(size_t)row * rows + c] * (double)r[(size_t)(g * K + kk) * nc + m];
+  }
   part[kk][threadIdx.x] = v;
   __syncthreads();
   if (threadIdx.x == 0) {
     double sum = 0.0;
     for (int t = 0; t < 64; ++t) sum += part[kk][t];
-    z[(long)row * K + kk] = (T)sum;
+    z[(size_t)(f * K + kk) * nc + n] = (T)sum;
   }
 }
 
-inline unsigned blocks_for(long n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+inline unsigned blocks_for(size_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+template <typename T, int OPV, int KV>
+void launch_fine(unsigned N, const T* s, const T* kref, const T* x, const OpArgs<T>& a, bool cheby,
+                 hipStream_t st) {
+  constexpr int FO = OpFields<OPV>::FO, FI = OpFields<OPV>::FI;
+  const size_t nn = (size_t)N * N * N;
+  const unsigned g = blocks_for(nn, 128);
+  const bool buf = nn * FI * KV * sizeof(T) < (size_t(1) << 32);
+#define PHZ_FK(CH, BUF) \
+  hipLaunchKernelGGL((k_fine_apply<T, FO, FI, KV, CH, BUF>), dim3(g), dim3(128), 0, st, N, s, kref, x, a)
+  if constexpr (FO == FI) {
+    if (cheby) {
+      if (buf) PHZ_FK(true, true);
+      else PHZ_FK(true, false);
+      return;
+    }
+  }
+  if (cheby) throw std::invalid_argument("Chebyshev epilogue needs a square block");
+  if (buf) PHZ_FK(false, true);
+  else PHZ_FK(false, false);
+#undef PHZ_FK
+}
+
+template <typename T, int FV, int KV>
+void launch_coarse(unsigned N, const T* S, const T* x, const OpArgs<T>& a, bool cheby, hipStream_t st) {
+  const size_t nn = (size_t)N * N * N;
+  const bool buf = nn * 27 * FV * FV * sizeof(T) < (size_t(1) << 32) && nn * FV * KV * sizeof(T) < (size_t(1) << 32);
+  // one thread per node when that already fills the chip, else per (node, column)
+  const bool per_node = KV == 1 || nn >= 131072;
+  const unsigned g = blocks_for(nn, 256);
+#define PHZ_CK(KK, CH, BUF, GY) \
+  hipLaunchKernelGGL((k_stencil_apply<T, FV, KV, KK, CH, BUF>), dim3(g, GY), dim3(256), 0, st, N, S, x, a)
+  if (per_node) {
+    if (cheby) { if (buf) PHZ_CK(KV, true, true, 1); else PHZ_CK(KV, true, false, 1); }
+    else { if (buf) PHZ_CK(KV, false, true, 1); else PHZ_CK(KV, false, false, 1); }
+  } else {
+    if (cheby) { if (buf) PHZ_CK(1, true, true, KV); else PHZ_CK(1, true, false, KV); }
+    else { if (buf) PHZ_CK(1, false, true, KV); else PHZ_CK(1, false, false, KV); }
+  }
+#undef PHZ_CK
+}
 
 }  // namespace
 
 template <typename T>
-void fine_apply(int op, int nrhs, int N, const T* s, const T* kref, const T* x, const T* yin,
-                T* y, T alpha, T beta, hipStream_t st) {
-  const long nn = (long)N * N * N;
-  const int bs = 128;
-  const unsigned g = blocks_for(nn, bs);
-#define PHZ_FA(OPV, KV)                                                                    \
-  hipLaunchKernelGGL((k_fine_apply<T, OpFields<OPV>::FO, OpFields<OPV>::FI, KV>), dim3(g),  \
-                     dim3(bs), 0, st, N, s, kref, x, yin, y, alpha, beta)
+void fine_apply(int op, int nrhs, int N, const T* s, const T* kref, const T* x, const OpArgs<T>& a, bool cheby,
+                hipStream_t st) {
+#define PHZ_FA(OPV, KV) launch_fine<T, OPV, KV>((unsigned)N, s, kref, x, a, cheby, st)
   if (nrhs == 1) {
     switch (op) {
       case 0: PHZ_FA(0, 1); break;
@@ -421,102 +561,87 @@ void fine_apply(int op, int nrhs, int N, const T* s, const T* kref, const T* x, 
 }
 
 template <typename T>
-void coarse_apply(int F, int nrhs, int N, const T* Ae, const T* x, const T* yin, T* y, T alpha,
-                  T beta, hipStream_t st) {
-  const long nn = (long)N * N * N;
-  const int bs = 128;
-  const unsigned g = blocks_for(nn, bs);
-#define PHZ_CA(FV, KV) \
-  hipLaunchKernelGGL((k_coarse_apply<T, FV, KV>), dim3(g), dim3(bs), 0, st, N, Ae, x, yin, y, alpha, beta)
-  if (F == 3 && nrhs == 1) PHZ_CA(3, 1);
-  else if (F == 3 && nrhs == 9) PHZ_CA(3, 9);
-  else if (F == 1 && nrhs == 1) PHZ_CA(1, 1);
-  else if (F == 1 && nrhs == 9) PHZ_CA(1, 9);
+void coarse_apply(int F, int nrhs, int N, const T* Ae, const T* x, const OpArgs<T>& a, bool cheby, hipStream_t st) {
+  if (F == 3 && nrhs == 1) launch_coarse<T, 3, 1>((unsigned)N, Ae, x, a, cheby, st);
+  else if (F == 3 && nrhs == 9) launch_coarse<T, 3, 9>((unsigned)N, Ae, x, a, cheby, st);
+  else if (F == 1 && nrhs == 1) launch_coarse<T, 1, 1>((unsigned)N, Ae, x, a, cheby, st);
+  else if (F == 1 && nrhs == 9) launch_coarse<T, 1, 9>((unsigned)N, Ae, x, a, cheby, st);
   else throw std::invalid_argument("coarse_apply");
-#undef PHZ_CA
   PHZ_LAUNCH_CHECK();
 }
 
-void galerkin_build(int F, int Nf, const double* s, const double* kref, const double* Afine,
-                    double* Acoarse, hipStream_t st) {
-  const long nec = (long)(Nf / 2) * (Nf / 2) * (Nf / 2);
-  if (F == 3) hipLaunchKernelGGL(k_galerkin<3>, dim3((unsigned)nec), dim3(576), 0, st, Nf, s, kref, Afine, Acoarse);
-  else if (F == 1) hipLaunchKernelGGL(k_galerkin<1>, dim3((unsigned)nec), dim3(64), 0, st, Nf, s, kref, Afine, Acoarse);
-  else throw std::invalid_argument("galerkin F");
+void galerkin_build(int F, int Nf, const double* s, const double* kref, const double* Afine, double* Acoarse,
+                    hipStream_t st) {
+  const unsigned nec = (unsigned)(Nf / 2) * (Nf / 2) * (Nf / 2);
+  if (F == 3)
+    hipLaunchKernelGGL(k_galerkin<3>, dim3(nec), dim3(576), 0, st, (unsigned)Nf, s, kref, Afine, Acoarse);
+  else if (F == 1)
+    hipLaunchKernelGGL(k_galerkin<1>, dim3(nec), dim3(64), 0, st, (unsigned)Nf, s, kref, Afine, Acoarse);
+  else
+    throw std::invalid_argument("galerkin F");
   PHZ_LAUNCH_CHECK();
 }
 
 void diag_inv_fine(int F, int N, const double* s, const double* kref, double* Dinv, hipStream_t st) {
-  const long nn = (long)N * N * N;
-  if (F == 3) hipLaunchKernelGGL(k_diag_fine<3>, dim3(blocks_for(nn, 256)), dim3(256), 0, st, N, s, kref, Dinv);
-  else hipLaunchKernelGGL(k_diag_fine<1>, dim3(blocks_for(nn, 256)), dim3(256), 0, st, N, s, kref, Dinv);
+  const size_t nn = (size_t)N * N * N;
+  if (F == 3) hipLaunchKernelGGL(k_diag_fine<3>, dim3(blocks_for(nn, 256)), dim3(256), 0, st, (unsigned)N, s, kref, Dinv);
+  else hipLaunchKernelGGL(k_diag_fine<1>, dim3(blocks_for(nn, 256)), dim3(256), 0, st, (unsigned)N, s, kref, Dinv);
   PHZ_LAUNCH_CHECK();
 }
 
 void diag_inv_coarse(int F, int N, const double* Ae, double* Dinv, hipStream_t st) {
-  const long nn = (long)N * N * N;
-  if (F == 3) hipLaunchKernelGGL(k_diag_coarse<3>, dim3(blocks_for(nn, 256)), dim3(256), 0, st, N, Ae, Dinv);
-  else hipLaunchKernelGGL(k_diag_coarse<1>, dim3(blocks_for(nn, 256)), dim3(256), 0, st, N, Ae, Dinv);
+  const size_t nn = (size_t)N * N * N;
+  if (F == 3) hipLaunchKernelGGL(k_diag_coarse<3>, dim3(blocks_for(nn, 256)), dim3(256), 0, st, (unsigned)N, Ae, Dinv);
+  else hipLaunchKernelGGL(k_diag_coarse<1>, dim3(blocks_for(nn, 256)), dim3(256), 0, st, (unsigned)N, Ae, Dinv);
   PHZ_LAUNCH_CHECK();
 }
 
 template <typename T>
-void cheby_step(int F, int nrhs, long nn, const T* Dinv, const T* r, T* d, T* x, T a, T b, bool xzero,
-                hipStream_t st) {
-  const unsigned g = blocks_for(nn, 256);
-#define PHZ_CH(FV, KV) \
-  hipLaunchKernelGGL((k_cheby<T, FV, KV>), dim3(g), dim3(256), 0, st, nn, Dinv, r, d, x, a, b, (int)xzero)
-  if (F == 3 && nrhs == 1) PHZ_CH(3, 1);
-  else if (F == 3 && nrhs == 9) PHZ_CH(3, 9);
-  else if (F == 1 && nrhs == 1) PHZ_CH(1, 1);
-  else if (F == 1 && nrhs == 9) PHZ_CH(1, 9);
-  else throw std::invalid_argument("cheby_step");
-#undef PHZ_CH
+void cheby_first(int F, int nrhs, long nn, const T* Dinv, const T* r, T* d, T* x, T cf, bool xzero, hipStream_t st) {
+  const dim3 g(blocks_for((size_t)nn, 256), nrhs);
+  if (F == 3)
+    hipLaunchKernelGGL((k_cheby_first<T, 3>), g, dim3(256), 0, st, (unsigned)nn, nrhs, Dinv, r, d, x, cf, (int)xzero);
+  else if (F == 1)
+    hipLaunchKernelGGL((k_cheby_first<T, 1>), g, dim3(256), 0, st, (unsigned)nn, nrhs, Dinv, r, d, x, cf, (int)xzero);
+  else
+    throw std::invalid_argument("cheby_first");
   PHZ_LAUNCH_CHECK();
 }
 
 template <typename T>
 void restrict_fw(int F, int nrhs, int Nc, const T* rf, T* rc, hipStream_t st) {
-  const long nc = (long)Nc * Nc * Nc;
-  const unsigned g = blocks_for(nc, 128);
-#define PHZ_RS(FV, KV) hipLaunchKernelGGL((k_restrict<T, FV, KV>), dim3(g), dim3(128), 0, st, Nc, rf, rc)
-  if (F == 3 && nrhs == 1) PHZ_RS(3, 1);
-  else if (F == 3 && nrhs == 9) PHZ_RS(3, 9);
-  else if (F == 1 && nrhs == 1) PHZ_RS(1, 1);
-  else if (F == 1 && nrhs == 9) PHZ_RS(1, 9);
-  else throw std::invalid_argument("restrict");
-#undef PHZ_RS
+  hipLaunchKernelGGL(k_restrict<T>, dim3(blocks_for((size_t)Nc * Nc * Nc, 256)), dim3(256), 0, st, (unsigned)Nc,
+                     F * nrhs, rf, rc);
   PHZ_LAUNCH_CHECK();
 }
 
 template <typename T>
 void prolong_add(int F, int nrhs, int Nc, const T* xc, T* xf, hipStream_t st) {
-  const long nf = 8L * Nc * Nc * Nc;
-  const unsigned g = blocks_for(nf, 128);
-#define PHZ_PR(FV, KV) hipLaunchKernelGGL((k_prolong<T, FV, KV>), dim3(g), dim3(128), 0, st, Nc, xc, xf)
-  if (F == 3 && nrhs == 1) PHZ_PR(3, 1);
-  else if (F == 3 && nrhs == 9) PHZ_PR(3, 9);
-  else if (F == 1 && nrhs == 1) PHZ_PR(1, 1);
-  else if (F == 1 && nrhs == 9) PHZ_PR(1, 9);
-  else throw std::invalid_argument("prolong");
-#undef PHZ_PR
+  hipLaunchKernelGGL(k_prolong<T>, dim3(blocks_for((size_t)8 * Nc * Nc * Nc, 256)), dim3(256), 0, st, (unsigned)Nc,
+                     F * nrhs, xc, xf);
+  PHZ_LAUNCH_CHECK();
+}
+
+void build_stencil(int F, int N, const double* Ae, double* S, hipStream_t st) {
+  const size_t nn = (size_t)N * N * N;
+  if (F == 3) hipLaunchKernelGGL(k_build_stencil<3>, dim3(blocks_for(nn, 128)), dim3(128), 0, st, (unsigned)N, Ae, S);
+  else hipLaunchKernelGGL(k_build_stencil<1>, dim3(blocks_for(nn, 128)), dim3(128), 0, st, (unsigned)N, Ae, S);
   PHZ_LAUNCH_CHECK();
 }
 
 template <typename T>
-void dense_apply(int rows, int nrhs, const double* Minv, const T* r, T* z, hipStream_t st) {
-  hipLaunchKernelGGL(k_dense_apply<T>, dim3(rows), dim3(64, nrhs), 0, st, rows, nrhs, Minv, r, z);
+void dense_apply(int F, int nc, int nrhs, const double* Minv, const T* r, T* z, hipStream_t st) {
+  hipLaunchKernelGGL(k_dense_apply<T>, dim3(F * nc), dim3(64, nrhs), 0, st, F, nc, nrhs, Minv, r, z);
   PHZ_LAUNCH_CHECK();
 }
 
-#define PHZ_INST(T)                                                                                 \
-  template void fine_apply<T>(int, int, int, const T*, const T*, const T*, const T*, T*, T, T,      \
-                              hipStream_t);                                                         \
-  template void coarse_apply<T>(int, int, int, const T*, const T*, const T*, T*, T, T, hipStream_t); \
-  template void cheby_step<T>(int, int, long, const T*, const T*, T*, T*, T, T, bool, hipStream_t); \
-  template void restrict_fw<T>(int, int, int, const T*, T*, hipStream_t);                          \
-  template void prolong_add<T>(int, int, int, const T*, T*, hipStream_t);                          \
-  template void dense_apply<T>(int, int, const double*, const T*, T*, hipStream_t);
+#define PHZ_INST(T)                                                                                            \
+  template void fine_apply<T>(int, int, int, const T*, const T*, const T*, const OpArgs<T>&, bool, hipStream_t); \
+  template void coarse_apply<T>(int, int, int, const T*, const T*, const OpArgs<T>&, bool, hipStream_t);         \
+  template void cheby_first<T>(int, int, long, const T*, const T*, T*, T*, T, bool, hipStream_t);               \
+  template void restrict_fw<T>(int, int, int, const T*, T*, hipStream_t);                                     \
+  template void prolong_add<T>(int, int, int, const T*, T*, hipStream_t);                                     \
+  template void dense_apply<T>(int, int, int, const double*, const T*, T*, hipStream_t);
 PHZ_INST(double)
 PHZ_INST(float)
 #undef PHZ_INST

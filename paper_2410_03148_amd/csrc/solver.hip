@@ -64,7 +64,8 @@ struct Level {
   int N = 0;
   long nn = 0;
   DevBuf<double> Ae;      // Galerkin element matrices (levels >= 1)
-  DevBuf<float> Ae32;
+  DevBuf<double> S;       // assembled 27-point node stencils (levels >= 1)
+  DevBuf<float> S32;
   DevBuf<double> Dinv;    // node-block diagonal inverse
   DevBuf<float> Dinv32;
   double lmax = 0.0;
@@ -80,14 +81,14 @@ struct Hierarchy {
 
 template <typename T>
 struct LevelWork {
-  DevBuf<T> b, x, r, d;
+  DevBuf<T> b, x, r, d, d2;
 };
 
 template <typename T>
 struct Work {
   int cap_k = 0, cap_m = 0;
   std::vector<std::unique_ptr<LevelWork<T>>> A, S;
-  DevBuf<T> ru, rp, zu, zp, t1u, t2u, t1p, t2p;   // preconditioner temporaries
+  DevBuf<T> t1u, t2u, t1p, t2p, t3p;   // preconditioner temporaries
   DevBuf<T> V, w, z, t, r, b, x;                  // GMRES
 };
 
@@ -218,6 +219,10 @@ static void build_levels(phz_ctx* c, Hierarchy& H, int F, int op) {
   }
 }
 
+// Krylov basis vectors are padded apart so that the many concurrent streams
+// of an Arnoldi pass do not sit at power-of-two distances
+static size_t basis_stride(long nn, int K) { return (size_t)nn * 4 * K + 512; }
+
 template <typename T>
 static void alloc_work(phz_ctx* c, Work<T>& W, int K, int m) {
   if (W.cap_k >= K && W.cap_m >= m && !W.A.empty()) return;
@@ -229,6 +234,7 @@ static void alloc_work(phz_ctx* c, Work<T>& W, int K, int m) {
       const size_t cnt = (size_t)H.lv[l]->nn * H.F * K;
       w->r.alloc(cnt);
       w->d.alloc(cnt);
+      w->d2.alloc(cnt);
       if (l > 0) {
         w->b.alloc(cnt);
         w->x.alloc(cnt);
@@ -239,9 +245,9 @@ static void alloc_work(phz_ctx* c, Work<T>& W, int K, int m) {
   mk(c->hA, W.A);
   mk(c->hS, W.S);
   const size_t u = (size_t)nn * 3 * K, p = (size_t)nn * K, full = (size_t)nn * 4 * K;
-  W.ru.alloc(u); W.zu.alloc(u); W.t1u.alloc(u); W.t2u.alloc(u);
-  W.rp.alloc(p); W.zp.alloc(p); W.t1p.alloc(p); W.t2p.alloc(p);
-  W.V.alloc(full * (m + 1));
+  W.t1u.alloc(u); W.t2u.alloc(u);
+  W.t1p.alloc(p); W.t2p.alloc(p); W.t3p.alloc(p);
+  W.V.alloc(basis_stride(nn, K) * (m + 1));
   W.w.alloc(full); W.z.alloc(full); W.t.alloc(full); W.r.alloc(full); W.b.alloc(full); W.x.alloc(full);
   W.cap_k = K;
   W.cap_m = m;
@@ -261,7 +267,7 @@ static void ensure_state_buffers(phz_ctx* c) {
   c->gm_h2.alloc((size_t)(kMaxRestart + 1) * K);
   c->gm_nrm.alloc(4 * K);
   c->gm_int.alloc(3 * K + 1);
-  c->red_work.alloc(reduce_work_size(400));
+  c->red_work.alloc(reduce_work_size());
   c->small.alloc(512);
 }
 
@@ -292,9 +298,9 @@ template <> const float* kref_of<float>(phz_ctx* c, int op) {
 template <typename T> static const T* s_of(phz_ctx* c);
 template <> const double* s_of<double>(phz_ctx* c) { return c->s.p; }
 template <> const float* s_of<float>(phz_ctx* c) { return c->s32.p; }
-template <typename T> static const T* ae_of(Level& L);
-template <> const double* ae_of<double>(Level& L) { return L.Ae.p; }
-template <> const float* ae_of<float>(Level& L) { return L.Ae32.p; }
+template <typename T> static const T* stencil_of(Level& L);
+template <> const double* stencil_of<double>(Level& L) { return L.S.p; }
+template <> const float* stencil_of<float>(Level& L) { return L.S32.p; }
 template <typename T> static const T* dinv_of(Level& L);
 template <> const double* dinv_of<double>(Level& L) { return L.Dinv.p; }
 template <> const float* dinv_of<float>(Level& L) { return L.Dinv32.p; }
@@ -311,24 +317,46 @@ static const char* kOpNames[4][2][2] = {
 
 // fine-level operator launch with optional timing
 template <typename T>
-static void op_apply(phz_ctx* c, int op, int K, const T* x, const T* yin, T* y, T alpha, T beta) {
+static void op_apply_args(phz_ctx* c, int op, int K, const T* x, const OpArgs<T>& a, bool cheby) {
   const long slot = time_begin(c, kOpNames[op][K == 9][sizeof(T) == 4]);
-  fine_apply<T>(op, K, c->N, s_of<T>(c), kref_of<T>(c, op), x, yin, y, alpha, beta, c->stream);
+  fine_apply<T>(op, K, c->N, s_of<T>(c), kref_of<T>(c, op), x, a, cheby, c->stream);
   time_end(c, slot);
 }
 
 template <typename T>
-static void level_apply(phz_ctx* c, Hierarchy& H, int l, int K, const T* x, const T* yin, T* y, T alpha,
-                        T beta) {
+static OpArgs<T> plain_args(const T* yin, T* y, T alpha, T beta) {
+  OpArgs<T> a;
+  a.yin = yin;
+  a.y = y;
+  a.alpha = alpha;
+  a.beta = beta;
+  return a;
+}
+
+// y = beta*yin + alpha*A x on the fine level
+template <typename T>
+static void op_apply(phz_ctx* c, int op, int K, const T* x, const T* yin, T* y, T alpha, T beta) {
+  op_apply_args<T>(c, op, K, x, plain_args<T>(yin, y, alpha, beta), false);
+}
+
+template <typename T>
+static void level_apply_args(phz_ctx* c, Hierarchy& H, int l, int K, const T* x, const OpArgs<T>& a, bool cheby) {
   Level& L = *H.lv[l];
   if (l == 0) {
-    op_apply<T>(c, H.op, K, x, yin, y, alpha, beta);
+    op_apply_args<T>(c, H.op, K, x, a, cheby);
   } else {
     const long slot = time_begin(c, H.F == 3 ? (sizeof(T) == 4 ? "coarse_A_f32" : "coarse_A_f64")
                                              : (sizeof(T) == 4 ? "coarse_S_f32" : "coarse_S_f64"));
-    coarse_apply<T>(H.F, K, L.N, ae_of<T>(L), x, yin, y, alpha, beta, c->stream);
+    coarse_apply<T>(H.F, K, L.N, stencil_of<T>(L), x, a, cheby, c->stream);
     time_end(c, slot);
   }
+}
+
+// y = beta*yin + alpha*A_l x
+template <typename T>
+static void level_apply(phz_ctx* c, Hierarchy& H, int l, int K, const T* x, const T* yin, T* y, T alpha,
+                        T beta) {
+  level_apply_args<T>(c, H, l, K, x, plain_args<T>(yin, y, alpha, beta), false);
 }
 
 // ------------------------------------------------------- multigrid set-up
@@ -342,10 +370,10 @@ static void host_element_matrices(phz_ctx* c, Hierarchy& H, int l, std::vector<d
     sync(c);
     const double* kref = F == 3 ? c->ref.A0 : c->ref.S0;
     for (int Lc = 0; Lc < 8; ++Lc)
-      for (long e = 0; e < L.nn; ++e)
-        for (int f = 0; f < F; ++f)
-          for (int col = 0; col < S; ++col)
-            Ae[(((size_t)Lc * L.nn + e) * F + f) * S + col] = sh[e] * kref[(Lc * F + f) * S + col];
+      for (int f = 0; f < F; ++f)
+        for (int col = 0; col < S; ++col)
+          for (long e = 0; e < L.nn; ++e)
+            Ae[((size_t)((Lc * F + f) * S + col)) * L.nn + e] = sh[e] * kref[(Lc * F + f) * S + col];
   } else {
     PHZ_HIP(hipMemcpyAsync(Ae.data(), L.Ae.p, Ae.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
     sync(c);
@@ -369,8 +397,8 @@ static void build_coarsest(phz_ctx* c, Hierarchy& H) {
       for (int f = 0; f < F; ++f)
         for (int Lp = 0; Lp < 8; ++Lp)
           for (int g = 0; g < F; ++g)
-            M[(size_t)(node[Lc] * F + f) * rows + node[Lp] * F + g] +=
-                Ae[(((size_t)Lc * L.nn + e) * F + f) * S + Lp * F + g];
+            M[(size_t)(f * L.nn + node[Lc]) * rows + g * L.nn + node[Lp]] +=
+                Ae[((size_t)((Lc * F + f) * S + Lp * F + g)) * L.nn + e];
   }
   // the periodic kernel is the constant field of each component; add
   // alpha/nn * 1 1^T per component so the matrix is SPD and zero-mean
@@ -380,7 +408,7 @@ static void build_coarsest(phz_ctx* c, Hierarchy& H) {
   const double alpha = tr / rows / (double)L.nn;
   for (long n = 0; n < L.nn; ++n)
     for (long m2 = 0; m2 < L.nn; ++m2)
-      for (int f = 0; f < F; ++f) M[(size_t)(n * F + f) * rows + m2 * F + f] += alpha;
+      for (int f = 0; f < F; ++f) M[(size_t)(f * L.nn + n) * rows + f * L.nn + m2] += alpha;
   if (!spd_inverse(rows, M)) throw std::runtime_error("coarsest multigrid matrix is not positive definite");
   H.rows = rows;
   H.Minv.upload(M.data(), M.size(), c->stream);
@@ -395,13 +423,13 @@ static double power_lmax(phz_ctx* c, Hierarchy& H, int l) {
   w.alloc(cnt);
   double* nrm = c->small.p;
   hash_fill(cnt, 12345u + 7u * l + 101u * H.F, v.p, c->stream);
-  col_norm2<double>(cnt, 1, v.p, nrm, c->red_work.p, c->stream);
+  col_norm2<double>(L.nn, H.F, 1, v.p, nrm, c->red_work.p, c->stream);
   normalize_by<double>(cnt, nrm, v.p, v.p, c->stream);
   const int iters = 20;
   for (int it = 0; it < iters; ++it) {
     level_apply<double>(c, H, l, 1, v.p, nullptr, w.p, 1.0, 0.0);
-    cheby_step<double>(H.F, 1, L.nn, L.Dinv.p, w.p, w.p, w.p, 0.0, 1.0, true, c->stream);
-    col_norm2<double>(cnt, 1, w.p, nrm, c->red_work.p, c->stream);
+    cheby_first<double>(H.F, 1, L.nn, L.Dinv.p, w.p, w.p, w.p, 1.0, true, c->stream);
+    col_norm2<double>(L.nn, H.F, 1, w.p, nrm, c->red_work.p, c->stream);
     normalize_by<double>(cnt, nrm, w.p, v.p, c->stream);
   }
   double h = 0.0;
@@ -423,6 +451,10 @@ static void setup_hierarchy(phz_ctx* c, Hierarchy& H) {
       else
         galerkin_build(F, H.lv[l - 1]->N, nullptr, nullptr, H.lv[l - 1]->Ae.p, L.Ae.p, c->stream);
     }
+    if (l > 0) {
+      L.S.alloc((size_t)27 * F * F * L.nn);
+      build_stencil(F, L.N, L.Ae.p, L.S.p, c->stream);
+    }
     if (l < nl - 1) {
       L.Dinv.alloc((size_t)L.nn * F * F);
       if (l == 0) diag_inv_fine(F, L.N, c->s.p, krefd, L.Dinv.p, c->stream);
@@ -434,9 +466,9 @@ static void setup_hierarchy(phz_ctx* c, Hierarchy& H) {
   if (c->opt.precision == PHZ_FP32_IR) {
     for (int l = 0; l < nl; ++l) {
       Level& L = *H.lv[l];
-      if (L.Ae.p) {
-        L.Ae32.alloc(L.Ae.n);
-        convert<double, float>((long)L.Ae.n, L.Ae.p, L.Ae32.p, c->stream);
+      if (L.S.p) {
+        L.S32.alloc(L.S.n);
+        convert<double, float>((long)L.S.n, L.S.p, L.S32.p, c->stream);
       }
       if (L.Dinv.p) {
         L.Dinv32.alloc(L.Dinv.n);
@@ -474,26 +506,43 @@ static void setup_preconditioner(phz_ctx* c) {
 }
 
 // ---------------------------------------------------------------- V-cycle
+// Chebyshev-Jacobi smoothing of degree d on A_l x = b (Saad, Iterative
+// Methods for Sparse Linear Systems, Alg. 12.1, with the block-Jacobi
+// preconditioner), interval [0.15, 1.1] * lambda_max(D^-1 A).  The residual
+// is carried along: on return r points at b - A (x - d) and dcur at the last
+// correction, so that b - A x = r - A dcur.
 template <typename T>
-static void cheby_smooth(phz_ctx* c, Hierarchy& H, int l, int K, const T* b, T* x, bool xzero,
-                         LevelWork<T>& W) {
+static void cheby_smooth(phz_ctx* c, Hierarchy& H, int l, int K, const T* b, T* x, bool xzero, LevelWork<T>& W,
+                         const T*& r, T*& dcur) {
   Level& L = *H.lv[l];
   const int deg = std::max(1, c->opt.cheby_degree);
   const double hi = 1.1 * L.lmax, lo = 0.15 * L.lmax;
   const double theta = 0.5 * (hi + lo), delta = 0.5 * (hi - lo), sigma = theta / delta;
   double rho = 1.0 / sigma;
-  const T* r = b;
+  r = b;
   if (!xzero) {
     level_apply<T>(c, H, l, K, x, b, W.r.p, T(-1), T(1));
     r = W.r.p;
   }
-  cheby_step<T>(H.F, K, L.nn, dinv_of<T>(L), r, W.d.p, x, T(0), T(1.0 / theta), xzero, c->stream);
+  cheby_first<T>(H.F, K, L.nn, dinv_of<T>(L), r, W.d.p, x, T(1.0 / theta), xzero, c->stream);
+  dcur = W.d.p;
+  T* dnext = W.d2.p;
   for (int i = 1; i < deg; ++i) {
-    level_apply<T>(c, H, l, K, W.d.p, r, W.r.p, T(-1), T(1));
-    r = W.r.p;
     const double rho_new = 1.0 / (2.0 * sigma - rho);
-    cheby_step<T>(H.F, K, L.nn, dinv_of<T>(L), r, W.d.p, x, T(rho_new * rho), T(2.0 * rho_new / delta), false,
-                  c->stream);
+    OpArgs<T> a;
+    a.yin = r;
+    a.y = W.r.p;
+    a.alpha = T(-1);
+    a.beta = T(1);
+    a.dinv = dinv_of<T>(L);
+    a.dold = dcur;
+    a.dnew = dnext;
+    a.x = x;
+    a.ca = T(rho_new * rho);
+    a.cb = T(2.0 * rho_new / delta);
+    level_apply_args<T>(c, H, l, K, dcur, a, true);
+    r = W.r.p;
+    std::swap(dcur, dnext);
     rho = rho_new;
   }
 }
@@ -504,17 +553,19 @@ static void vcycle(phz_ctx* c, Hierarchy& H, std::vector<std::unique_ptr<LevelWo
                    const T* b, T* x) {
   const int nl = (int)H.lv.size();
   if (l == nl - 1) {
-    dense_apply<T>(H.rows, K, H.Minv.p, b, x, c->stream);
+    dense_apply<T>(H.F, (int)H.lv[l]->nn, K, H.Minv.p, b, x, c->stream);
     return;
   }
   LevelWork<T>& W = *WL[l];
   LevelWork<T>& Wc = *WL[l + 1];
-  cheby_smooth<T>(c, H, l, K, b, x, true, W);
-  level_apply<T>(c, H, l, K, x, b, W.r.p, T(-1), T(1));
+  const T* r = nullptr;
+  T* dcur = nullptr;
+  cheby_smooth<T>(c, H, l, K, b, x, true, W, r, dcur);
+  level_apply<T>(c, H, l, K, dcur, r, W.r.p, T(-1), T(1));   // b - A x
   restrict_fw<T>(H.F, K, H.lv[l + 1]->N, W.r.p, Wc.b.p, c->stream);
   vcycle<T>(c, H, WL, l + 1, K, Wc.b.p, Wc.x.p);
   prolong_add<T>(H.F, K, H.lv[l + 1]->N, Wc.x.p, x, c->stream);
-  cheby_smooth<T>(c, H, l, K, b, x, false, W);
+  cheby_smooth<T>(c, H, l, K, b, x, false, W, r, dcur);
 }
 
 // x = (ncycles V-cycles) A^-1 b
@@ -522,25 +573,28 @@ template <typename T>
 static void block_solve(phz_ctx* c, Hierarchy& H, std::vector<std::unique_ptr<LevelWork<T>>>& WL, int K,
                         int ncycles, const T* b, T* x, T* tmp_r, T* tmp_e) {
   vcycle<T>(c, H, WL, 0, K, b, x);
-  const long cnt = H.lv[0]->nn * H.F;
   for (int it = 1; it < ncycles; ++it) {
     level_apply<T>(c, H, 0, K, x, b, tmp_r, T(-1), T(1));
     vcycle<T>(c, H, WL, 0, K, tmp_r, tmp_e);
-    axpy_cols<T, T>(cnt, K, nullptr, tmp_e, x, c->stream);
+    axpy_cols<T, T>(H.lv[0]->nn, H.F, K, nullptr, tmp_e, x, c->stream);
   }
 }
 
 // z = P^-1 r on [nn][4][K]
+// (structure of arrays: the displacement block of a 4-field vector is its
+// first 3K columns, the potential block the last K)
 template <typename T>
 static void precond_apply(phz_ctx* c, int K, const T* r, T* z) {
   Work<T>& W = work_of<T>(c);
-  const long nn = c->nn;
-  split_fields<T>(nn, K, r, W.ru.p, W.rp.p, c->stream);
-  block_solve<T>(c, c->hA, W.A, K, std::max(1, c->opt.vcycles_a), W.ru.p, W.zu.p, W.t1u.p, W.t2u.p);
+  const size_t off = (size_t)c->nn * 3 * K;
+  const T* ru = r;
+  const T* rp = r + off;
+  T* zu = z;
+  T* zp = z + off;
+  block_solve<T>(c, c->hA, W.A, K, std::max(1, c->opt.vcycles_a), ru, zu, W.t1u.p, W.t2u.p);
   // t = B z_u - r_p
-  op_apply<T>(c, 2, K, W.zu.p, W.rp.p, W.t1p.p, T(1), T(-1));
-  block_solve<T>(c, c->hS, W.S, K, std::max(1, c->opt.vcycles_s), W.t1p.p, W.zp.p, W.t2p.p, W.rp.p);
-  merge_fields<T>(nn, K, W.zu.p, W.zp.p, z, c->stream);
+  op_apply<T>(c, 2, K, zu, rp, W.t1p.p, T(1), T(-1));
+  block_solve<T>(c, c->hS, W.S, K, std::max(1, c->opt.vcycles_s), W.t1p.p, zp, W.t2p.p, W.t3p.p);
 }
 
 // ------------------------------------------------------------------ GMRES
@@ -560,15 +614,15 @@ template <typename T>
 static GmresResult gmres(phz_ctx* c, int K, const T* b, T* x, double rtol, int maxit, int hist_base,
                          bool record_hist, bool x_is_zero = false, bool one_cycle = false) {
   Work<T>& W = work_of<T>(c);
-  const long rows = c->nn * 4;
-  const long vs = rows * K;
+  const long nn = c->nn;
+  const long vs = (long)basis_stride(nn, K);
   const int m = c->opt.restart;
   GmresState S = gm_state(c);
   hipStream_t st = c->stream;
   GmresResult res;
   double* nrm = c->gm_nrm.p;
   // ||b||
-  col_norm2<T>(rows, K, b, nrm, c->red_work.p, st);
+  col_norm2<T>(nn, 4, K, b, nrm, c->red_work.p, st);
   {
     std::vector<double> h(K);
     PHZ_HIP(hipMemcpyAsync(h.data(), nrm, K * sizeof(double), hipMemcpyDeviceToHost, st));
@@ -585,10 +639,10 @@ static GmresResult gmres(phz_ctx* c, int K, const T* b, T* x, double rtol, int m
   for (int cycle = 0;; ++cycle) {
     // r = b - calA x
     if (cycle == 0 && x_is_zero)
-      PHZ_HIP(hipMemcpyAsync(W.r.p, b, (size_t)vs * sizeof(T), hipMemcpyDeviceToDevice, st));
+      PHZ_HIP(hipMemcpyAsync(W.r.p, b, (size_t)nn * 4 * K * sizeof(T), hipMemcpyDeviceToDevice, st));
     else
       op_apply<T>(c, 0, K, x, b, W.r.p, T(-1), T(1));
-    col_norm2<T>(rows, K, W.r.p, nrm, c->red_work.p, st);
+    col_norm2<T>(nn, 4, K, W.r.p, nrm, c->red_work.p, st);
     gmres_start(K, nrm, rtol, S, st);
     PHZ_HIP(hipMemcpyAsync(rn.data(), nrm, K * sizeof(double), hipMemcpyDeviceToHost, st));
     int nact = 0;
@@ -608,7 +662,7 @@ static GmresResult gmres(phz_ctx* c, int K, const T* b, T* x, double rtol, int m
     for (int k = 0; k < K; ++k)
       if (bn[k] > 0 && !(res.true_rel[k] <= rtol)) res.restarts[k] += 1;
     // V_0 = r / beta
-    scale_cols<T>(rows, K, W.r.p, S.scale, W.V.p, st);
+    scale_cols<T>(nn, 4, K, W.r.p, S.scale, W.V.p, st);
     int j = 0;
     for (; j < m; ++j) {
       T* Vj = W.V.p + (size_t)j * vs;
@@ -618,12 +672,12 @@ static GmresResult gmres(phz_ctx* c, int K, const T* b, T* x, double rtol, int m
       op_apply<T>(c, 0, K, W.z.p, (const T*)nullptr, W.w.p, T(1), T(0));
       // classical Gram-Schmidt, twice
       const long ts = time_begin(c, sizeof(T) == 4 ? "arnoldi_cgs2_f32" : "arnoldi_cgs2_f64");
-      arnoldi_dots<T>(rows, K, j, W.V.p, vs, W.w.p, c->gm_h1.p, c->red_work.p, st);
-      arnoldi_update<T>(rows, K, j, W.V.p, vs, W.w.p, c->gm_h1.p, c->gm_h2.p, nullptr, c->red_work.p, st);
-      arnoldi_update<T>(rows, K, j, W.V.p, vs, W.w.p, c->gm_h2.p, nullptr, nrm, c->red_work.p, st);
+      arnoldi_dots<T>(nn, 4, K, j, W.V.p, vs, W.w.p, c->gm_h1.p, c->red_work.p, st);
+      arnoldi_update<T>(nn, 4, K, j, W.V.p, vs, W.w.p, c->gm_h1.p, c->gm_h2.p, nullptr, c->red_work.p, st);
+      arnoldi_update<T>(nn, 4, K, j, W.V.p, vs, W.w.p, c->gm_h2.p, nullptr, nrm, c->red_work.p, st);
       time_end(c, ts);
       gmres_givens(K, m, j, c->gm_h1.p, c->gm_h2.p, nrm, rtol, S, st);
-      scale_cols<T>(rows, K, W.w.p, S.scale, W.V.p + (size_t)(j + 1) * vs, st);
+      scale_cols<T>(nn, 4, K, W.w.p, S.scale, W.V.p + (size_t)(j + 1) * vs, st);
       ++total;
       PHZ_HIP(hipMemcpyAsync(&nact, S.nactive, sizeof(int), hipMemcpyDeviceToHost, st));
       sync(c);
@@ -634,9 +688,9 @@ static GmresResult gmres(phz_ctx* c, int K, const T* b, T* x, double rtol, int m
     }
     // x += P^-1 (V y)
     gmres_solve_y(K, m, S, st);
-    combine<T>(rows, K, m, W.V.p, vs, S.y, S.kused, W.t.p, st);
+    combine<T>(nn, 4, K, W.V.p, vs, S.y, S.kused, W.t.p, st);
     precond_apply<T>(c, K, W.t.p, W.z.p);
-    axpy_cols<T, T>(rows, K, nullptr, W.z.p, x, st);
+    axpy_cols<T, T>(nn, 4, K, nullptr, W.z.p, x, st);
     PHZ_HIP(hipMemcpyAsync(kused.data(), S.kused, K * sizeof(int), hipMemcpyDeviceToHost, st));
     PHZ_HIP(hipMemcpyAsync(estbuf.data(), S.est, (size_t)m * K * sizeof(double), hipMemcpyDeviceToHost, st));
     sync(c);
@@ -667,11 +721,12 @@ static void solve_fp64(phz_ctx* c, int K, const double* b, double* x, double rto
 static int solve_ir(phz_ctx* c, int K, const double* b, double* x, double rtol, int hist_base, GmresResult& out) {
   alloc_work<float>(c, c->w32, K, c->opt.restart);
   Work<float>& W = c->w32;
-  const long rows = c->nn * 4;
+  const long nn = c->nn;
+  const long count = nn * 4 * K;
   hipStream_t st = c->stream;
   double* nrm = c->gm_nrm.p + 9;
   std::vector<double> bn(K), rn(K), scale(K), inv(K);
-  col_norm2<double>(rows, K, b, nrm, c->red_work.p, st);
+  col_norm2<double>(nn, 4, K, b, nrm, c->red_work.p, st);
   PHZ_HIP(hipMemcpyAsync(bn.data(), nrm, K * sizeof(double), hipMemcpyDeviceToHost, st));
   sync(c);
   for (int k = 0; k < K; ++k) bn[k] = std::sqrt(bn[k]);
@@ -682,7 +737,7 @@ static int solve_ir(phz_ctx* c, int K, const double* b, double* x, double rtol, 
   for (;;) {
     // r = b - calA x in float64
     op_apply<double>(c, 0, K, x, b, r64.p, -1.0, 1.0);
-    col_norm2<double>(rows, K, r64.p, nrm, c->red_work.p, st);
+    col_norm2<double>(nn, 4, K, r64.p, nrm, c->red_work.p, st);
     PHZ_HIP(hipMemcpyAsync(rn.data(), nrm, K * sizeof(double), hipMemcpyDeviceToHost, st));
     sync(c);
     bool done = true;
@@ -705,13 +760,13 @@ static int solve_ir(phz_ctx* c, int K, const double* b, double* x, double rtol, 
       inv[k] = act ? 1.0 / rn[k] : 0.0;
     }
     PHZ_HIP(hipMemcpyAsync(scp, inv.data(), K * sizeof(double), hipMemcpyHostToDevice, st));
-    scale_cols<double>(rows, K, r64.p, scp, r64.p, st);
-    convert<double, float>(rows * K, r64.p, W.b.p, st);
-    fill<float>(rows * K, 0.0f, W.x.p, st);
+    scale_cols<double>(nn, 4, K, r64.p, scp, r64.p, st);
+    convert<double, float>(count, r64.p, W.b.p, st);
+    fill<float>(count, 0.0f, W.x.p, st);
     GmresResult g = gmres<float>(c, K, W.b.p, W.x.p, c->opt.inner_rtol, c->opt.max_iters - used, hist_base, true,
                                  true, true);
     PHZ_HIP(hipMemcpyAsync(scp, scale.data(), K * sizeof(double), hipMemcpyHostToDevice, st));
-    axpy_cols<double, float>(rows, K, scp, W.x.p, x, st);
+    axpy_cols<double, float>(nn, 4, K, scp, W.x.p, x, st);
     sync(c);
     int mx = 0;
     for (int k = 0; k < K; ++k) {
@@ -751,25 +806,15 @@ static void compute_effective(phz_ctx* c) {
   for (int K = 0; K < 9; ++K)
     for (int L = 0; L < 9; ++L) c->MH[K * 9 + L] = h3 * ssum * R.M[K * 9 + L] + FY[K * 9 + L];
   // energy form: <s>M + FY + FY^T + X^T calA X
-  fine_apply<double>(0, 9, c->N, c->s.p, c->kref_full.p, c->X.p, nullptr, c->R64.p, 1.0, 0.0, st);
-  // cross dots X[:,K] . (calA X)[:,L] through the Arnoldi dot kernel on
-  // single columns would need 81 passes; use a host-side 9x9 from column
-  // extractions instead
+  op_apply<double>(c, 0, 9, c->X.p, (const double*)nullptr, c->R64.p, 1.0, 0.0);
   std::vector<double> XtAX(81, 0.0);
   {
-    DevBuf<double> xc, ac;
-    xc.alloc(nn * 4);
-    ac.alloc(nn * 4);
-    for (int K = 0; K < 9; ++K) {
-      extract_column(nn, K, c->X.p, xc.p, st);
-      // V = xc (one basis vector), w = calA X column L: use arnoldi_dots with j = 0
-      for (int L = 0; L < 9; ++L) {
-        extract_column(nn, L, c->R64.p, ac.p, st);
-        arnoldi_dots<double>(nn * 4, 1, 0, xc.p, 0, ac.p, c->small.p + 400 + K * 9 + L, c->red_work.p, st);
-      }
-    }
-    PHZ_HIP(hipMemcpyAsync(XtAX.data(), c->small.p + 400, 81 * sizeof(double), hipMemcpyDeviceToHost, st));
+    std::vector<double> h(81);
+    cross_dots(nn, c->X.p, c->R64.p, c->small.p + 400, c->red_work.p, st);
+    PHZ_HIP(hipMemcpyAsync(h.data(), c->small.p + 400, 81 * sizeof(double), hipMemcpyDeviceToHost, st));
     sync(c);
+    for (int a = 0; a < 9; ++a)
+      for (int b = 0; b < 9; ++b) XtAX[a * 9 + b] = h[b * 9 + a];
   }
   double mx = 0.0, df = 0.0;
   for (int K = 0; K < 9; ++K)
@@ -791,18 +836,18 @@ static void prepare_rhs(phz_ctx* c) {
   build_rhs(c->N, c->s.p, c->F0d.p, c->R64.p, st, true);
   double* nb = c->small.p;
   double* nref = c->small.p + 16;
-  col_norm2<double>(nn * 4, 9, c->R64.p, nref, c->red_work.p, st);
+  col_norm2<double>(nn, 4, 9, c->R64.p, nref, c->red_work.p, st);
   build_rhs(c->N, c->s.p, c->F0d.p, c->Bvec.p, st, false);
   field_sums<double>(nn, 4, 9, c->Bvec.p, c->small.p + 32, c->red_work.p, st);
   subtract_mean<double>(nn, 4, 9, c->small.p + 32, c->Bvec.p, st);
-  col_norm2<double>(nn * 4, 9, c->Bvec.p, nb, c->red_work.p, st);
+  col_norm2<double>(nn, 4, 9, c->Bvec.p, nb, c->red_work.p, st);
   double h[32];
   PHZ_HIP(hipMemcpyAsync(h, c->small.p, 32 * sizeof(double), hipMemcpyDeviceToHost, st));
   sync(c);
   double keep[9];
   for (int L = 0; L < 9; ++L) keep[L] = std::sqrt(h[L]) <= 1e-12 * std::sqrt(h[16 + L]) ? 0.0 : 1.0;
   PHZ_HIP(hipMemcpyAsync(c->small.p + 80, keep, 9 * sizeof(double), hipMemcpyHostToDevice, st));
-  scale_cols<double>(nn * 4, 9, c->Bvec.p, c->small.p + 80, c->Bvec.p, st);
+  scale_cols<double>(nn, 4, 9, c->Bvec.p, c->small.p + 80, c->Bvec.p, st);
   sync(c);
 }
 
@@ -1136,7 +1181,10 @@ int phz_get_solution(phz_ctx* c, double* X, int on_device) {
   if (!c || !X) return PHZ_E_INVALID;
   if (!c->have_solution) return PHZ_E_STATE;
   PHZ_GUARD_BEGIN
-  PHZ_HIP(hipMemcpyAsync(X, c->X.p, c->nn * 36 * sizeof(double),
+  // internal structure of arrays -> documented node-major [n][4][9]
+  c->R64.alloc(c->nn * 36);
+  soa_to_aos(c->nn, 36, c->X.p, c->R64.p, c->stream);
+  PHZ_HIP(hipMemcpyAsync(X, c->R64.p, c->nn * 36 * sizeof(double),
                          on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, c->stream));
   sync(c);
   return PHZ_OK;
@@ -1151,8 +1199,10 @@ int phz_set_initial_guess(phz_ctx* c, const double* X, int on_device) {
     return PHZ_OK;
   }
   c->guess.alloc(c->nn * 36);
-  PHZ_HIP(hipMemcpyAsync(c->guess.p, X, c->nn * 36 * sizeof(double),
+  c->R64.alloc(c->nn * 36);
+  PHZ_HIP(hipMemcpyAsync(c->R64.p, X, c->nn * 36 * sizeof(double),
                          on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, c->stream));
+  aos_to_soa(c->nn, 36, c->R64.p, c->guess.p, c->stream);
   if (count_nonfinite(c->nn * 36, c->guess.p, c->red_work.p, c->stream) > 0) {
     c->err = "initial guess holds NaN or Inf";
     return PHZ_E_NAN;
@@ -1169,7 +1219,8 @@ int phz_get_rhs(phz_ctx* c, double* b, int on_device) {
   c->Bvec.alloc(c->nn * 36);
   c->R64.alloc(c->nn * 36);
   prepare_rhs(c);
-  PHZ_HIP(hipMemcpyAsync(b, c->Bvec.p, c->nn * 36 * sizeof(double),
+  soa_to_aos(c->nn, 36, c->Bvec.p, c->R64.p, c->stream);
+  PHZ_HIP(hipMemcpyAsync(b, c->R64.p, c->nn * 36 * sizeof(double),
                          on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, c->stream));
   sync(c);
   return PHZ_OK;
@@ -1422,7 +1473,8 @@ int phz_coarse_apply(phz_ctx* c, int level, int op, int nrhs, const double* x, d
   setup_preconditioner(c);
   Hierarchy& H = op == PHZ_OP_A ? c->hA : c->hS;
   if (level < 1 || level >= (int)H.lv.size()) { c->err = "level out of range"; return PHZ_E_INVALID; }
-  coarse_apply<double>(H.F, nrhs, H.lv[level]->N, H.lv[level]->Ae.p, x, nullptr, y, 1.0, 0.0, c->stream);
+  coarse_apply<double>(H.F, nrhs, H.lv[level]->N, H.lv[level]->S.p, x, plain_args<double>(nullptr, y, 1.0, 0.0),
+                       false, c->stream);
   sync(c);
   return PHZ_OK;
   PHZ_GUARD_END(c)

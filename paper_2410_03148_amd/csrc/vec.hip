@@ -1,9 +1,14 @@
 // Vector, reduction, GMRES and per-element physics kernels (gfx950).
 //
-// Reductions are two-stage and deterministic: every block writes its partial
-// sums, one block adds the partials in a fixed order.  Krylov vectors may be
+// Internal vectors are structure of arrays: column f*K + k (field f, load
+// column k) holds nn contiguous node values.  Reductions are two-stage and
+// deterministic: blocks of a (slice, column) grid write partial sums, then
+// one block per output adds them in a fixed order.  Krylov vectors may be
 // float or double; every inner product accumulates in double.
+#include <algorithm>
+#include <array>
 #include <cmath>
+#include <utility>
 
 #include "common.hpp"
 
@@ -11,230 +16,265 @@ namespace phz {
 
 namespace {
 
-constexpr int kRedBlocks = 512;
+inline unsigned blocks_for(size_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
-inline unsigned blocks_for(long n, int bs) { return (unsigned)((n + bs - 1) / bs); }
-inline unsigned red_grid(long n, int bs) {
-  long g = (n + bs - 1) / bs;
-  if (g > kRedBlocks) g = kRedBlocks;
+constexpr int kMaxPartBlocks = 2048;
+
+// slices per column so that the reduction grid has ~2048 blocks
+inline unsigned slices_for(size_t nn, int ncol) {
+  size_t g = kMaxPartBlocks / (size_t)ncol;
+  const size_t cap = (nn + 255) / 256;
+  if (g > cap) g = cap;
   if (g < 1) g = 1;
   return (unsigned)g;
 }
-// block size that is a multiple of `slots` (<= 1024)
-inline int slot_block(int slots) { return slots * (1024 / slots); }
 
-__global__ void k_sum_partials(int nblocks, int nvals, const double* __restrict__ part,
-                               double* __restrict__ out) {
-  for (int v = threadIdx.x; v < nvals; v += blockDim.x) {
-    double s = 0.0;
-    for (int b = 0; b < nblocks; ++b) s += part[(long)b * nvals + v];
-    out[v] = s;
-  }
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
 }
 
-// sum (or sum of squares) of a flat array per slot = index % slots
+// sum over a 256-thread block; result valid in thread 0
+__device__ __forceinline__ double block_sum(double v, double* lds4) {
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (lane == 0) lds4[wv] = v;
+  __syncthreads();
+  double r = 0.0;
+  if (threadIdx.x == 0) r = lds4[0] + lds4[1] + lds4[2] + lds4[3];
+  __syncthreads();
+  return r;
+}
+
+// out[o] (o = (i - i0)*K + k) = sum_{f < F} sum_{b < G} part[((f*K + k)*G + b)*J + i];
+// one block per output, fixed summation order
+__global__ __launch_bounds__(256) void k_reduce_cols(int G, int F, int K, int J, int i0,
+                                                     const double* __restrict__ part, double* __restrict__ out) {
+  __shared__ double lds[256];
+  const int o = blockIdx.x;
+  const int i = i0 + o / K, k = o % K;
+  double s = 0.0;
+  for (int q = threadIdx.x; q < F * G; q += 256) {
+    const int f = q / G, b = q % G;
+    s += part[((size_t)(f * K + k) * G + b) * J + i];
+  }
+  lds[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) lds[threadIdx.x] += lds[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[o] = lds[0];
+}
+
+void reduce_cols(int G, int F, int K, int J, int i0, int nout_i, const double* part, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_reduce_cols, dim3(nout_i * K), dim3(256), 0, st, G, F, K, J, i0, part, out);
+}
+
+// per-column sums (or sums of squares) of column blockIdx.y over slice blockIdx.x
 template <typename T, bool SQ>
-__global__ void k_flat_sums(long count, int slots, const T* __restrict__ v, double* __restrict__ part) {
-  extern __shared__ double lds[];
-  const int bs = blockDim.x;
-  const int t = threadIdx.x;
+__global__ __launch_bounds__(256) void k_col_sums(unsigned nn, const T* __restrict__ v, double* __restrict__ part) {
+  __shared__ double lds4[4];
+  const T* col = v + (size_t)blockIdx.y * nn;
   double acc = 0.0;
-  for (long idx = (long)blockIdx.x * bs + t; idx < count; idx += (long)gridDim.x * bs) {
-    const double x = (double)v[idx];
+  for (unsigned n = blockIdx.x * 256 + threadIdx.x; n < nn; n += gridDim.x * 256) {
+    const double x = (double)col[n];
     acc += SQ ? x * x : x;
   }
-  lds[t] = acc;
-  __syncthreads();
-  if (t < slots) {
-    double s = 0.0;
-    for (int u = t; u < bs; u += slots) s += lds[u];
-    part[(long)blockIdx.x * slots + t] = s;
-  }
+  acc = block_sum(acc, lds4);
+  if (threadIdx.x == 0) part[(size_t)blockIdx.y * gridDim.x + blockIdx.x] = acc;
 }
 
 template <typename T, bool SQ>
-void flat_sums(long count, int slots, const T* v, double* out, double* work, hipStream_t st) {
-  const int bs = slot_block(slots);
-  const unsigned g = red_grid(count, bs);
-  hipLaunchKernelGGL((k_flat_sums<T, SQ>), dim3(g), dim3(bs), bs * sizeof(double), st, count, slots, v, work);
-  hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, st, (int)g, slots, work, out);
+void col_reduce(size_t nn, int F, int K, const T* v, double* out, double* work, hipStream_t st) {
+  const unsigned G = slices_for(nn, F * K);
+  hipLaunchKernelGGL((k_col_sums<T, SQ>), dim3(G, F * K), dim3(256), 0, st, (unsigned)nn, v, work);
+  reduce_cols((int)G, F, K, 1, 0, 1, work, out, st);
   PHZ_LAUNCH_CHECK();
 }
 
 // ---------------------------------------------------------------- Arnoldi
-template <typename T>
-__global__ __launch_bounds__(576) void k_arnoldi_dots(long count, int K, int j, const T* __restrict__ V, long vstride,
-                               const T* __restrict__ w, double* __restrict__ part) {
-  extern __shared__ double lds[];
-  const int bs = blockDim.x, t = threadIdx.x;
-  double acc[kMaxRestart + 1];
+// J = j + 1 basis vectors, a compile-time count so that every load of the
+// unrolled loops is unconditional and independent (memory-level
+// parallelism).  Grid (slices, F*K): each block stays on one column, so the
+// load column k = blockIdx.y % K and its coefficients are block-uniform.
+template <typename T, int J>
+__global__ __launch_bounds__(256) void k_arnoldi_dots(unsigned nn, const T* __restrict__ V, size_t vstride,
+                                                      const T* __restrict__ w, double* __restrict__ part) {
+  __shared__ double lds4[4];
+  const size_t co = (size_t)blockIdx.y * nn;
+  double acc[J];
 #pragma unroll
-  for (int i = 0; i <= kMaxRestart; ++i) acc[i] = 0.0;
-  for (long idx = (long)blockIdx.x * bs + t; idx < count; idx += (long)gridDim.x * bs) {
-    const double wv = (double)w[idx];
+  for (int i = 0; i < J; ++i) acc[i] = 0.0;
+  for (unsigned n = blockIdx.x * 256 + threadIdx.x; n < nn; n += gridDim.x * 256) {
+    const double wv = (double)w[co + n];
 #pragma unroll
-    for (int i = 0; i <= kMaxRestart; ++i)
-      if (i <= j) acc[i] += (double)V[(long)i * vstride + idx] * wv;
+    for (int i = 0; i < J; ++i) acc[i] += (double)V[i * vstride + co + n] * wv;
   }
-  const int nv = (j + 1) * K;
-  for (int i = 0; i <= j; ++i) {
-    double a = 0.0;
+  const size_t base = ((size_t)blockIdx.y * gridDim.x + blockIdx.x) * J;
 #pragma unroll
-    for (int u = 0; u <= kMaxRestart; ++u)
-      if (u == i) a = acc[u];
-    lds[t] = a;
-    __syncthreads();
-    if (t < K) {
-      double s = 0.0;
-      for (int u = t; u < bs; u += K) s += lds[u];
-      part[(long)blockIdx.x * nv + i * K + t] = s;
-    }
-    __syncthreads();
+  for (int i = 0; i < J; ++i) {
+    const double s = block_sum(acc[i], lds4);
+    if (threadIdx.x == 0) part[base + i] = s;
   }
 }
 
-template <typename T>
-__global__ __launch_bounds__(576) void k_arnoldi_update(long count, int K, int j, const T* __restrict__ V, long vstride,
-                                 T* __restrict__ w, const double* __restrict__ hin, int want_dots,
-                                 double* __restrict__ part) {
-  extern __shared__ double lds[];
-  const int bs = blockDim.x, t = threadIdx.x;
-  const int kk = t % K;  // block size and grid stride are multiples of K
-  __shared__ double hs[(kMaxRestart + 1) * 9];
-  for (int u = t; u < (j + 1) * K; u += bs) hs[u] = hin[u];
-  __syncthreads();
-  double acc[kMaxRestart + 1];
+// w -= sum_i V_i h[i][k]; then (DOTS) V^T w_new, and ||w_new||^2 (last slot)
+template <typename T, int J, bool DOTS>
+__global__ __launch_bounds__(256) void k_arnoldi_update(unsigned nn, int K, const T* __restrict__ V, size_t vstride,
+                                                        T* __restrict__ w, const double* __restrict__ hin,
+                                                        double* __restrict__ part) {
+  __shared__ double lds4[4];
+  const int kk = blockIdx.y % K;
+  const size_t co = (size_t)blockIdx.y * nn;
+  double h[J];
 #pragma unroll
-  for (int i = 0; i <= kMaxRestart; ++i) acc[i] = 0.0;
+  for (int i = 0; i < J; ++i) h[i] = hin[i * K + kk];
+  double acc[DOTS ? J : 1];
+#pragma unroll
+  for (int i = 0; i < (DOTS ? J : 1); ++i) acc[i] = 0.0;
   double nrm = 0.0;
-  for (long idx = (long)blockIdx.x * bs + t; idx < count; idx += (long)gridDim.x * bs) {
-    double wv = (double)w[idx];
+  for (unsigned n = blockIdx.x * 256 + threadIdx.x; n < nn; n += gridDim.x * 256) {
+    T vv[DOTS ? J : 1];
+    double wv = (double)w[co + n];
 #pragma unroll
-    for (int i = 0; i <= kMaxRestart; ++i)
-      if (i <= j) wv -= hs[i * K + kk] * (double)V[(long)i * vstride + idx];
+    for (int i = 0; i < J; ++i) {
+      const T v = V[i * vstride + co + n];
+      if constexpr (DOTS) vv[i] = v;
+      wv -= h[i] * (double)v;
+    }
     const T wt = (T)wv;
-    w[idx] = wt;
+    w[co + n] = wt;
     const double wr = (double)wt;
     nrm += wr * wr;
-    if (want_dots) {
+    if constexpr (DOTS) {
 #pragma unroll
-      for (int i = 0; i <= kMaxRestart; ++i)
-        if (i <= j) acc[i] += (double)V[(long)i * vstride + idx] * wr;
+      for (int i = 0; i < J; ++i) acc[i] += (double)vv[i] * wr;
     }
   }
-  const int nv = (want_dots ? (j + 1) : 0) * K + K;
-  const int nloop = want_dots ? j + 1 : 0;
-  for (int i = 0; i <= nloop; ++i) {
-    double a = 0.0;
-    if (i == nloop) a = nrm;
-    else {
+  constexpr int NV = (DOTS ? J : 0) + 1;
+  const size_t base = ((size_t)blockIdx.y * gridDim.x + blockIdx.x) * NV;
+  if constexpr (DOTS) {
 #pragma unroll
-      for (int u = 0; u <= kMaxRestart; ++u)
-        if (u == i) a = acc[u];
+    for (int i = 0; i < J; ++i) {
+      const double s = block_sum(acc[i], lds4);
+      if (threadIdx.x == 0) part[base + i] = s;
     }
-    lds[t] = a;
-    __syncthreads();
-    if (t < K) {
-      double s = 0.0;
-      for (int u = t; u < bs; u += K) s += lds[u];
-      part[(long)blockIdx.x * nv + i * K + t] = s;
-    }
-    __syncthreads();
   }
+  const double s = block_sum(nrm, lds4);
+  if (threadIdx.x == 0) part[base + NV - 1] = s;
 }
 
-__global__ void k_split_partials(int nblocks, int nv, int ndots, const double* __restrict__ part,
-                                 double* __restrict__ hout, double* __restrict__ nrmout) {
-  for (int v = threadIdx.x; v < nv; v += blockDim.x) {
-    double s = 0.0;
-    for (int b = 0; b < nblocks; ++b) s += part[(long)b * nv + v];
-    if (v < ndots) {
-      if (hout) hout[v] = s;
-    } else if (nrmout) {
-      nrmout[v - ndots] = s;
+constexpr int kFusedMaxJ = 16;
+
+template <typename T, int J>
+void launch_dots_J(dim3 g, hipStream_t st, unsigned nn, const T* V, size_t vs, const T* w, double* part) {
+  hipLaunchKernelGGL((k_arnoldi_dots<T, J>), g, dim3(256), 0, st, nn, V, vs, w, part);
+}
+template <typename T, int J>
+void launch_update_J(dim3 g, hipStream_t st, unsigned nn, int K, const T* V, size_t vs, T* w, const double* hin,
+                     int want, double* part) {
+  if constexpr (J <= kFusedMaxJ) {
+    if (want) {
+      hipLaunchKernelGGL((k_arnoldi_update<T, J, true>), g, dim3(256), 0, st, nn, K, V, vs, w, hin, part);
+      return;
     }
   }
+  hipLaunchKernelGGL((k_arnoldi_update<T, J, false>), g, dim3(256), 0, st, nn, K, V, vs, w, hin, part);
 }
-
 template <typename T>
-__global__ void k_scale_cols(long count, int K, const T* __restrict__ w, const double* __restrict__ scale,
+using DotsFn = void (*)(dim3, hipStream_t, unsigned, const T*, size_t, const T*, double*);
+template <typename T>
+using UpdFn = void (*)(dim3, hipStream_t, unsigned, int, const T*, size_t, T*, const double*, int, double*);
+template <typename T, int... Js>
+constexpr std::array<DotsFn<T>, sizeof...(Js)> dots_table(std::integer_sequence<int, Js...>) {
+  return {&launch_dots_J<T, Js + 1>...};
+}
+template <typename T, int... Js>
+constexpr std::array<UpdFn<T>, sizeof...(Js)> upd_table(std::integer_sequence<int, Js...>) {
+  return {&launch_update_J<T, Js + 1>...};
+}
+
+// ------------------------------------------------------------- elementwise
+template <typename T>
+__global__ void k_scale_cols(unsigned nn, int K, const T* __restrict__ w, const double* __restrict__ scale,
                              T* __restrict__ v) {
-  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= count) return;
-  v[idx] = (T)((double)w[idx] * scale[idx % K]);
+  const unsigned n = blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= nn) return;
+  const size_t o = (size_t)blockIdx.y * nn + n;
+  v[o] = (T)((double)w[o] * scale[blockIdx.y % K]);
 }
 
 template <typename T>
-__global__ void k_combine(long count, int K, int m, const T* __restrict__ V, long vstride,
-                          const double* __restrict__ y, const int* __restrict__ kused, T* __restrict__ t) {
-  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= count) return;
-  const int kk = (int)(idx % K);
+__global__ void k_combine(unsigned nn, int K, const T* __restrict__ V, size_t vstride, const double* __restrict__ y,
+                          const int* __restrict__ kused, T* __restrict__ t) {
+  const unsigned n = blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= nn) return;
+  const int kk = blockIdx.y % K;
   const int ku = kused[kk];
+  const size_t o = (size_t)blockIdx.y * nn + n;
   double s = 0.0;
-  for (int i = 0; i < ku; ++i) s += y[i * K + kk] * (double)V[(long)i * vstride + idx];
-  t[idx] = (T)s;
+  for (int i = 0; i < ku; ++i) s += y[i * K + kk] * (double)V[i * vstride + o];
+  t[o] = (T)s;
 }
 
 template <typename Tx, typename Tz>
-__global__ void k_axpy_cols(long count, int K, const double* __restrict__ a, const Tz* __restrict__ z,
+__global__ void k_axpy_cols(unsigned nn, int K, const double* __restrict__ a, const Tz* __restrict__ z,
                             Tx* __restrict__ x) {
-  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= count) return;
-  const double av = a ? a[idx % K] : 1.0;
-  x[idx] = (Tx)((double)x[idx] + av * (double)z[idx]);
+  const unsigned n = blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= nn) return;
+  const size_t o = (size_t)blockIdx.y * nn + n;
+  const double av = a ? a[blockIdx.y % K] : 1.0;
+  x[o] = (Tx)((double)x[o] + av * (double)z[o]);
 }
 
 template <typename Ts, typename Td>
-__global__ void k_convert(long count, const Ts* __restrict__ s, Td* __restrict__ d) {
-  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx < count) d[idx] = (Td)s[idx];
+__global__ void k_convert(size_t count, const Ts* __restrict__ s, Td* __restrict__ d) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (size_t)gridDim.x * blockDim.x)
+    d[i] = (Td)s[i];
 }
 
 template <typename T>
-__global__ void k_fill(long count, T v, T* __restrict__ d) {
-  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx < count) d[idx] = v;
+__global__ void k_fill(size_t count, T v, T* __restrict__ d) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (size_t)gridDim.x * blockDim.x)
+    d[i] = v;
 }
 
 template <typename T>
-__global__ void k_subtract_mean(long nn, int FK, const double* __restrict__ sums, T* __restrict__ v) {
-  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= nn * FK) return;
-  v[idx] = (T)((double)v[idx] - sums[idx % FK] / (double)nn);
+__global__ void k_subtract_mean(unsigned nn, const double* __restrict__ sums, T* __restrict__ v) {
+  const unsigned n = blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= nn) return;
+  const size_t o = (size_t)blockIdx.y * nn + n;
+  v[o] = (T)((double)v[o] - sums[blockIdx.y] / (double)nn);
 }
 
-template <typename T>
-__global__ void k_split(long nn, int K, const T* __restrict__ full, T* __restrict__ u, T* __restrict__ p) {
-  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= nn * 4 * K) return;
-  const long n = idx / (4 * K);
-  const int r = (int)(idx % (4 * K));
-  const int f = r / K, kk = r % K;
-  if (f < 3) u[n * 3 * K + f * K + kk] = full[idx];
-  else p[n * K + kk] = full[idx];
+// column f of a 4-field single-load vector <-> column f*9 + load of a 9-load block
+__global__ void k_extract_col(unsigned nn, int load, const double* __restrict__ block, double* __restrict__ col) {
+  const unsigned n = blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= nn) return;
+  col[(size_t)blockIdx.y * nn + n] = block[(size_t)(blockIdx.y * 9 + load) * nn + n];
+}
+__global__ void k_insert_col(unsigned nn, int load, const double* __restrict__ col, double* __restrict__ block) {
+  const unsigned n = blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= nn) return;
+  block[(size_t)(blockIdx.y * 9 + load) * nn + n] = col[(size_t)blockIdx.y * nn + n];
 }
 
-template <typename T>
-__global__ void k_merge(long nn, int K, const T* __restrict__ u, const T* __restrict__ p, T* __restrict__ full) {
-  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= nn * 4 * K) return;
-  const long n = idx / (4 * K);
-  const int r = (int)(idx % (4 * K));
-  const int f = r / K, kk = r % K;
-  full[idx] = f < 3 ? u[n * 3 * K + f * K + kk] : p[n * K + kk];
+// dst[n*ncol + c] = src[c*nn + n] (and back)
+__global__ void k_soa_to_aos(unsigned nn, int ncol, const double* __restrict__ src, double* __restrict__ dst) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (size_t)nn * ncol) return;
+  const unsigned n = (unsigned)(i / ncol);
+  const int c = (int)(i - (size_t)n * ncol);
+  dst[i] = src[(size_t)c * nn + n];
 }
-
-__global__ void k_extract_col(long nn, int load, const double* __restrict__ block, double* __restrict__ col) {
-  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= nn * 4) return;
-  col[idx] = block[idx * 9 + load];
-}
-
-__global__ void k_insert_col(long nn, int load, const double* __restrict__ col, double* __restrict__ block) {
-  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= nn * 4) return;
-  block[idx * 9 + load] = col[idx];
+__global__ void k_aos_to_soa(unsigned nn, int ncol, const double* __restrict__ src, double* __restrict__ dst) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (size_t)nn * ncol) return;
+  const unsigned n = (unsigned)(i / ncol);
+  const int c = (int)(i - (size_t)n * ncol);
+  dst[(size_t)c * nn + n] = src[i];
 }
 
 // --------------------------------------------------------------- GMRES small
@@ -283,19 +323,18 @@ __global__ void k_gmres_givens(int K, int m, int j, const double* __restrict__ h
     s.cs[j * K + k] = c;
     s.sn[j * K + k] = sn;
     col[j] = den;
-    for (int i = 0; i <= j; ++i) s.H[((long)i * m + j) * K + k] = col[i];
+    for (int i = 0; i <= j; ++i) s.H[((size_t)i * m + j) * K + k] = col[i];
     const double gj = s.g[j * K + k];
     s.g[(j + 1) * K + k] = -sn * gj;
     s.g[j * K + k] = c * gj;
     const double est = fabs(s.g[(j + 1) * K + k]) / s.bnorm[k];
     s.est[j * K + k] = est;
-    const bool stop = !(est > rtol) || !(hn > 1e-300 * den) || (j + 1 == m) || !isfinite(est);
+    const bool stop = !(est > rtol) || !(hn > 0.0) || (j + 1 == m) || !isfinite(est);
+    s.kused[k] = j + 1;
     if (stop) {
       s.active[k] = 0;
-      s.kused[k] = j + 1;
       s.scale[k] = 0.0;
     } else {
-      s.kused[k] = j + 1;
       s.scale[k] = 1.0 / hn;
       atomicAdd(&cnt, 1);
     }
@@ -312,21 +351,22 @@ __global__ void k_gmres_solve_y(int K, int m, GmresState s) {
   const int ku = s.kused[k];
   for (int i = ku - 1; i >= 0; --i) {
     double v = s.g[i * K + k];
-    for (int c = i + 1; c < ku; ++c) v -= s.H[((long)i * m + c) * K + k] * s.y[c * K + k];
-    const double d = s.H[((long)i * m + i) * K + k];
+    for (int c = i + 1; c < ku; ++c) v -= s.H[((size_t)i * m + c) * K + k] * s.y[c * K + k];
+    const double d = s.H[((size_t)i * m + i) * K + k];
     s.y[i * K + k] = d != 0.0 ? v / d : 0.0;
   }
 }
 
 // ---------------------------------------------------------------- physics
 struct Nb {
-  int i, j, k, im, jm, km, ip, jp, kp;
+  unsigned i, j, k, im, jm, km, ip, jp, kp;
 };
-__device__ __forceinline__ Nb nbr(long n, int N) {
+__device__ __forceinline__ Nb nbr(unsigned n, unsigned N) {
   Nb r;
-  r.i = (int)(n % N);
-  r.j = (int)((n / N) % N);
-  r.k = (int)(n / ((long)N * N));
+  const unsigned t = n / N;
+  r.i = n - t * N;
+  r.k = t / N;
+  r.j = t - r.k * N;
   r.im = r.i ? r.i - 1 : N - 1;
   r.jm = r.j ? r.j - 1 : N - 1;
   r.km = r.k ? r.k - 1 : N - 1;
@@ -335,14 +375,14 @@ __device__ __forceinline__ Nb nbr(long n, int N) {
   r.kp = r.k + 1 < N ? r.k + 1 : 0;
   return r;
 }
-__device__ __forceinline__ long at(int N, int i, int j, int k) { return (long)i + (long)N * (j + (long)N * k); }
+__device__ __forceinline__ unsigned at(unsigned N, unsigned i, unsigned j, unsigned k) { return i + N * (j + N * k); }
 
 // element e with origin (i,j,k): corner c is node (i + cx, j + cy, k + cz)
-__device__ __forceinline__ long corner_node(const Nb& q, int N, int c) {
+__device__ __forceinline__ unsigned corner_node(const Nb& q, unsigned N, int c) {
   return at(N, (c & 1) ? q.ip : q.i, (c & 2) ? q.jp : q.j, (c & 4) ? q.kp : q.k);
 }
 // node n is corner c of element with origin n - c
-__device__ __forceinline__ long elem_of_corner(const Nb& q, int N, int c) {
+__device__ __forceinline__ unsigned elem_of_corner(const Nb& q, unsigned N, int c) {
   return at(N, (c & 1) ? q.im : q.i, (c & 2) ? q.jm : q.j, (c & 4) ? q.km : q.k);
 }
 
@@ -356,10 +396,10 @@ __device__ __forceinline__ double sheaviside_d(double t, double eta) {
   return (1.0 + cos(M_PI * t / eta)) / (2.0 * eta);
 }
 
-__global__ void k_levelset_to_scale(int N, const double* __restrict__ phi, double eta, double ev,
+__global__ void k_levelset_to_scale(unsigned N, const double* __restrict__ phi, double eta, double ev,
                                     double* __restrict__ rho, double* __restrict__ s, float* __restrict__ s32) {
-  const long nn = (long)N * N * N;
-  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const unsigned nn = N * N * N;
+  const unsigned e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= nn) return;
   const Nb q = nbr(e, N);
   double m = 0.0;
@@ -372,74 +412,69 @@ __global__ void k_levelset_to_scale(int N, const double* __restrict__ phi, doubl
   s32[e] = (float)sv;
 }
 
-__global__ void k_density_to_scale(long nn, const double* __restrict__ rho, double ev, double* __restrict__ s,
+__global__ void k_density_to_scale(unsigned nn, const double* __restrict__ rho, double ev, double* __restrict__ s,
                                    float* __restrict__ s32) {
-  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const unsigned e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= nn) return;
   const double sv = ev + (1.0 - ev) * rho[e];
   s[e] = sv;
   s32[e] = (float)sv;
 }
 
-__global__ void k_build_rhs(int N, const double* __restrict__ s, const double* __restrict__ F0,
-                            double* __restrict__ b, int absval) {
-  const long nn = (long)N * N * N;
-  const long n = (long)blockIdx.x * blockDim.x + threadIdx.x;
+// b[(f*9 + L)][n] = -sum_c s_{n-c} F0[4c + f][L]   (absval: sum_c s |F0|)
+__global__ __launch_bounds__(128) void k_build_rhs(unsigned N, const double* __restrict__ s,
+                                                   const double* __restrict__ F0, double* __restrict__ b, int absval) {
+  const unsigned nn = N * N * N;
+  const unsigned n = blockIdx.x * blockDim.x + threadIdx.x;
   if (n >= nn) return;
   const Nb q = nbr(n, N);
-  double acc[36];
-  for (int t = 0; t < 36; ++t) acc[t] = 0.0;
-  for (int c = 0; c < 8; ++c) {
-    const double se = s[elem_of_corner(q, N, c)];
-    for (int f = 0; f < 4; ++f)
-      for (int L = 0; L < 9; ++L) {
+  double se[8];
+  for (int c = 0; c < 8; ++c) se[c] = s[elem_of_corner(q, N, c)];
+  for (int f = 0; f < 4; ++f)
+    for (int L = 0; L < 9; ++L) {
+      double acc = 0.0;
+      for (int c = 0; c < 8; ++c) {
         const double v = F0[(4 * c + f) * 9 + L];
-        acc[f * 9 + L] -= se * (absval ? -fabs(v) : v);
+        acc -= se[c] * (absval ? -fabs(v) : v);
       }
-  }
-  for (int t = 0; t < 36; ++t) b[n * 36 + t] = acc[t];
+      b[(size_t)(f * 9 + L) * nn + n] = acc;
+    }
 }
 
-// Y[(l, p)] = sum_n s_{n - c(l)} X[n][p], p = f*9 + L; plus sum_e s_e
-__global__ void k_reduce_effective(int N, const double* __restrict__ s, const double* __restrict__ X,
-                                   double* __restrict__ part) {
-  __shared__ double lds[576 * 9];
-  const long nn = (long)N * N * N;
-  const int t = threadIdx.x;  // 576 = 16 nodes x 36 values
-  const int p = t % 36, qo = t / 36;
-  double acc[9];
-  for (int u = 0; u < 9; ++u) acc[u] = 0.0;
-  for (long n = (long)blockIdx.x * 16 + qo; n < nn; n += (long)gridDim.x * 16) {
+// partial Y[(l, col)] = sum_n s_{n - c(l)} X[col][n] for column blockIdx.y
+__global__ __launch_bounds__(256) void k_reduce_effective(unsigned N, const double* __restrict__ s,
+                                                          const double* __restrict__ X, double* __restrict__ part) {
+  __shared__ double lds4[4];
+  const unsigned nn = N * N * N;
+  const double* col = X + (size_t)blockIdx.y * nn;
+  double acc[8];
+  for (int l = 0; l < 8; ++l) acc[l] = 0.0;
+  for (unsigned n = blockIdx.x * 256 + threadIdx.x; n < nn; n += gridDim.x * 256) {
     const Nb q = nbr(n, N);
-    const double xv = X[n * 36 + p];
+    const double xv = col[n];
     for (int l = 0; l < 8; ++l) acc[l] += s[elem_of_corner(q, N, l)] * xv;
-    if (p == 0) acc[8] += s[n];
   }
-  for (int u = 0; u < 9; ++u) lds[u * 576 + t] = acc[u];
-  __syncthreads();
-  for (int v = t; v < 289; v += blockDim.x) {
-    double sum = 0.0;
-    if (v < 288) {
-      const int l = v / 36, pp = v % 36;
-      for (int qq = 0; qq < 16; ++qq) sum += lds[l * 576 + qq * 36 + pp];
-    } else {
-      for (int qq = 0; qq < 16; ++qq) sum += lds[8 * 576 + qq * 36];
-    }
-    part[(long)blockIdx.x * 289 + v] = sum;
+  const size_t base = ((size_t)blockIdx.y * gridDim.x + blockIdx.x) * 8;
+  for (int l = 0; l < 8; ++l) {
+    const double v = block_sum(acc[l], lds4);
+    if (threadIdx.x == 0) part[base + l] = v;
   }
 }
 
 // dJ/drho_e = factor * ( cterm + <X_e, FW> + sum_{l,l'} <K0[l,l'], (x_l W) x_l'^T> )
-__global__ __launch_bounds__(128) void k_backward(int N, const double* __restrict__ X, const double* __restrict__ K0,
+__global__ __launch_bounds__(128) void k_backward(unsigned N, const double* __restrict__ X, const double* __restrict__ K0,
                                                   const double* __restrict__ FW, const double* __restrict__ W,
                                                   double cterm, double factor, double* __restrict__ grad) {
-  const long nn = (long)N * N * N;
-  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const unsigned nn = N * N * N;
+  const unsigned e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= nn) return;
   const Nb q = nbr(e, N);
+  unsigned cn[8];
+  for (int l = 0; l < 8; ++l) cn[l] = corner_node(q, N, l);
   double total = cterm;
   for (int l = 0; l < 8; ++l) {
-    const double* xl = X + corner_node(q, N, l) * 36;
+    double xl[36];
+    for (int t = 0; t < 36; ++t) xl[t] = X[(size_t)t * nn + cn[l]];
     double u[36];  // u = x_l W  (4 x 9)
     for (int f = 0; f < 4; ++f) {
       for (int L = 0; L < 9; ++L) {
@@ -451,27 +486,48 @@ __global__ __launch_bounds__(128) void k_backward(int N, const double* __restric
     for (int f = 0; f < 4; ++f)
       for (int L = 0; L < 9; ++L) total += xl[f * 9 + L] * FW[(4 * l + f) * 9 + L];
     for (int lp = 0; lp < 8; ++lp) {
-      const double* xm = X + corner_node(q, N, lp) * 36;
-      for (int f = 0; f < 4; ++f)
-        for (int fp = 0; fp < 4; ++fp) {
+      for (int fp = 0; fp < 4; ++fp) {
+        double xm[9];
+        for (int L = 0; L < 9; ++L) xm[L] = X[(size_t)(fp * 9 + L) * nn + cn[lp]];
+        for (int f = 0; f < 4; ++f) {
           double v = 0.0;
-          for (int L = 0; L < 9; ++L) v += u[f * 9 + L] * xm[fp * 9 + L];
+          for (int L = 0; L < 9; ++L) v += u[f * 9 + L] * xm[L];
           total += K0[(4 * l + f) * 32 + 4 * lp + fp] * v;
         }
+      }
     }
   }
   grad[e] = factor * total;
 }
 
-__global__ void k_grad_phi(int N, const double* __restrict__ phi, double eta, const double* __restrict__ grho,
+// partial cross products sum_n X[(f, a)][n] * Y[(f, b)][n] for (f, a) = blockIdx.y
+__global__ __launch_bounds__(256) void k_cross_dots(unsigned nn, const double* __restrict__ X,
+                                                    const double* __restrict__ Y, double* __restrict__ part) {
+  __shared__ double lds4[4];
+  const int f = blockIdx.y / 9;
+  const double* xc = X + (size_t)blockIdx.y * nn;
+  double acc[9];
+  for (int b = 0; b < 9; ++b) acc[b] = 0.0;
+  for (unsigned n = blockIdx.x * 256 + threadIdx.x; n < nn; n += gridDim.x * 256) {
+    const double xv = xc[n];
+    for (int b = 0; b < 9; ++b) acc[b] += xv * Y[(size_t)(f * 9 + b) * nn + n];
+  }
+  const size_t base = ((size_t)blockIdx.y * gridDim.x + blockIdx.x) * 9;
+  for (int b = 0; b < 9; ++b) {
+    const double v = block_sum(acc[b], lds4);
+    if (threadIdx.x == 0) part[base + b] = v;
+  }
+}
+
+__global__ void k_grad_phi(unsigned N, const double* __restrict__ phi, double eta, const double* __restrict__ grho,
                            double* __restrict__ out) {
-  const long nn = (long)N * N * N;
-  const long n = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const unsigned nn = N * N * N;
+  const unsigned n = blockIdx.x * blockDim.x + threadIdx.x;
   if (n >= nn) return;
   const Nb q = nbr(n, N);
   double acc = 0.0;
   for (int c = 0; c < 8; ++c) {
-    const long e = elem_of_corner(q, N, c);
+    const unsigned e = elem_of_corner(q, N, c);
     const Nb qe = nbr(e, N);
     double m = 0.0;
     for (int cc = 0; cc < 8; ++cc) m += phi[corner_node(qe, N, cc)];
@@ -481,9 +537,9 @@ __global__ void k_grad_phi(int N, const double* __restrict__ phi, double eta, co
   out[n] = acc * 0.125;
 }
 
-__global__ void k_nodal_mean(int N, const double* __restrict__ ge, double* __restrict__ vn) {
-  const long nn = (long)N * N * N;
-  const long n = (long)blockIdx.x * blockDim.x + threadIdx.x;
+__global__ void k_nodal_mean(unsigned N, const double* __restrict__ ge, double* __restrict__ vn) {
+  const unsigned nn = N * N * N;
+  const unsigned n = blockIdx.x * blockDim.x + threadIdx.x;
   if (n >= nn) return;
   const Nb q = nbr(n, N);
   double acc = 0.0;
@@ -491,10 +547,10 @@ __global__ void k_nodal_mean(int N, const double* __restrict__ ge, double* __res
   vn[n] = acc * 0.125;
 }
 
-__global__ void k_max_abs(long count, const double* __restrict__ v, double* __restrict__ part) {
+__global__ void k_max_abs(size_t count, const double* __restrict__ v, double* __restrict__ part) {
   __shared__ double lds[256];
   double m = 0.0;
-  for (long idx = (long)blockIdx.x * 256 + threadIdx.x; idx < count; idx += (long)gridDim.x * 256)
+  for (size_t idx = (size_t)blockIdx.x * 256 + threadIdx.x; idx < count; idx += (size_t)gridDim.x * 256)
     m = fmax(m, fabs(v[idx]));
   lds[threadIdx.x] = m;
   __syncthreads();
@@ -513,24 +569,19 @@ __global__ void k_max_partials(int nb, const double* __restrict__ part, double* 
   }
 }
 
-__global__ void k_count_nonfinite(long count, const double* __restrict__ v, double* __restrict__ part) {
-  __shared__ double lds[256];
+__global__ void k_count_nonfinite(size_t count, const double* __restrict__ v, double* __restrict__ part) {
+  __shared__ double lds4[4];
   double c = 0.0;
-  for (long idx = (long)blockIdx.x * 256 + threadIdx.x; idx < count; idx += (long)gridDim.x * 256)
+  for (size_t idx = (size_t)blockIdx.x * 256 + threadIdx.x; idx < count; idx += (size_t)gridDim.x * 256)
     c += isfinite(v[idx]) ? 0.0 : 1.0;
-  lds[threadIdx.x] = c;
-  __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
-    if (threadIdx.x < s) lds[threadIdx.x] += lds[threadIdx.x + s];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) part[blockIdx.x] = lds[0];
+  c = block_sum(c, lds4);
+  if (threadIdx.x == 0) part[blockIdx.x] = c;
 }
 
-__global__ void k_hj_step(int N, const double* __restrict__ phi, const double* __restrict__ v,
+__global__ void k_hj_step(unsigned N, const double* __restrict__ phi, const double* __restrict__ v,
                           const double* __restrict__ vmax, double dt, double* __restrict__ out) {
-  const long nn = (long)N * N * N;
-  const long n = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const unsigned nn = N * N * N;
+  const unsigned n = blockIdx.x * blockDim.x + threadIdx.x;
   if (n >= nn) return;
   const Nb q = nbr(n, N);
   const double h = 1.0 / N;
@@ -551,15 +602,16 @@ __global__ void k_hj_step(int N, const double* __restrict__ phi, const double* _
 }
 
 template <typename T>
-__global__ void k_normalize_by(long count, const double* __restrict__ nrm2, const T* __restrict__ w, T* __restrict__ v) {
-  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+__global__ void k_normalize_by(size_t count, const double* __restrict__ nrm2, const T* __restrict__ w,
+                               T* __restrict__ v) {
+  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= count) return;
   const double nr = sqrt(nrm2[0]);
   v[idx] = (T)(nr > 0.0 ? (double)w[idx] / nr : 0.0);
 }
 
-__global__ void k_hash_fill(long count, unsigned seed, double* __restrict__ v) {
-  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+__global__ void k_hash_fill(size_t count, unsigned seed, double* __restrict__ v) {
+  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= count) return;
   unsigned long long z = (unsigned long long)idx * 0x9E3779B97F4A7C15ULL + seed;
   z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
@@ -570,110 +622,100 @@ __global__ void k_hash_fill(long count, unsigned seed, double* __restrict__ v) {
 
 }  // namespace
 
-size_t reduce_work_size(int nvals) { return (size_t)kRedBlocks * (size_t)nvals; }
+size_t reduce_work_size() { return (size_t)kMaxPartBlocks * (kMaxRestart + 2) + 4096; }
 
 template <typename Ts, typename Td>
 void convert(long count, const Ts* src, Td* dst, hipStream_t st) {
   if (count <= 0) return;
-  hipLaunchKernelGGL((k_convert<Ts, Td>), dim3(blocks_for(count, 256)), dim3(256), 0, st, count, src, dst);
+  hipLaunchKernelGGL((k_convert<Ts, Td>), dim3(std::min<size_t>(blocks_for(count, 256), 65536)), dim3(256), 0, st,
+                     (size_t)count, src, dst);
   PHZ_LAUNCH_CHECK();
 }
 
 template <typename T>
 void fill(long count, T value, T* dst, hipStream_t st) {
   if (count <= 0) return;
-  hipLaunchKernelGGL((k_fill<T>), dim3(blocks_for(count, 256)), dim3(256), 0, st, count, value, dst);
+  hipLaunchKernelGGL((k_fill<T>), dim3(std::min<size_t>(blocks_for(count, 256), 65536)), dim3(256), 0, st,
+                     (size_t)count, value, dst);
   PHZ_LAUNCH_CHECK();
 }
 
 template <typename T>
-void col_norm2(long rows, int nrhs, const T* v, double* out, double* work, hipStream_t st) {
-  flat_sums<T, true>(rows * nrhs, nrhs, v, out, work, st);
+void col_norm2(long nn, int F, int K, const T* v, double* out, double* work, hipStream_t st) {
+  col_reduce<T, true>((size_t)nn, F, K, v, out, work, st);
 }
 
 template <typename T>
-void field_sums(long nn, int F, int nrhs, const T* v, double* out, double* work, hipStream_t st) {
-  flat_sums<T, false>(nn * F * nrhs, F * nrhs, v, out, work, st);
+void field_sums(long nn, int F, int K, const T* v, double* out, double* work, hipStream_t st) {
+  col_reduce<T, false>((size_t)nn, 1, F * K, v, out, work, st);
 }
 
 template <typename T>
-void subtract_mean(long nn, int F, int nrhs, const double* sums, T* v, hipStream_t st) {
-  const long count = nn * F * nrhs;
-  hipLaunchKernelGGL((k_subtract_mean<T>), dim3(blocks_for(count, 256)), dim3(256), 0, st, nn, F * nrhs, sums, v);
+void subtract_mean(long nn, int F, int K, const double* sums, T* v, hipStream_t st) {
+  hipLaunchKernelGGL((k_subtract_mean<T>), dim3(blocks_for(nn, 256), F * K), dim3(256), 0, st, (unsigned)nn, sums, v);
   PHZ_LAUNCH_CHECK();
 }
 
 template <typename T>
-void arnoldi_dots(long rows, int nrhs, int j, const T* V, long vstride, const T* w, double* hout, double* work,
+void arnoldi_dots(long nn, int F, int K, int j, const T* V, long vstride, const T* w, double* hout, double* work,
                   hipStream_t st) {
-  const long count = rows * nrhs;
-  const int bs = nrhs == 1 ? 256 : 64 * nrhs;
-  const unsigned g = red_grid(count, bs);
-  const int nv = (j + 1) * nrhs;
-  hipLaunchKernelGGL((k_arnoldi_dots<T>), dim3(g), dim3(bs), bs * sizeof(double), st, count, nrhs, j, V, vstride, w,
-                     work);
-  hipLaunchKernelGGL(k_split_partials, dim3(1), dim3(256), 0, st, (int)g, nv, nv, work, hout, (double*)nullptr);
+  static constexpr auto table = dots_table<T>(std::make_integer_sequence<int, kMaxRestart + 1>{});
+  const unsigned G = slices_for((size_t)nn, F * K);
+  table[j](dim3(G, F * K), st, (unsigned)nn, V, (size_t)vstride, w, work);
+  reduce_cols((int)G, F, K, j + 1, 0, j + 1, work, hout, st);
   PHZ_LAUNCH_CHECK();
 }
 
 template <typename T>
-void arnoldi_update(long rows, int nrhs, int j, const T* V, long vstride, T* w, const double* hin, double* hout,
+void arnoldi_update(long nn, int F, int K, int j, const T* V, long vstride, T* w, const double* hin, double* hout,
                     double* nrm2out, double* work, hipStream_t st) {
-  const long count = rows * nrhs;
-  const int bs = nrhs == 1 ? 256 : 64 * nrhs;
-  const unsigned g = red_grid(count, bs);
-  const int want = hout ? 1 : 0;
-  const int nd = want * (j + 1) * nrhs;
-  const int nv = nd + nrhs;
-  hipLaunchKernelGGL((k_arnoldi_update<T>), dim3(g), dim3(bs), bs * sizeof(double), st, count, nrhs, j, V, vstride, w,
-                     hin, want, work);
-  hipLaunchKernelGGL(k_split_partials, dim3(1), dim3(256), 0, st, (int)g, nv, nd, work, hout, nrm2out);
+  static constexpr auto table = upd_table<T>(std::make_integer_sequence<int, kMaxRestart + 1>{});
+  const unsigned G = slices_for((size_t)nn, F * K);
+  const bool fused = hout && j + 1 <= kFusedMaxJ;
+  const int NV = (fused ? j + 1 : 0) + 1;
+  table[j](dim3(G, F * K), st, (unsigned)nn, K, V, (size_t)vstride, w, hin, fused ? 1 : 0, work);
+  if (fused) reduce_cols((int)G, F, K, NV, 0, j + 1, work, hout, st);
+  if (nrm2out) reduce_cols((int)G, F, K, NV, NV - 1, 1, work, nrm2out, st);
+  PHZ_LAUNCH_CHECK();
+  if (hout && !fused) arnoldi_dots<T>(nn, F, K, j, V, vstride, w, hout, work, st);
+}
+
+template <typename T>
+void scale_cols(long nn, int F, int K, const T* w, const double* scale, T* v, hipStream_t st) {
+  hipLaunchKernelGGL((k_scale_cols<T>), dim3(blocks_for(nn, 256), F * K), dim3(256), 0, st, (unsigned)nn, K, w, scale, v);
   PHZ_LAUNCH_CHECK();
 }
 
 template <typename T>
-void scale_cols(long rows, int nrhs, const T* w, const double* scale, T* v, hipStream_t st) {
-  const long count = rows * nrhs;
-  hipLaunchKernelGGL((k_scale_cols<T>), dim3(blocks_for(count, 256)), dim3(256), 0, st, count, nrhs, w, scale, v);
-  PHZ_LAUNCH_CHECK();
-}
-
-template <typename T>
-void combine(long rows, int nrhs, int m, const T* V, long vstride, const double* y, const int* kused, T* t,
-             hipStream_t st) {
-  const long count = rows * nrhs;
-  hipLaunchKernelGGL((k_combine<T>), dim3(blocks_for(count, 256)), dim3(256), 0, st, count, nrhs, m, V, vstride, y,
-                     kused, t);
+void combine(long nn, int F, int K, const T* V, long vstride, const double* y, const int* kused, T* t, hipStream_t st) {
+  hipLaunchKernelGGL((k_combine<T>), dim3(blocks_for(nn, 256), F * K), dim3(256), 0, st, (unsigned)nn, K, V,
+                     (size_t)vstride, y, kused, t);
   PHZ_LAUNCH_CHECK();
 }
 
 template <typename Tx, typename Tz>
-void axpy_cols(long rows, int nrhs, const double* a, const Tz* z, Tx* x, hipStream_t st) {
-  const long count = rows * nrhs;
-  hipLaunchKernelGGL((k_axpy_cols<Tx, Tz>), dim3(blocks_for(count, 256)), dim3(256), 0, st, count, nrhs, a, z, x);
-  PHZ_LAUNCH_CHECK();
-}
-
-template <typename T>
-void split_fields(long nn, int nrhs, const T* full, T* u, T* p, hipStream_t st) {
-  const long count = nn * 4 * nrhs;
-  hipLaunchKernelGGL((k_split<T>), dim3(blocks_for(count, 256)), dim3(256), 0, st, nn, nrhs, full, u, p);
-  PHZ_LAUNCH_CHECK();
-}
-
-template <typename T>
-void merge_fields(long nn, int nrhs, const T* u, const T* p, T* full, hipStream_t st) {
-  const long count = nn * 4 * nrhs;
-  hipLaunchKernelGGL((k_merge<T>), dim3(blocks_for(count, 256)), dim3(256), 0, st, nn, nrhs, u, p, full);
+void axpy_cols(long nn, int F, int K, const double* a, const Tz* z, Tx* x, hipStream_t st) {
+  hipLaunchKernelGGL((k_axpy_cols<Tx, Tz>), dim3(blocks_for(nn, 256), F * K), dim3(256), 0, st, (unsigned)nn, K, a, z,
+                     x);
   PHZ_LAUNCH_CHECK();
 }
 
 void extract_column(long nn, int load, const double* block, double* col, hipStream_t st) {
-  hipLaunchKernelGGL(k_extract_col, dim3(blocks_for(nn * 4, 256)), dim3(256), 0, st, nn, load, block, col);
+  hipLaunchKernelGGL(k_extract_col, dim3(blocks_for(nn, 256), 4), dim3(256), 0, st, (unsigned)nn, load, block, col);
   PHZ_LAUNCH_CHECK();
 }
 void insert_column(long nn, int load, const double* col, double* block, hipStream_t st) {
-  hipLaunchKernelGGL(k_insert_col, dim3(blocks_for(nn * 4, 256)), dim3(256), 0, st, nn, load, col, block);
+  hipLaunchKernelGGL(k_insert_col, dim3(blocks_for(nn, 256), 4), dim3(256), 0, st, (unsigned)nn, load, col, block);
+  PHZ_LAUNCH_CHECK();
+}
+void soa_to_aos(long nn, int ncol, const double* src, double* dst, hipStream_t st) {
+  hipLaunchKernelGGL(k_soa_to_aos, dim3(blocks_for((size_t)nn * ncol, 256)), dim3(256), 0, st, (unsigned)nn, ncol, src,
+                     dst);
+  PHZ_LAUNCH_CHECK();
+}
+void aos_to_soa(long nn, int ncol, const double* src, double* dst, hipStream_t st) {
+  hipLaunchKernelGGL(k_aos_to_soa, dim3(blocks_for((size_t)nn * ncol, 256)), dim3(256), 0, st, (unsigned)nn, ncol, src,
+                     dst);
   PHZ_LAUNCH_CHECK();
 }
 
@@ -693,89 +735,98 @@ void gmres_solve_y(int nrhs, int m, GmresState s, hipStream_t st) {
 
 void levelset_to_scale(int N, const double* phi, double eta, double void_scale, double* rho, double* s, float* s32,
                        hipStream_t st) {
-  const long nn = (long)N * N * N;
-  hipLaunchKernelGGL(k_levelset_to_scale, dim3(blocks_for(nn, 256)), dim3(256), 0, st, N, phi, eta, void_scale, rho,
-                     s, s32);
+  const size_t nn = (size_t)N * N * N;
+  hipLaunchKernelGGL(k_levelset_to_scale, dim3(blocks_for(nn, 256)), dim3(256), 0, st, (unsigned)N, phi, eta,
+                     void_scale, rho, s, s32);
   PHZ_LAUNCH_CHECK();
 }
 void density_to_scale(long nn, const double* rho, double void_scale, double* s, float* s32, hipStream_t st) {
-  hipLaunchKernelGGL(k_density_to_scale, dim3(blocks_for(nn, 256)), dim3(256), 0, st, nn, rho, void_scale, s, s32);
+  hipLaunchKernelGGL(k_density_to_scale, dim3(blocks_for(nn, 256)), dim3(256), 0, st, (unsigned)nn, rho, void_scale, s,
+                     s32);
   PHZ_LAUNCH_CHECK();
 }
 void build_rhs(int N, const double* s, const double* F0, double* b, hipStream_t st, bool absval) {
-  const long nn = (long)N * N * N;
-  hipLaunchKernelGGL(k_build_rhs, dim3(blocks_for(nn, 128)), dim3(128), 0, st, N, s, F0, b, (int)absval);
+  const size_t nn = (size_t)N * N * N;
+  hipLaunchKernelGGL(k_build_rhs, dim3(blocks_for(nn, 128)), dim3(128), 0, st, (unsigned)N, s, F0, b, (int)absval);
   PHZ_LAUNCH_CHECK();
 }
 void reduce_effective(int N, const double* s, const double* X, double* out, double* work, hipStream_t st) {
-  const long nn = (long)N * N * N;
-  unsigned g = (unsigned)((nn + 15) / 16);
-  if (g > (unsigned)kRedBlocks) g = kRedBlocks;
-  hipLaunchKernelGGL(k_reduce_effective, dim3(g), dim3(576), 0, st, N, s, X, work);
-  hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(320), 0, st, (int)g, 289, work, out);
+  const size_t nn = (size_t)N * N * N;
+  const unsigned G = slices_for(nn, 36);
+  hipLaunchKernelGGL(k_reduce_effective, dim3(G, 36), dim3(256), 0, st, (unsigned)N, s, X, work);
+  // out[l*36 + col] = sum over slices
+  reduce_cols((int)G, 1, 36, 8, 0, 8, work, out, st);
+  // out[288] = sum_e s_e
+  col_reduce<double, false>(nn, 1, 1, s, out + 288, work, st);
+}
+void cross_dots(long nn, const double* X, const double* Y, double* out, double* work, hipStream_t st) {
+  const unsigned G = slices_for((size_t)nn, 36);
+  hipLaunchKernelGGL(k_cross_dots, dim3(G, 36), dim3(256), 0, st, (unsigned)nn, X, Y, work);
+  // out[b*9 + a] = sum_{f, slices} part[((f*9 + a)*G + slice)*9 + b]
+  reduce_cols((int)G, 4, 9, 9, 0, 9, work, out, st);
   PHZ_LAUNCH_CHECK();
 }
 void backward_elem(int N, const double* X, const double* K0, const double* FW, double cterm, double factor,
                    double* grad, hipStream_t st) {
   // W (9x9) is stored right after FW (32x9) in the same buffer
-  const long nn = (long)N * N * N;
-  hipLaunchKernelGGL(k_backward, dim3(blocks_for(nn, 128)), dim3(128), 0, st, N, X, K0, FW, FW + 288, cterm, factor,
-                     grad);
+  const size_t nn = (size_t)N * N * N;
+  hipLaunchKernelGGL(k_backward, dim3(blocks_for(nn, 128)), dim3(128), 0, st, (unsigned)N, X, K0, FW, FW + 288, cterm,
+                     factor, grad);
   PHZ_LAUNCH_CHECK();
 }
 void grad_phi(int N, const double* phi, double eta, const double* grad_rho, double* out, hipStream_t st) {
-  const long nn = (long)N * N * N;
-  hipLaunchKernelGGL(k_grad_phi, dim3(blocks_for(nn, 256)), dim3(256), 0, st, N, phi, eta, grad_rho, out);
+  const size_t nn = (size_t)N * N * N;
+  hipLaunchKernelGGL(k_grad_phi, dim3(blocks_for(nn, 256)), dim3(256), 0, st, (unsigned)N, phi, eta, grad_rho, out);
   PHZ_LAUNCH_CHECK();
 }
 void nodal_mean_of_elements(int N, const double* ge, double* vn, hipStream_t st) {
-  const long nn = (long)N * N * N;
-  hipLaunchKernelGGL(k_nodal_mean, dim3(blocks_for(nn, 256)), dim3(256), 0, st, N, ge, vn);
+  const size_t nn = (size_t)N * N * N;
+  hipLaunchKernelGGL(k_nodal_mean, dim3(blocks_for(nn, 256)), dim3(256), 0, st, (unsigned)N, ge, vn);
   PHZ_LAUNCH_CHECK();
 }
 void max_abs(long count, const double* v, double* out, double* work, hipStream_t st) {
-  const unsigned g = red_grid(count, 256);
-  hipLaunchKernelGGL(k_max_abs, dim3(g), dim3(256), 0, st, count, v, work);
+  unsigned g = blocks_for(count, 256);
+  if (g > 512) g = 512;
+  hipLaunchKernelGGL(k_max_abs, dim3(g), dim3(256), 0, st, (size_t)count, v, work);
   hipLaunchKernelGGL(k_max_partials, dim3(1), dim3(64), 0, st, (int)g, work, out);
   PHZ_LAUNCH_CHECK();
 }
 int count_nonfinite(long count, const double* v, double* work, hipStream_t st) {
-  const unsigned g = red_grid(count, 256);
-  hipLaunchKernelGGL(k_count_nonfinite, dim3(g), dim3(256), 0, st, count, v, work);
-  hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(64), 0, st, (int)g, 1, work, work + kRedBlocks);
+  unsigned g = blocks_for(count, 256);
+  if (g > 512) g = 512;
+  hipLaunchKernelGGL(k_count_nonfinite, dim3(g), dim3(256), 0, st, (size_t)count, v, work);
+  reduce_cols((int)g, 1, 1, 1, 0, 1, work, work + 1024, st);
   PHZ_LAUNCH_CHECK();
   double h = 0.0;
-  PHZ_HIP(hipMemcpyAsync(&h, work + kRedBlocks, sizeof(double), hipMemcpyDeviceToHost, st));
+  PHZ_HIP(hipMemcpyAsync(&h, work + 1024, sizeof(double), hipMemcpyDeviceToHost, st));
   PHZ_HIP(hipStreamSynchronize(st));
   return (int)h;
 }
 void hj_step(int N, const double* phi, const double* v, const double* vmax, double dt, double* out, hipStream_t st) {
-  const long nn = (long)N * N * N;
-  hipLaunchKernelGGL(k_hj_step, dim3(blocks_for(nn, 256)), dim3(256), 0, st, N, phi, v, vmax, dt, out);
+  const size_t nn = (size_t)N * N * N;
+  hipLaunchKernelGGL(k_hj_step, dim3(blocks_for(nn, 256)), dim3(256), 0, st, (unsigned)N, phi, v, vmax, dt, out);
   PHZ_LAUNCH_CHECK();
 }
 template <typename T>
 void normalize_by(long count, const double* nrm2, const T* w, T* v, hipStream_t st) {
-  hipLaunchKernelGGL((k_normalize_by<T>), dim3(blocks_for(count, 256)), dim3(256), 0, st, count, nrm2, w, v);
+  hipLaunchKernelGGL((k_normalize_by<T>), dim3(blocks_for(count, 256)), dim3(256), 0, st, (size_t)count, nrm2, w, v);
   PHZ_LAUNCH_CHECK();
 }
 void hash_fill(long count, unsigned seed, double* v, hipStream_t st) {
-  hipLaunchKernelGGL(k_hash_fill, dim3(blocks_for(count, 256)), dim3(256), 0, st, count, seed, v);
+  hipLaunchKernelGGL(k_hash_fill, dim3(blocks_for(count, 256)), dim3(256), 0, st, (size_t)count, seed, v);
   PHZ_LAUNCH_CHECK();
 }
 
 #define PHZ_VINST(T)                                                                                          \
   template void fill<T>(long, T, T*, hipStream_t);                                                            \
-  template void col_norm2<T>(long, int, const T*, double*, double*, hipStream_t);                             \
+  template void col_norm2<T>(long, int, int, const T*, double*, double*, hipStream_t);                       \
   template void field_sums<T>(long, int, int, const T*, double*, double*, hipStream_t);                      \
   template void subtract_mean<T>(long, int, int, const double*, T*, hipStream_t);                            \
-  template void arnoldi_dots<T>(long, int, int, const T*, long, const T*, double*, double*, hipStream_t);     \
-  template void arnoldi_update<T>(long, int, int, const T*, long, T*, const double*, double*, double*,        \
+  template void arnoldi_dots<T>(long, int, int, int, const T*, long, const T*, double*, double*, hipStream_t); \
+  template void arnoldi_update<T>(long, int, int, int, const T*, long, T*, const double*, double*, double*,   \
                                   double*, hipStream_t);                                                      \
-  template void scale_cols<T>(long, int, const T*, const double*, T*, hipStream_t);                          \
+  template void scale_cols<T>(long, int, int, const T*, const double*, T*, hipStream_t);                     \
   template void combine<T>(long, int, int, const T*, long, const double*, const int*, T*, hipStream_t);      \
-  template void split_fields<T>(long, int, const T*, T*, T*, hipStream_t);                                   \
-  template void merge_fields<T>(long, int, const T*, const T*, T*, hipStream_t);                             \
   template void normalize_by<T>(long, const double*, const T*, T*, hipStream_t);
 PHZ_VINST(double)
 PHZ_VINST(float)
@@ -783,8 +834,8 @@ PHZ_VINST(float)
 template void convert<double, float>(long, const double*, float*, hipStream_t);
 template void convert<float, double>(long, const float*, double*, hipStream_t);
 template void convert<double, double>(long, const double*, double*, hipStream_t);
-template void axpy_cols<double, double>(long, int, const double*, const double*, double*, hipStream_t);
-template void axpy_cols<double, float>(long, int, const double*, const float*, double*, hipStream_t);
-template void axpy_cols<float, float>(long, int, const double*, const float*, float*, hipStream_t);
+template void axpy_cols<double, double>(long, int, int, const double*, const double*, double*, hipStream_t);
+template void axpy_cols<double, float>(long, int, int, const double*, const float*, double*, hipStream_t);
+template void axpy_cols<float, float>(long, int, int, const double*, const float*, float*, hipStream_t);
 
 }  // namespace phz

@@ -43,6 +43,15 @@ def relmax(a, b):
     return np.abs(np.asarray(a) - np.asarray(b)).max() / max(np.abs(np.asarray(b)).max(), 1e-300)
 
 
+def to_soa(a, nn, F, K):
+    """node-major (nn*F, K) -> the library's device layout [F][K][nn]."""
+    return np.ascontiguousarray(np.asarray(a).reshape(nn, F, K).transpose(1, 2, 0))
+
+
+def from_soa(a, nn, F, K):
+    return np.asarray(a).reshape(F, K, nn).transpose(2, 0, 1).reshape(nn * F, K)
+
+
 def field_index(n, fields):
     d = np.arange(4 * n ** 3)
     return d[np.isin(d % 4, fields)]
@@ -69,15 +78,16 @@ def test_operator_blocks_fp64_and_fp32(torch_cuda, P, n, nrhs):
     with P.Context(n, MAT) as ctx:
         ctx.set_density(rho)
         for op, (M, fo, fi) in blocks.items():
-            x = rng.standard_normal((n ** 3 * fi, nrhs))
+            nn = n ** 3
+            x = rng.standard_normal((nn * fi, nrhs))
             yref = M @ x
             bound = abs(M) @ abs(x)
             for prec, dt, tol in ((P.PHZ_FP64, torch.float64, 1e-13), (P.PHZ_FP32_IR, torch.float32, 2e-5)):
-                xd = torch.tensor(x, dtype=dt, device="cuda").contiguous()
-                yd = torch.zeros((n ** 3 * fo, nrhs), dtype=dt, device="cuda")
+                xd = torch.tensor(to_soa(x, nn, fi, nrhs), dtype=dt, device="cuda").contiguous()
+                yd = torch.zeros((fo, nrhs, nn), dtype=dt, device="cuda")
                 ctx.apply(op, nrhs, prec, xd.data_ptr(), yd.data_ptr())
                 torch.cuda.synchronize()
-                y = yd.cpu().double().numpy()
+                y = from_soa(yd.cpu().double().numpy(), nn, fo, nrhs)
                 err = np.abs(y - yref) / np.maximum(bound, 1e-300)
                 # S_bar: the oracle inverts s_e A0 + delta I per element, the GPU
                 # s_e (A0 + delta I); they differ by O(delta / s_e) (a preconditioner)
@@ -140,10 +150,10 @@ def test_galerkin_coarse_operators(torch_cuda, P):
                 Ml = Pm.T @ Ml @ Pm
                 nl //= 2
                 x = rng.standard_normal((nl ** 3 * F, 9))
-                xd = torch.tensor(x, device="cuda")
+                xd = torch.tensor(to_soa(x, nl ** 3, F, 9), device="cuda")
                 yd = torch.zeros_like(xd)
                 ctx.coarse_apply(level, op, 9, xd.data_ptr(), yd.data_ptr())
-                y = yd.cpu().numpy()
+                y = from_soa(yd.cpu().numpy(), nl ** 3, F, 9)
                 ref = Ml @ x
                 tol = 1e-12 if op == P.OP_A else 1e-6
                 assert relmax(y, ref) < tol, (op, level, relmax(y, ref))
@@ -159,18 +169,19 @@ def test_preconditioner_is_good_approximate_inverse(torch_cuda, P):
     with P.Context(n, MAT) as ctx:
         ctx.set_levelset(phi)
         rng = np.random.default_rng(2)
-        x = rng.standard_normal((n ** 3 * 4, 9))
-        x -= x.reshape(n ** 3, 4, 9).mean(axis=0)[None].repeat(n ** 3, 0).reshape(-1, 9)
+        x = rng.standard_normal((4, 9, n ** 3))
+        x -= x.mean(axis=2, keepdims=True)
         xd = torch.tensor(x, device="cuda")
         ad = torch.zeros_like(xd)
         zd = torch.zeros_like(xd)
         ctx.apply(P.OP_FULL, 9, P.PHZ_FP64, xd.data_ptr(), ad.data_ptr())
         ctx.precondition(9, ad.data_ptr(), zd.data_ptr())
-        z = zd.cpu().numpy().reshape(n ** 3, 4, 9)
-        z -= z.mean(axis=0)[None]
+        z = zd.cpu().numpy()
+        z -= z.mean(axis=2, keepdims=True)
         assert np.all(np.isfinite(z))
         # the preconditioned residual operator is a contraction on random fields
-        e = np.linalg.norm(z.reshape(-1, 9) - x, axis=0) / np.linalg.norm(x, axis=0)
+        e = np.linalg.norm((z - x).transpose(1, 0, 2).reshape(9, -1), axis=1) / \
+            np.linalg.norm(x.transpose(1, 0, 2).reshape(9, -1), axis=1)
         assert e.max() < 1.0, e
 
 
