@@ -127,6 +127,50 @@ __device__ __forceinline__ double buf_load<double>(__amdgpu_buffer_rsrc_t r, uns
   return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, 0));
 }
 
+// Contribution of the neighbour m = n + (dx, dy, dz) to the FO x K outputs of
+// node n: its FO x FI stencil block (the reference element blocks of the
+// elements shared by n and m, weighted by their scales) times its FI x K
+// input columns.
+template <typename T, int FO, int FI, int K, bool BUF>
+__device__ __forceinline__ void fine_neighbour(unsigned m, int dx, int dy, int dz, unsigned nn, const T* se,
+                                               const T* kr, __amdgpu_buffer_rsrc_t xr, const T* __restrict__ x,
+                                               T* acc) {
+  T xv[FI * K];
+#pragma unroll
+  for (int col = 0; col < FI * K; ++col) {
+    if constexpr (BUF)
+      xv[col] = buf_load<T>(xr, m * (unsigned)sizeof(T), (unsigned)(col * nn * sizeof(T)));
+    else
+      xv[col] = x[(size_t)col * nn + m];
+  }
+  T blk[FO * FI];
+#pragma unroll
+  for (int t = 0; t < FO * FI; ++t) blk[t] = T(0);
+#pragma unroll
+  for (int c = 0; c < 8; ++c) {
+    const int mx = (c & 1) + dx, my = ((c >> 1) & 1) + dy, mz = ((c >> 2) & 1) + dz;
+    if (mx < 0 || mx > 1 || my < 0 || my > 1 || mz < 0 || mz > 1) continue;
+    const int lm = mx + 2 * my + 4 * mz;
+#pragma unroll
+    for (int fo = 0; fo < FO; ++fo)
+#pragma unroll
+      for (int fi = 0; fi < FI; ++fi) blk[fo * FI + fi] += se[c] * kr[(c * FO + fo) * (8 * FI) + lm * FI + fi];
+  }
+#pragma unroll
+  for (int fi = 0; fi < FI; ++fi)
+#pragma unroll
+    for (int kk = 0; kk < K; ++kk)
+#pragma unroll
+      for (int fo = 0; fo < FO; ++fo) acc[fo * K + kk] += blk[fo * FI + fi] * xv[fi * K + kk];
+}
+
+// Whether the 9 (dy, dz) rows of neighbours run as a runtime loop: that keeps
+// the compiler from holding the loads of many neighbours live at once, which
+// lowers register use (raising occupancy) for the FP32 A and S blocks; the
+// other variants use fewer registers fully unrolled.
+template <typename T, int FO, int FI>
+constexpr bool fine_row_loop() { return sizeof(T) == 4 && FO == FI && FO != 4; }
+
 // One thread per output node.  The reference block sits in LDS (a broadcast
 // read per coefficient, no scalar-register pressure); the 27 neighbour
 // records are read with buffer loads, all FI*K columns of a neighbour issued
@@ -155,38 +199,23 @@ __global__ __launch_bounds__(128) void k_fine_apply(unsigned N, const T* __restr
 #pragma unroll
   for (int t = 0; t < FO * K; ++t) acc[t] = T(0);
 
-#pragma unroll
-  for (int d = 0; d < 27; ++d) {
-    const int dx = d % 3 - 1, dy = (d / 3) % 3 - 1, dz = d / 9 - 1;
-    const unsigned m = nb_node(q, N, dx, dy, dz);
-    T xv[FI * K];
-#pragma unroll
-    for (int col = 0; col < FI * K; ++col) {
-      if constexpr (BUF)
-        xv[col] = buf_load<T>(xr, m * (unsigned)sizeof(T), (unsigned)(col * nn * sizeof(T)));
-      else
-        xv[col] = x[(size_t)col * nn + m];
+  if constexpr (fine_row_loop<T, FO, FI>()) {
+#pragma unroll 1
+    for (int r = 0; r < 9; ++r) {
+      const int dy = r % 3 - 1, dz = r / 3 - 1;
+      const unsigned ry = dy < 0 ? q.jm : (dy > 0 ? q.jp : q.j);
+      const unsigned rz = dz < 0 ? q.km : (dz > 0 ? q.kp : q.k);
+      const unsigned rowbase = N * (ry + N * rz);
+      fine_neighbour<T, FO, FI, K, BUF>(rowbase + q.im, -1, dy, dz, nn, se, kr, xr, x, acc);
+      fine_neighbour<T, FO, FI, K, BUF>(rowbase + q.i, 0, dy, dz, nn, se, kr, xr, x, acc);
+      fine_neighbour<T, FO, FI, K, BUF>(rowbase + q.ip, 1, dy, dz, nn, se, kr, xr, x, acc);
     }
-    T blk[FO * FI];
+  } else {
 #pragma unroll
-    for (int t = 0; t < FO * FI; ++t) blk[t] = T(0);
-#pragma unroll
-    for (int c = 0; c < 8; ++c) {
-      const int mx = (c & 1) + dx, my = ((c >> 1) & 1) + dy, mz = ((c >> 2) & 1) + dz;
-      if (mx < 0 || mx > 1 || my < 0 || my > 1 || mz < 0 || mz > 1) continue;
-      const int lm = mx + 2 * my + 4 * mz;
-#pragma unroll
-      for (int fo = 0; fo < FO; ++fo)
-#pragma unroll
-        for (int fi = 0; fi < FI; ++fi)
-          blk[fo * FI + fi] += se[c] * kr[(c * FO + fo) * (8 * FI) + lm * FI + fi];
+    for (int d = 0; d < 27; ++d) {
+      const int dx = d % 3 - 1, dy = (d / 3) % 3 - 1, dz = d / 9 - 1;
+      fine_neighbour<T, FO, FI, K, BUF>(nb_node(q, N, dx, dy, dz), dx, dy, dz, nn, se, kr, xr, x, acc);
     }
-#pragma unroll
-    for (int fi = 0; fi < FI; ++fi)
-#pragma unroll
-      for (int kk = 0; kk < K; ++kk)
-#pragma unroll
-        for (int fo = 0; fo < FO; ++fo) acc[fo * K + kk] += blk[fo * FI + fi] * xv[fi * K + kk];
   }
   epilogue<T, FO, K, CHEBY>(n, nn, acc, a);
 }

@@ -99,18 +99,29 @@ void col_reduce(size_t nn, int F, int K, const T* v, double* out, double* work, 
 // unrolled loops is unconditional and independent (memory-level
 // parallelism).  Grid (slices, F*K): each block stays on one column, so the
 // load column k = blockIdx.y % K and its coefficients are block-uniform.
+template <typename T> struct Vec2;
+template <> struct Vec2<float> { using type = float2; };
+template <> struct Vec2<double> { using type = double2; };
+
+// Two consecutive nodes per thread and load (nn is even: N is even), which
+// doubles the bytes in flight per instruction.
 template <typename T, int J>
 __global__ __launch_bounds__(256) void k_arnoldi_dots(unsigned nn, const T* __restrict__ V, size_t vstride,
                                                       const T* __restrict__ w, double* __restrict__ part) {
+  using V2 = typename Vec2<T>::type;
   __shared__ double lds4[4];
   const size_t co = (size_t)blockIdx.y * nn;
+  const unsigned nh = nn / 2;
   double acc[J];
 #pragma unroll
   for (int i = 0; i < J; ++i) acc[i] = 0.0;
-  for (unsigned n = blockIdx.x * 256 + threadIdx.x; n < nn; n += gridDim.x * 256) {
-    const double wv = (double)w[co + n];
+  for (unsigned h = blockIdx.x * 256 + threadIdx.x; h < nh; h += gridDim.x * 256) {
+    const V2 wv = reinterpret_cast<const V2*>(w + co)[h];
 #pragma unroll
-    for (int i = 0; i < J; ++i) acc[i] += (double)V[i * vstride + co + n] * wv;
+    for (int i = 0; i < J; ++i) {
+      const V2 v = reinterpret_cast<const V2*>(V + i * vstride + co)[h];
+      acc[i] += (double)v.x * (double)wv.x + (double)v.y * (double)wv.y;
+    }
   }
   const size_t base = ((size_t)blockIdx.y * gridDim.x + blockIdx.x) * J;
 #pragma unroll
@@ -125,9 +136,11 @@ template <typename T, int J, bool DOTS>
 __global__ __launch_bounds__(256) void k_arnoldi_update(unsigned nn, int K, const T* __restrict__ V, size_t vstride,
                                                         T* __restrict__ w, const double* __restrict__ hin,
                                                         double* __restrict__ part) {
+  using V2 = typename Vec2<T>::type;
   __shared__ double lds4[4];
   const int kk = blockIdx.y % K;
   const size_t co = (size_t)blockIdx.y * nn;
+  const unsigned nh = nn / 2;
   double h[J];
 #pragma unroll
   for (int i = 0; i < J; ++i) h[i] = hin[i * K + kk];
@@ -135,22 +148,27 @@ __global__ __launch_bounds__(256) void k_arnoldi_update(unsigned nn, int K, cons
 #pragma unroll
   for (int i = 0; i < (DOTS ? J : 1); ++i) acc[i] = 0.0;
   double nrm = 0.0;
-  for (unsigned n = blockIdx.x * 256 + threadIdx.x; n < nn; n += gridDim.x * 256) {
-    T vv[DOTS ? J : 1];
-    double wv = (double)w[co + n];
+  V2* w2 = reinterpret_cast<V2*>(w + co);
+  for (unsigned hh = blockIdx.x * 256 + threadIdx.x; hh < nh; hh += gridDim.x * 256) {
+    V2 vv[DOTS ? J : 1];
+    const V2 w0 = w2[hh];
+    double wx = (double)w0.x, wy = (double)w0.y;
 #pragma unroll
     for (int i = 0; i < J; ++i) {
-      const T v = V[i * vstride + co + n];
+      const V2 v = reinterpret_cast<const V2*>(V + i * vstride + co)[hh];
       if constexpr (DOTS) vv[i] = v;
-      wv -= h[i] * (double)v;
+      wx -= h[i] * (double)v.x;
+      wy -= h[i] * (double)v.y;
     }
-    const T wt = (T)wv;
-    w[co + n] = wt;
-    const double wr = (double)wt;
-    nrm += wr * wr;
+    V2 wt;
+    wt.x = (T)wx;
+    wt.y = (T)wy;
+    w2[hh] = wt;
+    const double rx = (double)wt.x, ry = (double)wt.y;
+    nrm += rx * rx + ry * ry;
     if constexpr (DOTS) {
 #pragma unroll
-      for (int i = 0; i < J; ++i) acc[i] += (double)vv[i] * wr;
+      for (int i = 0; i < J; ++i) acc[i] += (double)vv[i].x * rx + (double)vv[i].y * ry;
     }
   }
   constexpr int NV = (DOTS ? J : 0) + 1;
@@ -166,7 +184,7 @@ __global__ __launch_bounds__(256) void k_arnoldi_update(unsigned nn, int K, cons
   if (threadIdx.x == 0) part[base + NV - 1] = s;
 }
 
-constexpr int kFusedMaxJ = 16;
+constexpr int kFusedMaxJ = 12;
 
 template <typename T, int J>
 void launch_dots_J(dim3 g, hipStream_t st, unsigned nn, const T* V, size_t vs, const T* w, double* part) {
