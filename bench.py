@@ -22,20 +22,47 @@ sys.path.insert(0, ROOT)
 
 import numpy as np  # noqa: E402
 
-# dominant-kernel algorithmic work per node (fine levels, stencil formulation):
-# flops = 2 (64 FO FI + 27 FO FI K); bytes = (FI + FO) K w + w (x, y, s once)
+# Algorithmic work per node of a fine-level operator launch, by timing label
+# (fine_<block>_k<K>_<f32|f64>[_cheby]).  Stencil form: flops =
+# 2 (64 FO FI + 27 FO FI K) (block build + apply).  Bytes: the input columns
+# x (FI K), the scale s, the output y (FO K), plus the y_in read (FO K) of the
+# blocks that run as residual updates (A, B, S: y = y_in - A x); the full
+# operator runs as y = A x.  The fused Chebyshev step adds the Jacobi block
+# (FO^2), the iterate read and write (2 FO K) and the new correction
+# (FO K), with 2 FO^2 K + 4 FO K flops.
 OPS = {"full": (4, 4), "A": (3, 3), "B": (1, 3), "S": (1, 1)}
 
 
 def per_node(name):
-    # name like fine_A_k9_f32
-    _, op, k, prec = name.split("_")
+    parts = name.split("_")
+    op, k, prec = parts[1], parts[2], parts[3]
+    cheby = len(parts) > 4 and parts[4] == "cheby"
     fo, fi = OPS[op]
     K = int(k[1:])
     w = 4 if prec == "f32" else 8
     flops = 2 * (64 * fo * fi + 27 * fo * fi * K)
-    nbytes = (fi + fo) * K * w + w
-    return flops, nbytes, prec
+    words = fi * K + 1 + fo * K + (fo * K if op != "full" else 0)
+    if cheby:
+        flops += 2 * fo * fo * K + 4 * fo * K
+        words += fo * fo + 3 * fo * K
+    return flops, words * w, prec
+
+
+def measured_traffic(label):
+    """HBM bytes per launch of a timing label from the committed counter runs
+    (FETCH_SIZE and WRITE_SIZE, each scaled by a plain copy kernel), or None
+    when the kernel source has changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    with open(os.path.join(ROOT, rec["source"]), "rb") as f:
+        if hashlib.sha256(f.read()).hexdigest() != rec["source_sha256"]:
+            return None
+    k = rec["kernels"].get(label)
+    return None if k is None else k["bytes_per_launch"]
 
 
 def cpu_baseline(n_sample=16):
@@ -182,14 +209,15 @@ def main():
             ai = fl / by
             peak_tf = 78.6 if p == "f64" else 157.3
             ridge = peak_tf * 1e12 / 8e12
+            traffic = measured_traffic(name)
             if ai > ridge:
                 result["roofline"] = {"bound": "alu", "achieved": flops / avg_s / 1e12, "peak": peak_tf,
                                       "unit": "TFLOP/s", "frac": flops / avg_s / 1e12 / peak_tf,
-                                      "traffic": None, "kernel": name, "avg_ms": avg_s * 1e3,
+                                      "traffic": traffic, "kernel": name, "avg_ms": avg_s * 1e3,
                                       "algorithmic_bytes": nbytes, "algorithmic_flops": flops}
             else:
                 result["roofline"] = {"bound": "hbm", "achieved": nbytes / avg_s / 1e9, "peak": 8000.0,
-                                      "unit": "GB/s", "frac": nbytes / avg_s / 8e12, "traffic": None,
+                                      "unit": "GB/s", "frac": nbytes / avg_s / 8e12, "traffic": traffic,
                                       "kernel": name, "avg_ms": avg_s * 1e3,
                                       "algorithmic_bytes": nbytes, "algorithmic_flops": flops}
         result["kernel_ms_per_step"] = {k: v[1] / args.steps for k, v in sorted(ktimes.items())}

@@ -210,7 +210,8 @@ int phz_coarse_apply(phz_ctx* ctx, int level, int op, int nrhs,
  * context's stream.  Enabling (or disabling) clears the totals.
  * phz_get_kernel_timing writes one line "name count total_ms" per kernel
  * class into buf (NUL-terminated, truncated to cap) and the full length to
- * *len.  Names: fine_{full,A,B,S}_k{1,9}_f{64,32}, coarse_{A,S}_f{64,32},
+ * *len.  Names: fine_{full,A,B,S}_k{1,9}_f{64,32} (suffix _cheby for the
+ * launches that fuse a Chebyshev smoothing step), coarse_{A,S}_f{64,32},
  * precond_f{64,32}, arnoldi_cgs2_f{64,32}. */
 int phz_kernel_timing(phz_ctx* ctx, int enable);
 int phz_get_kernel_timing(phz_ctx* ctx, char* buf, int cap, int* len);

@@ -59,6 +59,18 @@ __device__ __forceinline__ unsigned nb_node(const NodeIdx& q, unsigned N, int dx
   return pick(dx, q.im, q.i, q.ip) + N * (pick(dy, q.jm, q.j, q.jp) + N * pick(dz, q.km, q.k, q.kp));
 }
 
+// Workgroups are handed to the eight XCDs round-robin (workgroup b runs on
+// XCD b % 8), and each XCD has its own L2.  A gather whose neighbours sit in
+// the neighbouring workgroups (the rows y +- 1) would therefore fetch every
+// row into three L2s.  This maps the hardware workgroup id to a logical one
+// so that each XCD owns one contiguous range of logical workgroups (a slab
+// of whole rows and planes): a bijection on [0, nb) for any nb.
+__device__ __forceinline__ unsigned xcd_block(unsigned b, unsigned nb) {
+  constexpr unsigned X = 8;
+  const unsigned q = nb / X, r = nb % X, x = b % X, i = b / X;
+  return x * q + (x < r ? x : r) + i;
+}
+
 template <int OP> struct OpFields;
 template <> struct OpFields<0> { static constexpr int FO = 4, FI = 4; };
 template <> struct OpFields<1> { static constexpr int FO = 3, FI = 3; };
@@ -184,7 +196,7 @@ __global__ __launch_bounds__(128) void k_fine_apply(unsigned N, const T* __restr
   for (int t = threadIdx.x; t < NK; t += blockDim.x) kr[t] = kref[t];
   __syncthreads();
   const unsigned nn = N * N * N;
-  const unsigned n = blockIdx.x * blockDim.x + threadIdx.x;
+  const unsigned n = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   if (n >= nn) return;
   const NodeIdx q = node_idx(n, N);
   // scale of the element whose corner c is this node (origin n - c)
@@ -229,7 +241,7 @@ template <typename T, int F, int K, int KK, bool CHEBY, bool BUF>
 __global__ __launch_bounds__(256) void k_stencil_apply(unsigned N, const T* __restrict__ S,
                                                        const T* __restrict__ x, OpArgs<T> a) {
   const unsigned nn = N * N * N;
-  const unsigned n = blockIdx.x * blockDim.x + threadIdx.x;
+  const unsigned n = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   if (n >= nn) return;
   const int k0 = KK == K ? 0 : (int)blockIdx.y;
   const NodeIdx q = node_idx(n, N);
@@ -440,7 +452,7 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_restrict(unsigned Nc, int ncol, const T* __restrict__ rf, T* __restrict__ rc) {
   const unsigned Nf = 2 * Nc;
   const unsigned nc = Nc * Nc * Nc, nf = Nf * Nf * Nf;
-  const unsigned I = blockIdx.x * blockDim.x + threadIdx.x;
+  const unsigned I = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   if (I >= nc) return;
   const unsigned ic = I % Nc, jc = (I / Nc) % Nc, kc = I / (Nc * Nc);
   const unsigned xs[3] = {(2 * ic + Nf - 1) % Nf, 2 * ic, 2 * ic + 1};
@@ -467,7 +479,7 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_prolong(unsigned Nc, int ncol, const T* __restrict__ xc, T* __restrict__ xf) {
   const unsigned Nf = 2 * Nc;
   const unsigned nc = Nc * Nc * Nc, nf = Nf * Nf * Nf;
-  const unsigned i = blockIdx.x * blockDim.x + threadIdx.x;
+  const unsigned i = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   if (i >= nf) return;
   const unsigned fi = i % Nf, fj = (i / Nf) % Nf, fk = i / (Nf * Nf);
   const unsigned bi = fi >> 1, bj = fj >> 1, bk = fk >> 1;

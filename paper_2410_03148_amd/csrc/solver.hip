@@ -308,17 +308,25 @@ template <typename T> static Work<T>& work_of(phz_ctx* c);
 template <> Work<double>& work_of<double>(phz_ctx* c) { return c->w64; }
 template <> Work<float>& work_of<float>(phz_ctx* c) { return c->w32; }
 
-// y = beta*yin + alpha*A_l x
-static const char* kOpNames[4][2][2] = {
-    {{"fine_full_k1_f64", "fine_full_k1_f32"}, {"fine_full_k9_f64", "fine_full_k9_f32"}},
-    {{"fine_A_k1_f64", "fine_A_k1_f32"}, {"fine_A_k9_f64", "fine_A_k9_f32"}},
-    {{"fine_B_k1_f64", "fine_B_k1_f32"}, {"fine_B_k9_f64", "fine_B_k9_f32"}},
-    {{"fine_S_k1_f64", "fine_S_k1_f32"}, {"fine_S_k9_f64", "fine_S_k9_f32"}}};
+// timing labels of the fine operator launches: block, load columns,
+// precision, and "_cheby" for the launches with the fused smoothing step
+static const char* fine_op_name(int op, int K, bool f32, bool cheby) {
+  static const char* names[4][2][2][2] = {
+      {{{"fine_full_k1_f64", "fine_full_k1_f64_cheby"}, {"fine_full_k1_f32", "fine_full_k1_f32_cheby"}},
+       {{"fine_full_k9_f64", "fine_full_k9_f64_cheby"}, {"fine_full_k9_f32", "fine_full_k9_f32_cheby"}}},
+      {{{"fine_A_k1_f64", "fine_A_k1_f64_cheby"}, {"fine_A_k1_f32", "fine_A_k1_f32_cheby"}},
+       {{"fine_A_k9_f64", "fine_A_k9_f64_cheby"}, {"fine_A_k9_f32", "fine_A_k9_f32_cheby"}}},
+      {{{"fine_B_k1_f64", "fine_B_k1_f64_cheby"}, {"fine_B_k1_f32", "fine_B_k1_f32_cheby"}},
+       {{"fine_B_k9_f64", "fine_B_k9_f64_cheby"}, {"fine_B_k9_f32", "fine_B_k9_f32_cheby"}}},
+      {{{"fine_S_k1_f64", "fine_S_k1_f64_cheby"}, {"fine_S_k1_f32", "fine_S_k1_f32_cheby"}},
+       {{"fine_S_k9_f64", "fine_S_k9_f64_cheby"}, {"fine_S_k9_f32", "fine_S_k9_f32_cheby"}}}};
+  return names[op][K == 9][f32][cheby];
+}
 
 // fine-level operator launch with optional timing
 template <typename T>
 static void op_apply_args(phz_ctx* c, int op, int K, const T* x, const OpArgs<T>& a, bool cheby) {
-  const long slot = time_begin(c, kOpNames[op][K == 9][sizeof(T) == 4]);
+  const long slot = time_begin(c, fine_op_name(op, K, sizeof(T) == 4, cheby));
   fine_apply<T>(op, K, c->N, s_of<T>(c), kref_of<T>(c, op), x, a, cheby, c->stream);
   time_end(c, slot);
 }
