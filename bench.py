@@ -3,12 +3,16 @@
 One step = the whole hot path on device-resident input: level set -> element
 scales -> load vectors -> preconditioner set-up (Galerkin multigrid,
 Chebyshev bounds, coarsest factorisation) -> SCP-GMRES for all nine loads
-(one 9-column block, FP32 operator / smoothers / Krylov basis inside FP64
-iterative refinement to a true FP64 residual of 1e-10) -> effective tensors
--> figures of merit -> density sensitivities of d_h -> one Hamilton-Jacobi
-step of the level set.
+(one 9-column block; by default the fine-level operators as split-BF16
+element contractions on the matrix cores with FP32 vectors and Krylov basis,
+inside FP64 iterative refinement to a true FP64 residual of 1e-10) ->
+effective tensors -> figures of merit -> density sensitivities of d_h -> one
+Hamilton-Jacobi step of the level set.
 
-Prints one JSON line (see the design doc for every figure's definition).
+Prints one JSON line: the throughput, the dominant kernel against its
+roofline, the outer operator's bandwidth, the other solve forms on the same
+cell (FP32 operators in FP64 refinement, FP64 batched, FP64 one load at a
+time) and the CPU oracle on a bounded sample.
 """
 import argparse
 import json
@@ -23,24 +27,32 @@ sys.path.insert(0, ROOT)
 import numpy as np  # noqa: E402
 
 # Algorithmic work per node of a fine-level operator launch, by timing label
-# (fine_<block>_k<K>_<f32|f64>[_cheby]).  Stencil form: flops =
-# 2 (64 FO FI + 27 FO FI K) (block build + apply).  Bytes: the input columns
-# x (FI K), the scale s, the output y (FO K), plus the y_in read (FO K) of the
+# (fine_<block>_k<K>_<f32|f64>[_cheby] for the float gather kernels,
+# elem_<block>_k<K>_bf16x<T>[_cheby] for the element contraction on MFMA).
+# Gather form: flops = 2 (64 FO FI + 27 FO FI K) (block build + apply).
+# Element form: T split products of the element block, 2 T (8 FO)(8 FI) K per
+# element (one element per node).  Bytes, both forms: the input columns x
+# (FI K), the scale s, the output y (FO K), plus the y_in read (FO K) of the
 # blocks that run as residual updates (A, B, S: y = y_in - A x); the full
 # operator runs as y = A x.  The fused Chebyshev step adds the Jacobi block
-# (FO^2), the iterate read and write (2 FO K) and the new correction
-# (FO K), with 2 FO^2 K + 4 FO K flops.
+# (FO^2), the iterate read and write (2 FO K) and the new correction (FO K),
+# with 2 FO^2 K + 4 FO K flops.
 OPS = {"full": (4, 4), "A": (3, 3), "B": (1, 3), "S": (1, 1)}
 
 
 def per_node(name):
     parts = name.split("_")
-    op, k, prec = parts[1], parts[2], parts[3]
+    form, op, k, prec = parts[0], parts[1], parts[2], parts[3]
     cheby = len(parts) > 4 and parts[4] == "cheby"
     fo, fi = OPS[op]
     K = int(k[1:])
-    w = 4 if prec == "f32" else 8
-    flops = 2 * (64 * fo * fi + 27 * fo * fi * K)
+    if form == "elem":
+        terms = int(prec[len("bf16x"):])
+        w = 4
+        flops = 2 * terms * (8 * fo) * (8 * fi) * K
+    else:
+        w = 4 if prec == "f32" else 8
+        flops = 2 * (64 * fo * fi + 27 * fo * fi * K)
     words = fi * K + 1 + fo * K + (fo * K if op != "full" else 0)
     if cheby:
         flops += 2 * fo * fo * K + 4 * fo * K
@@ -58,11 +70,13 @@ def measured_traffic(label):
         return None
     with open(path) as f:
         rec = json.load(f)
-    with open(os.path.join(ROOT, rec["source"]), "rb") as f:
-        if hashlib.sha256(f.read()).hexdigest() != rec["source_sha256"]:
-            return None
     k = rec["kernels"].get(label)
-    return None if k is None else k["bytes_per_launch"]
+    if k is None:
+        return None
+    with open(os.path.join(ROOT, k["source"]), "rb") as f:
+        if hashlib.sha256(f.read()).hexdigest() != k["source_sha256"]:
+            return None
+    return k["bytes_per_launch"]
 
 
 def cpu_baseline(n_sample=16):
@@ -88,7 +102,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=128)
     ap.add_argument("--solid-fraction", type=float, default=0.3)
-    ap.add_argument("--precision", choices=["fp32ir", "fp64"], default="fp32ir")
+    ap.add_argument("--precision", choices=["bf16x3ir", "fp32ir", "fp64"], default="bf16x3ir")
     ap.add_argument("--restart", type=int, default=12)
     ap.add_argument("--vcycles-a", type=int, default=2)
     ap.add_argument("--no-sequential", action="store_true", help="skip the plain FP64 sequential comparison")
@@ -115,12 +129,13 @@ def main():
     mat = synth.material_workload()
     phi = synth.grf_levelset(n, seed=2410, solid_fraction=args.solid_fraction)
     phi_d = torch.tensor(phi, device=dev)
-    prec = P.PHZ_FP32_IR if args.precision == "fp32ir" else P.PHZ_FP64
+    prec = {"bf16x3ir": P.PHZ_BF16X3_IR, "fp32ir": P.PHZ_FP32_IR, "fp64": P.PHZ_FP64}[args.precision]
 
     # solver settings per form (restart / V-cycles per A-block application
     # picked by a sweep on this workload); every form stops at a true FP64
     # residual of 1e-10 per load
     forms = {
+        "bf16x3ir": dict(precision=P.PHZ_BF16X3_IR, batched=1, restart=args.restart, vcycles_a=args.vcycles_a),
         "fp32ir": dict(precision=P.PHZ_FP32_IR, batched=1, restart=args.restart, vcycles_a=args.vcycles_a),
         "fp64": dict(precision=P.PHZ_FP64, batched=1, restart=15, vcycles_a=2),
         "fp64_sequential": dict(precision=P.PHZ_FP64, batched=0, restart=30, vcycles_a=2),
@@ -184,7 +199,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32" if prec == P.PHZ_FP32_IR else "f64",
+        "dtype": {"bf16x3ir": "bf16x3", "fp32ir": "f32", "fp64": "f64"}[args.precision],
         "data": "synthetic",
         "config": {"workload": f"{n}^3 periodic GRF level set (seed 2410, corr 0.1, solid {args.solid_fraction}), "
                                f"PZT-like base, 9 loads batched, GMRES({forms[args.precision]['restart']})+SCP/GMG "
@@ -193,25 +208,27 @@ def main():
                    "precision": args.precision, "status": status,
                    "iterations_max": max(stats["iterations"]), "refinements": stats["refinements"],
                    "true_residual_max": max(stats["true_residual"]),
-                   "setup_ms": stats["setup_ms"], "solve_ms": stats["solve_ms"]},
+                   "setup_ms": stats["setup_ms"], "solve_ms": stats["solve_ms"],
+                   "mfma_tiles_full_A_B_S": stats["elem_tile"]},
     }
 
     # dominant single kernel from the live event timing of the timed steps
-    single = {k: v for k, v in ktimes.items() if k.startswith("fine_") or k.startswith("coarse_")}
+    single = {k: v for k, v in ktimes.items() if k.startswith(("fine_", "elem_", "coarse_"))}
     if single:
         name = max(single, key=lambda k: single[k][1])
         cnt, tot = single[name]
         avg_s = tot / cnt * 1e-3
-        if name.startswith("fine_"):
+        if name.startswith(("fine_", "elem_")):
             fl, by, p = per_node(name)
             flops = fl * n ** 3
             nbytes = by * n ** 3
             ai = fl / by
-            peak_tf = 78.6 if p == "f64" else 157.3
+            # published MI355X peaks: fp64 78.6, fp32 vector 157.3, dense bf16 MFMA 2500 TFLOP/s
+            peak_tf = {"f64": 78.6, "f32": 157.3}.get(p, 2500.0)
             ridge = peak_tf * 1e12 / 8e12
             traffic = measured_traffic(name)
             if ai > ridge:
-                result["roofline"] = {"bound": "alu", "achieved": flops / avg_s / 1e12, "peak": peak_tf,
+                result["roofline"] = {"bound": "mfma" if name.startswith("elem_") else "alu", "achieved": flops / avg_s / 1e12, "peak": peak_tf,
                                       "unit": "TFLOP/s", "frac": flops / avg_s / 1e12 / peak_tf,
                                       "traffic": traffic, "kernel": name, "avg_ms": avg_s * 1e3,
                                       "algorithmic_bytes": nbytes, "algorithmic_flops": flops}
@@ -223,7 +240,7 @@ def main():
         result["kernel_ms_per_step"] = {k: v[1] / args.steps for k, v in sorted(ktimes.items())}
         # the outer operator apply (all four fields, nine loads) as achieved
         # algorithmic HBM bandwidth
-        ops = {k: v for k, v in ktimes.items() if k.startswith("fine_full_k9")}
+        ops = {k: v for k, v in ktimes.items() if k.startswith(("fine_full_k9", "elem_full_k9"))}
         if ops:
             name = max(ops, key=lambda k: ops[k][1])
             cnt, tot = ops[name]
@@ -234,7 +251,9 @@ def main():
 
     if not args.no_compare and prec != P.PHZ_FP64:
         cmp = {}
-        for form in ("fp64", "fp64_sequential"):
+        for form in ("fp32ir", "fp64", "fp64_sequential"):
+            if form == args.precision:
+                continue
             if form == "fp64_sequential" and args.no_sequential:
                 continue
             c64 = make_ctx(form)
@@ -246,7 +265,7 @@ def main():
                          "iterations_max": max(s64["iterations"]), "restart": forms[form]["restart"],
                          "rel_err_of_mixed": errs, "max_rel_err_of_mixed": max(errs.values())}
             log(f"{form} comparison done")
-        result["fp64_compare"] = cmp
+        result["compare"] = cmp
 
     if not args.no_cpu:
         log("cpu oracle baseline (16^3 sample)")

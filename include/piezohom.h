@@ -71,6 +71,16 @@ extern "C" {
 #define PHZ_FP32_IR 1    /* float32 operator, smoothers and Krylov basis inside
                             float64 iterative refinement; float64 residuals,
                             Hessenberg/Givens, coarse solve and reductions */
+#define PHZ_BF16X3_IR 2  /* as PHZ_FP32_IR, with the fine-level operators of
+                            the float solve computed as element contractions
+                            on the matrix cores in split-BF16 arithmetic: each
+                            float32 value x = hi + lo with hi, lo bfloat16, and
+                            products hi*hi + hi*lo + lo*hi accumulated in
+                            float32 (about 2^-16 relative per product).  The
+                            preconditioner's fine blocks always, the float
+                            GMRES operator if bf16_outer.  Float vectors stay
+                            float32; refinement, residuals, Hessenberg/Givens,
+                            coarse solve and reductions stay float64. */
 
 /* operator blocks for phz_apply (Sec. 2.5 block structure) */
 #define PHZ_OP_FULL 0    /* calA = [[A, B^T], [B, -C]] on [n][4][k]        */
@@ -105,6 +115,18 @@ typedef struct {
     int max_refine;         /* FP32_IR: cap on refinement steps, each one float
                                GMRES cycle of at most `restart` steps (default 50) */
     int verbose;            /* 0 silent; 1 per-solve summary on stderr          */
+    int bf16_terms;         /* PHZ_BF16X3_IR: 3 split products (default) or 1
+                               (hi*hi only, about 2^-8 relative)               */
+    int bf16_outer;         /* PHZ_BF16X3_IR: 1 (default) also runs the float
+                               GMRES operator on the matrix cores, 0 only the
+                               preconditioner's fine blocks                    */
+    int elem_tile;          /* PHZ_BF16X3_IR: workgroup tile of the element
+                               contraction, -1 (default) = timed choice per
+                               block at the first solve (autotune: every tile
+                               that divides N and the float32 gather kernel;
+                               a block whose gather kernel is faster stays on
+                               it), else an index in [0, 3): 8x8x4, 16x4x4,
+                               16x8x2 nodes, used for every block             */
 } phz_options;
 
 typedef struct {
@@ -117,6 +139,10 @@ typedef struct {
     double solve_ms;        /* whole phz_solve wall time                        */
     int mg_levels;          /* levels used                                      */
     double cheb_lambda[16]; /* lambda_max estimates, A then S_bar per level     */
+    int elem_tile[4];       /* PHZ_BF16X3_IR: tile used per fine block (full, A,
+                               B, S_bar), -1 where the block is not on MFMA
+                               (bf16_outer = 0, no tile divides N, or the
+                               float32 gather kernel timed faster)            */
 } phz_stats;
 
 typedef struct {
@@ -193,7 +219,10 @@ int phz_hj_step(phz_ctx* ctx, const double* velocity, double cfl,
  * nrhs in {1, 9} columns, device pointers.  These low-level entry points use
  * the library's internal structure-of-arrays layout [field][load][N^3]
  * (one contiguous column of node values per (field, load)).
- * precision PHZ_FP64 (double buffers) or PHZ_FP32_IR (float buffers). */
+ * precision PHZ_FP64 (double buffers), PHZ_FP32_IR (float buffers, float32
+ * gather kernel) or PHZ_BF16X3_IR (float buffers, nrhs = 9, the split-BF16
+ * element contraction with the context's bf16_terms and elem_tile; N must be
+ * a multiple of the tile). */
 int phz_apply(phz_ctx* ctx, int op, int nrhs, int precision,
               const void* x, void* y);
 /* Apply the SCP preconditioner z = P^-1 r (device, [4][nrhs][N^3], float64),

@@ -22,6 +22,7 @@ PHZ_OK = 0
 PHZ_NOT_CONVERGED = 1
 PHZ_FP64 = 0
 PHZ_FP32_IR = 1
+PHZ_BF16X3_IR = 2
 OP_FULL, OP_A, OP_B, OP_SBAR = 0, 1, 2, 3
 
 
@@ -35,14 +36,15 @@ class phz_options(C.Structure):
                 ("max_iters", C.c_int), ("rtol", C.c_double), ("cheby_degree", C.c_int),
                 ("mg_levels", C.c_int), ("smooth_width", C.c_double), ("vcycles_a", C.c_int),
                 ("vcycles_s", C.c_int), ("inner_rtol", C.c_double), ("max_refine", C.c_int),
-                ("verbose", C.c_int)]
+                ("verbose", C.c_int), ("bf16_terms", C.c_int), ("bf16_outer", C.c_int),
+                ("elem_tile", C.c_int)]
 
 
 class phz_stats(C.Structure):
     _fields_ = [("iterations", C.c_int * 9), ("restarts", C.c_int * 9), ("refinements", C.c_int),
                 ("true_residual", C.c_double * 9), ("flux_energy_defect", C.c_double),
                 ("setup_ms", C.c_double), ("solve_ms", C.c_double), ("mg_levels", C.c_int),
-                ("cheb_lambda", C.c_double * 16)]
+                ("cheb_lambda", C.c_double * 16), ("elem_tile", C.c_int * 4)]
 
 
 class phz_foms_t(C.Structure):
@@ -235,7 +237,7 @@ class Context:
             "refinements": s.refinements, "true_residual": list(s.true_residual),
             "flux_energy_defect": s.flux_energy_defect, "setup_ms": s.setup_ms,
             "solve_ms": s.solve_ms, "mg_levels": s.mg_levels,
-            "cheb_lambda": list(s.cheb_lambda),
+            "cheb_lambda": list(s.cheb_lambda), "elem_tile": list(s.elem_tile),
         }
 
     def history(self, load):

@@ -15,7 +15,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libpiezohom.so")
-SOURCES = ["ops.hip", "vec.hip", "solver.hip"]
+SOURCES = ["ops.hip", "elem.hip", "vec.hip", "solver.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

@@ -48,6 +48,18 @@ template <typename T>
 void fine_apply(int op, int nrhs, int N, const T* s, const T* kref, const T* x, const OpArgs<T>& a,
                 bool cheby, hipStream_t st);
 
+// Fine-level operator as an element contraction on MFMA in split-BF16
+// arithmetic (elem.hip), FP32 vectors, nine load columns.  kop holds the op's
+// reference block padded to 32 x 32 and split into bf16 hi and lo in MFMA
+// operand order (2048 values from elem_operand_host).  terms: 3 (hi*hi +
+// hi*lo + lo*hi) or 1 (hi*hi).  tile: a tile-shape index < elem_tile_count()
+// with elem_tile_fits(N, tile).
+int elem_tile_count();
+bool elem_tile_fits(int N, int tile);
+void elem_operand_host(int op, const double* kref, unsigned short* out);
+void elem_apply(int op, int nrhs, int N, int terms, int tile, const float* s, const void* kop, const float* x,
+                const OpArgs<float>& a, bool cheby, hipStream_t st);
+
 // Coarse-level apply with assembled 27-point node stencils S laid out
 // structure-of-arrays [(d*F + fo)*F + fi][node].
 template <typename T>

@@ -21,6 +21,7 @@
 #include <map>
 #include <memory>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "common.hpp"
@@ -106,6 +107,12 @@ struct phz_ctx {
   phz::RefElement ref;
   phz::DevBuf<double> kref_full, kref_A, kref_B, kref_S, F0d;
   phz::DevBuf<float> kref32_full, kref32_A, kref32_B, kref32_S;
+  // split-BF16 MFMA operands of the four fine blocks, their tile choice
+  // (-1 not yet chosen, -2 none divides N) and whether the block runs on
+  // MFMA (the timed choice may keep the float32 gather kernel)
+  phz::DevBuf<unsigned short> kop[4];
+  int elem_tile[4] = {-1, -1, -1, -1};
+  bool elem_use[4] = {false, false, false, false};
 
   phz::DevBuf<double> phi, rho, s, grad_rho, tmp_nodes;
   phz::DevBuf<float> s32;
@@ -201,6 +208,13 @@ static void upload_reference(phz_ctx* c) {
   up32(c->kref32_A, R.A0, 24 * 24);
   up32(c->kref32_B, R.B0, 8 * 24);
   up32(c->kref32_S, R.S0, 8 * 8);
+  std::vector<unsigned short> ops(2048);
+  const double* krefs[4] = {R.K0, R.A0, R.B0, R.S0};
+  for (int op = 0; op < 4; ++op) {
+    elem_operand_host(op, krefs[op], ops.data());
+    c->kop[op].upload(ops.data(), ops.size(), st);
+    sync(c);
+  }
 }
 
 static void build_levels(phz_ctx* c, Hierarchy& H, int F, int op) {
@@ -323,14 +337,6 @@ static const char* fine_op_name(int op, int K, bool f32, bool cheby) {
   return names[op][K == 9][f32][cheby];
 }
 
-// fine-level operator launch with optional timing
-template <typename T>
-static void op_apply_args(phz_ctx* c, int op, int K, const T* x, const OpArgs<T>& a, bool cheby) {
-  const long slot = time_begin(c, fine_op_name(op, K, sizeof(T) == 4, cheby));
-  fine_apply<T>(op, K, c->N, s_of<T>(c), kref_of<T>(c, op), x, a, cheby, c->stream);
-  time_end(c, slot);
-}
-
 template <typename T>
 static OpArgs<T> plain_args(const T* yin, T* y, T alpha, T beta) {
   OpArgs<T> a;
@@ -339,6 +345,100 @@ static OpArgs<T> plain_args(const T* yin, T* y, T alpha, T beta) {
   a.alpha = alpha;
   a.beta = beta;
   return a;
+}
+
+// timing labels of the split-BF16 element-contraction launches
+static const char* elem_op_name(int op, bool three_terms, bool cheby) {
+  static const char* names[4][2][2] = {
+      {{"elem_full_k9_bf16x1", "elem_full_k9_bf16x1_cheby"}, {"elem_full_k9_bf16x3", "elem_full_k9_bf16x3_cheby"}},
+      {{"elem_A_k9_bf16x1", "elem_A_k9_bf16x1_cheby"}, {"elem_A_k9_bf16x3", "elem_A_k9_bf16x3_cheby"}},
+      {{"elem_B_k9_bf16x1", "elem_B_k9_bf16x1_cheby"}, {"elem_B_k9_bf16x3", "elem_B_k9_bf16x3_cheby"}},
+      {{"elem_S_k9_bf16x1", "elem_S_k9_bf16x1_cheby"}, {"elem_S_k9_bf16x3", "elem_S_k9_bf16x3_cheby"}}};
+  return names[op][three_terms][cheby];
+}
+
+// Time block `op` (zero input, nine columns: the cost does not depend on the
+// values) as the element contraction with every tile shape that divides N,
+// and as the float32 gather kernel.  Sets c->elem_tile[op] to the fastest
+// tile (-2 if none fits) and c->elem_use[op] to whether it beats the gather.
+static void autotune_elem(phz_ctx* c, int op) {
+  const int fo = op == 0 ? 4 : op == 1 ? 3 : 1, fi = op == 0 ? 4 : op == 3 ? 1 : 3;
+  DevBuf<float> xb, yb;
+  xb.alloc((size_t)fi * 9 * c->nn);
+  yb.alloc((size_t)fo * 9 * c->nn);
+  PHZ_HIP(hipMemsetAsync(xb.p, 0, xb.n * sizeof(float), c->stream));
+  const OpArgs<float> a = plain_args<float>(nullptr, yb.p, 1.0f, 0.0f);
+  hipEvent_t e0, e1;
+  PHZ_HIP(hipEventCreate(&e0));
+  PHZ_HIP(hipEventCreate(&e1));
+  auto timed = [&](auto&& launch) {
+    launch();
+    PHZ_HIP(hipEventRecord(e0, c->stream));
+    for (int r = 0; r < 3; ++r) launch();
+    PHZ_HIP(hipEventRecord(e1, c->stream));
+    PHZ_HIP(hipEventSynchronize(e1));
+    float ms = 0.0f;
+    PHZ_HIP(hipEventElapsedTime(&ms, e0, e1));
+    return ms;
+  };
+  int best = -2;
+  float best_ms = 0.0f;
+  for (int t = 0; t < elem_tile_count(); ++t) {
+    if (!elem_tile_fits(c->N, t)) continue;
+    const float ms = timed([&] {
+      elem_apply(op, 9, c->N, c->opt.bf16_terms, t, c->s32.p, c->kop[op].p, xb.p, a, false, c->stream);
+    });
+    if (best < 0 || ms < best_ms) {
+      best = t;
+      best_ms = ms;
+    }
+  }
+  const float gather_ms =
+      timed([&] { fine_apply<float>(op, 9, c->N, c->s32.p, kref_of<float>(c, op), xb.p, a, false, c->stream); });
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  c->elem_tile[op] = best;
+  c->elem_use[op] = best >= 0 && best_ms < gather_ms;
+}
+
+// Tile of the element contraction for block `op`: the option's choice, or
+// the autotuned one (timed once per context); -1 if no tile divides N.
+static int elem_tile_of(phz_ctx* c, int op) {
+  if (c->elem_tile[op] == -1) {
+    if (c->opt.elem_tile >= 0) {
+      c->elem_tile[op] = elem_tile_fits(c->N, c->opt.elem_tile) ? c->opt.elem_tile : -2;
+      c->elem_use[op] = c->elem_tile[op] >= 0;
+    } else {
+      autotune_elem(c, op);
+    }
+  }
+  return c->elem_tile[op] >= 0 ? c->elem_tile[op] : -1;
+}
+
+// Whether block `op` of a K-column float solve runs as the split-BF16 element
+// contraction: PHZ_BF16X3_IR, the preconditioner's blocks (A, B, S_bar) and
+// the full operator too if bf16_outer, nine columns, a tile dividing N, and
+// (with the timed tile choice) faster than the float32 gather kernel.
+static bool use_elem(phz_ctx* c, int op, int K) {
+  if (c->opt.precision != PHZ_BF16X3_IR || K != 9) return false;
+  if (op == 0 && !c->opt.bf16_outer) return false;
+  return elem_tile_of(c, op) >= 0 && c->elem_use[op];
+}
+
+// fine-level operator launch with optional timing
+template <typename T>
+static void op_apply_args(phz_ctx* c, int op, int K, const T* x, const OpArgs<T>& a, bool cheby) {
+  if constexpr (std::is_same<T, float>::value) {
+    if (use_elem(c, op, K)) {
+      const long slot = time_begin(c, elem_op_name(op, c->opt.bf16_terms == 3, cheby));
+      elem_apply(op, K, c->N, c->opt.bf16_terms, c->elem_tile[op], c->s32.p, c->kop[op].p, x, a, cheby, c->stream);
+      time_end(c, slot);
+      return;
+    }
+  }
+  const long slot = time_begin(c, fine_op_name(op, K, sizeof(T) == 4, cheby));
+  fine_apply<T>(op, K, c->N, s_of<T>(c), kref_of<T>(c, op), x, a, cheby, c->stream);
+  time_end(c, slot);
 }
 
 // y = beta*yin + alpha*A x on the fine level
@@ -471,7 +571,7 @@ static void setup_hierarchy(phz_ctx* c, Hierarchy& H) {
   }
   for (int l = 0; l < nl - 1; ++l) H.lv[l]->lmax = power_lmax(c, H, l);
   build_coarsest(c, H);
-  if (c->opt.precision == PHZ_FP32_IR) {
+  if (c->opt.precision != PHZ_FP64) {
     for (int l = 0; l < nl; ++l) {
       Level& L = *H.lv[l];
       if (L.S.p) {
@@ -497,6 +597,10 @@ static void drop_level_work_if_changed(phz_ctx* c, Work<T>& W) {
 
 static void setup_preconditioner(phz_ctx* c) {
   if (c->precond_ready) return;
+  for (int op = 0; op < 4; ++op) c->stats.elem_tile[op] = -1;
+  if (c->opt.precision == PHZ_BF16X3_IR)
+    for (int op = (c->opt.bf16_outer ? 0 : 1); op < 4; ++op)
+      c->stats.elem_tile[op] = use_elem(c, op, 9) ? c->elem_tile[op] : -1;
   build_levels(c, c->hA, 3, 1);
   build_levels(c, c->hS, 1, 3);
   drop_level_work_if_changed(c, c->w64);
@@ -887,7 +991,7 @@ static int do_solve(phz_ctx* c) {
   bool conv = true;
   if (c->opt.batched) {
     GmresResult g;
-    if (c->opt.precision == PHZ_FP32_IR) c->stats.refinements = solve_ir(c, 9, c->Bvec.p, c->X.p, rtol, 0, g);
+    if (c->opt.precision != PHZ_FP64) c->stats.refinements = solve_ir(c, 9, c->Bvec.p, c->X.p, rtol, 0, g);
     else solve_fp64(c, 9, c->Bvec.p, c->X.p, rtol, 0, g);
     for (int k = 0; k < 9; ++k) {
       c->stats.iterations[k] = g.iters[k];
@@ -902,7 +1006,7 @@ static int do_solve(phz_ctx* c) {
       extract_column(nn, L, c->Bvec.p, c->col_b.p, st);
       extract_column(nn, L, c->X.p, c->col_x.p, st);
       GmresResult g;
-      if (c->opt.precision == PHZ_FP32_IR) c->stats.refinements += solve_ir(c, 1, c->col_b.p, c->col_x.p, rtol, L, g);
+      if (c->opt.precision != PHZ_FP64) c->stats.refinements += solve_ir(c, 1, c->col_b.p, c->col_x.p, rtol, L, g);
       else solve_fp64(c, 1, c->col_b.p, c->col_x.p, rtol, L, g);
       insert_column(nn, L, c->col_x.p, c->X.p, st);
       c->stats.iterations[L] = g.iters[0];
@@ -926,7 +1030,7 @@ static int do_solve(phz_ctx* c) {
     int mx = 0;
     for (int k = 0; k < 9; ++k) mx = std::max(mx, c->stats.iterations[k]);
     std::fprintf(stderr, "[piezohom] N=%d %s %s: max iters %d, refinements %d, setup %.2f ms, solve %.2f ms\n",
-                 c->N, c->opt.precision == PHZ_FP32_IR ? "fp32-ir" : "fp64", c->opt.batched ? "batched" : "sequential",
+                 c->N, c->opt.precision == PHZ_BF16X3_IR ? "bf16x3-ir" : c->opt.precision == PHZ_FP32_IR ? "fp32-ir" : "fp64", c->opt.batched ? "batched" : "sequential",
                  mx, c->stats.refinements, c->stats.setup_ms, c->stats.solve_ms);
   }
   if (!conv) {
@@ -999,6 +1103,9 @@ void phz_default_options(phz_options* o) {
   o->inner_rtol = 1e-5;
   o->max_refine = 50;
   o->verbose = 0;
+  o->bf16_terms = 3;
+  o->bf16_outer = 1;
+  o->elem_tile = -1;
 }
 
 const char* phz_strerror(int status) {
@@ -1011,7 +1118,10 @@ const char* phz_strerror(int status) {
 const char* phz_last_error(const phz_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
 
 static int check_options(const phz_options* o, std::string& err) {
-  if (o->precision != PHZ_FP64 && o->precision != PHZ_FP32_IR) { err = "precision must be PHZ_FP64 or PHZ_FP32_IR"; return PHZ_E_INVALID; }
+  if (o->precision != PHZ_FP64 && o->precision != PHZ_FP32_IR && o->precision != PHZ_BF16X3_IR) { err = "precision must be PHZ_FP64, PHZ_FP32_IR or PHZ_BF16X3_IR"; return PHZ_E_INVALID; }
+  if (o->bf16_terms != 1 && o->bf16_terms != 3) { err = "bf16_terms must be 1 or 3"; return PHZ_E_INVALID; }
+  if (o->bf16_outer != 0 && o->bf16_outer != 1) { err = "bf16_outer must be 0 or 1"; return PHZ_E_INVALID; }
+  if (o->elem_tile < -1 || o->elem_tile >= elem_tile_count()) { err = "elem_tile must be -1 or a tile index"; return PHZ_E_INVALID; }
   if (o->restart < 1 || o->restart > kMaxRestart) { err = "restart must be in [1, 32]"; return PHZ_E_INVALID; }
   if (o->max_iters < 1) { err = "max_iters must be >= 1"; return PHZ_E_INVALID; }
   if (!(o->rtol > 0 && o->rtol < 1)) { err = "rtol must be in (0, 1)"; return PHZ_E_INVALID; }
@@ -1037,6 +1147,7 @@ int phz_create(int n, const phz_material* mat, const phz_options* opt, void* str
   c->N = n;
   c->nn = (long)n * n * n;
   c->mat = *mat;
+  for (int op = 0; op < 4; ++op) c->stats.elem_tile[op] = -1;
   if (opt) c->opt = *opt;
   else phz_default_options(&c->opt);
   std::string err;
@@ -1080,6 +1191,8 @@ int phz_set_options(phz_ctx* c, const phz_options* opt) {
     c->w64.cap_m = 0;
     c->w32.cap_m = 0;
   }
+  if (opt->elem_tile != c->opt.elem_tile || opt->bf16_terms != c->opt.bf16_terms)
+    for (int op = 0; op < 4; ++op) c->elem_tile[op] = -1;
   c->opt = *opt;
   if (hier_change) c->precond_ready = false;
   ensure_state_buffers(c);
@@ -1449,7 +1562,15 @@ int phz_apply(phz_ctx* c, int op, int nrhs, int precision, const void* x, void* 
     op_apply<double>(c, op, nrhs, (const double*)x, (const double*)nullptr, (double*)y, 1.0, 0.0);
   else if (precision == PHZ_FP32_IR)
     op_apply<float>(c, op, nrhs, (const float*)x, (const float*)nullptr, (float*)y, 1.0f, 0.0f);
-  else
+  else if (precision == PHZ_BF16X3_IR) {
+    const int tile = nrhs == 9 ? elem_tile_of(c, op) : -1;
+    if (tile < 0) {
+      c->err = "split-BF16 apply needs nine columns and a tile that divides N";
+      return PHZ_E_INVALID;
+    }
+    elem_apply(op, 9, c->N, c->opt.bf16_terms, tile, c->s32.p, c->kop[op].p, (const float*)x,
+               plain_args<float>(nullptr, (float*)y, 1.0f, 0.0f), false, c->stream);
+  } else
     return PHZ_E_INVALID;
   return PHZ_OK;
   PHZ_GUARD_END(c)
