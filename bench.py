@@ -131,11 +131,13 @@ def main():
     phi_d = torch.tensor(phi, device=dev)
     prec = {"bf16x3ir": P.PHZ_BF16X3_IR, "fp32ir": P.PHZ_FP32_IR, "fp64": P.PHZ_FP64}[args.precision]
 
-    # solver settings per form (restart / V-cycles per A-block application
-    # picked by a sweep on this workload); every form stops at a true FP64
-    # residual of 1e-10 per load
+    # solver settings per form (restart, V-cycles per A-block application and
+    # the float cycles' relative target picked by sweeps on this workload; the
+    # split-BF16 operators floor a float cycle near 1.5e-5, so its cycles aim
+    # at 1e-4); every form stops at a true FP64 residual of 1e-10 per load
     forms = {
-        "bf16x3ir": dict(precision=P.PHZ_BF16X3_IR, batched=1, restart=args.restart, vcycles_a=args.vcycles_a),
+        "bf16x3ir": dict(precision=P.PHZ_BF16X3_IR, batched=1, restart=args.restart, vcycles_a=args.vcycles_a,
+                         inner_rtol=1e-4),
         "fp32ir": dict(precision=P.PHZ_FP32_IR, batched=1, restart=args.restart, vcycles_a=args.vcycles_a),
         "fp64": dict(precision=P.PHZ_FP64, batched=1, restart=15, vcycles_a=2),
         "fp64_sequential": dict(precision=P.PHZ_FP64, batched=0, restart=30, vcycles_a=2),

@@ -161,8 +161,11 @@ struct GmresState {
 // start of a cycle: beta = sqrt(nrm2); g[0] = beta; active if beta > tol*bnorm;
 // scale = 1/beta or 0.
 void gmres_start(int nrhs, const double* nrm2, double rtol, GmresState s, hipStream_t st);
+// Givens step j: a column stops at its tolerance, at the restart length, and,
+// with stall > 0, once its estimate fell by less than the factor `stall` over
+// two steps (a float cycle whose operator error floors it).
 void gmres_givens(int nrhs, int m, int j, const double* h1, const double* h2,
-                  const double* nrm2, double rtol, GmresState s, hipStream_t st);
+                  const double* nrm2, double rtol, double stall, GmresState s, hipStream_t st);
 void gmres_solve_y(int nrhs, int m, GmresState s, hipStream_t st);
 
 // physics

@@ -788,7 +788,9 @@ static GmresResult gmres(phz_ctx* c, int K, const T* b, T* x, double rtol, int m
       arnoldi_update<T>(nn, 4, K, j, W.V.p, vs, W.w.p, c->gm_h1.p, c->gm_h2.p, nullptr, c->red_work.p, st);
       arnoldi_update<T>(nn, 4, K, j, W.V.p, vs, W.w.p, c->gm_h2.p, nullptr, nrm, c->red_work.p, st);
       time_end(c, ts);
-      gmres_givens(K, m, j, c->gm_h1.p, c->gm_h2.p, nrm, rtol, S, st);
+      // a float refinement cycle ends when its estimate stalls (the float
+      // operator's own error floors it); the float64 refinement carries on
+      gmres_givens(K, m, j, c->gm_h1.p, c->gm_h2.p, nrm, rtol, one_cycle ? 0.9 : 0.0, S, st);
       scale_cols<T>(nn, 4, K, W.w.p, S.scale, W.V.p + (size_t)(j + 1) * vs, st);
       ++total;
       PHZ_HIP(hipMemcpyAsync(&nact, S.nactive, sizeof(int), hipMemcpyDeviceToHost, st));

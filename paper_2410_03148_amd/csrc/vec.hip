@@ -316,7 +316,7 @@ __global__ void k_gmres_start(int K, const double* __restrict__ nrm2, double rto
 }
 
 __global__ void k_gmres_givens(int K, int m, int j, const double* __restrict__ h1, const double* __restrict__ h2,
-                               const double* __restrict__ nrm2, double rtol, GmresState s) {
+                               const double* __restrict__ nrm2, double rtol, double stall, GmresState s) {
   __shared__ int cnt;
   if (threadIdx.x == 0) cnt = 0;
   __syncthreads();
@@ -347,7 +347,9 @@ __global__ void k_gmres_givens(int K, int m, int j, const double* __restrict__ h
     s.g[j * K + k] = c * gj;
     const double est = fabs(s.g[(j + 1) * K + k]) / s.bnorm[k];
     s.est[j * K + k] = est;
-    const bool stop = !(est > rtol) || !(hn > 0.0) || (j + 1 == m) || !isfinite(est);
+    // stall: the estimate fell by less than the factor `stall` over two steps
+    const bool stalled = stall > 0.0 && j >= 2 && est > stall * s.est[(j - 2) * K + k];
+    const bool stop = !(est > rtol) || !(hn > 0.0) || (j + 1 == m) || !isfinite(est) || stalled;
     s.kused[k] = j + 1;
     if (stop) {
       s.active[k] = 0;
@@ -742,8 +744,8 @@ void gmres_start(int nrhs, const double* nrm2, double rtol, GmresState s, hipStr
   PHZ_LAUNCH_CHECK();
 }
 void gmres_givens(int nrhs, int m, int j, const double* h1, const double* h2, const double* nrm2, double rtol,
-                  GmresState s, hipStream_t st) {
-  hipLaunchKernelGGL(k_gmres_givens, dim3(1), dim3(64), 0, st, nrhs, m, j, h1, h2, nrm2, rtol, s);
+                  double stall, GmresState s, hipStream_t st) {
+  hipLaunchKernelGGL(k_gmres_givens, dim3(1), dim3(64), 0, st, nrhs, m, j, h1, h2, nrm2, rtol, stall, s);
   PHZ_LAUNCH_CHECK();
 }
 void gmres_solve_y(int nrhs, int m, GmresState s, hipStream_t st) {
