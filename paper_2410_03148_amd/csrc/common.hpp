@@ -27,7 +27,8 @@ constexpr int kMaxRestart = 32;
 // ---- operators (ops.hip) -----------------------------------------------------
 // Output side of an operator launch: y = beta*yin + alpha*(A x), and with the
 // Chebyshev epilogue (square blocks only) also, per node and column,
-// dnew = ca*dold + cb*Dinv*y and x += dnew.  y may alias yin; dnew must not
+// dnew = ca*dold + cb*Dinv*y and x = xin + dnew (+ dold if fold_dold; xin
+// null reads as zero).  y may alias yin and x may alias xin; dnew must not
 // alias the operator input.
 template <typename T>
 struct OpArgs {
@@ -37,8 +38,10 @@ struct OpArgs {
   const T* dinv = nullptr;
   const T* dold = nullptr;
   T* dnew = nullptr;
+  const T* xin = nullptr;
   T* x = nullptr;
   T ca = T(0), cb = T(0);
+  int fold_dold = 0;
 };
 
 // Fine-level matrix-free block operator on sum_e s_e Kref.
@@ -80,10 +83,12 @@ void diag_inv_fine(int F, int N, const double* s, const double* kref, double* Di
                    hipStream_t st);
 void diag_inv_coarse(int F, int N, const double* Ae, double* Dinv, hipStream_t st);
 
-// First Chebyshev-Jacobi step: d = cf Dinv r; x = d if xzero else x += d.
-// r, d and x may alias (per-node in-place).
+// First Chebyshev-Jacobi step: d = cf Dinv r, and x per xmode: untouched
+// (kChebyXNone: the next step folds d into x), x = d (kChebyXSet) or x += d
+// (kChebyXAdd).  r, d and x may alias (per-node in-place).
+enum { kChebyXNone = 0, kChebyXSet = 1, kChebyXAdd = 2 };
 template <typename T>
-void cheby_first(int F, int nrhs, long nn, const T* Dinv, const T* r, T* d, T* x, T cf, bool xzero,
+void cheby_first(int F, int nrhs, long nn, const T* Dinv, const T* r, T* d, T* x, T cf, int xmode,
                  hipStream_t st);
 
 // Full-weighting restriction rc = P^T rf and prolongation xf += P xc (periodic,

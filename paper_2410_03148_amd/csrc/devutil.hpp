@@ -52,9 +52,13 @@ __device__ __forceinline__ void epilogue_cols(unsigned n, unsigned nn, int k0, c
 #pragma unroll
         for (int g = 0; g < FO; ++g) z += Di[f * FO + g] * out[g * KK + j];
         const size_t o = (size_t)(f * K + k0 + j) * nn + n;
-        const T dv = a.ca * a.dold[o] + a.cb * z;
+        const T dold = a.dold[o];
+        const T dv = a.ca * dold + a.cb * z;
         a.dnew[o] = dv;
-        a.x[o] += dv;
+        T xo = dv;
+        if (a.fold_dold) xo += dold;
+        if (a.xin) xo += a.xin[o];
+        a.x[o] = xo;
       }
   }
 }

@@ -171,7 +171,7 @@ __global__ __launch_bounds__(256) void k_elem_mfma(unsigned N, const float* __re
       eyin[f] = has_yin ? a.yin[o] : 0.f;
       if constexpr (CHEBY) {
         edold[f] = a.dold[o];
-        eit[f] = a.x[o];
+        eit[f] = a.xin ? a.xin[o] : 0.f;
       } else {
         edold[f] = 0.f;
         eit[f] = 0.f;
@@ -271,7 +271,9 @@ __global__ __launch_bounds__(256) void k_elem_mfma(unsigned N, const float* __re
         const size_t o = (size_t)(f * K + k) * nn + n;
         const float dv = a.ca * cdold[f] + a.cb * z;
         a.dnew[o] = dv;
-        a.x[o] = cxit[f] + dv;
+        float xo = dv;
+        if (a.fold_dold) xo += cdold[f];
+        a.x[o] = xo + cxit[f];
       }
     }
   }

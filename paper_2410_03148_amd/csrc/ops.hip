@@ -352,10 +352,11 @@ __global__ void k_diag_coarse(unsigned N, const double* __restrict__ Ae, double*
   store_inv<F>(n, nn, D, Dinv);
 }
 
-// First Chebyshev step for (node, column k = blockIdx.y): d = cf Dinv r; x = d or x += d
+// First Chebyshev step for (node, column k = blockIdx.y): d = cf Dinv r; x
+// untouched, x = d or x += d (xmode)
 template <typename T, int F>
 __global__ __launch_bounds__(256) void k_cheby_first(unsigned nn, int K, const T* __restrict__ Dinv,
-                                                     const T* r, T* d, T* x, T cf, int xzero) {
+                                                     const T* r, T* d, T* x, T cf, int xmode) {
   const unsigned n = blockIdx.x * blockDim.x + threadIdx.x;
   if (n >= nn) return;
   const int kk = blockIdx.y;
@@ -370,14 +371,15 @@ __global__ __launch_bounds__(256) void k_cheby_first(unsigned nn, int K, const T
     const T dv = cf * z;
     const size_t o = (size_t)(f * K + kk) * nn + n;
     d[o] = dv;
-    if (xzero) x[o] = dv;
-    else x[o] += dv;
+    if (xmode == kChebyXSet) x[o] = dv;
+    else if (xmode == kChebyXAdd) x[o] += dv;
   }
 }
 
-// rc[I] = sum_{d in {-1,0,1}^3} prod(1 - |d|/2) rf[2I + d], all ncol columns
+// rc[I] = sum_{d in {-1,0,1}^3} prod(1 - |d|/2) rf[2I + d], one thread per
+// (coarse node, column = blockIdx.y)
 template <typename T>
-__global__ __launch_bounds__(256) void k_restrict(unsigned Nc, int ncol, const T* __restrict__ rf, T* __restrict__ rc) {
+__global__ __launch_bounds__(256) void k_restrict(unsigned Nc, const T* __restrict__ rf, T* __restrict__ rc) {
   const unsigned Nf = 2 * Nc;
   const unsigned nc = Nc * Nc * Nc, nf = Nf * Nf * Nf;
   const unsigned I = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
@@ -386,25 +388,21 @@ __global__ __launch_bounds__(256) void k_restrict(unsigned Nc, int ncol, const T
   const unsigned xs[3] = {(2 * ic + Nf - 1) % Nf, 2 * ic, 2 * ic + 1};
   const unsigned ys[3] = {(2 * jc + Nf - 1) % Nf, 2 * jc, 2 * jc + 1};
   const unsigned zs[3] = {(2 * kc + Nf - 1) % Nf, 2 * kc, 2 * kc + 1};
-  unsigned off[27];
+  const T* src = rf + (size_t)blockIdx.y * nf;
+  T acc = T(0);
 #pragma unroll
-  for (int t = 0; t < 27; ++t) off[t] = xs[t % 3] + Nf * (ys[(t / 3) % 3] + Nf * zs[t / 9]);
-  for (int col = 0; col < ncol; ++col) {
-    const T* src = rf + (size_t)col * nf;
-    T acc = T(0);
-#pragma unroll
-    for (int t = 0; t < 27; ++t) {
-      const int dx = t % 3, dy = (t / 3) % 3, dz = t / 9;
-      const T w = T((dx == 1 ? 1.0 : 0.5) * (dy == 1 ? 1.0 : 0.5) * (dz == 1 ? 1.0 : 0.5));
-      acc += w * src[off[t]];
-    }
-    rc[(size_t)col * nc + I] = acc;
+  for (int t = 0; t < 27; ++t) {
+    const int dx = t % 3, dy = (t / 3) % 3, dz = t / 9;
+    const T w = T((dx == 1 ? 1.0 : 0.5) * (dy == 1 ? 1.0 : 0.5) * (dz == 1 ? 1.0 : 0.5));
+    acc += w * src[xs[dx] + Nf * (ys[dy] + Nf * zs[dz])];
   }
+  rc[(size_t)blockIdx.y * nc + I] = acc;
 }
 
-// xf[i] += sum_I P[i, I] xc[I], fine node i = 2I + c, all ncol columns
+// xf[i] += sum_I P[i, I] xc[I], fine node i = 2I + c, one thread per (fine
+// node, column = blockIdx.y)
 template <typename T>
-__global__ __launch_bounds__(256) void k_prolong(unsigned Nc, int ncol, const T* __restrict__ xc, T* __restrict__ xf) {
+__global__ __launch_bounds__(256) void k_prolong(unsigned Nc, const T* __restrict__ xc, T* __restrict__ xf) {
   const unsigned Nf = 2 * Nc;
   const unsigned nc = Nc * Nc * Nc, nf = Nf * Nf * Nf;
   const unsigned i = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
@@ -414,24 +412,16 @@ __global__ __launch_bounds__(256) void k_prolong(unsigned Nc, int ncol, const T*
   const unsigned oi = fi & 1, oj = fj & 1, ok = fk & 1;
   const unsigned bi1 = bi + 1 == Nc ? 0 : bi + 1, bj1 = bj + 1 == Nc ? 0 : bj + 1, bk1 = bk + 1 == Nc ? 0 : bk + 1;
   const T w = T((oi ? 0.5 : 1.0) * (oj ? 0.5 : 1.0) * (ok ? 0.5 : 1.0));
-  unsigned src_idx[8];
-  int cnt = 0;
+  const T* src = xc + (size_t)blockIdx.y * nc;
+  T acc = T(0);
 #pragma unroll
   for (int c = 0; c < 8; ++c) {
     const unsigned ax = c & 1, ay = (c >> 1) & 1, az = (c >> 2) & 1;
-    const bool use = !((ax && !oi) || (ay && !oj) || (az && !ok));
-    src_idx[c] = (ax ? bi1 : bi) + Nc * ((ay ? bj1 : bj) + Nc * (az ? bk1 : bk));
-    if (use) ++cnt;
-    if (!use) src_idx[c] = 0xFFFFFFFFu;
+    // a coarse corner contributes only along the axes where the fine node is odd
+    if ((ax && !oi) || (ay && !oj) || (az && !ok)) continue;
+    acc += src[(ax ? bi1 : bi) + Nc * ((ay ? bj1 : bj) + Nc * (az ? bk1 : bk))];
   }
-  for (int col = 0; col < ncol; ++col) {
-    const T* src = xc + (size_t)col * nc;
-    T acc = T(0);
-#pragma unroll
-    for (int c = 0; c < 8; ++c)
-      if (src_idx[c] != 0xFFFFFFFFu) acc += src[src_idx[c]];
-    xf[(size_t)col * nf + i] += w * acc;
-  }
+  xf[(size_t)blockIdx.y * nf + i] += w * acc;
 }
 
 // z[(f, k, n)] = sum_{(g, m)} Minv[(f*nc + n), (g*nc + m)] r[(g, k, m)]
@@ -566,12 +556,12 @@ void diag_inv_coarse(int F, int N, const double* Ae, double* Dinv, hipStream_t s
 }
 
 template <typename T>
-void cheby_first(int F, int nrhs, long nn, const T* Dinv, const T* r, T* d, T* x, T cf, bool xzero, hipStream_t st) {
+void cheby_first(int F, int nrhs, long nn, const T* Dinv, const T* r, T* d, T* x, T cf, int xmode, hipStream_t st) {
   const dim3 g(blocks_for((size_t)nn, 256), nrhs);
   if (F == 3)
-    hipLaunchKernelGGL((k_cheby_first<T, 3>), g, dim3(256), 0, st, (unsigned)nn, nrhs, Dinv, r, d, x, cf, (int)xzero);
+    hipLaunchKernelGGL((k_cheby_first<T, 3>), g, dim3(256), 0, st, (unsigned)nn, nrhs, Dinv, r, d, x, cf, xmode);
   else if (F == 1)
-    hipLaunchKernelGGL((k_cheby_first<T, 1>), g, dim3(256), 0, st, (unsigned)nn, nrhs, Dinv, r, d, x, cf, (int)xzero);
+    hipLaunchKernelGGL((k_cheby_first<T, 1>), g, dim3(256), 0, st, (unsigned)nn, nrhs, Dinv, r, d, x, cf, xmode);
   else
     throw std::invalid_argument("cheby_first");
   PHZ_LAUNCH_CHECK();
@@ -579,15 +569,15 @@ void cheby_first(int F, int nrhs, long nn, const T* Dinv, const T* r, T* d, T* x
 
 template <typename T>
 void restrict_fw(int F, int nrhs, int Nc, const T* rf, T* rc, hipStream_t st) {
-  hipLaunchKernelGGL(k_restrict<T>, dim3(blocks_for((size_t)Nc * Nc * Nc, 256)), dim3(256), 0, st, (unsigned)Nc,
-                     F * nrhs, rf, rc);
+  hipLaunchKernelGGL(k_restrict<T>, dim3(blocks_for((size_t)Nc * Nc * Nc, 256), F * nrhs), dim3(256), 0, st,
+                     (unsigned)Nc, rf, rc);
   PHZ_LAUNCH_CHECK();
 }
 
 template <typename T>
 void prolong_add(int F, int nrhs, int Nc, const T* xc, T* xf, hipStream_t st) {
-  hipLaunchKernelGGL(k_prolong<T>, dim3(blocks_for((size_t)8 * Nc * Nc * Nc, 256)), dim3(256), 0, st, (unsigned)Nc,
-                     F * nrhs, xc, xf);
+  hipLaunchKernelGGL(k_prolong<T>, dim3(blocks_for((size_t)8 * Nc * Nc * Nc, 256), F * nrhs), dim3(256), 0, st,
+                     (unsigned)Nc, xc, xf);
   PHZ_LAUNCH_CHECK();
 }
 
@@ -607,7 +597,7 @@ void dense_apply(int F, int nc, int nrhs, const double* Minv, const T* r, T* z, 
 #define PHZ_INST(T)                                                                                            \
   template void fine_apply<T>(int, int, int, const T*, const T*, const T*, const OpArgs<T>&, bool, hipStream_t); \
   template void coarse_apply<T>(int, int, int, const T*, const T*, const OpArgs<T>&, bool, hipStream_t);         \
-  template void cheby_first<T>(int, int, long, const T*, const T*, T*, T*, T, bool, hipStream_t);               \
+  template void cheby_first<T>(int, int, long, const T*, const T*, T*, T*, T, int, hipStream_t);               \
   template void restrict_fw<T>(int, int, int, const T*, T*, hipStream_t);                                     \
   template void prolong_add<T>(int, int, int, const T*, T*, hipStream_t);                                     \
   template void dense_apply<T>(int, int, int, const double*, const T*, T*, hipStream_t);

@@ -536,7 +536,7 @@ static double power_lmax(phz_ctx* c, Hierarchy& H, int l) {
   const int iters = 20;
   for (int it = 0; it < iters; ++it) {
     level_apply<double>(c, H, l, 1, v.p, nullptr, w.p, 1.0, 0.0);
-    cheby_first<double>(H.F, 1, L.nn, L.Dinv.p, w.p, w.p, w.p, 1.0, true, c->stream);
+    cheby_first<double>(H.F, 1, L.nn, L.Dinv.p, w.p, w.p, w.p, 1.0, kChebyXNone, c->stream);
     col_norm2<double>(L.nn, H.F, 1, w.p, nrm, c->red_work.p, c->stream);
     normalize_by<double>(cnt, nrm, w.p, v.p, c->stream);
   }
@@ -636,7 +636,10 @@ static void cheby_smooth(phz_ctx* c, Hierarchy& H, int l, int K, const T* b, T* 
     level_apply<T>(c, H, l, K, x, b, W.r.p, T(-1), T(1));
     r = W.r.p;
   }
-  cheby_first<T>(H.F, K, L.nn, dinv_of<T>(L), r, W.d.p, x, T(1.0 / theta), xzero, c->stream);
+  // with more steps to come the first correction is folded into x by the
+  // next fused step (x = x_in + d_1 + d_2), which saves a pass over x
+  const int xmode = deg > 1 ? kChebyXNone : (xzero ? kChebyXSet : kChebyXAdd);
+  cheby_first<T>(H.F, K, L.nn, dinv_of<T>(L), r, W.d.p, x, T(1.0 / theta), xmode, c->stream);
   dcur = W.d.p;
   T* dnext = W.d2.p;
   for (int i = 1; i < deg; ++i) {
@@ -650,6 +653,8 @@ static void cheby_smooth(phz_ctx* c, Hierarchy& H, int l, int K, const T* b, T* 
     a.dold = dcur;
     a.dnew = dnext;
     a.x = x;
+    a.xin = (i == 1 && xzero) ? nullptr : x;
+    a.fold_dold = i == 1 ? 1 : 0;
     a.ca = T(rho_new * rho);
     a.cb = T(2.0 * rho_new / delta);
     level_apply_args<T>(c, H, l, K, dcur, a, true);
