@@ -376,9 +376,10 @@ __global__ __launch_bounds__(256) void k_cheby_first(unsigned nn, int K, const T
   }
 }
 
-// rc[I] = sum_{d in {-1,0,1}^3} prod(1 - |d|/2) rf[2I + d], one thread per
-// (coarse node, column = blockIdx.y)
-template <typename T>
+// rc[I] = sum_{d in {-1,0,1}^3} prod(1 - |d|/2) rf[2I + d]: one thread per
+// (coarse node, chunk of CPT columns starting at CPT * blockIdx.y); the index
+// arithmetic is shared by the chunk, whose loads are independent
+template <typename T, int CPT>
 __global__ __launch_bounds__(256) void k_restrict(unsigned Nc, const T* __restrict__ rf, T* __restrict__ rc) {
   const unsigned Nf = 2 * Nc;
   const unsigned nc = Nc * Nc * Nc, nf = Nf * Nf * Nf;
@@ -388,20 +389,25 @@ __global__ __launch_bounds__(256) void k_restrict(unsigned Nc, const T* __restri
   const unsigned xs[3] = {(2 * ic + Nf - 1) % Nf, 2 * ic, 2 * ic + 1};
   const unsigned ys[3] = {(2 * jc + Nf - 1) % Nf, 2 * jc, 2 * jc + 1};
   const unsigned zs[3] = {(2 * kc + Nf - 1) % Nf, 2 * kc, 2 * kc + 1};
-  const T* src = rf + (size_t)blockIdx.y * nf;
-  T acc = T(0);
+  const T* src = rf + (size_t)blockIdx.y * CPT * nf;
+  T acc[CPT];
+#pragma unroll
+  for (int q = 0; q < CPT; ++q) acc[q] = T(0);
 #pragma unroll
   for (int t = 0; t < 27; ++t) {
     const int dx = t % 3, dy = (t / 3) % 3, dz = t / 9;
     const T w = T((dx == 1 ? 1.0 : 0.5) * (dy == 1 ? 1.0 : 0.5) * (dz == 1 ? 1.0 : 0.5));
-    acc += w * src[xs[dx] + Nf * (ys[dy] + Nf * zs[dz])];
+    const unsigned o = xs[dx] + Nf * (ys[dy] + Nf * zs[dz]);
+#pragma unroll
+    for (int q = 0; q < CPT; ++q) acc[q] += w * src[(size_t)q * nf + o];
   }
-  rc[(size_t)blockIdx.y * nc + I] = acc;
+#pragma unroll
+  for (int q = 0; q < CPT; ++q) rc[((size_t)blockIdx.y * CPT + q) * nc + I] = acc[q];
 }
 
-// xf[i] += sum_I P[i, I] xc[I], fine node i = 2I + c, one thread per (fine
-// node, column = blockIdx.y)
-template <typename T>
+// xf[i] += sum_I P[i, I] xc[I], fine node i = 2I + c: one thread per (fine
+// node, chunk of CPT columns starting at CPT * blockIdx.y)
+template <typename T, int CPT>
 __global__ __launch_bounds__(256) void k_prolong(unsigned Nc, const T* __restrict__ xc, T* __restrict__ xf) {
   const unsigned Nf = 2 * Nc;
   const unsigned nc = Nc * Nc * Nc, nf = Nf * Nf * Nf;
@@ -412,16 +418,29 @@ __global__ __launch_bounds__(256) void k_prolong(unsigned Nc, const T* __restric
   const unsigned oi = fi & 1, oj = fj & 1, ok = fk & 1;
   const unsigned bi1 = bi + 1 == Nc ? 0 : bi + 1, bj1 = bj + 1 == Nc ? 0 : bj + 1, bk1 = bk + 1 == Nc ? 0 : bk + 1;
   const T w = T((oi ? 0.5 : 1.0) * (oj ? 0.5 : 1.0) * (ok ? 0.5 : 1.0));
-  const T* src = xc + (size_t)blockIdx.y * nc;
-  T acc = T(0);
+  // coarse corners that contribute (only along the axes where the fine node
+  // is odd); the others repeat corner 0 with weight 0
+  unsigned src_idx[8];
+  T cw[8];
 #pragma unroll
   for (int c = 0; c < 8; ++c) {
     const unsigned ax = c & 1, ay = (c >> 1) & 1, az = (c >> 2) & 1;
-    // a coarse corner contributes only along the axes where the fine node is odd
-    if ((ax && !oi) || (ay && !oj) || (az && !ok)) continue;
-    acc += src[(ax ? bi1 : bi) + Nc * ((ay ? bj1 : bj) + Nc * (az ? bk1 : bk))];
+    const bool use = !((ax && !oi) || (ay && !oj) || (az && !ok));
+    src_idx[c] = use ? (ax ? bi1 : bi) + Nc * ((ay ? bj1 : bj) + Nc * (az ? bk1 : bk)) : bi + Nc * (bj + Nc * bk);
+    cw[c] = use ? w : T(0);
   }
-  xf[(size_t)blockIdx.y * nf + i] += w * acc;
+  const size_t c0 = (size_t)blockIdx.y * CPT;
+  T acc[CPT];
+#pragma unroll
+  for (int q = 0; q < CPT; ++q) {
+    const T* src = xc + (c0 + q) * nc;
+    T a = T(0);
+#pragma unroll
+    for (int c = 0; c < 8; ++c) a += cw[c] * src[src_idx[c]];
+    acc[q] = a;
+  }
+#pragma unroll
+  for (int q = 0; q < CPT; ++q) xf[(c0 + q) * nf + i] += acc[q];
 }
 
 // z[(f, k, n)] = sum_{(g, m)} Minv[(f*nc + n), (g*nc + m)] r[(g, k, m)]
@@ -569,15 +588,21 @@ void cheby_first(int F, int nrhs, long nn, const T* Dinv, const T* r, T* d, T* x
 
 template <typename T>
 void restrict_fw(int F, int nrhs, int Nc, const T* rf, T* rc, hipStream_t st) {
-  hipLaunchKernelGGL(k_restrict<T>, dim3(blocks_for((size_t)Nc * Nc * Nc, 256), F * nrhs), dim3(256), 0, st,
-                     (unsigned)Nc, rf, rc);
+  const int ncol = F * nrhs;
+  const unsigned g = blocks_for((size_t)Nc * Nc * Nc, 256);
+  if (ncol % 9 == 0) hipLaunchKernelGGL((k_restrict<T, 9>), dim3(g, ncol / 9), dim3(256), 0, st, (unsigned)Nc, rf, rc);
+  else if (ncol % 3 == 0) hipLaunchKernelGGL((k_restrict<T, 3>), dim3(g, ncol / 3), dim3(256), 0, st, (unsigned)Nc, rf, rc);
+  else hipLaunchKernelGGL((k_restrict<T, 1>), dim3(g, ncol), dim3(256), 0, st, (unsigned)Nc, rf, rc);
   PHZ_LAUNCH_CHECK();
 }
 
 template <typename T>
 void prolong_add(int F, int nrhs, int Nc, const T* xc, T* xf, hipStream_t st) {
-  hipLaunchKernelGGL(k_prolong<T>, dim3(blocks_for((size_t)8 * Nc * Nc * Nc, 256), F * nrhs), dim3(256), 0, st,
-                     (unsigned)Nc, xc, xf);
+  const int ncol = F * nrhs;
+  const unsigned g = blocks_for((size_t)8 * Nc * Nc * Nc, 256);
+  if (ncol % 9 == 0) hipLaunchKernelGGL((k_prolong<T, 9>), dim3(g, ncol / 9), dim3(256), 0, st, (unsigned)Nc, xc, xf);
+  else if (ncol % 3 == 0) hipLaunchKernelGGL((k_prolong<T, 3>), dim3(g, ncol / 3), dim3(256), 0, st, (unsigned)Nc, xc, xf);
+  else hipLaunchKernelGGL((k_prolong<T, 1>), dim3(g, ncol), dim3(256), 0, st, (unsigned)Nc, xc, xf);
   PHZ_LAUNCH_CHECK();
 }
 
