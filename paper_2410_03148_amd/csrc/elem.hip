@@ -21,10 +21,11 @@
 //      Y = lo(K) hi(D) + hi(K) lo(D) + hi(K) hi(D) accumulated in FP32 (the
 //      dropped lo*lo term is about 2^-18 relative); the error then scales
 //      with the differences across an element, not with the nodal values,
-//      which keeps the residuals of smooth fields accurate.  Each element's
-//      outputs are scaled by s_e and stored in LDS by (corner, element);
-//   3. sums, for its node, the outputs of the eight elements around it in a
-//      fixed corner order (deterministic, no atomics), then runs the same
+//      which keeps the residuals of smooth fields accurate.  The element
+//      outputs are stored in LDS by (corner, element);
+//   3. sums, for its node, the outputs of the eight elements around it times
+//      their scales s_e in a fixed corner order (deterministic, no atomics),
+//      then runs the same
 //      output epilogue as the gather kernels (residual form and the fused
 //      Chebyshev step).
 // Elements on the tile's halo are contracted by every tile that touches
@@ -186,6 +187,16 @@ __global__ __launch_bounds__(256) void k_elem_mfma(unsigned N, const float* __re
   }
   fetch(0);
 
+  // scales of the eight elements around this thread's node (the same for
+  // every column)
+  __syncthreads();
+  float sg[8];
+#pragma unroll
+  for (int c = 0; c < 8; ++c) {
+    const int cx = c & 1, cy = (c >> 1) & 1, cz = c >> 2;
+    sg[c] = se[(ti + 1 - cx) + EX * ((tj + 1 - cy) + EY * (tk + 1 - cz))];
+  }
+
   for (int k = 0; k < K; ++k) {
     __syncthreads();  // the previous column's LDS reads are complete
 #pragma unroll
@@ -228,17 +239,16 @@ __global__ __launch_bounds__(256) void k_elem_mfma(unsigned N, const float* __re
         }
         d0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[0], bh, d0, 0, 0, 0);
         d1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[1], bh, d1, 0, 0, 0);
-        const float sc = se[e];
-        // rows of row tile t: corner 4t + g, field slots 0..3
+        // rows of row tile t: corner 4t + g, field slots 0..3 (unscaled: the
+        // gather applies s_e)
         if constexpr (FO == 4) {
-          *reinterpret_cast<float4*>(&zs[(g * NEP + e) * 4]) = float4{sc * d0[0], sc * d0[1], sc * d0[2], sc * d0[3]};
-          *reinterpret_cast<float4*>(&zs[((4 + g) * NEP + e) * 4]) =
-              float4{sc * d1[0], sc * d1[1], sc * d1[2], sc * d1[3]};
+          *reinterpret_cast<float4*>(&zs[(g * NEP + e) * 4]) = float4{d0[0], d0[1], d0[2], d0[3]};
+          *reinterpret_cast<float4*>(&zs[((4 + g) * NEP + e) * 4]) = float4{d1[0], d1[1], d1[2], d1[3]};
         } else {
 #pragma unroll
           for (int fo = 0; fo < FO; ++fo) {
-            zs[(g * NEP + e) * FO + fo] = sc * d0[fo];
-            zs[((4 + g) * NEP + e) * FO + fo] = sc * d1[fo];
+            zs[(g * NEP + e) * FO + fo] = d0[fo];
+            zs[((4 + g) * NEP + e) * FO + fo] = d1[fo];
           }
         }
       }
@@ -252,7 +262,7 @@ __global__ __launch_bounds__(256) void k_elem_mfma(unsigned N, const float* __re
       const int cx = c & 1, cy = (c >> 1) & 1, cz = c >> 2;
       const int ee = (ti + 1 - cx) + EX * ((tj + 1 - cy) + EY * (tk + 1 - cz));
 #pragma unroll
-      for (int fo = 0; fo < FO; ++fo) acc[fo] += zs[(c * NEP + ee) * FO + fo];
+      for (int fo = 0; fo < FO; ++fo) acc[fo] += sg[c] * zs[(c * NEP + ee) * FO + fo];
     }
     // y = beta y_in + alpha acc; with the Chebyshev step also
     // d_new = ca d_old + cb Dinv y and x += d_new
