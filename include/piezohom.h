@@ -127,6 +127,13 @@ typedef struct {
                                a block whose gather kernel is faster stays on
                                it), else an index in [0, 3): 8x8x4, 16x4x4,
                                16x8x2 nodes, used for every block             */
+    int use_graph;          /* 1: each GMRES Arnoldi step (preconditioner,
+                               operator, orthogonalisation, Givens update) is
+                               captured once as a HIP graph and replayed; the
+                               graphs survive geometry changes and are
+                               re-captured when options or workspaces change.
+                               Per-kernel timing (phz_kernel_timing) runs the
+                               steps eagerly.  Default 0                      */
 } phz_options;
 
 typedef struct {

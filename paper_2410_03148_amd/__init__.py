@@ -37,7 +37,7 @@ class phz_options(C.Structure):
                 ("mg_levels", C.c_int), ("smooth_width", C.c_double), ("vcycles_a", C.c_int),
                 ("vcycles_s", C.c_int), ("inner_rtol", C.c_double), ("max_refine", C.c_int),
                 ("verbose", C.c_int), ("bf16_terms", C.c_int), ("bf16_outer", C.c_int),
-                ("elem_tile", C.c_int)]
+                ("elem_tile", C.c_int), ("use_graph", C.c_int)]
 
 
 class phz_stats(C.Structure):

@@ -28,8 +28,8 @@ constexpr int kMaxRestart = 32;
 // Output side of an operator launch: y = beta*yin + alpha*(A x), and with the
 // Chebyshev epilogue (square blocks only) also, per node and column,
 // dnew = ca*dold + cb*Dinv*y and x = xin + dnew (+ dold if fold_dold; xin
-// null reads as zero).  y may alias yin and x may alias xin; dnew must not
-// alias the operator input.
+// null reads as zero), with (ca, cb) = (cab[0], cab[1]) read on the device.
+// y may alias yin and x may alias xin; dnew must not alias the operator input.
 template <typename T>
 struct OpArgs {
   const T* yin = nullptr;
@@ -40,7 +40,7 @@ struct OpArgs {
   T* dnew = nullptr;
   const T* xin = nullptr;
   T* x = nullptr;
-  T ca = T(0), cb = T(0);
+  const T* cab = nullptr;
   int fold_dold = 0;
 };
 
@@ -83,12 +83,13 @@ void diag_inv_fine(int F, int N, const double* s, const double* kref, double* Di
                    hipStream_t st);
 void diag_inv_coarse(int F, int N, const double* Ae, double* Dinv, hipStream_t st);
 
-// First Chebyshev-Jacobi step: d = cf Dinv r, and x per xmode: untouched
-// (kChebyXNone: the next step folds d into x), x = d (kChebyXSet) or x += d
-// (kChebyXAdd).  r, d and x may alias (per-node in-place).
+// First Chebyshev-Jacobi step: d = cf[0] Dinv r (cf on the device), and x
+// per xmode: untouched (kChebyXNone: the next step folds d into x), x = d
+// (kChebyXSet) or x += d (kChebyXAdd).  r, d and x may alias (per-node
+// in-place).
 enum { kChebyXNone = 0, kChebyXSet = 1, kChebyXAdd = 2 };
 template <typename T>
-void cheby_first(int F, int nrhs, long nn, const T* Dinv, const T* r, T* d, T* x, T cf, int xmode,
+void cheby_first(int F, int nrhs, long nn, const T* Dinv, const T* r, T* d, T* x, const T* cf, int xmode,
                  hipStream_t st);
 
 // Full-weighting restriction rc = P^T rf and prolongation xf += P xc (periodic,

@@ -41,6 +41,7 @@ __device__ __forceinline__ void epilogue_cols(unsigned n, unsigned nn, int k0, c
 #pragma unroll
     for (int j = 0; j < KK; ++j) a.y[(size_t)(f * K + k0 + j) * nn + n] = out[f * KK + j];
   if constexpr (CHEBY) {
+    const T ca = a.cab[0], cb = a.cab[1];
     T Di[FO * FO];
 #pragma unroll
     for (int t = 0; t < FO * FO; ++t) Di[t] = a.dinv[(size_t)t * nn + n];
@@ -53,7 +54,7 @@ __device__ __forceinline__ void epilogue_cols(unsigned n, unsigned nn, int k0, c
         for (int g = 0; g < FO; ++g) z += Di[f * FO + g] * out[g * KK + j];
         const size_t o = (size_t)(f * K + k0 + j) * nn + n;
         const T dold = a.dold[o];
-        const T dv = a.ca * dold + a.cb * z;
+        const T dv = ca * dold + cb * z;
         a.dnew[o] = dv;
         T xo = dv;
         if (a.fold_dold) xo += dold;

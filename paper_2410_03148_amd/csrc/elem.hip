@@ -179,9 +179,12 @@ __global__ __launch_bounds__(256) void k_elem_mfma(unsigned N, const float* __re
       }
     }
   };
-  // the node's Jacobi block, the same for every column
+  // the node's Jacobi block and the step's coefficients, the same for every column
   float Di[CHEBY ? FO * FO : 1];
+  float ca = 0.f, cb = 0.f;
   if constexpr (CHEBY) {
+    ca = a.cab[0];
+    cb = a.cab[1];
 #pragma unroll
     for (int t = 0; t < FO * FO; ++t) Di[t] = a.dinv[(size_t)t * nn + n];
   }
@@ -279,7 +282,7 @@ __global__ __launch_bounds__(256) void k_elem_mfma(unsigned N, const float* __re
 #pragma unroll
         for (int q = 0; q < FO; ++q) z += Di[f * FO + q] * out[q];
         const size_t o = (size_t)(f * K + k) * nn + n;
-        const float dv = a.ca * cdold[f] + a.cb * z;
+        const float dv = ca * cdold[f] + cb * z;
         a.dnew[o] = dv;
         float xo = dv;
         if (a.fold_dold) xo += cdold[f];

@@ -356,10 +356,12 @@ __global__ void k_diag_coarse(unsigned N, const double* __restrict__ Ae, double*
 // untouched, x = d or x += d (xmode)
 template <typename T, int F>
 __global__ __launch_bounds__(256) void k_cheby_first(unsigned nn, int K, const T* __restrict__ Dinv,
-                                                     const T* r, T* d, T* x, T cf, int xmode) {
+                                                     const T* r, T* d, T* x, const T* __restrict__ cfp,
+                                                     int xmode) {
   const unsigned n = blockIdx.x * blockDim.x + threadIdx.x;
   if (n >= nn) return;
   const int kk = blockIdx.y;
+  const T cf = cfp[0];
   T rv[F];
 #pragma unroll
   for (int f = 0; f < F; ++f) rv[f] = r[(size_t)(f * K + kk) * nn + n];
@@ -575,7 +577,8 @@ void diag_inv_coarse(int F, int N, const double* Ae, double* Dinv, hipStream_t s
 }
 
 template <typename T>
-void cheby_first(int F, int nrhs, long nn, const T* Dinv, const T* r, T* d, T* x, T cf, int xmode, hipStream_t st) {
+void cheby_first(int F, int nrhs, long nn, const T* Dinv, const T* r, T* d, T* x, const T* cf, int xmode,
+                 hipStream_t st) {
   const dim3 g(blocks_for((size_t)nn, 256), nrhs);
   if (F == 3)
     hipLaunchKernelGGL((k_cheby_first<T, 3>), g, dim3(256), 0, st, (unsigned)nn, nrhs, Dinv, r, d, x, cf, xmode);
@@ -622,7 +625,7 @@ void dense_apply(int F, int nc, int nrhs, const double* Minv, const T* r, T* z, 
 #define PHZ_INST(T)                                                                                            \
   template void fine_apply<T>(int, int, int, const T*, const T*, const T*, const OpArgs<T>&, bool, hipStream_t); \
   template void coarse_apply<T>(int, int, int, const T*, const T*, const OpArgs<T>&, bool, hipStream_t);         \
-  template void cheby_first<T>(int, int, long, const T*, const T*, T*, T*, T, int, hipStream_t);               \
+  template void cheby_first<T>(int, int, long, const T*, const T*, T*, T*, const T*, int, hipStream_t);               \
   template void restrict_fw<T>(int, int, int, const T*, T*, hipStream_t);                                     \
   template void prolong_add<T>(int, int, int, const T*, T*, hipStream_t);                                     \
   template void dense_apply<T>(int, int, int, const double*, const T*, T*, hipStream_t);

@@ -70,6 +70,13 @@ struct Level {
   DevBuf<double> Dinv;    // node-block diagonal inverse
   DevBuf<float> Dinv32;
   double lmax = 0.0;
+  // Chebyshev coefficients on the device, read by the smoothing kernels (so a
+  // captured launch sequence stays valid when the geometry changes):
+  // [0] = 1/theta, [2i] = ca_i, [2i+1] = cb_i for steps i = 1 .. degree-1
+  std::vector<double> cheb_host;
+  std::vector<float> cheb_host32;
+  DevBuf<double> cheb;
+  DevBuf<float> cheb32;
 };
 
 struct Hierarchy {
@@ -91,6 +98,17 @@ struct Work {
   std::vector<std::unique_ptr<LevelWork<T>>> A, S;
   DevBuf<T> t1u, t2u, t1p, t2p, t3p;   // preconditioner temporaries
   DevBuf<T> V, w, z, t, r, b, x;                  // GMRES
+};
+
+// One Arnoldi step (preconditioner, operator, orthogonalisation, Givens,
+// next basis vector) captured as a HIP graph.  Valid while the buffers it
+// was captured on stay in place (graph epoch) and for the same columns,
+// tolerance and stall factor.
+struct StepGraph {
+  hipGraphExec_t exec = nullptr;
+  int K = 0;
+  double rtol = 0.0, stall = 0.0;
+  long epoch = -1;
 };
 
 }  // namespace phz
@@ -128,6 +146,12 @@ struct phz_ctx {
   phz::DevBuf<double> red_work, small;   // reduction scratch, small device values
   phz::DevBuf<double> gm_H, gm_cs, gm_sn, gm_g, gm_y, gm_est, gm_bnorm, gm_scale, gm_h1, gm_h2, gm_nrm;
   phz::DevBuf<int> gm_int;
+
+  // captured Arnoldi steps (use_graph), per precision and step index; the
+  // epoch advances whenever a buffer they reference may have moved
+  std::vector<phz::StepGraph> graphs64, graphs32;
+  long graph_epoch = 0;
+  phz::DevBuf<double> one64;   // the constant 1.0 (power-iteration Jacobi step)
 
   // optional per-kernel timing with HIP events on the context stream
   bool ktime = false;
@@ -217,20 +241,31 @@ static void upload_reference(phz_ctx* c) {
   }
 }
 
+// Level sizes N, N/2, ... while N is even and above 4 (or mg_levels levels).
+// Existing levels of the same structure are kept, so their device buffers
+// (and any launch sequence captured on them) stay where they are.
 static void build_levels(phz_ctx* c, Hierarchy& H, int F, int op) {
+  std::vector<int> sizes;
+  int N = c->N;
+  const int maxl = c->opt.mg_levels > 0 ? c->opt.mg_levels : 64;
+  for (;;) {
+    sizes.push_back(N);
+    if (!(N % 2 == 0 && N > 4 && (int)sizes.size() < maxl)) break;
+    N /= 2;
+  }
+  bool same = H.F == F && H.op == op && H.lv.size() == sizes.size();
+  for (size_t l = 0; same && l < sizes.size(); ++l) same = H.lv[l]->N == sizes[l];
+  if (same) return;
   H.F = F;
   H.op = op;
   H.lv.clear();
-  int N = c->N;
-  const int maxl = c->opt.mg_levels > 0 ? c->opt.mg_levels : 64;
-  for (int l = 0;; ++l) {
+  for (int n : sizes) {
     auto L = std::make_unique<Level>();
-    L->N = N;
-    L->nn = (long)N * N * N;
+    L->N = n;
+    L->nn = (long)n * n * n;
     H.lv.push_back(std::move(L));
-    if (!(N % 2 == 0 && N > 4 && (int)H.lv.size() < maxl)) break;
-    N /= 2;
   }
+  ++c->graph_epoch;
 }
 
 // Krylov basis vectors are padded apart so that the many concurrent streams
@@ -240,6 +275,7 @@ static size_t basis_stride(long nn, int K) { return (size_t)nn * 4 * K + 512; }
 template <typename T>
 static void alloc_work(phz_ctx* c, Work<T>& W, int K, int m) {
   if (W.cap_k >= K && W.cap_m >= m && !W.A.empty()) return;
+  ++c->graph_epoch;
   const long nn = c->nn;
   auto mk = [&](Hierarchy& H, std::vector<std::unique_ptr<LevelWork<T>>>& out) {
     out.clear();
@@ -536,7 +572,7 @@ static double power_lmax(phz_ctx* c, Hierarchy& H, int l) {
   const int iters = 20;
   for (int it = 0; it < iters; ++it) {
     level_apply<double>(c, H, l, 1, v.p, nullptr, w.p, 1.0, 0.0);
-    cheby_first<double>(H.F, 1, L.nn, L.Dinv.p, w.p, w.p, w.p, 1.0, kChebyXNone, c->stream);
+    cheby_first<double>(H.F, 1, L.nn, L.Dinv.p, w.p, w.p, w.p, c->one64.p, kChebyXNone, c->stream);
     col_norm2<double>(L.nn, H.F, 1, w.p, nrm, c->red_work.p, c->stream);
     normalize_by<double>(cnt, nrm, w.p, v.p, c->stream);
   }
@@ -569,7 +605,26 @@ static void setup_hierarchy(phz_ctx* c, Hierarchy& H) {
       else diag_inv_coarse(F, L.N, L.Ae.p, L.Dinv.p, c->stream);
     }
   }
-  for (int l = 0; l < nl - 1; ++l) H.lv[l]->lmax = power_lmax(c, H, l);
+  for (int l = 0; l < nl - 1; ++l) {
+    Level& L = *H.lv[l];
+    L.lmax = power_lmax(c, H, l);
+    // Chebyshev-Jacobi on [0.15, 1.1] lambda_max (Saad, Alg. 12.1)
+    const int deg = std::max(1, c->opt.cheby_degree);
+    const double hi = 1.1 * L.lmax, lo = 0.15 * L.lmax;
+    const double theta = 0.5 * (hi + lo), delta = 0.5 * (hi - lo), sigma = theta / delta;
+    L.cheb_host.assign(2 * deg, 0.0);
+    L.cheb_host[0] = 1.0 / theta;
+    double rho = 1.0 / sigma;
+    for (int i = 1; i < deg; ++i) {
+      const double rho_new = 1.0 / (2.0 * sigma - rho);
+      L.cheb_host[2 * i] = rho_new * rho;
+      L.cheb_host[2 * i + 1] = 2.0 * rho_new / delta;
+      rho = rho_new;
+    }
+    L.cheb_host32.assign(L.cheb_host.begin(), L.cheb_host.end());
+    L.cheb.upload(L.cheb_host.data(), L.cheb_host.size(), c->stream);
+    L.cheb32.upload(L.cheb_host32.data(), L.cheb_host32.size(), c->stream);
+  }
   build_coarsest(c, H);
   if (c->opt.precision != PHZ_FP64) {
     for (int l = 0; l < nl; ++l) {
@@ -623,14 +678,16 @@ static void setup_preconditioner(phz_ctx* c) {
 // preconditioner), interval [0.15, 1.1] * lambda_max(D^-1 A).  The residual
 // is carried along: on return r points at b - A (x - d) and dcur at the last
 // correction, so that b - A x = r - A dcur.
+template <typename T> static const T* cheb_of(Level& L);
+template <> const double* cheb_of<double>(Level& L) { return L.cheb.p; }
+template <> const float* cheb_of<float>(Level& L) { return L.cheb32.p; }
+
 template <typename T>
 static void cheby_smooth(phz_ctx* c, Hierarchy& H, int l, int K, const T* b, T* x, bool xzero, LevelWork<T>& W,
                          const T*& r, T*& dcur) {
   Level& L = *H.lv[l];
   const int deg = std::max(1, c->opt.cheby_degree);
-  const double hi = 1.1 * L.lmax, lo = 0.15 * L.lmax;
-  const double theta = 0.5 * (hi + lo), delta = 0.5 * (hi - lo), sigma = theta / delta;
-  double rho = 1.0 / sigma;
+  const T* coef = cheb_of<T>(L);
   r = b;
   if (!xzero) {
     level_apply<T>(c, H, l, K, x, b, W.r.p, T(-1), T(1));
@@ -639,11 +696,10 @@ static void cheby_smooth(phz_ctx* c, Hierarchy& H, int l, int K, const T* b, T* 
   // with more steps to come the first correction is folded into x by the
   // next fused step (x = x_in + d_1 + d_2), which saves a pass over x
   const int xmode = deg > 1 ? kChebyXNone : (xzero ? kChebyXSet : kChebyXAdd);
-  cheby_first<T>(H.F, K, L.nn, dinv_of<T>(L), r, W.d.p, x, T(1.0 / theta), xmode, c->stream);
+  cheby_first<T>(H.F, K, L.nn, dinv_of<T>(L), r, W.d.p, x, coef, xmode, c->stream);
   dcur = W.d.p;
   T* dnext = W.d2.p;
   for (int i = 1; i < deg; ++i) {
-    const double rho_new = 1.0 / (2.0 * sigma - rho);
     OpArgs<T> a;
     a.yin = r;
     a.y = W.r.p;
@@ -655,12 +711,10 @@ static void cheby_smooth(phz_ctx* c, Hierarchy& H, int l, int K, const T* b, T* 
     a.x = x;
     a.xin = (i == 1 && xzero) ? nullptr : x;
     a.fold_dold = i == 1 ? 1 : 0;
-    a.ca = T(rho_new * rho);
-    a.cb = T(2.0 * rho_new / delta);
+    a.cab = coef + 2 * i;
     level_apply_args<T>(c, H, l, K, dcur, a, true);
     r = W.r.p;
     std::swap(dcur, dnext);
-    rho = rho_new;
   }
 }
 
@@ -722,6 +776,47 @@ struct GmresResult {
   bool converged = false;
 };
 
+template <typename T> static std::vector<StepGraph>& graphs_of(phz_ctx* c);
+template <> std::vector<StepGraph>& graphs_of<double>(phz_ctx* c) { return c->graphs64; }
+template <> std::vector<StepGraph>& graphs_of<float>(phz_ctx* c) { return c->graphs32; }
+
+static void drop_graphs(std::vector<StepGraph>& G) {
+  for (auto& g : G)
+    if (g.exec) hipGraphExecDestroy(g.exec);
+  G.clear();
+}
+
+// Run Arnoldi step j from its captured graph, capturing `body` (the step's
+// launches, no host synchronisation or allocation) on first use.
+template <typename T, typename Body>
+static void run_step_graph(phz_ctx* c, int K, int j, double rtol, double stall, Body&& body) {
+  std::vector<StepGraph>& G = graphs_of<T>(c);
+  if ((int)G.size() <= j) G.resize(j + 1);
+  StepGraph& g = G[j];
+  if (!g.exec || g.K != K || g.rtol != rtol || g.stall != stall || g.epoch != c->graph_epoch) {
+    if (g.exec) hipGraphExecDestroy(g.exec);
+    g.exec = nullptr;
+    hipGraph_t graph = nullptr;
+    PHZ_HIP(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+    try {
+      body();
+    } catch (...) {
+      hipStreamEndCapture(c->stream, &graph);
+      if (graph) hipGraphDestroy(graph);
+      throw;
+    }
+    PHZ_HIP(hipStreamEndCapture(c->stream, &graph));
+    const hipError_t e = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0);
+    hipGraphDestroy(graph);
+    PHZ_HIP(e);
+    g.K = K;
+    g.rtol = rtol;
+    g.stall = stall;
+    g.epoch = c->graph_epoch;
+  }
+  PHZ_HIP(hipGraphLaunch(g.exec, c->stream));
+}
+
 // Solve calA x = b (x holds the initial guess), K columns, storage T.
 // true residuals are evaluated in T (the caller refines in float64 if T is float).
 // x_is_zero: skip the first residual apply (r = b).  one_cycle: run one
@@ -781,22 +876,28 @@ static GmresResult gmres(phz_ctx* c, int K, const T* b, T* x, double rtol, int m
     // V_0 = r / beta
     scale_cols<T>(nn, 4, K, W.r.p, S.scale, W.V.p, st);
     int j = 0;
+    // a float refinement cycle ends when its estimate stalls (the float
+    // operator's own error floors it); the float64 refinement carries on
+    const double stall = one_cycle ? 0.9 : 0.0;
     for (; j < m; ++j) {
-      T* Vj = W.V.p + (size_t)j * vs;
-      const long tp = time_begin(c, sizeof(T) == 4 ? "precond_f32" : "precond_f64");
-      precond_apply<T>(c, K, Vj, W.z.p);
-      time_end(c, tp);
-      op_apply<T>(c, 0, K, W.z.p, (const T*)nullptr, W.w.p, T(1), T(0));
-      // classical Gram-Schmidt, twice
-      const long ts = time_begin(c, sizeof(T) == 4 ? "arnoldi_cgs2_f32" : "arnoldi_cgs2_f64");
-      arnoldi_dots<T>(nn, 4, K, j, W.V.p, vs, W.w.p, c->gm_h1.p, c->red_work.p, st);
-      arnoldi_update<T>(nn, 4, K, j, W.V.p, vs, W.w.p, c->gm_h1.p, c->gm_h2.p, nullptr, c->red_work.p, st);
-      arnoldi_update<T>(nn, 4, K, j, W.V.p, vs, W.w.p, c->gm_h2.p, nullptr, nrm, c->red_work.p, st);
-      time_end(c, ts);
-      // a float refinement cycle ends when its estimate stalls (the float
-      // operator's own error floors it); the float64 refinement carries on
-      gmres_givens(K, m, j, c->gm_h1.p, c->gm_h2.p, nrm, rtol, one_cycle ? 0.9 : 0.0, S, st);
-      scale_cols<T>(nn, 4, K, W.w.p, S.scale, W.V.p + (size_t)(j + 1) * vs, st);
+      auto step = [&] {
+        T* Vj = W.V.p + (size_t)j * vs;
+        const long tp = time_begin(c, sizeof(T) == 4 ? "precond_f32" : "precond_f64");
+        precond_apply<T>(c, K, Vj, W.z.p);
+        time_end(c, tp);
+        op_apply<T>(c, 0, K, W.z.p, (const T*)nullptr, W.w.p, T(1), T(0));
+        // classical Gram-Schmidt, twice
+        const long ts = time_begin(c, sizeof(T) == 4 ? "arnoldi_cgs2_f32" : "arnoldi_cgs2_f64");
+        arnoldi_dots<T>(nn, 4, K, j, W.V.p, vs, W.w.p, c->gm_h1.p, c->red_work.p, st);
+        arnoldi_update<T>(nn, 4, K, j, W.V.p, vs, W.w.p, c->gm_h1.p, c->gm_h2.p, nullptr, c->red_work.p, st);
+        arnoldi_update<T>(nn, 4, K, j, W.V.p, vs, W.w.p, c->gm_h2.p, nullptr, nrm, c->red_work.p, st);
+        time_end(c, ts);
+        gmres_givens(K, m, j, c->gm_h1.p, c->gm_h2.p, nrm, rtol, stall, S, st);
+        scale_cols<T>(nn, 4, K, W.w.p, S.scale, W.V.p + (size_t)(j + 1) * vs, st);
+      };
+      // per-kernel timing needs eager launches
+      if (c->opt.use_graph && !c->ktime) run_step_graph<T>(c, K, j, rtol, stall, step);
+      else step();
       ++total;
       PHZ_HIP(hipMemcpyAsync(&nact, S.nactive, sizeof(int), hipMemcpyDeviceToHost, st));
       sync(c);
@@ -1113,6 +1214,7 @@ void phz_default_options(phz_options* o) {
   o->bf16_terms = 3;
   o->bf16_outer = 1;
   o->elem_tile = -1;
+  o->use_graph = 0;
 }
 
 const char* phz_strerror(int status) {
@@ -1129,6 +1231,7 @@ static int check_options(const phz_options* o, std::string& err) {
   if (o->bf16_terms != 1 && o->bf16_terms != 3) { err = "bf16_terms must be 1 or 3"; return PHZ_E_INVALID; }
   if (o->bf16_outer != 0 && o->bf16_outer != 1) { err = "bf16_outer must be 0 or 1"; return PHZ_E_INVALID; }
   if (o->elem_tile < -1 || o->elem_tile >= elem_tile_count()) { err = "elem_tile must be -1 or a tile index"; return PHZ_E_INVALID; }
+  if (o->use_graph != 0 && o->use_graph != 1) { err = "use_graph must be 0 or 1"; return PHZ_E_INVALID; }
   if (o->restart < 1 || o->restart > kMaxRestart) { err = "restart must be in [1, 32]"; return PHZ_E_INVALID; }
   if (o->max_iters < 1) { err = "max_iters must be >= 1"; return PHZ_E_INVALID; }
   if (!(o->rtol > 0 && o->rtol < 1)) { err = "rtol must be in (0, 1)"; return PHZ_E_INVALID; }
@@ -1167,6 +1270,8 @@ int phz_create(int n, const phz_material* mat, const phz_options* opt, void* str
     c->own_stream = true;
   }
   upload_reference(c.get());
+  static const double kOne = 1.0;
+  c->one64.upload(&kOne, 1, c->stream);
   c->phi.alloc(c->nn);
   c->rho.alloc(c->nn);
   c->s.alloc(c->nn);
@@ -1182,6 +1287,8 @@ void phz_destroy(phz_ctx* ctx) {
   if (!ctx) return;
   if (ctx->stream) hipStreamSynchronize(ctx->stream);
   for (hipEvent_t e : ctx->ev) hipEventDestroy(e);
+  phz::drop_graphs(ctx->graphs64);
+  phz::drop_graphs(ctx->graphs32);
   hipStream_t st = ctx->stream;
   bool own = ctx->own_stream;
   delete ctx;
@@ -1201,6 +1308,7 @@ int phz_set_options(phz_ctx* c, const phz_options* opt) {
   if (opt->elem_tile != c->opt.elem_tile || opt->bf16_terms != c->opt.bf16_terms)
     for (int op = 0; op < 4; ++op) c->elem_tile[op] = -1;
   c->opt = *opt;
+  ++c->graph_epoch;
   if (hier_change) c->precond_ready = false;
   ensure_state_buffers(c);
   return PHZ_OK;
