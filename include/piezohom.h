@@ -121,12 +121,11 @@ typedef struct {
                                GMRES operator on the matrix cores, 0 only the
                                preconditioner's fine blocks                    */
     int elem_tile;          /* PHZ_BF16X3_IR: workgroup tile of the element
-                               contraction, -1 (default) = timed choice per
-                               block at the first solve (autotune: every tile
-                               that divides N and the float32 gather kernel;
-                               a block whose gather kernel is faster stays on
-                               it), else an index in [0, 3): 8x8x4, 16x4x4,
-                               16x8x2 nodes, used for every block             */
+                               contraction, -1 (default) = the fastest tile
+                               that divides N, timed per block (and the block
+                               runs on whichever kernel, fine_kernel, timed
+                               fastest), else an index in [0, 3): 8x8x4,
+                               16x4x4, 16x8x2 nodes, used for every block    */
     int use_graph;          /* 1: each GMRES Arnoldi step (preconditioner,
                                operator, orthogonalisation, Givens update) is
                                captured once as a HIP graph and replayed; the
@@ -134,6 +133,13 @@ typedef struct {
                                re-captured when options or workspaces change.
                                Per-kernel timing (phz_kernel_timing) runs the
                                steps eagerly.  Default 0                      */
+    int fine_kernel;        /* float32 nine-column fine blocks: -1 (default)
+                               the fastest of those that apply, timed once per
+                               context; 0 the direct gather; 1 the gather with
+                               the input tile staged in LDS (N a multiple of
+                               16); 2 the element contraction (PHZ_BF16X3_IR).
+                               A kernel that does not apply falls back to 0.
+                               In PHZ_BF16X3_IR a fixed elem_tile selects 2. */
 } phz_options;
 
 typedef struct {
@@ -148,8 +154,11 @@ typedef struct {
     double cheb_lambda[16]; /* lambda_max estimates, A then S_bar per level     */
     int elem_tile[4];       /* PHZ_BF16X3_IR: tile used per fine block (full, A,
                                B, S_bar), -1 where the block is not on MFMA
-                               (bf16_outer = 0, no tile divides N, or the
-                               float32 gather kernel timed faster)            */
+                               (bf16_outer = 0, no tile divides N, or another
+                               kernel timed faster)                           */
+    int fine_kernel[4];     /* kernel of each fine block's float32 nine-column
+                               launches (fine_kernel codes), -1 if the solve
+                               has none (FP64, or loads one at a time)        */
 } phz_stats;
 
 typedef struct {

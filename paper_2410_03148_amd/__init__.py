@@ -37,14 +37,15 @@ class phz_options(C.Structure):
                 ("mg_levels", C.c_int), ("smooth_width", C.c_double), ("vcycles_a", C.c_int),
                 ("vcycles_s", C.c_int), ("inner_rtol", C.c_double), ("max_refine", C.c_int),
                 ("verbose", C.c_int), ("bf16_terms", C.c_int), ("bf16_outer", C.c_int),
-                ("elem_tile", C.c_int), ("use_graph", C.c_int)]
+                ("elem_tile", C.c_int), ("use_graph", C.c_int), ("fine_kernel", C.c_int)]
 
 
 class phz_stats(C.Structure):
     _fields_ = [("iterations", C.c_int * 9), ("restarts", C.c_int * 9), ("refinements", C.c_int),
                 ("true_residual", C.c_double * 9), ("flux_energy_defect", C.c_double),
                 ("setup_ms", C.c_double), ("solve_ms", C.c_double), ("mg_levels", C.c_int),
-                ("cheb_lambda", C.c_double * 16), ("elem_tile", C.c_int * 4)]
+                ("cheb_lambda", C.c_double * 16), ("elem_tile", C.c_int * 4),
+                ("fine_kernel", C.c_int * 4)]
 
 
 class phz_foms_t(C.Structure):
@@ -238,6 +239,7 @@ class Context:
             "flux_energy_defect": s.flux_energy_defect, "setup_ms": s.setup_ms,
             "solve_ms": s.solve_ms, "mg_levels": s.mg_levels,
             "cheb_lambda": list(s.cheb_lambda), "elem_tile": list(s.elem_tile),
+            "fine_kernel": list(s.fine_kernel),
         }
 
     def history(self, load):

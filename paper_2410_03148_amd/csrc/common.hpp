@@ -51,6 +51,13 @@ template <typename T>
 void fine_apply(int op, int nrhs, int N, const T* s, const T* kref, const T* x, const OpArgs<T>& a,
                 bool cheby, hipStream_t st);
 
+// The float32 fine-level gather with the workgroup's input tile (16 x 4 x 4
+// nodes and a one-node halo, all columns) staged in LDS; nine columns, N a
+// multiple of 16 (fine_tiled_fits).
+bool fine_tiled_fits(int N);
+void fine_apply_tiled(int op, int nrhs, int N, const float* s, const float* kref, const float* x,
+                      const OpArgs<float>& a, bool cheby, hipStream_t st);
+
 // Fine-level operator as an element contraction on MFMA in split-BF16
 // arithmetic (elem.hip), FP32 vectors, nine load columns.  kop holds the op's
 // reference block padded to 32 x 32 and split into bf16 hi and lo in MFMA

@@ -160,6 +160,128 @@ __global__ __launch_bounds__(128) void k_fine_apply(unsigned N, const T* __restr
   epilogue<T, FO, K, CHEBY>(n, nn, acc, a);
 }
 
+// ---------------------------------------------------------------------------
+// LDS-tiled variant of the float32 gather (nine load columns).  A workgroup
+// owns a GTX x GTY x GTZ tile of 256 output nodes (one per thread) and first
+// stages the tile's input nodes plus a one-node halo, all FI*K columns of
+// each, in LDS as rows of CP floats (CP = FI*K rounded up to a multiple of 4,
+// so a row is whole 16-byte words and eight consecutive rows of a wave's
+// ds_read_b128 phase fall on disjoint banks for CP = 12, 28 and 36).  The 27
+// neighbour records of every node are then LDS reads instead of global
+// loads; the block build and the epilogue are those of the direct gather.
+constexpr int GTX = 16, GTY = 4, GTZ = 4;
+constexpr int GNX = GTX + 2, GNY = GTY + 2, GNZ = GTZ + 2, GNI = GNX * GNY * GNZ;
+
+__device__ __forceinline__ unsigned wrap1(int v, unsigned N) {
+  return v < 0 ? (unsigned)(v + (int)N) : ((unsigned)v >= N ? (unsigned)v - N : (unsigned)v);
+}
+
+template <int FO, int FI, int K, int CP>
+__device__ __forceinline__ void tiled_neighbour(const float4* __restrict__ row, int dx, int dy, int dz,
+                                                const float* se, const float* kr, float* acc) {
+  float xv[CP];
+#pragma unroll
+  for (int c4 = 0; c4 < CP / 4; ++c4) {
+    const float4 v = row[c4];
+    xv[4 * c4] = v.x;
+    xv[4 * c4 + 1] = v.y;
+    xv[4 * c4 + 2] = v.z;
+    xv[4 * c4 + 3] = v.w;
+  }
+  float blk[FO * FI];
+#pragma unroll
+  for (int t = 0; t < FO * FI; ++t) blk[t] = 0.f;
+#pragma unroll
+  for (int c = 0; c < 8; ++c) {
+    const int mx = (c & 1) + dx, my = ((c >> 1) & 1) + dy, mz = ((c >> 2) & 1) + dz;
+    if (mx < 0 || mx > 1 || my < 0 || my > 1 || mz < 0 || mz > 1) continue;
+    const int lm = mx + 2 * my + 4 * mz;
+#pragma unroll
+    for (int fo = 0; fo < FO; ++fo)
+#pragma unroll
+      for (int fi = 0; fi < FI; ++fi) blk[fo * FI + fi] += se[c] * kr[(c * FO + fo) * (8 * FI) + lm * FI + fi];
+  }
+#pragma unroll
+  for (int fi = 0; fi < FI; ++fi)
+#pragma unroll
+    for (int kk = 0; kk < K; ++kk)
+#pragma unroll
+      for (int fo = 0; fo < FO; ++fo) acc[fo * K + kk] += blk[fo * FI + fi] * xv[fi * K + kk];
+}
+
+template <int FO, int FI, int K, bool CHEBY>
+__global__ __launch_bounds__(256) void k_fine_tiled(unsigned N, const float* __restrict__ s,
+                                                    const float* __restrict__ kref, const float* __restrict__ x,
+                                                    OpArgs<float> a) {
+  constexpr int C = FI * K, CP = (C + 3) / 4 * 4, NK = 64 * FO * FI;
+  __shared__ float kr[NK];
+  __shared__ float4 xs[GNI * (CP / 4)];
+  const unsigned nn = N * N * N;
+  const unsigned ntx = N / GTX, nty = N / GTY;
+  const unsigned b = xcd_block(blockIdx.x, gridDim.x);
+  const int x0 = (int)((b % ntx) * GTX), y0 = (int)(((b / ntx) % nty) * GTY), z0 = (int)((b / (ntx * nty)) * GTZ);
+  const int tid = threadIdx.x;
+  for (int t = tid; t < NK; t += 256) kr[t] = kref[t];
+  for (int q = tid; q < GNI; q += 256) {
+    const int li = q % GNX, lj = (q / GNX) % GNY, lk = q / (GNX * GNY);
+    const unsigned m = wrap1(x0 - 1 + li, N) + N * (wrap1(y0 - 1 + lj, N) + N * wrap1(z0 - 1 + lk, N));
+#pragma unroll
+    for (int c4 = 0; c4 < CP / 4; ++c4) {
+      float v[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int col = 4 * c4 + u;
+        v[u] = col < C ? x[(size_t)col * nn + m] : 0.f;
+      }
+      xs[q * (CP / 4) + c4] = make_float4(v[0], v[1], v[2], v[3]);
+    }
+  }
+  const int ti = tid % GTX, tj = (tid / GTX) % GTY, tk = tid / (GTX * GTY);
+  const unsigned n = (unsigned)(x0 + ti) + N * ((unsigned)(y0 + tj) + N * (unsigned)(z0 + tk));
+  // scale of the element whose corner c is this node (origin n - c)
+  float se[8];
+#pragma unroll
+  for (int c = 0; c < 8; ++c)
+    se[c] = s[wrap1(x0 + ti - (c & 1), N) + N * (wrap1(y0 + tj - ((c >> 1) & 1), N) + N * wrap1(z0 + tk - (c >> 2), N))];
+  float acc[FO * K];
+#pragma unroll
+  for (int t = 0; t < FO * K; ++t) acc[t] = 0.f;
+  __syncthreads();
+  const int qc = (ti + 1) + GNX * ((tj + 1) + GNY * (tk + 1));
+  if constexpr (fine_row_loop<float, FO, FI>()) {
+#pragma unroll 1
+    for (int r = 0; r < 9; ++r) {
+      const int dy = r % 3 - 1, dz = r / 3 - 1;
+      const float4* row = xs + (qc + GNX * (dy + GNY * dz)) * (CP / 4);
+      tiled_neighbour<FO, FI, K, CP>(row - CP / 4, -1, dy, dz, se, kr, acc);
+      tiled_neighbour<FO, FI, K, CP>(row, 0, dy, dz, se, kr, acc);
+      tiled_neighbour<FO, FI, K, CP>(row + CP / 4, 1, dy, dz, se, kr, acc);
+    }
+  } else {
+#pragma unroll
+    for (int d = 0; d < 27; ++d) {
+      const int dx = d % 3 - 1, dy = (d / 3) % 3 - 1, dz = d / 9 - 1;
+      tiled_neighbour<FO, FI, K, CP>(xs + (qc + dx + GNX * (dy + GNY * dz)) * (CP / 4), dx, dy, dz, se, kr, acc);
+    }
+  }
+  epilogue<float, FO, K, CHEBY>(n, nn, acc, a);
+}
+
+template <int OPV>
+void launch_tiled(unsigned N, const float* s, const float* kref, const float* x, const OpArgs<float>& a, bool cheby,
+                  hipStream_t st) {
+  constexpr int FO = OpFields<OPV>::FO, FI = OpFields<OPV>::FI;
+  const unsigned g = (N / GTX) * (N / GTY) * (N / GTZ);
+  if constexpr (FO == FI) {
+    if (cheby) {
+      hipLaunchKernelGGL((k_fine_tiled<FO, FI, 9, true>), dim3(g), dim3(256), 0, st, N, s, kref, x, a);
+      return;
+    }
+  }
+  if (cheby) throw std::invalid_argument("Chebyshev epilogue needs a square block");
+  hipLaunchKernelGGL((k_fine_tiled<FO, FI, 9, false>), dim3(g), dim3(256), 0, st, N, s, kref, x, a);
+}
+
 // Coarse levels: assembled 27-point node stencils S[(d*F + fo)*F + fi][n]
 // (block coupling node n to neighbour d).  KK = K: one thread per node and
 // all load columns (large levels: each stencil coefficient read once);
@@ -537,6 +659,21 @@ void fine_apply(int op, int nrhs, int N, const T* s, const T* kref, const T* x, 
     throw std::invalid_argument("fine_apply nrhs");
   }
 #undef PHZ_FA
+  PHZ_LAUNCH_CHECK();
+}
+
+bool fine_tiled_fits(int N) { return N >= GTX && N % GTX == 0 && N % GTY == 0 && N % GTZ == 0; }
+
+void fine_apply_tiled(int op, int nrhs, int N, const float* s, const float* kref, const float* x,
+                      const OpArgs<float>& a, bool cheby, hipStream_t st) {
+  if (nrhs != 9 || !fine_tiled_fits(N)) throw std::invalid_argument("fine_apply_tiled: nine columns, N a multiple of 16");
+  switch (op) {
+    case 0: launch_tiled<0>((unsigned)N, s, kref, x, a, cheby, st); break;
+    case 1: launch_tiled<1>((unsigned)N, s, kref, x, a, cheby, st); break;
+    case 2: launch_tiled<2>((unsigned)N, s, kref, x, a, cheby, st); break;
+    case 3: launch_tiled<3>((unsigned)N, s, kref, x, a, cheby, st); break;
+    default: throw std::invalid_argument("fine_apply_tiled op");
+  }
   PHZ_LAUNCH_CHECK();
 }
 

@@ -126,11 +126,11 @@ struct phz_ctx {
   phz::DevBuf<double> kref_full, kref_A, kref_B, kref_S, F0d;
   phz::DevBuf<float> kref32_full, kref32_A, kref32_B, kref32_S;
   // split-BF16 MFMA operands of the four fine blocks, their tile choice
-  // (-1 not yet chosen, -2 none divides N) and whether the block runs on
-  // MFMA (the timed choice may keep the float32 gather kernel)
+  // (-1 not yet chosen, -2 none divides N), and the kernel chosen for each
+  // block's float32 nine-column launches
   phz::DevBuf<unsigned short> kop[4];
   int elem_tile[4] = {-1, -1, -1, -1};
-  bool elem_use[4] = {false, false, false, false};
+  int fkind[4] = {-1, -1, -1, -1};   // kernel of the float32 nine-column launches, -1 not yet chosen
 
   phz::DevBuf<double> phi, rho, s, grad_rho, tmp_nodes;
   phz::DevBuf<float> s32;
@@ -393,83 +393,148 @@ static const char* elem_op_name(int op, bool three_terms, bool cheby) {
   return names[op][three_terms][cheby];
 }
 
-// Time block `op` (zero input, nine columns: the cost does not depend on the
-// values) as the element contraction with every tile shape that divides N,
-// and as the float32 gather kernel.  Sets c->elem_tile[op] to the fastest
-// tile (-2 if none fits) and c->elem_use[op] to whether it beats the gather.
-static void autotune_elem(phz_ctx* c, int op) {
-  const int fo = op == 0 ? 4 : op == 1 ? 3 : 1, fi = op == 0 ? 4 : op == 3 ? 1 : 3;
-  DevBuf<float> xb, yb;
-  xb.alloc((size_t)fi * 9 * c->nn);
-  yb.alloc((size_t)fo * 9 * c->nn);
-  PHZ_HIP(hipMemsetAsync(xb.p, 0, xb.n * sizeof(float), c->stream));
-  const OpArgs<float> a = plain_args<float>(nullptr, yb.p, 1.0f, 0.0f);
+// Kinds of a float32 nine-column fine-block launch.
+enum { kFineDirect = 0, kFineTiled = 1, kFineElem = 2 };
+
+static const char* tiled_op_name(int op, bool cheby) {
+  static const char* names[4][2] = {{"tiled_full_k9_f32", "tiled_full_k9_f32_cheby"},
+                                    {"tiled_A_k9_f32", "tiled_A_k9_f32_cheby"},
+                                    {"tiled_B_k9_f32", "tiled_B_k9_f32_cheby"},
+                                    {"tiled_S_k9_f32", "tiled_S_k9_f32_cheby"}};
+  return names[op][cheby];
+}
+
+// Average time of a launch over three repetitions after one warm-up (HIP
+// events on the context stream).
+template <typename F>
+static float time_launch(phz_ctx* c, F&& launch) {
   hipEvent_t e0, e1;
   PHZ_HIP(hipEventCreate(&e0));
   PHZ_HIP(hipEventCreate(&e1));
-  auto timed = [&](auto&& launch) {
-    launch();
-    PHZ_HIP(hipEventRecord(e0, c->stream));
-    for (int r = 0; r < 3; ++r) launch();
-    PHZ_HIP(hipEventRecord(e1, c->stream));
-    PHZ_HIP(hipEventSynchronize(e1));
-    float ms = 0.0f;
-    PHZ_HIP(hipEventElapsedTime(&ms, e0, e1));
-    return ms;
-  };
-  int best = -2;
-  float best_ms = 0.0f;
-  for (int t = 0; t < elem_tile_count(); ++t) {
-    if (!elem_tile_fits(c->N, t)) continue;
-    const float ms = timed([&] {
-      elem_apply(op, 9, c->N, c->opt.bf16_terms, t, c->s32.p, c->kop[op].p, xb.p, a, false, c->stream);
-    });
-    if (best < 0 || ms < best_ms) {
-      best = t;
-      best_ms = ms;
-    }
-  }
-  const float gather_ms =
-      timed([&] { fine_apply<float>(op, 9, c->N, c->s32.p, kref_of<float>(c, op), xb.p, a, false, c->stream); });
+  launch();
+  PHZ_HIP(hipEventRecord(e0, c->stream));
+  for (int r = 0; r < 3; ++r) launch();
+  PHZ_HIP(hipEventRecord(e1, c->stream));
+  PHZ_HIP(hipEventSynchronize(e1));
+  float ms = 0.0f;
+  PHZ_HIP(hipEventElapsedTime(&ms, e0, e1));
   hipEventDestroy(e0);
   hipEventDestroy(e1);
-  c->elem_tile[op] = best;
-  c->elem_use[op] = best >= 0 && best_ms < gather_ms;
+  return ms;
+}
+
+// Zero input and an output buffer for timing block `op` (the cost does not
+// depend on the values).
+struct TuneBufs {
+  DevBuf<float> x, y;
+  OpArgs<float> a;
+};
+static void tune_bufs(phz_ctx* c, int op, TuneBufs& b) {
+  const int fo = op == 0 ? 4 : op == 1 ? 3 : 1, fi = op == 0 ? 4 : op == 3 ? 1 : 3;
+  b.x.alloc((size_t)fi * 9 * c->nn);
+  b.y.alloc((size_t)fo * 9 * c->nn);
+  PHZ_HIP(hipMemsetAsync(b.x.p, 0, b.x.n * sizeof(float), c->stream));
+  b.a = plain_args<float>(nullptr, b.y.p, 1.0f, 0.0f);
+}
+
+// Whether block `op` may run as the split-BF16 element contraction: the
+// PHZ_BF16X3_IR form, and for the full operator only with bf16_outer.
+static bool elem_eligible(phz_ctx* c, int op) {
+  return c->opt.precision == PHZ_BF16X3_IR && (op != 0 || c->opt.bf16_outer);
 }
 
 // Tile of the element contraction for block `op`: the option's choice, or
-// the autotuned one (timed once per context); -1 if no tile divides N.
+// the fastest tile that divides N (timed once per context); -1 if none fits.
 static int elem_tile_of(phz_ctx* c, int op) {
   if (c->elem_tile[op] == -1) {
     if (c->opt.elem_tile >= 0) {
       c->elem_tile[op] = elem_tile_fits(c->N, c->opt.elem_tile) ? c->opt.elem_tile : -2;
-      c->elem_use[op] = c->elem_tile[op] >= 0;
     } else {
-      autotune_elem(c, op);
+      TuneBufs b;
+      tune_bufs(c, op, b);
+      int best = -2;
+      float best_ms = 0.0f;
+      for (int t = 0; t < elem_tile_count(); ++t) {
+        if (!elem_tile_fits(c->N, t)) continue;
+        const float ms = time_launch(c, [&] {
+          elem_apply(op, 9, c->N, c->opt.bf16_terms, t, c->s32.p, c->kop[op].p, b.x.p, b.a, false, c->stream);
+        });
+        if (best < 0 || ms < best_ms) {
+          best = t;
+          best_ms = ms;
+        }
+      }
+      c->elem_tile[op] = best;
     }
   }
   return c->elem_tile[op] >= 0 ? c->elem_tile[op] : -1;
 }
 
-// Whether block `op` of a K-column float solve runs as the split-BF16 element
-// contraction: PHZ_BF16X3_IR, the preconditioner's blocks (A, B, S_bar) and
-// the full operator too if bf16_outer, nine columns, a tile dividing N, and
-// (with the timed tile choice) faster than the float32 gather kernel.
-static bool use_elem(phz_ctx* c, int op, int K) {
-  if (c->opt.precision != PHZ_BF16X3_IR || K != 9) return false;
-  if (op == 0 && !c->opt.bf16_outer) return false;
-  return elem_tile_of(c, op) >= 0 && c->elem_use[op];
+// Kernel of the float32 nine-column launches of block `op`:
+//  * PHZ_BF16X3_IR with a fixed elem_tile: the element contraction;
+//  * fine_kernel >= 0: that kernel where it applies, else the direct gather;
+//  * otherwise the fastest of the direct gather, the LDS-tiled gather (N a
+//    multiple of 16) and, where eligible, the element contraction on its
+//    best tile, timed once per context.
+static int fine_kind_of(phz_ctx* c, int op) {
+  if (c->fkind[op] >= 0) return c->fkind[op];
+  const bool elem_ok = elem_eligible(c, op);
+  const bool tiled_ok = fine_tiled_fits(c->N);
+  int kind = kFineDirect;
+  if (elem_ok && c->opt.elem_tile >= 0 && elem_tile_of(c, op) >= 0) {
+    kind = kFineElem;
+  } else if (c->opt.fine_kernel >= 0) {
+    kind = c->opt.fine_kernel;
+    if ((kind == kFineTiled && !tiled_ok) || (kind == kFineElem && !(elem_ok && elem_tile_of(c, op) >= 0)))
+      kind = kFineDirect;
+  } else {
+    TuneBufs b;
+    tune_bufs(c, op, b);
+    float best_ms = time_launch(c, [&] {
+      fine_apply<float>(op, 9, c->N, c->s32.p, kref_of<float>(c, op), b.x.p, b.a, false, c->stream);
+    });
+    if (tiled_ok) {
+      const float ms = time_launch(c, [&] {
+        fine_apply_tiled(op, 9, c->N, c->s32.p, kref_of<float>(c, op), b.x.p, b.a, false, c->stream);
+      });
+      if (ms < best_ms) {
+        best_ms = ms;
+        kind = kFineTiled;
+      }
+    }
+    if (elem_ok && elem_tile_of(c, op) >= 0) {
+      const int t = c->elem_tile[op];
+      const float ms = time_launch(c, [&] {
+        elem_apply(op, 9, c->N, c->opt.bf16_terms, t, c->s32.p, c->kop[op].p, b.x.p, b.a, false, c->stream);
+      });
+      if (ms < best_ms) {
+        best_ms = ms;
+        kind = kFineElem;
+      }
+    }
+  }
+  c->fkind[op] = kind;
+  return kind;
 }
 
 // fine-level operator launch with optional timing
 template <typename T>
 static void op_apply_args(phz_ctx* c, int op, int K, const T* x, const OpArgs<T>& a, bool cheby) {
   if constexpr (std::is_same<T, float>::value) {
-    if (use_elem(c, op, K)) {
-      const long slot = time_begin(c, elem_op_name(op, c->opt.bf16_terms == 3, cheby));
-      elem_apply(op, K, c->N, c->opt.bf16_terms, c->elem_tile[op], c->s32.p, c->kop[op].p, x, a, cheby, c->stream);
-      time_end(c, slot);
-      return;
+    if (K == 9) {
+      const int kind = fine_kind_of(c, op);
+      if (kind == kFineElem) {
+        const long slot = time_begin(c, elem_op_name(op, c->opt.bf16_terms == 3, cheby));
+        elem_apply(op, K, c->N, c->opt.bf16_terms, c->elem_tile[op], c->s32.p, c->kop[op].p, x, a, cheby, c->stream);
+        time_end(c, slot);
+        return;
+      }
+      if (kind == kFineTiled) {
+        const long slot = time_begin(c, tiled_op_name(op, cheby));
+        fine_apply_tiled(op, K, c->N, c->s32.p, kref_of<float>(c, op), x, a, cheby, c->stream);
+        time_end(c, slot);
+        return;
+      }
     }
   }
   const long slot = time_begin(c, fine_op_name(op, K, sizeof(T) == 4, cheby));
@@ -652,10 +717,16 @@ static void drop_level_work_if_changed(phz_ctx* c, Work<T>& W) {
 
 static void setup_preconditioner(phz_ctx* c) {
   if (c->precond_ready) return;
-  for (int op = 0; op < 4; ++op) c->stats.elem_tile[op] = -1;
-  if (c->opt.precision == PHZ_BF16X3_IR)
-    for (int op = (c->opt.bf16_outer ? 0 : 1); op < 4; ++op)
-      c->stats.elem_tile[op] = use_elem(c, op, 9) ? c->elem_tile[op] : -1;
+  // choose (time) the float32 kernels before any solve launches them, so no
+  // tuning runs inside a solve or a graph capture
+  for (int op = 0; op < 4; ++op) {
+    c->stats.elem_tile[op] = -1;
+    c->stats.fine_kernel[op] = -1;
+    if (c->opt.precision != PHZ_FP64 && c->opt.batched) {
+      c->stats.fine_kernel[op] = fine_kind_of(c, op);
+      if (c->stats.fine_kernel[op] == kFineElem) c->stats.elem_tile[op] = c->elem_tile[op];
+    }
+  }
   build_levels(c, c->hA, 3, 1);
   build_levels(c, c->hS, 1, 3);
   drop_level_work_if_changed(c, c->w64);
@@ -1215,6 +1286,7 @@ void phz_default_options(phz_options* o) {
   o->bf16_outer = 1;
   o->elem_tile = -1;
   o->use_graph = 0;
+  o->fine_kernel = -1;
 }
 
 const char* phz_strerror(int status) {
@@ -1232,6 +1304,7 @@ static int check_options(const phz_options* o, std::string& err) {
   if (o->bf16_outer != 0 && o->bf16_outer != 1) { err = "bf16_outer must be 0 or 1"; return PHZ_E_INVALID; }
   if (o->elem_tile < -1 || o->elem_tile >= elem_tile_count()) { err = "elem_tile must be -1 or a tile index"; return PHZ_E_INVALID; }
   if (o->use_graph != 0 && o->use_graph != 1) { err = "use_graph must be 0 or 1"; return PHZ_E_INVALID; }
+  if (o->fine_kernel < -1 || o->fine_kernel > 2) { err = "fine_kernel must be -1, 0, 1 or 2"; return PHZ_E_INVALID; }
   if (o->restart < 1 || o->restart > kMaxRestart) { err = "restart must be in [1, 32]"; return PHZ_E_INVALID; }
   if (o->max_iters < 1) { err = "max_iters must be >= 1"; return PHZ_E_INVALID; }
   if (!(o->rtol > 0 && o->rtol < 1)) { err = "rtol must be in (0, 1)"; return PHZ_E_INVALID; }
@@ -1257,7 +1330,7 @@ int phz_create(int n, const phz_material* mat, const phz_options* opt, void* str
   c->N = n;
   c->nn = (long)n * n * n;
   c->mat = *mat;
-  for (int op = 0; op < 4; ++op) c->stats.elem_tile[op] = -1;
+  for (int op = 0; op < 4; ++op) c->stats.elem_tile[op] = c->stats.fine_kernel[op] = -1;
   if (opt) c->opt = *opt;
   else phz_default_options(&c->opt);
   std::string err;
@@ -1305,8 +1378,10 @@ int phz_set_options(phz_ctx* c, const phz_options* opt) {
     c->w64.cap_m = 0;
     c->w32.cap_m = 0;
   }
-  if (opt->elem_tile != c->opt.elem_tile || opt->bf16_terms != c->opt.bf16_terms)
-    for (int op = 0; op < 4; ++op) c->elem_tile[op] = -1;
+  for (int op = 0; op < 4; ++op) {
+    c->elem_tile[op] = -1;
+    c->fkind[op] = -1;
+  }
   c->opt = *opt;
   ++c->graph_epoch;
   if (hier_change) c->precond_ready = false;
