@@ -27,7 +27,8 @@ sys.path.insert(0, ROOT)
 import numpy as np  # noqa: E402
 
 # Algorithmic work per node of a fine-level operator launch, by timing label
-# (fine_<block>_k<K>_<f32|f64>[_cheby] for the float gather kernels,
+# (fine_<block>_k<K>_<f32|f64>[_cheby] for the direct gather kernels,
+# tiled_<block>_k9_f32[_cheby] for the LDS-tiled gather, and
 # elem_<block>_k<K>_bf16x<T>[_cheby] for the element contraction on MFMA).
 # Gather form: flops = 2 (64 FO FI + 27 FO FI K) (block build + apply).
 # Element form: T split products of the element block, 2 T (8 FO)(8 FI) K per
@@ -190,7 +191,51 @@ def main():
     stats = ctx.stats()
     ktimes = ctx.kernel_times()
     ctx.kernel_timing(False)
+    # the gradient pass on its own (part of every step above): d_h's density
+    # sensitivities of a fresh solve (each step's HJ update moved the geometry)
+    ctx.set_levelset(phi_d)
+    ctx.solve()
+    Cm_, e_, k_ = ctx.effective()
+    _, (gC_, ge_, gk_) = P.foms(Cm_, e_, k_, grad_of="d_h")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(5):
+        ctx.backward(gC_, ge_, gk_, out_rho=grad_d)
+    torch.cuda.synchronize()
+    backward_ms = (time.perf_counter() - t0) / 5 * 1e3
     ctx.close()
+
+    def operator_bench(form, prec_code, apply_code, reps=50):
+        """Median of `reps` full-operator applies (9 columns) after 5 warm-ups."""
+        c = make_ctx(form)
+        c.set_levelset(phi_d)
+        dt = torch.float64 if apply_code == P.PHZ_FP64 else torch.float32
+        xb = torch.randn((4, 9, n ** 3), dtype=dt, device=dev)
+        yb = torch.empty_like(xb)
+        for _ in range(5):
+            c.apply(P.OP_FULL, 9, apply_code, xb.data_ptr(), yb.data_ptr())
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+        for a, b in evs:
+            a.record(stream)
+            c.apply(P.OP_FULL, 9, apply_code, xb.data_ptr(), yb.data_ptr())
+            b.record(stream)
+        torch.cuda.synchronize()
+        t = float(np.median([a.elapsed_time(b) for a, b in evs])) * 1e-3
+        kind = c.stats()["fine_kernel"][0] if apply_code == P.PHZ_FP32_IR else None
+        c.close()
+        w = 8 if apply_code == P.PHZ_FP64 else 4
+        nbytes = (4 * 9 + 1 + 4 * 9) * w * n ** 3
+        return {"median_ms": t * 1e3, "GB/s": nbytes / t / 1e9, "hbm_frac": nbytes / t / 8e12,
+                "algorithmic_bytes": nbytes, "kernel": {None: "gather_f64" if w == 8 else "elem_bf16x3",
+                                                        0: "gather_f32", 1: "tiled_gather_f32",
+                                                        2: "elem_bf16x3"}[kind]}
+
+    op_bench = {}
+    if not args.no_compare:
+        op_bench["fp64"] = operator_bench("fp64", P.PHZ_FP64, P.PHZ_FP64)
+        op_bench["fp32"] = operator_bench("fp32ir", P.PHZ_FP32_IR, P.PHZ_FP32_IR)
+        op_bench["bf16x3"] = operator_bench("bf16x3ir", P.PHZ_BF16X3_IR, P.PHZ_BF16X3_IR)
+        log("operator benchmark done")
 
     result = {
         "metric": "128\u00b3 9-load homogenisation solves/s, mixed vs FP64 at \u22641e-6 rel err; op GB/s",
@@ -215,12 +260,12 @@ def main():
     }
 
     # dominant single kernel from the live event timing of the timed steps
-    single = {k: v for k, v in ktimes.items() if k.startswith(("fine_", "elem_", "coarse_"))}
+    single = {k: v for k, v in ktimes.items() if k.startswith(("fine_", "tiled_", "elem_", "coarse_"))}
     if single:
         name = max(single, key=lambda k: single[k][1])
         cnt, tot = single[name]
         avg_s = tot / cnt * 1e-3
-        if name.startswith(("fine_", "elem_")):
+        if name.startswith(("fine_", "tiled_", "elem_")):
             fl, by, p = per_node(name)
             flops = fl * n ** 3
             nbytes = by * n ** 3
@@ -242,7 +287,7 @@ def main():
         result["kernel_ms_per_step"] = {k: v[1] / args.steps for k, v in sorted(ktimes.items())}
         # the outer operator apply (all four fields, nine loads) as achieved
         # algorithmic HBM bandwidth
-        ops = {k: v for k, v in ktimes.items() if k.startswith(("fine_full_k9", "elem_full_k9"))}
+        ops = {k: v for k, v in ktimes.items() if k.startswith(("fine_full_k9", "tiled_full_k9", "elem_full_k9"))}
         if ops:
             name = max(ops, key=lambda k: ops[k][1])
             cnt, tot = ops[name]
@@ -250,6 +295,10 @@ def main():
             fl, by, _ = per_node(name)
             result["operator"] = {"kernel": name, "avg_ms": avg_s * 1e3, "GB/s": by * n ** 3 / avg_s / 1e9,
                                   "hbm_frac": by * n ** 3 / avg_s / 8e12, "TFLOP/s": fl * n ** 3 / avg_s / 1e12}
+    if op_bench:
+        # y = calA x on all nine columns, 50 timed applies each, median
+        result.setdefault("operator", {})["apply_median"] = op_bench
+    result["backward_ms"] = backward_ms
 
     if not args.no_compare and prec != P.PHZ_FP64:
         cmp = {}
@@ -264,19 +313,20 @@ def main():
             c64.close()
             errs = {nm: float(np.linalg.norm(a - b) / np.linalg.norm(b)) for nm, a, b in zip(("C", "e", "kappa"), tens, t64)}
             cmp[form] = {"solves_per_s": 1.0 / ms64, "speedup_of_mixed": ms64 / ms, "status": st64,
-                         "iterations_max": max(s64["iterations"]), "restart": forms[form]["restart"],
+                         "iterations_max": max(s64["iterations"]), "refinements": s64["refinements"],
+                         "true_residual_max": max(s64["true_residual"]), "restart": forms[form]["restart"],
                          "rel_err_of_mixed": errs, "max_rel_err_of_mixed": max(errs.values())}
             log(f"{form} comparison done")
         result["compare"] = cmp
 
     if not args.no_cpu:
-        log("cpu oracle baseline (16^3 sample)")
-        t_cpu = cpu_baseline(16)
+        log("cpu oracle baseline (16^3 sample, median of 3)")
+        t_cpu = float(np.median([cpu_baseline(16) for _ in range(3)]))
         result["cpu_baseline"] = {
             "value": (16 ** 3 / n ** 3) / t_cpu, "unit": "solves/s", "cores": 1, "kind": "oracle",
-            "sample": f"one 16^3 nine-load oracle homogenisation (sparse LU, 16,384 dofs) took {t_cpu:.2f} s on "
-                      f"one host core; value scales it linearly in dofs to {n}^3 (optimistic: LU cost grows "
-                      "faster than linearly)",
+            "sample": f"a 16^3 nine-load oracle homogenisation (sparse LU, 16,384 dofs; median of 3 runs) took "
+                      f"{t_cpu:.2f} s on one host core; value scales it linearly in dofs to {n}^3 (optimistic: "
+                      "LU cost grows faster than linearly)",
             "host_cores_available": len(os.sched_getaffinity(0)),
         }
     print(json.dumps(result))

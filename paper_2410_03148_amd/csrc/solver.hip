@@ -514,6 +514,8 @@ static int fine_kind_of(phz_ctx* c, int op) {
     }
   }
   c->fkind[op] = kind;
+  c->stats.fine_kernel[op] = kind;
+  c->stats.elem_tile[op] = kind == kFineElem ? c->elem_tile[op] : -1;
   return kind;
 }
 
