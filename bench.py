@@ -61,10 +61,11 @@ def per_node(name):
     return flops, words * w, prec
 
 
-def measured_traffic(label):
+def measured_traffic(label, tile=None):
     """HBM bytes per launch of a timing label from the committed counter runs
     (FETCH_SIZE and WRITE_SIZE, each scaled by a plain copy kernel), or None
-    when the kernel source has changed since the counters were taken."""
+    when the kernel source has changed since the counters were taken or, for
+    the element contraction, the run used another workgroup tile."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
     if not os.path.exists(path):
@@ -72,7 +73,7 @@ def measured_traffic(label):
     with open(path) as f:
         rec = json.load(f)
     k = rec["kernels"].get(label)
-    if k is None:
+    if k is None or k.get("tile") != tile:
         return None
     with open(os.path.join(ROOT, k["source"]), "rb") as f:
         if hashlib.sha256(f.read()).hexdigest() != k["source_sha256"]:
@@ -112,6 +113,11 @@ def main():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first run a plain device copy kernel (y = -x, fp32) over MIB MiB three times, "
                          "to scale hardware byte counters")
+    ap.add_argument("--block-kernels", default=None, metavar="K0,K1,K2,K3",
+                    help="pin the fine blocks' (full, A, B, S) float kernels, as reported in config.fine_kernels "
+                         "(-1 = timed choice); for profiling runs whose timing would change the choice")
+    ap.add_argument("--block-tiles", default=None, metavar="T0,T1,T2,T3",
+                    help="pin the element-contraction tile per fine block (-1 = timed choice)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the solve runs on a single MI355X; "
@@ -144,8 +150,15 @@ def main():
         "fp64_sequential": dict(precision=P.PHZ_FP64, batched=0, restart=30, vcycles_a=2),
     }
 
+    pins = {}
+    if args.block_kernels:
+        pins["block_kernel"] = [int(v) for v in args.block_kernels.split(",")]
+    if args.block_tiles:
+        pins["block_tile"] = [int(v) for v in args.block_tiles.split(",")]
+
     def make_ctx(form):
-        return P.Context(n, mat, stream=stream.cuda_stream, rtol=1e-10, **forms[form])
+        return P.Context(n, mat, stream=stream.cuda_stream, rtol=1e-10, **forms[form],
+                         **(pins if form == args.precision else {}))
 
     grad_d = torch.empty(n ** 3, dtype=torch.float64, device=dev)
 
@@ -256,7 +269,7 @@ def main():
                    "iterations_max": max(stats["iterations"]), "refinements": stats["refinements"],
                    "true_residual_max": max(stats["true_residual"]),
                    "setup_ms": stats["setup_ms"], "solve_ms": stats["solve_ms"],
-                   "mfma_tiles_full_A_B_S": stats["elem_tile"]},
+                   "fine_kernels": stats["fine_kernel"], "mfma_tiles_full_A_B_S": stats["elem_tile"]},
     }
 
     # dominant single kernel from the live event timing of the timed steps
@@ -273,7 +286,8 @@ def main():
             # published MI355X peaks: fp64 78.6, fp32 vector 157.3, dense bf16 MFMA 2500 TFLOP/s
             peak_tf = {"f64": 78.6, "f32": 157.3}.get(p, 2500.0)
             ridge = peak_tf * 1e12 / 8e12
-            traffic = measured_traffic(name)
+            tile = stats["elem_tile"][list(OPS).index(name.split("_")[1])] if name.startswith("elem_") else None
+            traffic = measured_traffic(name, tile)
             if ai > ridge:
                 result["roofline"] = {"bound": "mfma" if name.startswith("elem_") else "alu", "achieved": flops / avg_s / 1e12, "peak": peak_tf,
                                       "unit": "TFLOP/s", "frac": flops / avg_s / 1e12 / peak_tf,

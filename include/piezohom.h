@@ -124,7 +124,9 @@ typedef struct {
                                contraction, -1 (default) = the fastest tile
                                that divides N, timed per block (and the block
                                runs on whichever kernel, fine_kernel, timed
-                               fastest), else an index in [0, 3): 8x8x4,
+                               fastest; in both choices a later candidate
+                               must be more than 3% faster to replace an
+                               earlier one), else an index in [0, 3): 8x8x4,
                                16x4x4, 16x8x2 nodes, used for every block    */
     int use_graph;          /* 1: each GMRES Arnoldi step (preconditioner,
                                operator, orthogonalisation, Givens update) is
@@ -140,6 +142,14 @@ typedef struct {
                                16); 2 the element contraction (PHZ_BF16X3_IR).
                                A kernel that does not apply falls back to 0.
                                In PHZ_BF16X3_IR a fixed elem_tile selects 2. */
+    int block_kernel[4];    /* per fine block (full, A, B, S_bar): -1 (default)
+                               follows elem_tile / fine_kernel above, else pins
+                               that block's float32 nine-column kernel (0, 1, 2
+                               as in fine_kernel; one that does not apply falls
+                               back to 0).  For reproducible profiling: pin
+                               the choice that phz_get_stats reported        */
+    int block_tile[4];      /* per fine block: -1 (default) follows elem_tile,
+                               else pins the element-contraction tile index  */
 } phz_options;
 
 typedef struct {

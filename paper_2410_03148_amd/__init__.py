@@ -37,7 +37,20 @@ class phz_options(C.Structure):
                 ("mg_levels", C.c_int), ("smooth_width", C.c_double), ("vcycles_a", C.c_int),
                 ("vcycles_s", C.c_int), ("inner_rtol", C.c_double), ("max_refine", C.c_int),
                 ("verbose", C.c_int), ("bf16_terms", C.c_int), ("bf16_outer", C.c_int),
-                ("elem_tile", C.c_int), ("use_graph", C.c_int), ("fine_kernel", C.c_int)]
+                ("elem_tile", C.c_int), ("use_graph", C.c_int), ("fine_kernel", C.c_int),
+                ("block_kernel", C.c_int * 4), ("block_tile", C.c_int * 4)]
+
+
+def _set_option(o, k, v):
+    if not hasattr(o, k):
+        raise TypeError(f"unknown option {k!r}")
+    cur = getattr(o, k)
+    if isinstance(cur, C.Array):
+        if len(v) != len(cur):
+            raise ValueError(f"option {k!r} takes {len(cur)} values")
+        cur[:] = [int(x) for x in v]
+    else:
+        setattr(o, k, v)
 
 
 class phz_stats(C.Structure):
@@ -115,9 +128,7 @@ def default_options(**overrides):
     o = phz_options()
     _lib.phz_default_options(C.byref(o))
     for k, v in overrides.items():
-        if not hasattr(o, k):
-            raise TypeError(f"unknown option {k!r}")
-        setattr(o, k, v)
+        _set_option(o, k, v)
     return o
 
 
@@ -200,7 +211,7 @@ class Context:
 
     def set_options(self, **opts):
         for k, v in opts.items():
-            setattr(self._opt, k, v)
+            _set_option(self._opt, k, v)
         self._check(_lib.phz_set_options(self._h, C.byref(self._opt)), "phz_set_options")
 
     def set_levelset(self, phi):

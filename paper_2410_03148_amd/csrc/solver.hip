@@ -443,12 +443,18 @@ static bool elem_eligible(phz_ctx* c, int op) {
   return c->opt.precision == PHZ_BF16X3_IR && (op != 0 || c->opt.bf16_outer);
 }
 
+// A timed candidate replaces the current choice only when it is more than 3%
+// faster, so that near-equal candidates resolve to the earlier one in the
+// fixed candidate order instead of to launch-to-launch noise.
+static bool clearly_faster(float ms, float best_ms) { return ms < 0.97f * best_ms; }
+
 // Tile of the element contraction for block `op`: the option's choice, or
 // the fastest tile that divides N (timed once per context); -1 if none fits.
 static int elem_tile_of(phz_ctx* c, int op) {
   if (c->elem_tile[op] == -1) {
-    if (c->opt.elem_tile >= 0) {
-      c->elem_tile[op] = elem_tile_fits(c->N, c->opt.elem_tile) ? c->opt.elem_tile : -2;
+    const int pinned = c->opt.block_tile[op] >= 0 ? c->opt.block_tile[op] : c->opt.elem_tile;
+    if (pinned >= 0) {
+      c->elem_tile[op] = elem_tile_fits(c->N, pinned) ? pinned : -2;
     } else {
       TuneBufs b;
       tune_bufs(c, op, b);
@@ -459,7 +465,7 @@ static int elem_tile_of(phz_ctx* c, int op) {
         const float ms = time_launch(c, [&] {
           elem_apply(op, 9, c->N, c->opt.bf16_terms, t, c->s32.p, c->kop[op].p, b.x.p, b.a, false, c->stream);
         });
-        if (best < 0 || ms < best_ms) {
+        if (best < 0 || clearly_faster(ms, best_ms)) {
           best = t;
           best_ms = ms;
         }
@@ -471,6 +477,8 @@ static int elem_tile_of(phz_ctx* c, int op) {
 }
 
 // Kernel of the float32 nine-column launches of block `op`:
+//  * block_kernel[op] >= 0: that kernel where it applies, else the direct
+//    gather;
 //  * PHZ_BF16X3_IR with a fixed elem_tile: the element contraction;
 //  * fine_kernel >= 0: that kernel where it applies, else the direct gather;
 //  * otherwise the fastest of the direct gather, the LDS-tiled gather (N a
@@ -481,10 +489,10 @@ static int fine_kind_of(phz_ctx* c, int op) {
   const bool elem_ok = elem_eligible(c, op);
   const bool tiled_ok = fine_tiled_fits(c->N);
   int kind = kFineDirect;
-  if (elem_ok && c->opt.elem_tile >= 0 && elem_tile_of(c, op) >= 0) {
+  if (c->opt.block_kernel[op] < 0 && elem_ok && c->opt.elem_tile >= 0 && elem_tile_of(c, op) >= 0) {
     kind = kFineElem;
-  } else if (c->opt.fine_kernel >= 0) {
-    kind = c->opt.fine_kernel;
+  } else if (c->opt.block_kernel[op] >= 0 || c->opt.fine_kernel >= 0) {
+    kind = c->opt.block_kernel[op] >= 0 ? c->opt.block_kernel[op] : c->opt.fine_kernel;
     if ((kind == kFineTiled && !tiled_ok) || (kind == kFineElem && !(elem_ok && elem_tile_of(c, op) >= 0)))
       kind = kFineDirect;
   } else {
@@ -497,7 +505,7 @@ static int fine_kind_of(phz_ctx* c, int op) {
       const float ms = time_launch(c, [&] {
         fine_apply_tiled(op, 9, c->N, c->s32.p, kref_of<float>(c, op), b.x.p, b.a, false, c->stream);
       });
-      if (ms < best_ms) {
+      if (clearly_faster(ms, best_ms)) {
         best_ms = ms;
         kind = kFineTiled;
       }
@@ -507,7 +515,7 @@ static int fine_kind_of(phz_ctx* c, int op) {
       const float ms = time_launch(c, [&] {
         elem_apply(op, 9, c->N, c->opt.bf16_terms, t, c->s32.p, c->kop[op].p, b.x.p, b.a, false, c->stream);
       });
-      if (ms < best_ms) {
+      if (clearly_faster(ms, best_ms)) {
         best_ms = ms;
         kind = kFineElem;
       }
@@ -1289,6 +1297,7 @@ void phz_default_options(phz_options* o) {
   o->elem_tile = -1;
   o->use_graph = 0;
   o->fine_kernel = -1;
+  for (int op = 0; op < 4; ++op) o->block_kernel[op] = o->block_tile[op] = -1;
 }
 
 const char* phz_strerror(int status) {
@@ -1307,6 +1316,13 @@ static int check_options(const phz_options* o, std::string& err) {
   if (o->elem_tile < -1 || o->elem_tile >= elem_tile_count()) { err = "elem_tile must be -1 or a tile index"; return PHZ_E_INVALID; }
   if (o->use_graph != 0 && o->use_graph != 1) { err = "use_graph must be 0 or 1"; return PHZ_E_INVALID; }
   if (o->fine_kernel < -1 || o->fine_kernel > 2) { err = "fine_kernel must be -1, 0, 1 or 2"; return PHZ_E_INVALID; }
+  for (int op = 0; op < 4; ++op) {
+    if (o->block_kernel[op] < -1 || o->block_kernel[op] > 2) { err = "block_kernel entries must be -1, 0, 1 or 2"; return PHZ_E_INVALID; }
+    if (o->block_tile[op] < -1 || o->block_tile[op] >= elem_tile_count()) {
+      err = "block_tile entries must be -1 or a tile index";
+      return PHZ_E_INVALID;
+    }
+  }
   if (o->restart < 1 || o->restart > kMaxRestart) { err = "restart must be in [1, 32]"; return PHZ_E_INVALID; }
   if (o->max_iters < 1) { err = "max_iters must be >= 1"; return PHZ_E_INVALID; }
   if (!(o->rtol > 0 && o->rtol < 1)) { err = "rtol must be in (0, 1)"; return PHZ_E_INVALID; }

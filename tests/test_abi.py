@@ -56,6 +56,24 @@ def test_strerror_and_defaults():
     assert P._lib.phz_strerror(-2) == b"NaN or Inf"
     o = P.default_options()
     assert o.restart == 30 and o.rtol == 1e-10 and o.batched == 1 and o.cheby_degree == 2
+    assert list(o.block_kernel) == [-1] * 4 and list(o.block_tile) == [-1] * 4
+
+
+def test_options_rejected_before_device_use():
+    """phz_create validates the options before it touches a device, so bad
+    per-block pins fail on a host without a GPU."""
+    import ctypes as C
+    import synth
+    import paper_2410_03148_amd as P
+    m = P.make_material(synth.material_workload())
+    h = C.c_void_p()
+    for field, val in (("block_kernel", [0, 3, -1, -1]), ("block_kernel", [-2, 0, 0, 0]),
+                       ("block_tile", [0, 0, 0, 3]), ("fine_kernel", 5), ("elem_tile", 7)):
+        o = P.default_options(**{field: val})
+        assert P._lib.phz_create(16, C.byref(m), C.byref(o), None, C.byref(h)) == -1, field
+        assert not h.value
+    with pytest.raises(ValueError):
+        P.default_options(block_tile=[0, 1])
 
 
 @pytest.mark.parametrize("name", ["d_h", "g_h", "B_voigt", "B_reuss", "k_h"])

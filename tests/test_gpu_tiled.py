@@ -96,3 +96,22 @@ def test_grf16_solve_with_tiled_gather(P, precision):
         MH, _ = ctx.effective_nd()
         ref = np.array(g["MH"])
         assert np.abs(MH - ref).max() / np.abs(ref).max() < 1e-8
+
+
+def test_per_block_pins(P):
+    """block_kernel / block_tile pin each fine block's kernel and tile; the
+    stats report the pinned choice and the solve still matches the oracle."""
+    g = json.load(open(os.path.join(HERE, "golden", "grf16.json")))
+    say("per-block pins")
+    kinds, tiles = [2, 2, 1, 0], [1, 0, -1, -1]
+    with P.Context(16, MAT, precision=P.PHZ_BF16X3_IR, block_kernel=kinds, block_tile=tiles,
+                   inner_rtol=1e-4, rtol=1e-10) as ctx:
+        ctx.set_levelset(synth.grf_levelset(16, seed=2410, solid_fraction=0.5))
+        assert ctx.solve() == P.PHZ_OK
+        st = ctx.stats()
+        print("kernels", st["fine_kernel"], "tiles", st["elem_tile"])
+        assert st["fine_kernel"] == kinds
+        assert st["elem_tile"] == tiles
+        MH, _ = ctx.effective_nd()
+        ref = np.array(g["MH"])
+        assert np.abs(MH - ref).max() / np.abs(ref).max() < 1e-8
