@@ -269,7 +269,8 @@ def main():
                    "iterations_max": max(stats["iterations"]), "refinements": stats["refinements"],
                    "true_residual_max": max(stats["true_residual"]),
                    "setup_ms": stats["setup_ms"], "solve_ms": stats["solve_ms"],
-                   "fine_kernels": stats["fine_kernel"], "mfma_tiles_full_A_B_S": stats["elem_tile"]},
+                   "fine_kernels": stats["fine_kernel"], "mfma_tiles_full_A_B_S": stats["elem_tile"],
+                   "coarse_kernels_A_S": [stats["coarse_kernel"][1:8], stats["coarse_kernel"][9:16]]},
     }
 
     # dominant single kernel from the live event timing of the timed steps

@@ -150,6 +150,13 @@ typedef struct {
                                the choice that phz_get_stats reported        */
     int block_tile[4];      /* per fine block: -1 (default) follows elem_tile,
                                else pins the element-contraction tile index  */
+    int coarse_kernel;      /* float32 nine-column applies of the coarse
+                               multigrid levels: -1 (default) per level the
+                               faster (timed once; the tiled one must be more
+                               than 3% faster) of 0 the direct stencil apply
+                               and 1 the apply with the input tile staged in
+                               LDS (levels with N a multiple of 16); 0 or 1
+                               forces that kernel where it applies           */
 } phz_options;
 
 typedef struct {
@@ -169,6 +176,11 @@ typedef struct {
     int fine_kernel[4];     /* kernel of each fine block's float32 nine-column
                                launches (fine_kernel codes), -1 if the solve
                                has none (FP64, or loads one at a time)        */
+    int coarse_kernel[16];  /* kernel of the float32 nine-column applies per
+                               coarse level (coarse_kernel codes): [l] for the
+                               A hierarchy, [8 + l] for S_bar, l >= 1; -1 for
+                               level 0, absent levels, FP64 and single-load
+                               solves                                          */
 } phz_stats;
 
 typedef struct {
@@ -254,10 +266,14 @@ int phz_apply(phz_ctx* ctx, int op, int nrhs, int precision,
 /* Apply the SCP preconditioner z = P^-1 r (device, [4][nrhs][N^3], float64),
  * building it for the current geometry if needed. */
 int phz_precondition(phz_ctx* ctx, int nrhs, const double* r, double* z);
-/* Galerkin coarse operator of multigrid level >= 1 applied to x (device,
- * float64): block PHZ_OP_A ([3][nrhs][nc]) or PHZ_OP_SBAR ([nrhs][nc]). */
-int phz_coarse_apply(phz_ctx* ctx, int level, int op, int nrhs,
-                     const double* x, double* y);
+/* Galerkin coarse operator of multigrid level >= 1 applied to x (device):
+ * block PHZ_OP_A ([3][nrhs][nc]) or PHZ_OP_SBAR ([nrhs][nc]).  precision
+ * PHZ_FP64 (double buffers, the FP64 stencils) or PHZ_FP32_IR (float buffers,
+ * the float32 stencils of a context in a float form, and for nrhs = 9 the
+ * kernel the context chose for that level, coarse_kernel); PHZ_E_STATE if a
+ * float apply is asked of an FP64 context. */
+int phz_coarse_apply(phz_ctx* ctx, int level, int op, int nrhs, int precision,
+                     const void* x, void* y);
 
 /* Per-kernel timing.  With timing enabled, every operator launch (fine
  * blocks, coarse levels), every SCP preconditioner application and every
@@ -267,6 +283,7 @@ int phz_coarse_apply(phz_ctx* ctx, int level, int op, int nrhs,
  * class into buf (NUL-terminated, truncated to cap) and the full length to
  * *len.  Names: fine_{full,A,B,S}_k{1,9}_f{64,32} (suffix _cheby for the
  * launches that fuse a Chebyshev smoothing step), coarse_{A,S}_f{64,32},
+ * coarse_tiled_{A,S}_f32 (the LDS-tiled coarse apply),
  * precond_f{64,32}, arnoldi_cgs2_f{64,32}. */
 int phz_kernel_timing(phz_ctx* ctx, int enable);
 int phz_get_kernel_timing(phz_ctx* ctx, char* buf, int cap, int* len);

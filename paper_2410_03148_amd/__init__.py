@@ -38,7 +38,7 @@ class phz_options(C.Structure):
                 ("vcycles_s", C.c_int), ("inner_rtol", C.c_double), ("max_refine", C.c_int),
                 ("verbose", C.c_int), ("bf16_terms", C.c_int), ("bf16_outer", C.c_int),
                 ("elem_tile", C.c_int), ("use_graph", C.c_int), ("fine_kernel", C.c_int),
-                ("block_kernel", C.c_int * 4), ("block_tile", C.c_int * 4)]
+                ("block_kernel", C.c_int * 4), ("block_tile", C.c_int * 4), ("coarse_kernel", C.c_int)]
 
 
 def _set_option(o, k, v):
@@ -58,7 +58,7 @@ class phz_stats(C.Structure):
                 ("true_residual", C.c_double * 9), ("flux_energy_defect", C.c_double),
                 ("setup_ms", C.c_double), ("solve_ms", C.c_double), ("mg_levels", C.c_int),
                 ("cheb_lambda", C.c_double * 16), ("elem_tile", C.c_int * 4),
-                ("fine_kernel", C.c_int * 4)]
+                ("fine_kernel", C.c_int * 4), ("coarse_kernel", C.c_int * 16)]
 
 
 class phz_foms_t(C.Structure):
@@ -104,7 +104,7 @@ def _load():
         "phz_hj_step": (ip, [vp, vp, C.c_double, vp, ip]),
         "phz_apply": (ip, [vp, ip, ip, ip, vp, vp]),
         "phz_precondition": (ip, [vp, ip, vp, vp]),
-        "phz_coarse_apply": (ip, [vp, ip, ip, ip, vp, vp]),
+        "phz_coarse_apply": (ip, [vp, ip, ip, ip, ip, vp, vp]),
         "phz_kernel_timing": (ip, [vp, ip]),
         "phz_get_kernel_timing": (ip, [vp, C.c_char_p, ip, C.POINTER(ip)]),
     }
@@ -250,7 +250,7 @@ class Context:
             "flux_energy_defect": s.flux_energy_defect, "setup_ms": s.setup_ms,
             "solve_ms": s.solve_ms, "mg_levels": s.mg_levels,
             "cheb_lambda": list(s.cheb_lambda), "elem_tile": list(s.elem_tile),
-            "fine_kernel": list(s.fine_kernel),
+            "fine_kernel": list(s.fine_kernel), "coarse_kernel": list(s.coarse_kernel),
         }
 
     def history(self, load):
@@ -335,9 +335,9 @@ class Context:
         self._check(_lib.phz_precondition(self._h, nrhs, C.c_void_p(r_ptr), C.c_void_p(z_ptr)),
                     "phz_precondition")
 
-    def coarse_apply(self, level, op, nrhs, x_ptr, y_ptr):
-        self._check(_lib.phz_coarse_apply(self._h, level, op, nrhs, C.c_void_p(x_ptr), C.c_void_p(y_ptr)),
-                    "phz_coarse_apply")
+    def coarse_apply(self, level, op, nrhs, x_ptr, y_ptr, precision=PHZ_FP64):
+        self._check(_lib.phz_coarse_apply(self._h, level, op, nrhs, precision, C.c_void_p(x_ptr),
+                                          C.c_void_p(y_ptr)), "phz_coarse_apply")
 
 
 def homogenise(n, material, phi=None, rho=None, **opts):

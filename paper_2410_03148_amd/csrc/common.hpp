@@ -75,6 +75,12 @@ void elem_apply(int op, int nrhs, int N, int terms, int tile, const float* s, co
 template <typename T>
 void coarse_apply(int F, int nrhs, int N, const T* S, const T* x, const OpArgs<T>& a, bool cheby,
                   hipStream_t st);
+// The float32 nine-column coarse apply with the workgroup's input tile
+// (16 x 4 x 4 nodes and a one-node halo) staged in LDS; N a multiple of 16
+// (coarse_tiled_fits).
+bool coarse_tiled_fits(int N);
+void coarse_apply_tiled(int F, int N, const float* S, const float* x, const OpArgs<float>& a, bool cheby,
+                        hipStream_t st);
 // Node stencils of a coarse level from its Galerkin element matrices
 // (structure-of-arrays [corner L][row f][col][element]).
 void build_stencil(int F, int N, const double* Ae, double* S, hipStream_t st);

@@ -176,6 +176,34 @@ __device__ __forceinline__ unsigned wrap1(int v, unsigned N) {
   return v < 0 ? (unsigned)(v + (int)N) : ((unsigned)v >= N ? (unsigned)v - N : (unsigned)v);
 }
 
+// Stage the workgroup's input tile plus a one-node halo (GNI nodes, C
+// columns each) in LDS as rows of CP floats.  Every global load of the
+// thread's (at most three) staged nodes is issued before the first LDS
+// write, so the loads' latencies overlap instead of adding up node by node.
+template <int C, int CP>
+__device__ __forceinline__ void stage_tile(float4* xs, const float* __restrict__ x, unsigned N, unsigned nn, int x0,
+                                           int y0, int z0, int tid) {
+  constexpr int PF = (GNI + 255) / 256;
+  float v[PF][CP];
+#pragma unroll
+  for (int p = 0; p < PF; ++p) {
+    const int q = tid + 256 * p;
+    const int li = q % GNX, lj = (q / GNX) % GNY, lk = q / (GNX * GNY);
+    const unsigned m = wrap1(x0 - 1 + li, N) + N * (wrap1(y0 - 1 + lj, N) + N * wrap1(z0 - 1 + lk, N));
+#pragma unroll
+    for (int col = 0; col < CP; ++col) v[p][col] = (q < GNI && col < C) ? x[(size_t)col * nn + m] : 0.f;
+  }
+#pragma unroll
+  for (int p = 0; p < PF; ++p) {
+    const int q = tid + 256 * p;
+    if (q < GNI) {
+#pragma unroll
+      for (int c4 = 0; c4 < CP / 4; ++c4)
+        xs[q * (CP / 4) + c4] = make_float4(v[p][4 * c4], v[p][4 * c4 + 1], v[p][4 * c4 + 2], v[p][4 * c4 + 3]);
+    }
+  }
+}
+
 template <int FO, int FI, int K, int CP>
 __device__ __forceinline__ void tiled_neighbour(const float4* __restrict__ row, int dx, int dy, int dz,
                                                 const float* se, const float* kr, float* acc) {
@@ -222,20 +250,7 @@ __global__ __launch_bounds__(256) void k_fine_tiled(unsigned N, const float* __r
   const int x0 = (int)((b % ntx) * GTX), y0 = (int)(((b / ntx) % nty) * GTY), z0 = (int)((b / (ntx * nty)) * GTZ);
   const int tid = threadIdx.x;
   for (int t = tid; t < NK; t += 256) kr[t] = kref[t];
-  for (int q = tid; q < GNI; q += 256) {
-    const int li = q % GNX, lj = (q / GNX) % GNY, lk = q / (GNX * GNY);
-    const unsigned m = wrap1(x0 - 1 + li, N) + N * (wrap1(y0 - 1 + lj, N) + N * wrap1(z0 - 1 + lk, N));
-#pragma unroll
-    for (int c4 = 0; c4 < CP / 4; ++c4) {
-      float v[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int col = 4 * c4 + u;
-        v[u] = col < C ? x[(size_t)col * nn + m] : 0.f;
-      }
-      xs[q * (CP / 4) + c4] = make_float4(v[0], v[1], v[2], v[3]);
-    }
-  }
+  stage_tile<C, CP>(xs, x, N, nn, x0, y0, z0, tid);
   const int ti = tid % GTX, tj = (tid / GTX) % GTY, tk = tid / (GTX * GTY);
   const unsigned n = (unsigned)(x0 + ti) + N * ((unsigned)(y0 + tj) + N * (unsigned)(z0 + tk));
   // scale of the element whose corner c is this node (origin n - c)
@@ -280,6 +295,80 @@ void launch_tiled(unsigned N, const float* s, const float* kref, const float* x,
   }
   if (cheby) throw std::invalid_argument("Chebyshev epilogue needs a square block");
   hipLaunchKernelGGL((k_fine_tiled<FO, FI, 9, false>), dim3(g), dim3(256), 0, st, N, s, kref, x, a);
+}
+
+// LDS-tiled variant of the coarse-level stencil apply (float32, nine load
+// columns, one thread per node of a GTX x GTY x GTZ tile).  The direct kernel
+// below reads every input value 27 times through the caches, which at 64^3
+// and nine columns is more traffic than the L2 delivers at HBM speed; here
+// the tile's input nodes plus a one-node halo are staged once in LDS (rows of
+// CP floats as in the tiled fine gather) and each node's 27 stencil blocks
+// are streamed from HBM once.
+template <int F, bool CHEBY, bool BUF>
+__global__ __launch_bounds__(256) void k_stencil_tiled(unsigned N, const float* __restrict__ S,
+                                                       const float* __restrict__ x, OpArgs<float> a) {
+  constexpr int K = 9, C = F * K, CP = (C + 3) / 4 * 4;
+  __shared__ float4 xs[GNI * (CP / 4)];
+  const unsigned nn = N * N * N;
+  const unsigned ntx = N / GTX, nty = N / GTY;
+  const unsigned b = xcd_block(blockIdx.x, gridDim.x);
+  const int x0 = (int)((b % ntx) * GTX), y0 = (int)(((b / ntx) % nty) * GTY), z0 = (int)((b / (ntx * nty)) * GTZ);
+  const int tid = threadIdx.x;
+  stage_tile<C, CP>(xs, x, N, nn, x0, y0, z0, tid);
+  const int ti = tid % GTX, tj = (tid / GTX) % GTY, tk = tid / (GTX * GTY);
+  const unsigned n = (unsigned)(x0 + ti) + N * ((unsigned)(y0 + tj) + N * (unsigned)(z0 + tk));
+  __amdgpu_buffer_rsrc_t sr;
+  if constexpr (BUF) sr = make_rsrc(S, (unsigned)((size_t)27 * F * F * nn * sizeof(float)));
+  float acc[F * K];
+#pragma unroll
+  for (int t = 0; t < F * K; ++t) acc[t] = 0.f;
+  __syncthreads();
+  const int qc = (ti + 1) + GNX * ((tj + 1) + GNY * (tk + 1));
+  // the stencil blocks stream from HBM two neighbours ahead of their use
+  auto load_block = [&](int d, float* sv) {
+#pragma unroll
+    for (int t = 0; t < F * F; ++t) {
+      if constexpr (BUF) sv[t] = buf_load<float>(sr, n * (unsigned)sizeof(float), (unsigned)((d * F * F + t) * nn * sizeof(float)));
+      else sv[t] = S[(size_t)(d * F * F + t) * nn + n];
+    }
+  };
+  float sq[3][F * F];
+  load_block(0, sq[0]);
+  load_block(1, sq[1]);
+#pragma unroll
+  for (int d = 0; d < 27; ++d) {
+    const int dx = d % 3 - 1, dy = (d / 3) % 3 - 1, dz = d / 9 - 1;
+    if (d + 2 < 27) load_block(d + 2, sq[(d + 2) % 3]);
+    const float* sv = sq[d % 3];
+    const float4* row = xs + (qc + dx + GNX * (dy + GNY * dz)) * (CP / 4);
+    float xv[CP];
+#pragma unroll
+    for (int c4 = 0; c4 < CP / 4; ++c4) {
+      const float4 v = row[c4];
+      xv[4 * c4] = v.x;
+      xv[4 * c4 + 1] = v.y;
+      xv[4 * c4 + 2] = v.z;
+      xv[4 * c4 + 3] = v.w;
+    }
+#pragma unroll
+    for (int fi = 0; fi < F; ++fi)
+#pragma unroll
+      for (int j = 0; j < K; ++j)
+#pragma unroll
+        for (int fo = 0; fo < F; ++fo) acc[fo * K + j] += sv[fo * F + fi] * xv[fi * K + j];
+  }
+  epilogue_cols<float, F, K, K, CHEBY>(n, nn, 0, acc, a);
+}
+
+template <int F>
+void launch_stencil_tiled(unsigned N, const float* S, const float* x, const OpArgs<float>& a, bool cheby,
+                          hipStream_t st) {
+  const unsigned g = (N / GTX) * (N / GTY) * (N / GTZ);
+  const bool buf = (size_t)N * N * N * 27 * F * F * sizeof(float) < (size_t(1) << 32);
+#define PHZ_ST(CH, BUF) hipLaunchKernelGGL((k_stencil_tiled<F, CH, BUF>), dim3(g), dim3(256), 0, st, N, S, x, a)
+  if (cheby) { if (buf) PHZ_ST(true, true); else PHZ_ST(true, false); }
+  else { if (buf) PHZ_ST(false, true); else PHZ_ST(false, false); }
+#undef PHZ_ST
 }
 
 // Coarse levels: assembled 27-point node stencils S[(d*F + fo)*F + fi][n]
@@ -684,6 +773,17 @@ void coarse_apply(int F, int nrhs, int N, const T* Ae, const T* x, const OpArgs<
   else if (F == 1 && nrhs == 1) launch_coarse<T, 1, 1>((unsigned)N, Ae, x, a, cheby, st);
   else if (F == 1 && nrhs == 9) launch_coarse<T, 1, 9>((unsigned)N, Ae, x, a, cheby, st);
   else throw std::invalid_argument("coarse_apply");
+  PHZ_LAUNCH_CHECK();
+}
+
+bool coarse_tiled_fits(int N) { return fine_tiled_fits(N); }
+
+void coarse_apply_tiled(int F, int N, const float* S, const float* x, const OpArgs<float>& a, bool cheby,
+                        hipStream_t st) {
+  if (!coarse_tiled_fits(N)) throw std::invalid_argument("coarse_apply_tiled: N must be a multiple of 16");
+  if (F == 3) launch_stencil_tiled<3>((unsigned)N, S, x, a, cheby, st);
+  else if (F == 1) launch_stencil_tiled<1>((unsigned)N, S, x, a, cheby, st);
+  else throw std::invalid_argument("coarse_apply_tiled F");
   PHZ_LAUNCH_CHECK();
 }
 

@@ -77,6 +77,9 @@ struct Level {
   std::vector<float> cheb_host32;
   DevBuf<double> cheb;
   DevBuf<float> cheb32;
+  // kernel of the float32 nine-column applies of this coarse level: 0 the
+  // direct stencil apply, 1 the LDS-tiled one, -1 not yet chosen
+  int ckind = -1;
 };
 
 struct Hierarchy {
@@ -564,6 +567,14 @@ static void level_apply_args(phz_ctx* c, Hierarchy& H, int l, int K, const T* x,
   if (l == 0) {
     op_apply_args<T>(c, H.op, K, x, a, cheby);
   } else {
+    if constexpr (sizeof(T) == 4) {
+      if (K == 9 && L.ckind == 1) {
+        const long slot = time_begin(c, H.F == 3 ? "coarse_tiled_A_f32" : "coarse_tiled_S_f32");
+        coarse_apply_tiled(H.F, L.N, L.S32.p, x, a, cheby, c->stream);
+        time_end(c, slot);
+        return;
+      }
+    }
     const long slot = time_begin(c, H.F == 3 ? (sizeof(T) == 4 ? "coarse_A_f32" : "coarse_A_f64")
                                              : (sizeof(T) == 4 ? "coarse_S_f32" : "coarse_S_f64"));
     coarse_apply<T>(H.F, K, L.N, stencil_of<T>(L), x, a, cheby, c->stream);
@@ -725,6 +736,8 @@ static void drop_level_work_if_changed(phz_ctx* c, Work<T>& W) {
   }
 }
 
+static int coarse_kind_of(phz_ctx* c, Hierarchy& H, int l);
+
 static void setup_preconditioner(phz_ctx* c) {
   if (c->precond_ready) return;
   // choose (time) the float32 kernels before any solve launches them, so no
@@ -743,6 +756,11 @@ static void setup_preconditioner(phz_ctx* c) {
   drop_level_work_if_changed(c, c->w32);
   setup_hierarchy(c, c->hA);
   setup_hierarchy(c, c->hS);
+  for (int q = 0; q < 16; ++q) c->stats.coarse_kernel[q] = -1;
+  if (c->opt.precision != PHZ_FP64 && c->opt.batched) {
+    for (size_t l = 1; l < c->hA.lv.size() && l < 8; ++l) c->stats.coarse_kernel[l] = coarse_kind_of(c, c->hA, (int)l);
+    for (size_t l = 1; l < c->hS.lv.size() && l < 8; ++l) c->stats.coarse_kernel[8 + l] = coarse_kind_of(c, c->hS, (int)l);
+  }
   sync(c);
   c->precond_ready = true;
   c->stats.mg_levels = (int)c->hA.lv.size();
@@ -751,6 +769,32 @@ static void setup_preconditioner(phz_ctx* c) {
     if (q < 16) c->stats.cheb_lambda[q++] = L->lmax;
   for (auto& L : c->hS.lv)
     if (q < 16) c->stats.cheb_lambda[q++] = L->lmax;
+}
+
+// Kernel of the float32 nine-column applies of coarse level l: the option's
+// choice where it applies, else the faster of the direct and the LDS-tiled
+// stencil apply (timed once per level; the tiled one must be more than 3%
+// faster).
+static int coarse_kind_of(phz_ctx* c, Hierarchy& H, int l) {
+  Level& L = *H.lv[l];
+  if (L.ckind >= 0) return L.ckind;
+  int kind = 0;
+  if (coarse_tiled_fits(L.N) && c->opt.coarse_kernel != 0) {
+    if (c->opt.coarse_kernel == 1) {
+      kind = 1;
+    } else {
+      DevBuf<float> x, y;
+      x.alloc((size_t)H.F * 9 * L.nn);
+      y.alloc((size_t)H.F * 9 * L.nn);
+      PHZ_HIP(hipMemsetAsync(x.p, 0, x.n * sizeof(float), c->stream));
+      const OpArgs<float> a = plain_args<float>(nullptr, y.p, 1.0f, 0.0f);
+      const float direct = time_launch(c, [&] { coarse_apply<float>(H.F, 9, L.N, L.S32.p, x.p, a, false, c->stream); });
+      const float tiled = time_launch(c, [&] { coarse_apply_tiled(H.F, L.N, L.S32.p, x.p, a, false, c->stream); });
+      if (clearly_faster(tiled, direct)) kind = 1;
+    }
+  }
+  L.ckind = kind;
+  return kind;
 }
 
 // ---------------------------------------------------------------- V-cycle
@@ -1298,6 +1342,7 @@ void phz_default_options(phz_options* o) {
   o->use_graph = 0;
   o->fine_kernel = -1;
   for (int op = 0; op < 4; ++op) o->block_kernel[op] = o->block_tile[op] = -1;
+  o->coarse_kernel = -1;
 }
 
 const char* phz_strerror(int status) {
@@ -1316,6 +1361,7 @@ static int check_options(const phz_options* o, std::string& err) {
   if (o->elem_tile < -1 || o->elem_tile >= elem_tile_count()) { err = "elem_tile must be -1 or a tile index"; return PHZ_E_INVALID; }
   if (o->use_graph != 0 && o->use_graph != 1) { err = "use_graph must be 0 or 1"; return PHZ_E_INVALID; }
   if (o->fine_kernel < -1 || o->fine_kernel > 2) { err = "fine_kernel must be -1, 0, 1 or 2"; return PHZ_E_INVALID; }
+  if (o->coarse_kernel < -1 || o->coarse_kernel > 1) { err = "coarse_kernel must be -1, 0 or 1"; return PHZ_E_INVALID; }
   for (int op = 0; op < 4; ++op) {
     if (o->block_kernel[op] < -1 || o->block_kernel[op] > 2) { err = "block_kernel entries must be -1, 0, 1 or 2"; return PHZ_E_INVALID; }
     if (o->block_tile[op] < -1 || o->block_tile[op] >= elem_tile_count()) {
@@ -1349,6 +1395,7 @@ int phz_create(int n, const phz_material* mat, const phz_options* opt, void* str
   c->nn = (long)n * n * n;
   c->mat = *mat;
   for (int op = 0; op < 4; ++op) c->stats.elem_tile[op] = c->stats.fine_kernel[op] = -1;
+  for (int q = 0; q < 16; ++q) c->stats.coarse_kernel[q] = -1;
   if (opt) c->opt = *opt;
   else phz_default_options(&c->opt);
   std::string err;
@@ -1399,6 +1446,12 @@ int phz_set_options(phz_ctx* c, const phz_options* opt) {
   for (int op = 0; op < 4; ++op) {
     c->elem_tile[op] = -1;
     c->fkind[op] = -1;
+  }
+  if (opt->coarse_kernel != c->opt.coarse_kernel) {
+    // the per-level choice is made again with the hierarchy
+    for (auto& L : c->hA.lv) L->ckind = -1;
+    for (auto& L : c->hS.lv) L->ckind = -1;
+    c->precond_ready = false;
   }
   c->opt = *opt;
   ++c->graph_epoch;
@@ -1802,16 +1855,25 @@ int phz_precondition(phz_ctx* c, int nrhs, const double* r, double* z) {
   PHZ_GUARD_END(c)
 }
 
-int phz_coarse_apply(phz_ctx* c, int level, int op, int nrhs, const double* x, double* y) {
+int phz_coarse_apply(phz_ctx* c, int level, int op, int nrhs, int precision, const void* x, void* y) {
   if (!c || !x || !y || (nrhs != 1 && nrhs != 9) || (op != PHZ_OP_A && op != PHZ_OP_SBAR)) return PHZ_E_INVALID;
+  if (precision != PHZ_FP64 && precision != PHZ_FP32_IR) return PHZ_E_INVALID;
   if (!c->have_s) return PHZ_E_STATE;
   PHZ_GUARD_BEGIN
   ensure_state_buffers(c);
   setup_preconditioner(c);
   Hierarchy& H = op == PHZ_OP_A ? c->hA : c->hS;
   if (level < 1 || level >= (int)H.lv.size()) { c->err = "level out of range"; return PHZ_E_INVALID; }
-  coarse_apply<double>(H.F, nrhs, H.lv[level]->N, H.lv[level]->S.p, x, plain_args<double>(nullptr, y, 1.0, 0.0),
-                       false, c->stream);
+  Level& L = *H.lv[level];
+  if (precision == PHZ_FP64) {
+    coarse_apply<double>(H.F, nrhs, L.N, L.S.p, (const double*)x, plain_args<double>(nullptr, (double*)y, 1.0, 0.0),
+                         false, c->stream);
+  } else {
+    if (!L.S32.p) { c->err = "float32 coarse operators exist only in the float forms"; return PHZ_E_STATE; }
+    const OpArgs<float> a = plain_args<float>(nullptr, (float*)y, 1.0f, 0.0f);
+    if (nrhs == 9 && coarse_kind_of(c, H, level) == 1) coarse_apply_tiled(H.F, L.N, L.S32.p, (const float*)x, a, false, c->stream);
+    else coarse_apply<float>(H.F, nrhs, L.N, L.S32.p, (const float*)x, a, false, c->stream);
+  }
   sync(c);
   return PHZ_OK;
   PHZ_GUARD_END(c)

@@ -115,3 +115,73 @@ def test_per_block_pins(P):
         MH, _ = ctx.effective_nd()
         ref = np.array(g["MH"])
         assert np.abs(MH - ref).max() / np.abs(ref).max() < 1e-8
+
+
+def prolongation_sparse(nc, F):
+    """Periodic trilinear prolongation (fine (2nc)^3 F x nc^3 F), sparse: a
+    fine node at an even index coincides with coarse node i/2, at an odd index
+    it takes half of each of its two coarse neighbours, per direction."""
+    import scipy.sparse as sp
+    nf = 2 * nc
+    i = np.arange(nf)
+    # per direction: (coarse index, weight) pairs; even fine indices get a
+    # second pair of weight 0
+    c0, c1 = i // 2, (i // 2 + 1) % nc
+    w0 = np.where(i % 2 == 0, 1.0, 0.5)
+    w1 = np.where(i % 2 == 0, 0.0, 0.5)
+    cx = np.stack([c0, c1]), np.stack([w0, w1])
+    rows, cols, vals = [], [], []
+    K, J, I = np.meshgrid(i, i, i, indexing="ij")
+    fine = (I + nf * (J + nf * K)).ravel()
+    for a in range(2):
+        for b in range(2):
+            for c in range(2):
+                w = (cx[1][a][I] * cx[1][b][J] * cx[1][c][K]).ravel()
+                col = (cx[0][a][I] + nc * (cx[0][b][J] + nc * cx[0][c][K])).ravel()
+                keep = w != 0
+                rows.append(fine[keep]); cols.append(col[keep]); vals.append(w[keep])
+    Pm = sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
+                       shape=(nf ** 3, nc ** 3))
+    return sp.kron(Pm, sp.identity(F), format="csr")
+
+
+def test_tiled_coarse_stencil_vs_oracle(torch_cuda, P):
+    """Float32 Galerkin coarse operators (levels 1 and 2 of a 32^3 cell) with
+    the LDS-tiled stencil apply forced where it applies (16^3; 8^3 falls back
+    to the direct apply) against the oracle's R A P with trilinear P."""
+    torch = torch_cuda
+    n = 32
+    say("tiled coarse stencil", n)
+    rho = synth.random_density(n, seed=33)
+    s = fe.ersatz_scale(rho, MAT.void_scale)
+    K, _ = cell.assemble(n, s, MND)
+    iu = field_index(n, [0, 1, 2])
+    A = K[iu][:, iu].tocsr()
+    Sb = krylov.schur_elementwise(n, s, MND).tocsr()
+    rng = np.random.default_rng(4)
+    with P.Context(n, MAT, precision=P.PHZ_FP32_IR, coarse_kernel=1) as ctx:
+        ctx.set_density(rho)
+        for op, M0, F in ((P.OP_A, A, 3), (P.OP_SBAR, Sb, 1)):
+            Ml = M0
+            nl = n
+            for level in (1, 2):
+                Pm = prolongation_sparse(nl // 2, F)
+                Ml = (Pm.T @ Ml @ Pm).tocsr()
+                nl //= 2
+                x = rng.standard_normal((nl ** 3 * F, 9))
+                xd = torch.tensor(to_soa(x, nl ** 3, F, 9), dtype=torch.float32, device="cuda").contiguous()
+                yd = torch.zeros_like(xd)
+                ctx.coarse_apply(level, op, 9, xd.data_ptr(), yd.data_ptr(), precision=P.PHZ_FP32_IR)
+                torch.cuda.synchronize()
+                y = from_soa(yd.cpu().double().numpy(), nl ** 3, F, 9)
+                ref = Ml @ x
+                bound = abs(Ml) @ abs(x)
+                err = (np.abs(y - ref) / np.maximum(bound, 1e-300)).max()
+                print("op", op, "level", level, "max error / term magnitude", err)
+                # float32 stencil (rounded from FP64) and float32 products
+                assert err < 2e-6, (op, level, err)
+        # the first apply built the hierarchy and chose the kernels
+        st = ctx.stats()
+        print("coarse kernels", st["coarse_kernel"])
+        assert st["coarse_kernel"][1] == 1 and st["coarse_kernel"][2] == 0
+        assert st["coarse_kernel"][9] == 1 and st["coarse_kernel"][10] == 0
