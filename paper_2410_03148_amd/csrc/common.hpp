@@ -42,6 +42,11 @@ struct OpArgs {
   T* x = nullptr;
   const T* cab = nullptr;
   int fold_dold = 0;
+  // plain (non-Chebyshev) epilogue of a square block: when set, also the
+  // first Chebyshev step on the output, d1 = cab[0] * dinv y (no iterate
+  // update), so that a residual and the next smoothing step's first
+  // correction come out of one pass
+  T* d1 = nullptr;
 };
 
 // Fine-level matrix-free block operator on sum_e s_e Kref.

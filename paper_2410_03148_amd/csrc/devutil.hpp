@@ -19,8 +19,9 @@ __device__ __forceinline__ unsigned xcd_block(unsigned b, unsigned nb) {
   return x * q + (x < r ? x : r) + i;
 }
 
-// y = beta*yin + alpha*acc, optional Chebyshev epilogue (FO == FI), for the
-// KK load columns k0 .. k0+KK-1 of a node (column (f, k) at (f*K + k)*nn)
+// y = beta*yin + alpha*acc, optional Chebyshev epilogue (FO == FI) or first
+// Chebyshev step on y (a.d1), for the KK load columns k0 .. k0+KK-1 of a node
+// (column (f, k) at (f*K + k)*nn)
 template <typename T, int FO, int K, int KK, bool CHEBY>
 __device__ __forceinline__ void epilogue_cols(unsigned n, unsigned nn, int k0, const T* acc, const OpArgs<T>& a) {
   T out[FO * KK];
@@ -61,6 +62,22 @@ __device__ __forceinline__ void epilogue_cols(unsigned n, unsigned nn, int k0, c
         if (a.xin) xo += a.xin[o];
         a.x[o] = xo;
       }
+  } else {
+    if (a.d1) {
+      const T c0 = a.cab[0];
+      T Di[FO * FO];
+#pragma unroll
+      for (int t = 0; t < FO * FO; ++t) Di[t] = a.dinv[(size_t)t * nn + n];
+#pragma unroll
+      for (int j = 0; j < KK; ++j)
+#pragma unroll
+        for (int f = 0; f < FO; ++f) {
+          T z = T(0);
+#pragma unroll
+          for (int g = 0; g < FO; ++g) z += Di[f * FO + g] * out[g * KK + j];
+          a.d1[(size_t)(f * K + k0 + j) * nn + n] = c0 * z;
+        }
+    }
   }
 }
 

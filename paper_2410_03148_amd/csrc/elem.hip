@@ -58,6 +58,12 @@ struct ElemTile {
   static constexpr int CT = (NE + 15) / 16;                                        // MFMA column tiles
   static constexpr int NEP = 16 * CT;          // elements padded to whole column tiles
   static constexpr int MT = (CT + 3) / 4;      // column tiles per wave (at most)
+  // LDS of a workgroup (staged nodes, element outputs, element scales) and
+  // the waves per SIMD to ask the register allocator for: three where three
+  // workgroups' LDS fits in a CU's 160 KiB (the three-field blocks on the
+  // 8x8x4 and 16x4x4 tiles), else two
+  static constexpr int lds_bytes(int fo) { return (NI + 2) * 16 + 8 * NEP * fo * 4 + NEP * 4; }
+  static constexpr int waves(int fo) { return fo == 3 && 3 * lds_bytes(fo) <= 160 * 1024 ? 3 : 2; }
 };
 
 // periodic wrap of a coordinate in [-1, N]
@@ -90,7 +96,7 @@ __device__ __forceinline__ void split_corners(float4 p, float4 q, float4 base, b
 }
 
 template <int FO, int FI, int K, int TERMS, bool CHEBY, int TX, int TY, int TZ>
-__global__ __launch_bounds__(256) void k_elem_mfma(unsigned N, const float* __restrict__ s,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(ElemTile<TX, TY, TZ>::waves(FO)))) void k_elem_mfma(unsigned N, const float* __restrict__ s,
                                                    const bf16x8* __restrict__ kop,
                                                    const float* __restrict__ x, OpArgs<float> a) {
   using TL = ElemTile<TX, TY, TZ>;
@@ -154,11 +160,11 @@ __global__ __launch_bounds__(256) void k_elem_mfma(unsigned N, const float* __re
     }
   }
 
-  // input values of column k for the staged nodes, and this node's epilogue
-  // operands of column k (residual input, previous correction, iterate), all
-  // fetched one column ahead so their latency overlaps a column of work
+  // input values of column k for the staged nodes and this node's residual
+  // input of column k, fetched one column ahead so their latency overlaps a
+  // column of work
   float pv[PF][FI];
-  float eyin[FO], edold[FO], eit[FO];
+  float eyin[FO];
   const bool has_yin = a.beta != 0.f;
   auto fetch = [&](int k) {
 #pragma unroll
@@ -167,24 +173,16 @@ __global__ __launch_bounds__(256) void k_elem_mfma(unsigned N, const float* __re
       for (int f = 0; f < FI; ++f)
         pv[p][f] = (tid + 256 * p < NI) ? x[(size_t)(f * K + k) * nn + gm[p]] : 0.f;
 #pragma unroll
-    for (int f = 0; f < FO; ++f) {
-      const size_t o = (size_t)(f * K + k) * nn + n;
-      eyin[f] = has_yin ? a.yin[o] : 0.f;
-      if constexpr (CHEBY) {
-        edold[f] = a.dold[o];
-        eit[f] = a.xin ? a.xin[o] : 0.f;
-      } else {
-        edold[f] = 0.f;
-        eit[f] = 0.f;
-      }
-    }
+    for (int f = 0; f < FO; ++f) eyin[f] = has_yin ? a.yin[(size_t)(f * K + k) * nn + n] : 0.f;
   };
-  // the node's Jacobi block and the step's coefficients, the same for every column
-  float Di[CHEBY ? FO * FO : 1];
+  // the node's Jacobi block and the step's coefficients, the same for every
+  // column (Chebyshev epilogue, or the first step on the output, a.d1)
+  float Di[FO * FO];
   float ca = 0.f, cb = 0.f;
-  if constexpr (CHEBY) {
+  const bool with_d1 = !CHEBY && a.d1 != nullptr;
+  if (CHEBY || with_d1) {
     ca = a.cab[0];
-    cb = a.cab[1];
+    if constexpr (CHEBY) cb = a.cab[1];
 #pragma unroll
     for (int t = 0; t < FO * FO; ++t) Di[t] = a.dinv[(size_t)t * nn + n];
   }
@@ -213,13 +211,21 @@ __global__ __launch_bounds__(256) void k_elem_mfma(unsigned N, const float* __re
         xs[t] = v;
       }
     }
-    // this column's epilogue operands leave the prefetch registers now
+    // the Chebyshev step's operands of column k (previous correction,
+    // iterate) are issued now, in flight during the contraction: fetching
+    // them a column ahead too would hold more registers than three waves
+    // per SIMD allow
     float cyin[FO], cdold[FO], cxit[FO];
 #pragma unroll
     for (int f = 0; f < FO; ++f) {
+      const size_t o = (size_t)(f * K + k) * nn + n;
       cyin[f] = eyin[f];
-      cdold[f] = edold[f];
-      cxit[f] = eit[f];
+      cdold[f] = 0.f;
+      cxit[f] = 0.f;
+      if constexpr (CHEBY) {
+        cdold[f] = a.dold[o];
+        if (a.xin) cxit[f] = a.xin[o];
+      }
     }
     if (k + 1 < K) fetch(k + 1);  // in flight during this column's contraction
     __syncthreads();
@@ -287,6 +293,16 @@ __global__ __launch_bounds__(256) void k_elem_mfma(unsigned N, const float* __re
         float xo = dv;
         if (a.fold_dold) xo += cdold[f];
         a.x[o] = xo + cxit[f];
+      }
+    } else {
+      if (with_d1) {
+#pragma unroll
+        for (int f = 0; f < FO; ++f) {
+          float z = 0.f;
+#pragma unroll
+          for (int q = 0; q < FO; ++q) z += Di[f * FO + q] * out[q];
+          a.d1[(size_t)(f * K + k) * nn + n] = ca * z;
+        }
       }
     }
   }

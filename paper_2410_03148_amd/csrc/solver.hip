@@ -814,14 +814,21 @@ static void cheby_smooth(phz_ctx* c, Hierarchy& H, int l, int K, const T* b, T* 
   const int deg = std::max(1, c->opt.cheby_degree);
   const T* coef = cheb_of<T>(L);
   r = b;
-  if (!xzero) {
-    level_apply<T>(c, H, l, K, x, b, W.r.p, T(-1), T(1));
-    r = W.r.p;
-  }
   // with more steps to come the first correction is folded into x by the
   // next fused step (x = x_in + d_1 + d_2), which saves a pass over x
   const int xmode = deg > 1 ? kChebyXNone : (xzero ? kChebyXSet : kChebyXAdd);
-  cheby_first<T>(H.F, K, L.nn, dinv_of<T>(L), r, W.d.p, x, coef, xmode, c->stream);
+  if (!xzero) {
+    OpArgs<T> a = plain_args<T>(b, W.r.p, T(-1), T(1));
+    if (xmode == kChebyXNone) {
+      // the residual's pass also writes the first correction d_1
+      a.dinv = dinv_of<T>(L);
+      a.cab = coef;
+      a.d1 = W.d.p;
+    }
+    level_apply_args<T>(c, H, l, K, x, a, false);
+    r = W.r.p;
+  }
+  if (xzero || xmode != kChebyXNone) cheby_first<T>(H.F, K, L.nn, dinv_of<T>(L), r, W.d.p, x, coef, xmode, c->stream);
   dcur = W.d.p;
   T* dnext = W.d2.p;
   for (int i = 1; i < deg; ++i) {
