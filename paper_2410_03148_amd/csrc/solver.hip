@@ -850,12 +850,17 @@ static void cheby_smooth(phz_ctx* c, Hierarchy& H, int l, int K, const T* b, T* 
   }
 }
 
-// x = V-cycle approximation of A_l^-1 b (zero initial guess)
+// One V-cycle for A_l x = b: from a zero initial guess (xzero), else from
+// the x passed in, which it updates in place (the same as adding the
+// zero-guess cycle of the residual b - A x, without a separate residual,
+// correction vector and update pass).  Below level l the cycles start from
+// zero; the coarsest level is solved directly and needs xzero.
 template <typename T>
 static void vcycle(phz_ctx* c, Hierarchy& H, std::vector<std::unique_ptr<LevelWork<T>>>& WL, int l, int K,
-                   const T* b, T* x) {
+                   const T* b, T* x, bool xzero = true) {
   const int nl = (int)H.lv.size();
   if (l == nl - 1) {
+    if (!xzero) throw std::logic_error("vcycle: the coarsest level needs a zero initial guess");
     dense_apply<T>(H.F, (int)H.lv[l]->nn, K, H.Minv.p, b, x, c->stream);
     return;
   }
@@ -863,7 +868,7 @@ static void vcycle(phz_ctx* c, Hierarchy& H, std::vector<std::unique_ptr<LevelWo
   LevelWork<T>& Wc = *WL[l + 1];
   const T* r = nullptr;
   T* dcur = nullptr;
-  cheby_smooth<T>(c, H, l, K, b, x, true, W, r, dcur);
+  cheby_smooth<T>(c, H, l, K, b, x, xzero, W, r, dcur);
   level_apply<T>(c, H, l, K, dcur, r, W.r.p, T(-1), T(1));   // b - A x
   restrict_fw<T>(H.F, K, H.lv[l + 1]->N, W.r.p, Wc.b.p, c->stream);
   vcycle<T>(c, H, WL, l + 1, K, Wc.b.p, Wc.x.p);
@@ -877,9 +882,14 @@ static void block_solve(phz_ctx* c, Hierarchy& H, std::vector<std::unique_ptr<Le
                         int ncycles, const T* b, T* x, T* tmp_r, T* tmp_e) {
   vcycle<T>(c, H, WL, 0, K, b, x);
   for (int it = 1; it < ncycles; ++it) {
-    level_apply<T>(c, H, 0, K, x, b, tmp_r, T(-1), T(1));
-    vcycle<T>(c, H, WL, 0, K, tmp_r, tmp_e);
-    axpy_cols<T, T>(H.lv[0]->nn, H.F, K, nullptr, tmp_e, x, c->stream);
+    if (H.lv.size() > 1) {
+      vcycle<T>(c, H, WL, 0, K, b, x, false);
+    } else {
+      // a single (directly solved) level: correction from the residual
+      level_apply<T>(c, H, 0, K, x, b, tmp_r, T(-1), T(1));
+      vcycle<T>(c, H, WL, 0, K, tmp_r, tmp_e);
+      axpy_cols<T, T>(H.lv[0]->nn, H.F, K, nullptr, tmp_e, x, c->stream);
+    }
   }
 }
 
