@@ -118,6 +118,9 @@ def main():
                          "(-1 = timed choice); for profiling runs whose timing would change the choice")
     ap.add_argument("--block-tiles", default=None, metavar="T0,T1,T2,T3",
                     help="pin the element-contraction tile per fine block (-1 = timed choice)")
+    ap.add_argument("--coarse-kernel", type=int, default=-1, choices=[-1, 0, 1],
+                    help="pin the coarse levels' float kernel (0 direct, 1 LDS-tiled where N %% 16 == 0; "
+                         "-1 = timed choice per level)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the solve runs on a single MI355X; "
@@ -155,6 +158,8 @@ def main():
         pins["block_kernel"] = [int(v) for v in args.block_kernels.split(",")]
     if args.block_tiles:
         pins["block_tile"] = [int(v) for v in args.block_tiles.split(",")]
+    if args.coarse_kernel >= 0:
+        pins["coarse_kernel"] = args.coarse_kernel
 
     def make_ctx(form):
         return P.Context(n, mat, stream=stream.cuda_stream, rtol=1e-10, **forms[form],
