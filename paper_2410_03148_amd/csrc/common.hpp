@@ -181,6 +181,7 @@ struct GmresState {
   int* active;      // [K]
   int* kused;       // [K]
   int* nactive;     // [1]
+  const double* tol = nullptr;  // [K] per-column relative tolerance, or nullptr: the scalar one
 };
 // start of a cycle: beta = sqrt(nrm2); g[0] = beta; active if beta > tol*bnorm;
 // scale = 1/beta or 0.

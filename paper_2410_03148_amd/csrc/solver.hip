@@ -101,6 +101,7 @@ struct Work {
   std::vector<std::unique_ptr<LevelWork<T>>> A, S;
   DevBuf<T> t1u, t2u, t1p, t2p, t3p;   // preconditioner temporaries
   DevBuf<T> V, w, z, t, r, b, x;                  // GMRES
+  DevBuf<T> Z;  // preconditioned basis P^-1 V_j (flexible GMRES, the float cycles)
 };
 
 // One Arnoldi step (preconditioner, operator, orthogonalisation, Givens,
@@ -111,6 +112,7 @@ struct StepGraph {
   hipGraphExec_t exec = nullptr;
   int K = 0;
   double rtol = 0.0, stall = 0.0;
+  const double* tol = nullptr;
   long epoch = -1;
 };
 
@@ -148,6 +150,7 @@ struct phz_ctx {
   phz::DevBuf<double> X, Bvec, R64, guess, col_b, col_x, col_r;  // [nn][4][9] and columns
   phz::DevBuf<double> red_work, small;   // reduction scratch, small device values
   phz::DevBuf<double> gm_H, gm_cs, gm_sn, gm_g, gm_y, gm_est, gm_bnorm, gm_scale, gm_h1, gm_h2, gm_nrm;
+  phz::DevBuf<double> gm_tol;  // per-column relative targets of a float refinement cycle
   phz::DevBuf<int> gm_int;
 
   // captured Arnoldi steps (use_graph), per precision and step index; the
@@ -301,6 +304,7 @@ static void alloc_work(phz_ctx* c, Work<T>& W, int K, int m) {
   W.t1u.alloc(u); W.t2u.alloc(u);
   W.t1p.alloc(p); W.t2p.alloc(p); W.t3p.alloc(p);
   W.V.alloc(basis_stride(nn, K) * (m + 1));
+  if (std::is_same<T, float>::value) W.Z.alloc(basis_stride(nn, K) * m);
   W.w.alloc(full); W.z.alloc(full); W.t.alloc(full); W.r.alloc(full); W.b.alloc(full); W.x.alloc(full);
   W.cap_k = K;
   W.cap_m = m;
@@ -320,6 +324,7 @@ static void ensure_state_buffers(phz_ctx* c) {
   c->gm_h2.alloc((size_t)(kMaxRestart + 1) * K);
   c->gm_nrm.alloc(4 * K);
   c->gm_int.alloc(3 * K + 1);
+  c->gm_tol.alloc(K);
   c->red_work.alloc(reduce_work_size());
   c->small.alloc(512);
 }
@@ -931,11 +936,11 @@ static void drop_graphs(std::vector<StepGraph>& G) {
 // Run Arnoldi step j from its captured graph, capturing `body` (the step's
 // launches, no host synchronisation or allocation) on first use.
 template <typename T, typename Body>
-static void run_step_graph(phz_ctx* c, int K, int j, double rtol, double stall, Body&& body) {
+static void run_step_graph(phz_ctx* c, int K, int j, double rtol, double stall, const double* tol, Body&& body) {
   std::vector<StepGraph>& G = graphs_of<T>(c);
   if ((int)G.size() <= j) G.resize(j + 1);
   StepGraph& g = G[j];
-  if (!g.exec || g.K != K || g.rtol != rtol || g.stall != stall || g.epoch != c->graph_epoch) {
+  if (!g.exec || g.K != K || g.rtol != rtol || g.stall != stall || g.tol != tol || g.epoch != c->graph_epoch) {
     if (g.exec) hipGraphExecDestroy(g.exec);
     g.exec = nullptr;
     hipGraph_t graph = nullptr;
@@ -954,6 +959,7 @@ static void run_step_graph(phz_ctx* c, int K, int j, double rtol, double stall, 
     g.K = K;
     g.rtol = rtol;
     g.stall = stall;
+    g.tol = tol;
     g.epoch = c->graph_epoch;
   }
   PHZ_HIP(hipGraphLaunch(g.exec, c->stream));
@@ -966,12 +972,18 @@ static void run_step_graph(phz_ctx* c, int K, int j, double rtol, double stall, 
 // iterative refinement evaluates it in float64).
 template <typename T>
 static GmresResult gmres(phz_ctx* c, int K, const T* b, T* x, double rtol, int maxit, int hist_base,
-                         bool record_hist, bool x_is_zero = false, bool one_cycle = false) {
+                         bool record_hist, bool x_is_zero = false, bool one_cycle = false,
+                         const double* coltol = nullptr) {
   Work<T>& W = work_of<T>(c);
   const long nn = c->nn;
   const long vs = (long)basis_stride(nn, K);
   const int m = c->opt.restart;
+  // the float cycles keep P^-1 V_j (flexible GMRES): the correction is then
+  // Z y with no further preconditioner application, and the preconditioner's
+  // input-dependent rounding does not enter the Arnoldi relation
+  constexpr bool flexible = std::is_same<T, float>::value;
   GmresState S = gm_state(c);
+  S.tol = coltol;
   hipStream_t st = c->stream;
   GmresResult res;
   double* nrm = c->gm_nrm.p;
@@ -1024,10 +1036,11 @@ static GmresResult gmres(phz_ctx* c, int K, const T* b, T* x, double rtol, int m
     for (; j < m; ++j) {
       auto step = [&] {
         T* Vj = W.V.p + (size_t)j * vs;
+        T* Zj = flexible ? W.Z.p + (size_t)j * vs : W.z.p;
         const long tp = time_begin(c, sizeof(T) == 4 ? "precond_f32" : "precond_f64");
-        precond_apply<T>(c, K, Vj, W.z.p);
+        precond_apply<T>(c, K, Vj, Zj);
         time_end(c, tp);
-        op_apply<T>(c, 0, K, W.z.p, (const T*)nullptr, W.w.p, T(1), T(0));
+        op_apply<T>(c, 0, K, Zj, (const T*)nullptr, W.w.p, T(1), T(0));
         // classical Gram-Schmidt, twice
         const long ts = time_begin(c, sizeof(T) == 4 ? "arnoldi_cgs2_f32" : "arnoldi_cgs2_f64");
         arnoldi_dots<T>(nn, 4, K, j, W.V.p, vs, W.w.p, c->gm_h1.p, c->red_work.p, st);
@@ -1038,7 +1051,7 @@ static GmresResult gmres(phz_ctx* c, int K, const T* b, T* x, double rtol, int m
         scale_cols<T>(nn, 4, K, W.w.p, S.scale, W.V.p + (size_t)(j + 1) * vs, st);
       };
       // per-kernel timing needs eager launches
-      if (c->opt.use_graph && !c->ktime) run_step_graph<T>(c, K, j, rtol, stall, step);
+      if (c->opt.use_graph && !c->ktime) run_step_graph<T>(c, K, j, rtol, stall, coltol, step);
       else step();
       ++total;
       PHZ_HIP(hipMemcpyAsync(&nact, S.nactive, sizeof(int), hipMemcpyDeviceToHost, st));
@@ -1048,11 +1061,16 @@ static GmresResult gmres(phz_ctx* c, int K, const T* b, T* x, double rtol, int m
         break;
       }
     }
-    // x += P^-1 (V y)
+    // x += P^-1 (V y), or Z y when the cycle kept Z = P^-1 V
     gmres_solve_y(K, m, S, st);
-    combine<T>(nn, 4, K, W.V.p, vs, S.y, S.kused, W.t.p, st);
-    precond_apply<T>(c, K, W.t.p, W.z.p);
-    axpy_cols<T, T>(nn, 4, K, nullptr, W.z.p, x, st);
+    if (flexible) {
+      combine<T>(nn, 4, K, W.Z.p, vs, S.y, S.kused, W.t.p, st);
+      axpy_cols<T, T>(nn, 4, K, nullptr, W.t.p, x, st);
+    } else {
+      combine<T>(nn, 4, K, W.V.p, vs, S.y, S.kused, W.t.p, st);
+      precond_apply<T>(c, K, W.t.p, W.z.p);
+      axpy_cols<T, T>(nn, 4, K, nullptr, W.z.p, x, st);
+    }
     PHZ_HIP(hipMemcpyAsync(kused.data(), S.kused, K * sizeof(int), hipMemcpyDeviceToHost, st));
     PHZ_HIP(hipMemcpyAsync(estbuf.data(), S.est, (size_t)m * K * sizeof(double), hipMemcpyDeviceToHost, st));
     sync(c);
@@ -1087,7 +1105,7 @@ static int solve_ir(phz_ctx* c, int K, const double* b, double* x, double rtol, 
   const long count = nn * 4 * K;
   hipStream_t st = c->stream;
   double* nrm = c->gm_nrm.p + 9;
-  std::vector<double> bn(K), rn(K), scale(K), inv(K);
+  std::vector<double> bn(K), rn(K), scale(K), inv(K), tol(K);
   col_norm2<double>(nn, 4, K, b, nrm, c->red_work.p, st);
   PHZ_HIP(hipMemcpyAsync(bn.data(), nrm, K * sizeof(double), hipMemcpyDeviceToHost, st));
   sync(c);
@@ -1115,18 +1133,23 @@ static int solve_ir(phz_ctx* c, int K, const double* b, double* x, double rtol, 
       break;
     }
     if (steps >= c->opt.max_refine || used >= c->opt.max_iters) break;
-    // solve calA d = r / ||r|| in float, x += ||r|| d
+    // solve calA d = r / ||r|| in float, x += ||r|| d.  A load's cycle aims
+    // at inner_rtol, or, when less than that remains to its target, at what
+    // remains (with a margin of 4 for the float estimate): the last cycle
+    // stops as soon as the float64 target is in reach
     for (int k = 0; k < K; ++k) {
       const bool act = bn[k] > 0 && !(out.true_rel[k] <= rtol);
       scale[k] = act ? rn[k] : 0.0;
       inv[k] = act ? 1.0 / rn[k] : 0.0;
+      tol[k] = act ? std::max(c->opt.inner_rtol, 0.25 * rtol / out.true_rel[k]) : c->opt.inner_rtol;
     }
+    PHZ_HIP(hipMemcpyAsync(c->gm_tol.p, tol.data(), K * sizeof(double), hipMemcpyHostToDevice, st));
     PHZ_HIP(hipMemcpyAsync(scp, inv.data(), K * sizeof(double), hipMemcpyHostToDevice, st));
     scale_cols<double>(nn, 4, K, r64.p, scp, r64.p, st);
     convert<double, float>(count, r64.p, W.b.p, st);
     fill<float>(count, 0.0f, W.x.p, st);
     GmresResult g = gmres<float>(c, K, W.b.p, W.x.p, c->opt.inner_rtol, c->opt.max_iters - used, hist_base, true,
-                                 true, true);
+                                 true, true, c->gm_tol.p);
     PHZ_HIP(hipMemcpyAsync(scp, scale.data(), K * sizeof(double), hipMemcpyHostToDevice, st));
     axpy_cols<double, float>(nn, 4, K, scp, W.x.p, x, st);
     sync(c);

@@ -305,7 +305,8 @@ __global__ void k_gmres_start(int K, const double* __restrict__ nrm2, double rto
     const double beta = sqrt(nrm2[k]);
     s.g[k] = beta;
     const double bn = s.bnorm[k];
-    const int act = (bn > 0.0) && (beta > rtol * bn) && isfinite(beta);
+    const double tk = s.tol ? s.tol[k] : rtol;
+    const int act = (bn > 0.0) && (beta > tk * bn) && isfinite(beta);
     s.active[k] = act;
     s.kused[k] = 0;
     s.scale[k] = act ? 1.0 / beta : 0.0;
@@ -349,7 +350,8 @@ __global__ void k_gmres_givens(int K, int m, int j, const double* __restrict__ h
     s.est[j * K + k] = est;
     // stall: the estimate fell by less than the factor `stall` over two steps
     const bool stalled = stall > 0.0 && j >= 2 && est > stall * s.est[(j - 2) * K + k];
-    const bool stop = !(est > rtol) || !(hn > 0.0) || (j + 1 == m) || !isfinite(est) || stalled;
+    const double tk = s.tol ? s.tol[k] : rtol;
+    const bool stop = !(est > tk) || !(hn > 0.0) || (j + 1 == m) || !isfinite(est) || stalled;
     s.kused[k] = j + 1;
     if (stop) {
       s.active[k] = 0;
