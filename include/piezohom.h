@@ -82,11 +82,19 @@ extern "C" {
                             float32; refinement, residuals, Hessenberg/Givens,
                             coarse solve and reductions stay float64. */
 
+/* preconditioners of phz_options.solver (Sec. 2.5): both right-precondition
+ * GMRES on calA */
+#define PHZ_SOLVER_SCP 0 /* approximate Schur complement, lower block-triangular
+                            [[A, 0], [-B, S_bar]] (SCP-GMRES, the default)   */
+#define PHZ_SOLVER_DBP 1 /* block diagonal [[A, 0], [0, -C]] (DBP-GMRES)     */
+
 /* operator blocks for phz_apply (Sec. 2.5 block structure) */
 #define PHZ_OP_FULL 0    /* calA = [[A, B^T], [B, -C]] on [n][4][k]        */
 #define PHZ_OP_A 1       /* A (elasticity) on [n][3][k]                    */
 #define PHZ_OP_B 2       /* B (coupling) [n][3][k] -> [n][1][k]            */
 #define PHZ_OP_SBAR 3    /* element-wise approximate Schur S_bar on [n][1][k] */
+#define PHZ_OP_C 4       /* C (dielectric; calA's (phi, phi) block is -C) on
+                            [n][1][k]                                       */
 
 typedef struct phz_ctx phz_ctx;
 
@@ -157,6 +165,18 @@ typedef struct {
                                and 1 the apply with the input tile staged in
                                LDS (levels with N a multiple of 16); 0 or 1
                                forces that kernel where it applies           */
+    int solver;             /* PHZ_SOLVER_SCP (default) or PHZ_SOLVER_DBP     */
+    int inner;              /* block maps v -> A^-1 v and the potential block's
+                               inverse (S_bar or C): 0 (default) fixed V-cycle
+                               counts (vcycles_a, vcycles_s), a fixed linear
+                               preconditioner; 1 conjugate gradients with one
+                               V-cycle per iteration to the relative tolerance
+                               inner_eps (inexact inner solves, Sec. 2.5; the
+                               GMRES cycles are then flexible, keeping the
+                               preconditioned basis, and are not captured in
+                               graphs)                                        */
+    double inner_eps;       /* inner = 1: relative tolerance, default 1e-2     */
+    int inner_maxit;        /* inner = 1: iterations per map, default 200      */
 } phz_options;
 
 typedef struct {
@@ -181,6 +201,10 @@ typedef struct {
                                A hierarchy, [8 + l] for S_bar, l >= 1; -1 for
                                level 0, absent levels, FP64 and single-load
                                solves                                          */
+    long inner_iters[2];    /* inner = 1: conjugate-gradient iterations summed
+                               over the solve, [0] the A maps, [1] the
+                               potential block's maps                          */
+    long inner_calls[2];    /* inner = 1: number of those maps                 */
 } phz_stats;
 
 typedef struct {

@@ -23,7 +23,8 @@ PHZ_NOT_CONVERGED = 1
 PHZ_FP64 = 0
 PHZ_FP32_IR = 1
 PHZ_BF16X3_IR = 2
-OP_FULL, OP_A, OP_B, OP_SBAR = 0, 1, 2, 3
+PHZ_SOLVER_SCP, PHZ_SOLVER_DBP = 0, 1
+OP_FULL, OP_A, OP_B, OP_SBAR, OP_C = 0, 1, 2, 3, 4
 
 
 class phz_material(C.Structure):
@@ -38,7 +39,8 @@ class phz_options(C.Structure):
                 ("vcycles_s", C.c_int), ("inner_rtol", C.c_double), ("max_refine", C.c_int),
                 ("verbose", C.c_int), ("bf16_terms", C.c_int), ("bf16_outer", C.c_int),
                 ("elem_tile", C.c_int), ("use_graph", C.c_int), ("fine_kernel", C.c_int),
-                ("block_kernel", C.c_int * 4), ("block_tile", C.c_int * 4), ("coarse_kernel", C.c_int)]
+                ("block_kernel", C.c_int * 4), ("block_tile", C.c_int * 4), ("coarse_kernel", C.c_int),
+                ("solver", C.c_int), ("inner", C.c_int), ("inner_eps", C.c_double), ("inner_maxit", C.c_int)]
 
 
 def _set_option(o, k, v):
@@ -58,7 +60,8 @@ class phz_stats(C.Structure):
                 ("true_residual", C.c_double * 9), ("flux_energy_defect", C.c_double),
                 ("setup_ms", C.c_double), ("solve_ms", C.c_double), ("mg_levels", C.c_int),
                 ("cheb_lambda", C.c_double * 16), ("elem_tile", C.c_int * 4),
-                ("fine_kernel", C.c_int * 4), ("coarse_kernel", C.c_int * 16)]
+                ("fine_kernel", C.c_int * 4), ("coarse_kernel", C.c_int * 16), ("inner_iters", C.c_long * 2),
+                ("inner_calls", C.c_long * 2)]
 
 
 class phz_foms_t(C.Structure):
@@ -251,6 +254,7 @@ class Context:
             "solve_ms": s.solve_ms, "mg_levels": s.mg_levels,
             "cheb_lambda": list(s.cheb_lambda), "elem_tile": list(s.elem_tile),
             "fine_kernel": list(s.fine_kernel), "coarse_kernel": list(s.coarse_kernel),
+            "inner_iters": list(s.inner_iters), "inner_calls": list(s.inner_calls),
         }
 
     def history(self, load):

@@ -134,6 +134,12 @@ size_t reduce_work_size();
 // out[k] = sum over fields and nodes of v^2, per load column k (double)
 template <typename T>
 void col_norm2(long nn, int F, int K, const T* v, double* out, double* work, hipStream_t st);
+// out[k] = sum over the F fields of column k of a . b (float64 accumulation)
+template <typename T>
+void col_dot(long nn, int F, int K, const T* a, const T* b, double* out, double* work, hipStream_t st);
+// p = z + beta[k] p, per load column k
+template <typename T>
+void xpby_cols(long nn, int F, int K, const double* beta, const T* z, T* p, hipStream_t st);
 // out[f*K + k] = sum over nodes of column (f, k)
 template <typename T>
 void field_sums(long nn, int F, int K, const T* v, double* out, double* work, hipStream_t st);

@@ -33,6 +33,7 @@ struct RefElement {
   double A0[24 * 24];    // (3l+f, 3l'+f')
   double B0[8 * 24];     // (l, 3l'+f')
   double S0[8 * 8];      // (l, l')
+  double C0[8 * 8];      // (l, l'): the dielectric block; the operator's (phi, phi) block is -C0
   double Kfull[32 * 32]; // same as K0 (4l+f, 4l'+f'), kept for clarity
 };
 
@@ -150,6 +151,8 @@ inline RefElement build_ref_element(const phz_material& mat, double h, double de
     for (int lp = 0; lp < 8; ++lp)
       for (int fp = 0; fp < 3; ++fp)
         R.B0[l * 24 + 3 * lp + fp] = R.K0[(4 * l + 3) * 32 + 4 * lp + fp];
+  for (int l = 0; l < 8; ++l)
+    for (int lp = 0; lp < 8; ++lp) R.C0[l * 8 + lp] = -R.K0[(4 * l + 3) * 32 + 4 * lp + 3];
   // S0 = C0 + B0 (A0 + delta I)^-1 B0^T
   double Bt[24 * 8], Z[24 * 8];
   for (int i = 0; i < 24; ++i)

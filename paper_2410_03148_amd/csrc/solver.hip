@@ -98,8 +98,9 @@ struct LevelWork {
 template <typename T>
 struct Work {
   int cap_k = 0, cap_m = 0;
-  std::vector<std::unique_ptr<LevelWork<T>>> A, S;
+  std::vector<std::unique_ptr<LevelWork<T>>> A, S, C;
   DevBuf<T> t1u, t2u, t1p, t2p, t3p;   // preconditioner temporaries
+  DevBuf<T> pr, pz, pp, pq;            // conjugate gradients of the inexact block maps
   DevBuf<T> V, w, z, t, r, b, x;                  // GMRES
   DevBuf<T> Z;  // preconditioned basis P^-1 V_j (flexible GMRES, the float cycles)
 };
@@ -128,12 +129,15 @@ struct phz_ctx {
   std::string err;
 
   phz::RefElement ref;
-  phz::DevBuf<double> kref_full, kref_A, kref_B, kref_S, F0d;
-  phz::DevBuf<float> kref32_full, kref32_A, kref32_B, kref32_S;
-  // split-BF16 MFMA operands of the four fine blocks, their tile choice
-  // (-1 not yet chosen, -2 none divides N), and the kernel chosen for each
-  // block's float32 nine-column launches
-  phz::DevBuf<unsigned short> kop[4];
+  // reference blocks: 0 full, 1 A, 2 B, 3 S_bar, and 4 C (the dielectric
+  // block, a 1 -> 1 block like S_bar, used by the block-diagonal
+  // preconditioner)
+  phz::DevBuf<double> kref_full, kref_A, kref_B, kref_S, kref_C, F0d;
+  phz::DevBuf<float> kref32_full, kref32_A, kref32_B, kref32_S, kref32_C;
+  // split-BF16 MFMA operands of the five fine blocks, the tile choice of the
+  // four block shapes (-1 not yet chosen, -2 none divides N), and the kernel
+  // chosen for each shape's float32 nine-column launches
+  phz::DevBuf<unsigned short> kop[5];
   int elem_tile[4] = {-1, -1, -1, -1};
   int fkind[4] = {-1, -1, -1, -1};   // kernel of the float32 nine-column launches, -1 not yet chosen
 
@@ -143,7 +147,7 @@ struct phz_ctx {
   bool precond_ready = false;
   bool have_guess = false;
 
-  phz::Hierarchy hA, hS;
+  phz::Hierarchy hA, hS, hC;   // hC: only for the block-diagonal preconditioner
   phz::Work<double> w64;
   phz::Work<float> w32;
 
@@ -158,6 +162,8 @@ struct phz_ctx {
   std::vector<phz::StepGraph> graphs64, graphs32;
   long graph_epoch = 0;
   phz::DevBuf<double> one64;   // the constant 1.0 (power-iteration Jacobi step)
+  phz::DevBuf<double> negone;  // nine copies of -1.0 (block-diagonal preconditioner)
+  phz::DevBuf<double> pcg_dev; // per-column scalars of the inexact block maps
 
   // optional per-kernel timing with HIP events on the context stream
   bool ktime = false;
@@ -227,6 +233,7 @@ static void upload_reference(phz_ctx* c) {
   c->kref_A.upload(R.A0, 24 * 24, st);
   c->kref_B.upload(R.B0, 8 * 24, st);
   c->kref_S.upload(R.S0, 8 * 8, st);
+  c->kref_C.upload(R.C0, 8 * 8, st);
   c->F0d.upload(R.F0, 32 * 9, st);
   std::vector<float> f(32 * 32);
   auto up32 = [&](DevBuf<float>& d, const double* h, int n) {
@@ -238,10 +245,11 @@ static void upload_reference(phz_ctx* c) {
   up32(c->kref32_A, R.A0, 24 * 24);
   up32(c->kref32_B, R.B0, 8 * 24);
   up32(c->kref32_S, R.S0, 8 * 8);
+  up32(c->kref32_C, R.C0, 8 * 8);
   std::vector<unsigned short> ops(2048);
-  const double* krefs[4] = {R.K0, R.A0, R.B0, R.S0};
-  for (int op = 0; op < 4; ++op) {
-    elem_operand_host(op, krefs[op], ops.data());
+  const double* krefs[5] = {R.K0, R.A0, R.B0, R.S0, R.C0};
+  for (int op = 0; op < 5; ++op) {
+    elem_operand_host(op == 4 ? 3 : op, krefs[op], ops.data());
     c->kop[op].upload(ops.data(), ops.size(), st);
     sync(c);
   }
@@ -300,11 +308,12 @@ static void alloc_work(phz_ctx* c, Work<T>& W, int K, int m) {
   };
   mk(c->hA, W.A);
   mk(c->hS, W.S);
+  mk(c->hC, W.C);
   const size_t u = (size_t)nn * 3 * K, p = (size_t)nn * K, full = (size_t)nn * 4 * K;
   W.t1u.alloc(u); W.t2u.alloc(u);
   W.t1p.alloc(p); W.t2p.alloc(p); W.t3p.alloc(p);
   W.V.alloc(basis_stride(nn, K) * (m + 1));
-  if (std::is_same<T, float>::value) W.Z.alloc(basis_stride(nn, K) * m);
+  if (std::is_same<T, float>::value || c->opt.inner == 1) W.Z.alloc(basis_stride(nn, K) * m);
   W.w.alloc(full); W.z.alloc(full); W.t.alloc(full); W.r.alloc(full); W.b.alloc(full); W.x.alloc(full);
   W.cap_k = K;
   W.cap_m = m;
@@ -348,11 +357,14 @@ static GmresState gm_state(phz_ctx* c) {
 // ---------------------------------------------------------- level operators
 template <typename T> static const T* kref_of(phz_ctx* c, int op);
 template <> const double* kref_of<double>(phz_ctx* c, int op) {
-  return op == 0 ? c->kref_full.p : op == 1 ? c->kref_A.p : op == 2 ? c->kref_B.p : c->kref_S.p;
+  return op == 0 ? c->kref_full.p : op == 1 ? c->kref_A.p : op == 2 ? c->kref_B.p : op == 3 ? c->kref_S.p : c->kref_C.p;
 }
 template <> const float* kref_of<float>(phz_ctx* c, int op) {
-  return op == 0 ? c->kref32_full.p : op == 1 ? c->kref32_A.p : op == 2 ? c->kref32_B.p : c->kref32_S.p;
+  return op == 0 ? c->kref32_full.p : op == 1 ? c->kref32_A.p : op == 2 ? c->kref32_B.p
+       : op == 3 ? c->kref32_S.p : c->kref32_C.p;
 }
+// launch shape (fields in and out) of a reference block: C is shaped like S_bar
+static int shape_of(int op) { return op == 4 ? 3 : op; }
 template <typename T> static const T* s_of(phz_ctx* c);
 template <> const double* s_of<double>(phz_ctx* c) { return c->s.p; }
 template <> const float* s_of<float>(phz_ctx* c) { return c->s32.p; }
@@ -536,27 +548,30 @@ static int fine_kind_of(phz_ctx* c, int op) {
 }
 
 // fine-level operator launch with optional timing
+// (blk: reference block 0..4; launches use its shape, whose kernel and tile
+// choices it shares)
 template <typename T>
-static void op_apply_args(phz_ctx* c, int op, int K, const T* x, const OpArgs<T>& a, bool cheby) {
+static void op_apply_args(phz_ctx* c, int blk, int K, const T* x, const OpArgs<T>& a, bool cheby) {
+  const int op = shape_of(blk);
   if constexpr (std::is_same<T, float>::value) {
     if (K == 9) {
       const int kind = fine_kind_of(c, op);
       if (kind == kFineElem) {
         const long slot = time_begin(c, elem_op_name(op, c->opt.bf16_terms == 3, cheby));
-        elem_apply(op, K, c->N, c->opt.bf16_terms, c->elem_tile[op], c->s32.p, c->kop[op].p, x, a, cheby, c->stream);
+        elem_apply(op, K, c->N, c->opt.bf16_terms, c->elem_tile[op], c->s32.p, c->kop[blk].p, x, a, cheby, c->stream);
         time_end(c, slot);
         return;
       }
       if (kind == kFineTiled) {
         const long slot = time_begin(c, tiled_op_name(op, cheby));
-        fine_apply_tiled(op, K, c->N, c->s32.p, kref_of<float>(c, op), x, a, cheby, c->stream);
+        fine_apply_tiled(op, K, c->N, c->s32.p, kref_of<float>(c, blk), x, a, cheby, c->stream);
         time_end(c, slot);
         return;
       }
     }
   }
   const long slot = time_begin(c, fine_op_name(op, K, sizeof(T) == 4, cheby));
-  fine_apply<T>(op, K, c->N, s_of<T>(c), kref_of<T>(c, op), x, a, cheby, c->stream);
+  fine_apply<T>(op, K, c->N, s_of<T>(c), kref_of<T>(c, blk), x, a, cheby, c->stream);
   time_end(c, slot);
 }
 
@@ -603,7 +618,7 @@ static void host_element_matrices(phz_ctx* c, Hierarchy& H, int l, std::vector<d
     std::vector<double> sh(L.nn);
     PHZ_HIP(hipMemcpyAsync(sh.data(), c->s.p, L.nn * sizeof(double), hipMemcpyDeviceToHost, c->stream));
     sync(c);
-    const double* kref = F == 3 ? c->ref.A0 : c->ref.S0;
+    const double* kref = F == 3 ? c->ref.A0 : H.op == 4 ? c->ref.C0 : c->ref.S0;
     for (int Lc = 0; Lc < 8; ++Lc)
       for (int f = 0; f < F; ++f)
         for (int col = 0; col < S; ++col)
@@ -675,7 +690,7 @@ static double power_lmax(phz_ctx* c, Hierarchy& H, int l) {
 
 static void setup_hierarchy(phz_ctx* c, Hierarchy& H) {
   const int F = H.F;
-  const double* krefd = F == 3 ? c->kref_A.p : c->kref_S.p;
+  const double* krefd = F == 3 ? c->kref_A.p : H.op == 4 ? c->kref_C.p : c->kref_S.p;
   const int nl = (int)H.lv.size();
   for (int l = 0; l < nl; ++l) {
     Level& L = *H.lv[l];
@@ -734,9 +749,10 @@ static void setup_hierarchy(phz_ctx* c, Hierarchy& H) {
 
 template <typename T>
 static void drop_level_work_if_changed(phz_ctx* c, Work<T>& W) {
-  if (W.A.size() != c->hA.lv.size() || W.S.size() != c->hS.lv.size()) {
+  if (W.A.size() != c->hA.lv.size() || W.S.size() != c->hS.lv.size() || W.C.size() != c->hC.lv.size()) {
     W.A.clear();
     W.S.clear();
+    W.C.clear();
     W.cap_k = 0;
   }
 }
@@ -757,14 +773,23 @@ static void setup_preconditioner(phz_ctx* c) {
   }
   build_levels(c, c->hA, 3, 1);
   build_levels(c, c->hS, 1, 3);
+  // the C hierarchy only exists for the block-diagonal preconditioner
+  if (c->opt.solver == PHZ_SOLVER_DBP) {
+    build_levels(c, c->hC, 1, 4);
+  } else if (!c->hC.lv.empty()) {
+    c->hC.lv.clear();
+    ++c->graph_epoch;
+  }
   drop_level_work_if_changed(c, c->w64);
   drop_level_work_if_changed(c, c->w32);
   setup_hierarchy(c, c->hA);
   setup_hierarchy(c, c->hS);
+  if (!c->hC.lv.empty()) setup_hierarchy(c, c->hC);
   for (int q = 0; q < 16; ++q) c->stats.coarse_kernel[q] = -1;
   if (c->opt.precision != PHZ_FP64 && c->opt.batched) {
     for (size_t l = 1; l < c->hA.lv.size() && l < 8; ++l) c->stats.coarse_kernel[l] = coarse_kind_of(c, c->hA, (int)l);
     for (size_t l = 1; l < c->hS.lv.size() && l < 8; ++l) c->stats.coarse_kernel[8 + l] = coarse_kind_of(c, c->hS, (int)l);
+    for (size_t l = 1; l < c->hC.lv.size(); ++l) coarse_kind_of(c, c->hC, (int)l);
   }
   sync(c);
   c->precond_ready = true;
@@ -901,6 +926,99 @@ static void block_solve(phz_ctx* c, Hierarchy& H, std::vector<std::unique_ptr<Le
 // z = P^-1 r on [nn][4][K]
 // (structure of arrays: the displacement block of a 4-field vector is its
 // first 3K columns, the potential block the last K)
+// Inexact block map x ~= M^-1 b for the fine-level operator M of hierarchy
+// H (A, S_bar or C): conjugate gradients preconditioned by one V-cycle, from
+// x = 0, until ||b - M x|| <= inner_eps ||b|| in every load column or
+// inner_maxit iterations.  M is singular on the periodic cell (constants per
+// field), so b and every preconditioned residual are projected onto zero
+// field means, which keeps the iteration in M's range.  Returns the number
+// of iterations.
+template <typename T>
+static int pcg_block(phz_ctx* c, Hierarchy& H, std::vector<std::unique_ptr<LevelWork<T>>>& WL, int K, const T* b,
+                     T* x) {
+  Work<T>& W = work_of<T>(c);
+  const long nn = c->nn;
+  const int F = H.F;
+  const size_t cnt = (size_t)nn * F * K;
+  hipStream_t st = c->stream;
+  if (c->pcg_dev.n < (size_t)(3 * K + F * K)) throw std::logic_error("pcg_block: scalar workspace too small");
+  for (DevBuf<T>* v : {&W.pr, &W.pz, &W.pp, &W.pq})
+    if (v->n < (size_t)nn * 3 * K) v->alloc((size_t)nn * 3 * K);
+  T *r = W.pr.p, *z = W.pz.p, *p = W.pp.p, *q = W.pq.p;
+  double* dv = c->pcg_dev.p;     // [0, K) alpha, [K, 2K) -alpha, [2K, 3K) beta, [3K, 3K + F K) reductions
+  double* red = dv + 3 * K;
+  std::vector<double> bn(K), rz(K), h(K), al(2 * K), be(K);
+  std::vector<int> act(K);
+  auto to_host = [&](std::vector<double>& out) {
+    PHZ_HIP(hipMemcpyAsync(out.data(), red, K * sizeof(double), hipMemcpyDeviceToHost, st));
+    sync(c);
+  };
+  auto project = [&](T* v) {
+    field_sums<T>(nn, F, K, v, red, c->red_work.p, st);
+    subtract_mean<T>(nn, F, K, red, v, st);
+  };
+  PHZ_HIP(hipMemcpyAsync(r, b, cnt * sizeof(T), hipMemcpyDeviceToDevice, st));
+  project(r);
+  fill<T>((long)cnt, T(0), x, st);
+  col_norm2<T>(nn, F, K, r, red, c->red_work.p, st);
+  to_host(bn);
+  int nact = 0;
+  for (int k = 0; k < K; ++k) {
+    bn[k] = std::sqrt(bn[k]);
+    act[k] = bn[k] > 0.0;
+    nact += act[k];
+  }
+  if (nact == 0) return 0;
+  vcycle<T>(c, H, WL, 0, K, r, z);
+  project(z);
+  PHZ_HIP(hipMemcpyAsync(p, z, cnt * sizeof(T), hipMemcpyDeviceToDevice, st));
+  col_dot<T>(nn, F, K, r, z, red, c->red_work.p, st);
+  to_host(rz);
+  int it = 0;
+  const double eps = c->opt.inner_eps;
+  while (it < c->opt.inner_maxit) {
+    level_apply<T>(c, H, 0, K, p, (const T*)nullptr, q, T(1), T(0));
+    col_dot<T>(nn, F, K, p, q, red, c->red_work.p, st);
+    to_host(h);
+    for (int k = 0; k < K; ++k) {
+      const double a = act[k] && h[k] > 0.0 ? rz[k] / h[k] : 0.0;
+      al[k] = a;
+      al[K + k] = -a;
+    }
+    PHZ_HIP(hipMemcpyAsync(dv, al.data(), 2 * K * sizeof(double), hipMemcpyHostToDevice, st));
+    axpy_cols<T, T>(nn, F, K, dv, p, x, st);
+    axpy_cols<T, T>(nn, F, K, dv + K, q, r, st);
+    ++it;
+    col_norm2<T>(nn, F, K, r, red, c->red_work.p, st);
+    to_host(h);
+    nact = 0;
+    for (int k = 0; k < K; ++k) {
+      if (act[k] && (std::sqrt(h[k]) <= eps * bn[k] || !(h[k] >= 0.0))) act[k] = 0;
+      nact += act[k];
+    }
+    if (nact == 0) break;
+    vcycle<T>(c, H, WL, 0, K, r, z);
+    project(z);
+    col_dot<T>(nn, F, K, r, z, red, c->red_work.p, st);
+    to_host(h);
+    for (int k = 0; k < K; ++k) {
+      be[k] = act[k] && rz[k] != 0.0 ? h[k] / rz[k] : 0.0;
+      rz[k] = h[k];
+    }
+    PHZ_HIP(hipMemcpyAsync(dv + 2 * K, be.data(), K * sizeof(double), hipMemcpyHostToDevice, st));
+    xpby_cols<T>(nn, F, K, dv + 2 * K, z, p, st);
+  }
+  return it;
+}
+
+// z = P^-1 r on [nn][4][K]
+// (structure of arrays: the displacement block of a 4-field vector is its
+// first 3K columns, the potential block the last K).  SCP (the approximate
+// Schur complement, lower block-triangular): z_u = A^-1 r_u, then
+// z_p = S_bar^-1 (B z_u - r_p).  DBP (block diagonal diag(A, -C)):
+// z_u = A^-1 r_u, z_p = -C^-1 r_p.  The block maps are fixed V-cycle counts
+// (vcycles_a, vcycles_s) or, with inner = 1, conjugate gradients to
+// inner_eps.
 template <typename T>
 static void precond_apply(phz_ctx* c, int K, const T* r, T* z) {
   Work<T>& W = work_of<T>(c);
@@ -909,10 +1027,29 @@ static void precond_apply(phz_ctx* c, int K, const T* r, T* z) {
   const T* rp = r + off;
   T* zu = z;
   T* zp = z + off;
-  block_solve<T>(c, c->hA, W.A, K, std::max(1, c->opt.vcycles_a), ru, zu, W.t1u.p, W.t2u.p);
-  // t = B z_u - r_p
-  op_apply<T>(c, 2, K, zu, rp, W.t1p.p, T(1), T(-1));
-  block_solve<T>(c, c->hS, W.S, K, std::max(1, c->opt.vcycles_s), W.t1p.p, zp, W.t2p.p, W.t3p.p);
+  const bool pcg = c->opt.inner == 1;
+  if (pcg) {
+    c->stats.inner_iters[0] += pcg_block<T>(c, c->hA, W.A, K, ru, zu);
+    c->stats.inner_calls[0] += 1;
+  } else {
+    block_solve<T>(c, c->hA, W.A, K, std::max(1, c->opt.vcycles_a), ru, zu, W.t1u.p, W.t2u.p);
+  }
+  const bool dbp = c->opt.solver == PHZ_SOLVER_DBP;
+  Hierarchy& Hp = dbp ? c->hC : c->hS;
+  auto& WLp = dbp ? W.C : W.S;
+  if (dbp) {
+    // t = -r_p
+    scale_cols<T>((long)c->nn, 1, K, rp, c->negone.p, W.t1p.p, c->stream);
+  } else {
+    // t = B z_u - r_p
+    op_apply<T>(c, 2, K, zu, rp, W.t1p.p, T(1), T(-1));
+  }
+  if (pcg) {
+    c->stats.inner_iters[1] += pcg_block<T>(c, Hp, WLp, K, W.t1p.p, zp);
+    c->stats.inner_calls[1] += 1;
+  } else {
+    block_solve<T>(c, Hp, WLp, K, std::max(1, c->opt.vcycles_s), W.t1p.p, zp, W.t2p.p, W.t3p.p);
+  }
 }
 
 // ------------------------------------------------------------------ GMRES
@@ -981,7 +1118,10 @@ static GmresResult gmres(phz_ctx* c, int K, const T* b, T* x, double rtol, int m
   // the float cycles keep P^-1 V_j (flexible GMRES): the correction is then
   // Z y with no further preconditioner application, and the preconditioner's
   // input-dependent rounding does not enter the Arnoldi relation
-  constexpr bool flexible = std::is_same<T, float>::value;
+  // (and so does every cycle whose block maps are conjugate-gradient solves,
+  // a preconditioner that changes from one application to the next)
+  const bool flexible = std::is_same<T, float>::value || c->opt.inner == 1;
+  if (flexible && W.Z.n < (size_t)vs * m) W.Z.alloc((size_t)vs * m);
   GmresState S = gm_state(c);
   S.tol = coltol;
   hipStream_t st = c->stream;
@@ -1051,7 +1191,8 @@ static GmresResult gmres(phz_ctx* c, int K, const T* b, T* x, double rtol, int m
         scale_cols<T>(nn, 4, K, W.w.p, S.scale, W.V.p + (size_t)(j + 1) * vs, st);
       };
       // per-kernel timing needs eager launches
-      if (c->opt.use_graph && !c->ktime) run_step_graph<T>(c, K, j, rtol, stall, coltol, step);
+      // (inexact block maps synchronise with the host: never captured)
+      if (c->opt.use_graph && !c->ktime && c->opt.inner == 0) run_step_graph<T>(c, K, j, rtol, stall, coltol, step);
       else step();
       ++total;
       PHZ_HIP(hipMemcpyAsync(&nact, S.nactive, sizeof(int), hipMemcpyDeviceToHost, st));
@@ -1247,6 +1388,7 @@ static int do_solve(phz_ctx* c) {
   std::memset(c->stats.iterations, 0, sizeof(c->stats.iterations));
   std::memset(c->stats.restarts, 0, sizeof(c->stats.restarts));
   c->stats.refinements = 0;
+  for (int i = 0; i < 2; ++i) c->stats.inner_iters[i] = c->stats.inner_calls[i] = 0;
   for (auto& h : c->hist) h.clear();
   ensure_state_buffers(c);
   c->X.alloc(nn * 36);
@@ -1383,6 +1525,10 @@ void phz_default_options(phz_options* o) {
   o->fine_kernel = -1;
   for (int op = 0; op < 4; ++op) o->block_kernel[op] = o->block_tile[op] = -1;
   o->coarse_kernel = -1;
+  o->solver = PHZ_SOLVER_SCP;
+  o->inner = 0;
+  o->inner_eps = 1e-2;
+  o->inner_maxit = 200;
 }
 
 const char* phz_strerror(int status) {
@@ -1402,6 +1548,10 @@ static int check_options(const phz_options* o, std::string& err) {
   if (o->use_graph != 0 && o->use_graph != 1) { err = "use_graph must be 0 or 1"; return PHZ_E_INVALID; }
   if (o->fine_kernel < -1 || o->fine_kernel > 2) { err = "fine_kernel must be -1, 0, 1 or 2"; return PHZ_E_INVALID; }
   if (o->coarse_kernel < -1 || o->coarse_kernel > 1) { err = "coarse_kernel must be -1, 0 or 1"; return PHZ_E_INVALID; }
+  if (o->solver != PHZ_SOLVER_SCP && o->solver != PHZ_SOLVER_DBP) { err = "solver must be PHZ_SOLVER_SCP or PHZ_SOLVER_DBP"; return PHZ_E_INVALID; }
+  if (o->inner != 0 && o->inner != 1) { err = "inner must be 0 or 1"; return PHZ_E_INVALID; }
+  if (!(o->inner_eps > 0 && o->inner_eps < 1)) { err = "inner_eps must be in (0, 1)"; return PHZ_E_INVALID; }
+  if (o->inner_maxit < 1) { err = "inner_maxit must be positive"; return PHZ_E_INVALID; }
   for (int op = 0; op < 4; ++op) {
     if (o->block_kernel[op] < -1 || o->block_kernel[op] > 2) { err = "block_kernel entries must be -1, 0, 1 or 2"; return PHZ_E_INVALID; }
     if (o->block_tile[op] < -1 || o->block_tile[op] >= elem_tile_count()) {
@@ -1450,6 +1600,9 @@ int phz_create(int n, const phz_material* mat, const phz_options* opt, void* str
   upload_reference(c.get());
   static const double kOne = 1.0;
   c->one64.upload(&kOne, 1, c->stream);
+  const double neg[9] = {-1.0, -1.0, -1.0, -1.0, -1.0, -1.0, -1.0, -1.0, -1.0};
+  c->negone.upload(neg, 9, c->stream);
+  c->pcg_dev.alloc(3 * 9 + 4 * 9);   // alpha, -alpha, beta; then up to 4 x 9 reductions
   c->phi.alloc(c->nn);
   c->rho.alloc(c->nn);
   c->s.alloc(c->nn);
@@ -1487,6 +1640,7 @@ int phz_set_options(phz_ctx* c, const phz_options* opt) {
     c->elem_tile[op] = -1;
     c->fkind[op] = -1;
   }
+  if (opt->solver != c->opt.solver) c->precond_ready = false;   // the C hierarchy comes or goes
   if (opt->coarse_kernel != c->opt.coarse_kernel) {
     // the per-level choice is made again with the hierarchy
     for (auto& L : c->hA.lv) L->ckind = -1;
@@ -1856,7 +2010,7 @@ int phz_get_kernel_timing(phz_ctx* c, char* buf, int cap, int* len) {
 }
 
 int phz_apply(phz_ctx* c, int op, int nrhs, int precision, const void* x, void* y) {
-  if (!c || !x || !y || op < 0 || op > 3 || (nrhs != 1 && nrhs != 9)) return PHZ_E_INVALID;
+  if (!c || !x || !y || op < 0 || op > 4 || (nrhs != 1 && nrhs != 9)) return PHZ_E_INVALID;
   if (!c->have_s) return PHZ_E_STATE;
   PHZ_GUARD_BEGIN
   if (precision == PHZ_FP64)
@@ -1864,12 +2018,12 @@ int phz_apply(phz_ctx* c, int op, int nrhs, int precision, const void* x, void* 
   else if (precision == PHZ_FP32_IR)
     op_apply<float>(c, op, nrhs, (const float*)x, (const float*)nullptr, (float*)y, 1.0f, 0.0f);
   else if (precision == PHZ_BF16X3_IR) {
-    const int tile = nrhs == 9 ? elem_tile_of(c, op) : -1;
+    const int tile = nrhs == 9 ? elem_tile_of(c, shape_of(op)) : -1;
     if (tile < 0) {
       c->err = "split-BF16 apply needs nine columns and a tile that divides N";
       return PHZ_E_INVALID;
     }
-    elem_apply(op, 9, c->N, c->opt.bf16_terms, tile, c->s32.p, c->kop[op].p, (const float*)x,
+    elem_apply(shape_of(op), 9, c->N, c->opt.bf16_terms, tile, c->s32.p, c->kop[op].p, (const float*)x,
                plain_args<float>(nullptr, (float*)y, 1.0f, 0.0f), false, c->stream);
   } else
     return PHZ_E_INVALID;

@@ -86,6 +86,19 @@ __global__ __launch_bounds__(256) void k_col_sums(unsigned nn, const T* __restri
   if (threadIdx.x == 0) part[(size_t)blockIdx.y * gridDim.x + blockIdx.x] = acc;
 }
 
+// per-column dot products a.b of column blockIdx.y over slice blockIdx.x
+template <typename T>
+__global__ __launch_bounds__(256) void k_col_dots(unsigned nn, const T* __restrict__ a, const T* __restrict__ b,
+                                                  double* __restrict__ part) {
+  __shared__ double lds4[4];
+  const size_t co = (size_t)blockIdx.y * nn;
+  double acc = 0.0;
+  for (unsigned n = blockIdx.x * 256 + threadIdx.x; n < nn; n += gridDim.x * 256)
+    acc += (double)a[co + n] * (double)b[co + n];
+  acc = block_sum(acc, lds4);
+  if (threadIdx.x == 0) part[(size_t)blockIdx.y * gridDim.x + blockIdx.x] = acc;
+}
+
 template <typename T, bool SQ>
 void col_reduce(size_t nn, int F, int K, const T* v, double* out, double* work, hipStream_t st) {
   const unsigned G = slices_for(nn, F * K);
@@ -245,6 +258,16 @@ __global__ void k_axpy_cols(unsigned nn, int K, const double* __restrict__ a, co
   const size_t o = (size_t)blockIdx.y * nn + n;
   const double av = a ? a[blockIdx.y % K] : 1.0;
   x[o] = (Tx)((double)x[o] + av * (double)z[o]);
+}
+
+// p = z + beta_k p (per load column k)
+template <typename T>
+__global__ void k_xpby_cols(unsigned nn, int K, const double* __restrict__ beta, const T* __restrict__ z,
+                            T* __restrict__ p) {
+  const unsigned n = blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= nn) return;
+  const size_t o = (size_t)blockIdx.y * nn + n;
+  p[o] = (T)((double)z[o] + beta[blockIdx.y % K] * (double)p[o]);
 }
 
 template <typename Ts, typename Td>
@@ -668,6 +691,21 @@ void col_norm2(long nn, int F, int K, const T* v, double* out, double* work, hip
 }
 
 template <typename T>
+void col_dot(long nn, int F, int K, const T* a, const T* b, double* out, double* work, hipStream_t st) {
+  const unsigned G = slices_for((size_t)nn, F * K);
+  hipLaunchKernelGGL((k_col_dots<T>), dim3(G, F * K), dim3(256), 0, st, (unsigned)nn, a, b, work);
+  reduce_cols((int)G, F, K, 1, 0, 1, work, out, st);
+  PHZ_LAUNCH_CHECK();
+}
+
+template <typename T>
+void xpby_cols(long nn, int F, int K, const double* beta, const T* z, T* p, hipStream_t st) {
+  hipLaunchKernelGGL((k_xpby_cols<T>), dim3(blocks_for(nn, 256), F * K), dim3(256), 0, st, (unsigned)nn, K, beta, z,
+                     p);
+  PHZ_LAUNCH_CHECK();
+}
+
+template <typename T>
 void field_sums(long nn, int F, int K, const T* v, double* out, double* work, hipStream_t st) {
   col_reduce<T, false>((size_t)nn, 1, F * K, v, out, work, st);
 }
@@ -842,6 +880,8 @@ void hash_fill(long count, unsigned seed, double* v, hipStream_t st) {
 #define PHZ_VINST(T)                                                                                          \
   template void fill<T>(long, T, T*, hipStream_t);                                                            \
   template void col_norm2<T>(long, int, int, const T*, double*, double*, hipStream_t);                       \
+  template void col_dot<T>(long, int, int, const T*, const T*, double*, double*, hipStream_t);               \
+  template void xpby_cols<T>(long, int, int, const double*, const T*, T*, hipStream_t);                      \
   template void field_sums<T>(long, int, int, const T*, double*, double*, hipStream_t);                      \
   template void subtract_mean<T>(long, int, int, const double*, T*, hipStream_t);                            \
   template void arnoldi_dots<T>(long, int, int, int, const T*, long, const T*, double*, double*, hipStream_t); \
