@@ -97,6 +97,47 @@ def cpu_baseline(n_sample=16):
     return float(out.stdout.strip().splitlines()[-1])
 
 
+def solver_study(P, torch, synth, mat, dev):
+    """Outer GMRES iterations, inner conjugate-gradient iterations per block
+    map and times of the preconditioner forms (the analogue of the paper's
+    Table 1 on one GPU: multigrid instead of algebraic multigrid inside the
+    block maps, all nine loads batched; load 0 is the eps^11 load the paper
+    reports)."""
+    forms = [("SCP-GMRES", P.PHZ_SOLVER_SCP, 0, None), ("SCP-GMRES", P.PHZ_SOLVER_SCP, 1, 1e-8),
+             ("SCP-GMRES", P.PHZ_SOLVER_SCP, 1, 1e-4), ("SCP-GMRES", P.PHZ_SOLVER_SCP, 1, 1e-2),
+             ("DBP-GMRES", P.PHZ_SOLVER_DBP, 0, None), ("DBP-GMRES", P.PHZ_SOLVER_DBP, 1, 1e-8),
+             ("DBP-GMRES", P.PHZ_SOLVER_DBP, 1, 1e-4), ("DBP-GMRES", P.PHZ_SOLVER_DBP, 1, 1e-2)]
+    rows = []
+    for n in (64, 128):
+        phi = torch.tensor(synth.paper_levelset(n), device=dev)
+        for name, solver, inner, eps in forms:
+            opts = dict(precision=P.PHZ_FP64, solver=solver, inner=inner, rtol=1e-8, restart=30, vcycles_a=2,
+                        max_iters=600)
+            if eps is not None:
+                opts["inner_eps"] = eps
+            with P.Context(n, mat, stream=torch.cuda.current_stream().cuda_stream, **opts) as ctx:
+                ctx.set_levelset(phi)
+                ctx.solve()
+                ctx.set_levelset(phi)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                status = ctx.solve()
+                torch.cuda.synchronize()
+                dt = time.perf_counter() - t0
+                st = ctx.stats()
+            calls = st["inner_calls"]
+            rows.append({"n": n, "dofs": 4 * n ** 3, "solver": name,
+                         "block_maps": "V-cycles (A 2, potential 1)" if not inner else f"CG to {eps:g}",
+                         "status": status, "outer_iters_load0": st["iterations"][0],
+                         "outer_iters_max": max(st["iterations"]),
+                         "cg_iters_per_A_map": st["inner_iters"][0] / calls[0] if calls[0] else None,
+                         "cg_iters_per_potential_map": st["inner_iters"][1] / calls[1] if calls[1] else None,
+                         "time_s": dt, "setup_ms": st["setup_ms"], "true_residual_max": max(st["true_residual"])})
+            print(f"[bench] {rows[-1]}", file=sys.stderr, flush=True)
+    return {"study": "preconditioner forms, float64, rtol 1e-8, geometry -prod cos(2 pi x_i) - 0.2, nine loads",
+            "rows": rows}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -118,6 +159,10 @@ def main():
                          "(-1 = timed choice); for profiling runs whose timing would change the choice")
     ap.add_argument("--block-tiles", default=None, metavar="T0,T1,T2,T3",
                     help="pin the element-contraction tile per fine block (-1 = timed choice)")
+    ap.add_argument("--solver-study", action="store_true",
+                    help="instead of the step benchmark: the solver comparison of Sec. 2.5 (SCP-GMRES and DBP-GMRES, "
+                         "fixed V-cycle block maps or conjugate-gradient maps to 1e-8, 1e-4, 1e-2) on the paper's test "
+                         "geometry at 64^3 and 128^3, float64, relative tolerance 1e-8; prints one JSON line")
     ap.add_argument("--coarse-kernel", type=int, default=-1, choices=[-1, 0, 1],
                     help="pin the coarse levels' float kernel (0 direct, 1 LDS-tiled where N %% 16 == 0; "
                          "-1 = timed choice per level)")
@@ -193,6 +238,10 @@ def main():
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         return dt / steps, st, tens, f
+
+    if args.solver_study:
+        print(json.dumps(solver_study(P, torch, synth, mat, dev)))
+        return
 
     if args.copy_calibration:
         cnt = args.copy_calibration * 2 ** 20 // 4
