@@ -277,6 +277,40 @@ int phz_backward(phz_ctx* ctx, const double gC[36], const double ge[18],
 int phz_hj_step(phz_ctx* ctx, const double* velocity, double cfl,
                 double* phi_out, int on_device);
 
+/* ---- the optimisation loop around the solve (Sec. 2.1, Sec. 3) ---- */
+
+/* Reinitialise the context's level set towards a signed distance (Sec. 3:
+ * a standard first-order scheme): `steps` pseudo-time steps of
+ * phi_t + S(phi0) (|grad phi| - 1) = 0, S = phi0 / sqrt(phi0^2 + h^2), with the
+ * HJ step's first-order Godunov upwinding, dtau = cfl * h.  The result becomes
+ * the geometry and is written to phi_out ([N^3], may be NULL). */
+int phz_reinit(phz_ctx* ctx, int steps, double cfl, double* phi_out, int on_device);
+/* Chain rule of the density map rho_e = 1 - H(mean of phi over element e)
+ * (Sec. 2.1, Sec. 3 smoothing): grad_phi[N^3] = dJ/dphi from any element
+ * gradient grad_rho[N^3] (e.g. 1/N^3 for the volume). */
+int phz_levelset_gradient(phz_ctx* ctx, const double* grad_rho, double* grad_phi, int on_device);
+/* Riesz representatives in the Hilbert space of the velocity extension:
+ * g = H^-1 j for ncol (<= 9) device node columns [ncol][N^3], with
+ * H = alpha^2 K + M the trilinear finite-element Laplace and mass matrices of
+ * the periodic grid (alpha: length scale, cell units).  Conjugate gradients
+ * to a relative residual of 1e-12; *iters (may be NULL) gets the count. */
+int phz_riesz(phz_ctx* ctx, int ncol, double alpha, const double* j, double* g, int* iters);
+/* Velocity of one constrained optimisation step by projection in that
+ * Hilbert space (the paper uses a Hilbertian projection method for its
+ * equality constraints).  j_obj[N^3] = -dJ/dphi (J to be increased),
+ * j_cons[i][N^3] = -dC_i/dphi, viol[i] = current relative violations
+ * (host), i < m <= 8.  With g = H^-1 j, G_ik = j_i . g_k:
+ *   theta_J = g_0 - sum_i g_i (G^-1 b)_i,  b_k = j_k . g_0,
+ *   theta_C = -sum_i g_i (G^-1 viol)_i,
+ *   v = theta_J / max|theta_J| + gamma / (cfl h) theta_C, scaled to max|v| <= 1,
+ * so that an HJ step of cfl moves the boundary by up to cfl h along the
+ * objective's direction with the constraints' first-order changes removed,
+ * and removes a fraction gamma of each violation to first order.
+ * alpha <= 0 selects 4h.  Vectors on the host or (on_device) the device. */
+int phz_hpm_velocity(phz_ctx* ctx, int m, const double* j_obj, const double* const* j_cons,
+                     const double* viol, double alpha, double cfl, double gamma, double* v_out,
+                     int on_device);
+
 /* Low-level operator apply on the current geometry: y = calA_block x for
  * nrhs in {1, 9} columns, device pointers.  These low-level entry points use
  * the library's internal structure-of-arrays layout [field][load][N^3]

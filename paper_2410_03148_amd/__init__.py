@@ -74,7 +74,8 @@ EXPORTS = [
     "phz_set_options", "phz_set_levelset", "phz_set_density", "phz_get_scale", "phz_solve",
     "phz_get_effective", "phz_get_effective_nd", "phz_get_history", "phz_get_stats",
     "phz_get_solution", "phz_set_initial_guess", "phz_get_rhs", "phz_foms", "phz_backward",
-    "phz_hj_step", "phz_apply", "phz_precondition", "phz_coarse_apply",
+    "phz_hj_step", "phz_apply", "phz_precondition", "phz_coarse_apply", "phz_reinit", "phz_levelset_gradient",
+    "phz_riesz", "phz_hpm_velocity",
     "phz_kernel_timing", "phz_get_kernel_timing",
 ]
 
@@ -108,6 +109,11 @@ def _load():
         "phz_apply": (ip, [vp, ip, ip, ip, vp, vp]),
         "phz_precondition": (ip, [vp, ip, vp, vp]),
         "phz_coarse_apply": (ip, [vp, ip, ip, ip, ip, vp, vp]),
+        "phz_reinit": (ip, [vp, ip, C.c_double, vp, ip]),
+        "phz_levelset_gradient": (ip, [vp, vp, vp, ip]),
+        "phz_riesz": (ip, [vp, ip, C.c_double, vp, vp, C.POINTER(ip)]),
+        "phz_hpm_velocity": (ip, [vp, ip, vp, C.POINTER(C.c_void_p), vp, C.c_double, C.c_double, C.c_double,
+                                  vp, ip]),
         "phz_kernel_timing": (ip, [vp, ip]),
         "phz_get_kernel_timing": (ip, [vp, C.c_char_p, ip, C.POINTER(ip)]),
     }
@@ -312,6 +318,39 @@ class Context:
             v = np.ascontiguousarray(velocity, dtype=np.float64).ravel()
             st = _lib.phz_hj_step(self._h, C.c_void_p(v.ctypes.data), cfl, optr, 0)
         self._check(st, "phz_hj_step")
+        return out
+
+    def reinit(self, steps=20, cfl=0.5, return_phi=True):
+        """Reinitialise the level set towards a signed distance (phz_reinit)."""
+        out = np.zeros(self.nn) if return_phi else None
+        self._check(_lib.phz_reinit(self._h, steps, cfl, C.c_void_p(out.ctypes.data) if return_phi else None, 0),
+                    "phz_reinit")
+        return out
+
+    def levelset_gradient(self, grad_rho):
+        """dJ/dphi from an element gradient dJ/drho (phz_levelset_gradient)."""
+        g = np.ascontiguousarray(grad_rho, dtype=np.float64).ravel()
+        out = np.zeros(self.nn)
+        self._check(_lib.phz_levelset_gradient(self._h, _dptr(g), C.c_void_p(out.ctypes.data), 0),
+                    "phz_levelset_gradient")
+        return out
+
+    def riesz(self, ncol, alpha, j_ptr, g_ptr):
+        """g = (alpha^2 K + M)^-1 j on ncol device node columns; returns the iterations."""
+        it = C.c_int()
+        self._check(_lib.phz_riesz(self._h, ncol, alpha, C.c_void_p(j_ptr), C.c_void_p(g_ptr), C.byref(it)),
+                    "phz_riesz")
+        return it.value
+
+    def hpm_velocity(self, j_obj, j_cons=(), viol=(), alpha=0.0, cfl=0.5, gamma=0.5):
+        """Velocity of one constrained step (phz_hpm_velocity), host arrays."""
+        jo = np.ascontiguousarray(j_obj, dtype=np.float64).ravel()
+        jc = [np.ascontiguousarray(j, dtype=np.float64).ravel() for j in j_cons]
+        vi = np.ascontiguousarray(viol, dtype=np.float64).ravel()
+        ptrs = (C.c_void_p * max(len(jc), 1))(*[j.ctypes.data for j in jc])
+        out = np.zeros(self.nn)
+        self._check(_lib.phz_hpm_velocity(self._h, len(jc), _dptr(jo), ptrs, _dptr(vi) if len(jc) else None,
+                                          alpha, cfl, gamma, C.c_void_p(out.ctypes.data), 0), "phz_hpm_velocity")
         return out
 
     def kernel_timing(self, enable=True):

@@ -163,6 +163,9 @@ struct phz_ctx {
   long graph_epoch = 0;
   phz::DevBuf<double> one64;   // the constant 1.0 (power-iteration Jacobi step)
   phz::DevBuf<double> negone;  // nine copies of -1.0 (block-diagonal preconditioner)
+  // optimisation step: Helmholtz stencil, conjugate-gradient vectors and
+  // scalars of the Riesz solves, the velocity's direction vectors
+  phz::DevBuf<double> helm_w, rz_r, rz_z, rz_p, rz_q, rz_g, rz_j, rz_dev;
   phz::DevBuf<double> pcg_dev; // per-column scalars of the inexact block maps
 
   // optional per-kernel timing with HIP events on the context stream
@@ -1973,6 +1976,270 @@ int phz_hj_step(phz_ctx* c, const double* velocity, double cfl, double* phi_out,
   c->precond_ready = false;
   c->have_solution = false;
   c->have_grad = false;
+  return PHZ_OK;
+  PHZ_GUARD_END(c)
+}
+
+// ------------------------------------------------------- optimisation step
+namespace phz {
+
+// 27 weights of H = alpha^2 K + M on the periodic node grid, K and M the
+// trilinear finite-element Laplace and mass matrices: on a tensor grid both
+// are tensor products of the assembled one-dimensional stencils, mass
+// h/6 (1, 4, 1) and Laplace (1/h) (-1, 2, -1).
+static void helmholtz_weights(int N, double alpha, double* w) {
+  const double h = 1.0 / N;
+  const double m1[3] = {h / 6.0, 4.0 * h / 6.0, h / 6.0}, k1[3] = {-1.0 / h, 2.0 / h, -1.0 / h};
+  for (int d = 0; d < 27; ++d) {
+    const int a = d % 3, b = (d / 3) % 3, e = d / 9;
+    const double mass = m1[a] * m1[b] * m1[e];
+    const double lap = k1[a] * m1[b] * m1[e] + m1[a] * k1[b] * m1[e] + m1[a] * m1[b] * k1[e];
+    w[d] = alpha * alpha * lap + mass;
+  }
+}
+
+// g = H^-1 j for K node columns (device), conjugate gradients with the
+// (constant) diagonal as preconditioner, to a relative residual of 1e-12
+// per column; returns the iterations
+static int riesz_solve(phz_ctx* c, int K, double alpha, const double* j, double* g) {
+  const long nn = c->nn;
+  hipStream_t st = c->stream;
+  double w[27];
+  helmholtz_weights(c->N, alpha, w);
+  c->helm_w.upload(w, 27, st);
+  for (DevBuf<double>* v : {&c->rz_r, &c->rz_z, &c->rz_p, &c->rz_q})
+    if (v->n < (size_t)nn * K) v->alloc((size_t)nn * K);
+  c->rz_dev.alloc(4 * 9);
+  double* dv = c->rz_dev.p;  // [0, K) alpha, [K, 2K) -alpha, [2K, 3K) beta, [3K, 4K) reductions
+  double* red = dv + 27;
+  const double dinv = 1.0 / w[13];
+  std::vector<double> dsc(K, dinv), bn(K), rz(K), h(K), al(2 * K), be(K);
+  std::vector<int> act(K);
+  auto to_host = [&](std::vector<double>& out) {
+    PHZ_HIP(hipMemcpyAsync(out.data(), red, K * sizeof(double), hipMemcpyDeviceToHost, st));
+    sync(c);
+  };
+  double *r = c->rz_r.p, *z = c->rz_z.p, *p = c->rz_p.p, *q = c->rz_q.p;
+  PHZ_HIP(hipMemcpyAsync(r, j, (size_t)nn * K * sizeof(double), hipMemcpyDeviceToDevice, st));
+  fill<double>(nn * K, 0.0, g, st);
+  col_norm2<double>(nn, 1, K, r, red, c->red_work.p, st);
+  to_host(bn);
+  for (int k = 0; k < K; ++k) {
+    bn[k] = std::sqrt(bn[k]);
+    act[k] = bn[k] > 0.0;
+  }
+  PHZ_HIP(hipMemcpyAsync(dv + 2 * K, dsc.data(), K * sizeof(double), hipMemcpyHostToDevice, st));
+  scale_cols<double>(nn, 1, K, r, dv + 2 * K, z, st);
+  PHZ_HIP(hipMemcpyAsync(p, z, (size_t)nn * K * sizeof(double), hipMemcpyDeviceToDevice, st));
+  col_dot<double>(nn, 1, K, r, z, red, c->red_work.p, st);
+  to_host(rz);
+  int it = 0;
+  for (; it < 2000; ++it) {
+    int nact = 0;
+    for (int k = 0; k < K; ++k) nact += act[k];
+    if (nact == 0) break;
+    const_stencil_apply(c->N, K, c->helm_w.p, p, q, st);
+    col_dot<double>(nn, 1, K, p, q, red, c->red_work.p, st);
+    to_host(h);
+    for (int k = 0; k < K; ++k) {
+      const double a = act[k] && h[k] > 0.0 ? rz[k] / h[k] : 0.0;
+      al[k] = a;
+      al[K + k] = -a;
+    }
+    PHZ_HIP(hipMemcpyAsync(dv, al.data(), 2 * K * sizeof(double), hipMemcpyHostToDevice, st));
+    axpy_cols<double, double>(nn, 1, K, dv, p, g, st);
+    axpy_cols<double, double>(nn, 1, K, dv + K, q, r, st);
+    col_norm2<double>(nn, 1, K, r, red, c->red_work.p, st);
+    to_host(h);
+    for (int k = 0; k < K; ++k)
+      if (act[k] && !(std::sqrt(h[k]) > 1e-12 * bn[k])) act[k] = 0;
+    PHZ_HIP(hipMemcpyAsync(dv + 2 * K, dsc.data(), K * sizeof(double), hipMemcpyHostToDevice, st));
+    scale_cols<double>(nn, 1, K, r, dv + 2 * K, z, st);
+    col_dot<double>(nn, 1, K, r, z, red, c->red_work.p, st);
+    to_host(h);
+    for (int k = 0; k < K; ++k) {
+      be[k] = act[k] && rz[k] != 0.0 ? h[k] / rz[k] : 0.0;
+      rz[k] = h[k];
+    }
+    PHZ_HIP(hipMemcpyAsync(dv + 2 * K, be.data(), K * sizeof(double), hipMemcpyHostToDevice, st));
+    xpby_cols<double>(nn, 1, K, dv + 2 * K, z, p, st);
+  }
+  return it;
+}
+
+// copies K host or device node vectors into one device block of K columns
+static void gather_columns(phz_ctx* c, int K, const double* const* src, int on_device, DevBuf<double>& dst) {
+  dst.alloc((size_t)c->nn * K);
+  for (int k = 0; k < K; ++k)
+    PHZ_HIP(hipMemcpyAsync(dst.p + (size_t)k * c->nn, src[k], c->nn * sizeof(double),
+                           on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, c->stream));
+}
+
+static double device_max_abs(phz_ctx* c, const double* v) {
+  double* out = c->small.p + 500;
+  max_abs(c->nn, v, out, c->red_work.p, c->stream);
+  double mx = 0.0;
+  PHZ_HIP(hipMemcpyAsync(&mx, out, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  sync(c);
+  return mx;
+}
+
+static double device_dot(phz_ctx* c, const double* a, const double* b) {
+  double* out = c->small.p + 501;
+  col_dot<double>(c->nn, 1, 1, a, b, out, c->red_work.p, c->stream);
+  double d = 0.0;
+  PHZ_HIP(hipMemcpyAsync(&d, out, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  sync(c);
+  return d;
+}
+
+}  // namespace phz
+
+int phz_reinit(phz_ctx* c, int steps, double cfl, double* phi_out, int on_device) {
+  if (!c || steps < 0 || !(cfl > 0)) return PHZ_E_INVALID;
+  if (!c->have_phi) { c->err = "reinitialisation needs a level set"; return PHZ_E_STATE; }
+  PHZ_GUARD_BEGIN
+  DevBuf<double> phi0, tmp;
+  phi0.alloc(c->nn);
+  tmp.alloc(c->nn);
+  PHZ_HIP(hipMemcpyAsync(phi0.p, c->phi.p, c->nn * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+  for (int i = 0; i < steps; ++i) {
+    reinit_step(c->N, c->phi.p, phi0.p, cfl / c->N, tmp.p, c->stream);
+    PHZ_HIP(hipMemcpyAsync(c->phi.p, tmp.p, c->nn * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+  }
+  levelset_to_scale(c->N, c->phi.p, c->opt.smooth_width / c->N, c->mat.void_scale, c->rho.p, c->s.p, c->s32.p,
+                    c->stream);
+  if (phi_out)
+    PHZ_HIP(hipMemcpyAsync(phi_out, c->phi.p, c->nn * sizeof(double),
+                           on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, c->stream));
+  sync(c);
+  c->precond_ready = false;
+  c->have_solution = false;
+  c->have_grad = false;
+  return PHZ_OK;
+  PHZ_GUARD_END(c)
+}
+
+int phz_levelset_gradient(phz_ctx* c, const double* grad_rho, double* grad_phi, int on_device) {
+  if (!c || !grad_rho || !grad_phi) return PHZ_E_INVALID;
+  if (!c->have_phi) { c->err = "the chain rule needs a level set"; return PHZ_E_STATE; }
+  PHZ_GUARD_BEGIN
+  DevBuf<double> g, out;
+  const double* gr = grad_rho;
+  if (!on_device) {
+    g.upload(grad_rho, c->nn, c->stream);
+    gr = g.p;
+  }
+  double* o = grad_phi;
+  if (!on_device) {
+    out.alloc(c->nn);
+    o = out.p;
+  }
+  phz::grad_phi(c->N, c->phi.p, c->opt.smooth_width / c->N, gr, o, c->stream);
+  if (!on_device) PHZ_HIP(hipMemcpyAsync(grad_phi, o, c->nn * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  sync(c);
+  return PHZ_OK;
+  PHZ_GUARD_END(c)
+}
+
+int phz_riesz(phz_ctx* c, int ncol, double alpha, const double* j, double* g, int* iters) {
+  if (!c || !j || !g || ncol < 1 || ncol > 9 || !(alpha >= 0)) return PHZ_E_INVALID;
+  PHZ_GUARD_BEGIN
+  const int it = riesz_solve(c, ncol, alpha, j, g);
+  sync(c);
+  if (iters) *iters = it;
+  return PHZ_OK;
+  PHZ_GUARD_END(c)
+}
+
+int phz_hpm_velocity(phz_ctx* c, int m, const double* j_obj, const double* const* j_cons, const double* viol,
+                     double alpha, double cfl, double gamma, double* v_out, int on_device) {
+  if (!c || !j_obj || !v_out || m < 0 || m > 8 || (m > 0 && (!j_cons || !viol)) || !(cfl > 0) || !(gamma >= 0))
+    return PHZ_E_INVALID;
+  for (int i = 0; i < m; ++i)
+    if (!j_cons[i] || !std::isfinite(viol[i])) return PHZ_E_INVALID;
+  PHZ_GUARD_BEGIN
+  const long nn = c->nn;
+  const int K = 1 + m;
+  const double h = 1.0 / c->N;
+  if (!(alpha > 0)) alpha = 4.0 * h;
+  std::vector<const double*> src(K);
+  src[0] = j_obj;
+  for (int i = 0; i < m; ++i) src[1 + i] = j_cons[i];
+  gather_columns(c, K, src.data(), on_device, c->rz_j);
+  c->rz_g.alloc((size_t)nn * K);
+  riesz_solve(c, K, alpha, c->rz_j.p, c->rz_g.p);
+  const double* jv = c->rz_j.p;
+  const double* gv = c->rz_g.p;
+  auto col = [&](const double* base, int k) { return base + (size_t)k * nn; };
+  // Gram matrix of the constraint directions and their products with g_0
+  std::vector<double> G((size_t)m * m), b(m), lb(m), lc(m);
+  for (int i = 0; i < m; ++i) {
+    b[i] = device_dot(c, col(jv, 1 + i), col(gv, 0));
+    for (int k = 0; k < m; ++k) G[(size_t)i * m + k] = device_dot(c, col(jv, 1 + i), col(gv, 1 + k));
+  }
+  if (m > 0) {
+    // small dense solves G lb = b, G lc = viol (Gaussian elimination, partial pivoting)
+    std::vector<double> A = G, rb = b, rc(viol, viol + m);
+    for (int p = 0; p < m; ++p) {
+      int piv = p;
+      for (int r = p + 1; r < m; ++r)
+        if (std::fabs(A[(size_t)r * m + p]) > std::fabs(A[(size_t)piv * m + p])) piv = r;
+      if (!(std::fabs(A[(size_t)piv * m + p]) > 0)) throw std::runtime_error("constraint directions are dependent");
+      if (piv != p) {
+        for (int q = 0; q < m; ++q) std::swap(A[(size_t)p * m + q], A[(size_t)piv * m + q]);
+        std::swap(rb[p], rb[piv]);
+        std::swap(rc[p], rc[piv]);
+      }
+      for (int r = p + 1; r < m; ++r) {
+        const double f = A[(size_t)r * m + p] / A[(size_t)p * m + p];
+        for (int q = p; q < m; ++q) A[(size_t)r * m + q] -= f * A[(size_t)p * m + q];
+        rb[r] -= f * rb[p];
+        rc[r] -= f * rc[p];
+      }
+    }
+    for (int p = m - 1; p >= 0; --p) {
+      double sb = rb[p], sc = rc[p];
+      for (int q = p + 1; q < m; ++q) {
+        sb -= A[(size_t)p * m + q] * lb[q];
+        sc -= A[(size_t)p * m + q] * lc[q];
+      }
+      lb[p] = sb / A[(size_t)p * m + p];
+      lc[p] = sc / A[(size_t)p * m + p];
+    }
+  }
+  // theta_J = g_0 - sum_i lb_i g_i into the output
+  DevBuf<double> vdev;
+  double* v = v_out;
+  if (!on_device) {
+    vdev.alloc(nn);
+    v = vdev.p;
+  }
+  PHZ_HIP(hipMemcpyAsync(v, col(gv, 0), nn * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+  double* cf = c->small.p + 502;
+  auto add = [&](double a, const double* x) {
+    PHZ_HIP(hipMemcpyAsync(cf, &a, sizeof(double), hipMemcpyHostToDevice, c->stream));
+    axpy_cols<double, double>(nn, 1, 1, cf, x, v, c->stream);
+    sync(c);
+  };
+  for (int i = 0; i < m; ++i) add(-lb[i], col(gv, 1 + i));
+  const double mj = device_max_abs(c, v);
+  if (!(mj > 0)) throw std::runtime_error("the objective direction vanishes");
+  // v = theta_J / max|theta_J| + (gamma / (cfl h)) theta_C, theta_C = -sum_i lc_i g_i
+  std::vector<double> one{1.0 / mj};
+  PHZ_HIP(hipMemcpyAsync(cf, one.data(), sizeof(double), hipMemcpyHostToDevice, c->stream));
+  scale_cols<double>(nn, 1, 1, v, cf, v, c->stream);
+  sync(c);
+  const double sC = gamma / (cfl * h);
+  for (int i = 0; i < m; ++i) add(-sC * lc[i], col(gv, 1 + i));
+  const double mv = device_max_abs(c, v);
+  if (mv > 1.0) {
+    one[0] = 1.0 / mv;
+    PHZ_HIP(hipMemcpyAsync(cf, one.data(), sizeof(double), hipMemcpyHostToDevice, c->stream));
+    scale_cols<double>(nn, 1, 1, v, cf, v, c->stream);
+  }
+  if (!on_device) PHZ_HIP(hipMemcpyAsync(v_out, v, nn * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  sync(c);
   return PHZ_OK;
   PHZ_GUARD_END(c)
 }

@@ -646,6 +646,47 @@ __global__ void k_hj_step(unsigned N, const double* __restrict__ phi, const doub
   out[n] = f0 - dt * (fmax(vv, 0.0) * sqrt(gp) + fmin(vv, 0.0) * sqrt(gm));
 }
 
+// One pseudo-time step of the reinitialisation equation
+// phi_t + S(phi0) (|grad phi| - 1) = 0, S = phi0 / sqrt(phi0^2 + h^2), with the
+// first-order Godunov upwinding of the HJ step
+__global__ void k_reinit_step(unsigned N, const double* __restrict__ phi, const double* __restrict__ phi0, double dt,
+                              double* __restrict__ out) {
+  const unsigned nn = N * N * N;
+  const unsigned n = blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= nn) return;
+  const Nb q = nbr(n, N);
+  const double h = 1.0 / N;
+  const double f0 = phi[n];
+  const double fx[2] = {phi[at(N, q.im, q.j, q.k)], phi[at(N, q.ip, q.j, q.k)]};
+  const double fy[2] = {phi[at(N, q.i, q.jm, q.k)], phi[at(N, q.i, q.jp, q.k)]};
+  const double fz[2] = {phi[at(N, q.i, q.j, q.km)], phi[at(N, q.i, q.j, q.kp)]};
+  const double* nb[3] = {fx, fy, fz};
+  double gp = 0.0, gm = 0.0;
+  for (int a = 0; a < 3; ++a) {
+    const double dm = (f0 - nb[a][0]) / h, dp = (nb[a][1] - f0) / h;
+    gp += fmax(dm, 0.0) * fmax(dm, 0.0) + fmin(dp, 0.0) * fmin(dp, 0.0);
+    gm += fmin(dm, 0.0) * fmin(dm, 0.0) + fmax(dp, 0.0) * fmax(dp, 0.0);
+  }
+  const double p0 = phi0[n];
+  const double S = p0 / sqrt(p0 * p0 + h * h);
+  out[n] = f0 - dt * (fmax(S, 0.0) * sqrt(gp) + fmin(S, 0.0) * sqrt(gm) - S);
+}
+
+// y = W x for a constant 27-point node stencil w[d] (d = dx + 3 dy + 9 dz,
+// offsets -1..1), K columns
+__global__ __launch_bounds__(256) void k_const_stencil(unsigned N, const double* __restrict__ w,
+                                                       const double* __restrict__ x, double* __restrict__ y) {
+  const unsigned nn = N * N * N;
+  const unsigned n = blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= nn) return;
+  const size_t co = (size_t)blockIdx.y * nn;
+  const Nb q = nbr(n, N);
+  const unsigned xs[3] = {q.im, q.i, q.ip}, ys[3] = {q.jm, q.j, q.jp}, zs[3] = {q.km, q.k, q.kp};
+  double acc = 0.0;
+  for (int d = 0; d < 27; ++d) acc += w[d] * x[co + at(N, xs[d % 3], ys[(d / 3) % 3], zs[d / 9])];
+  y[co + n] = acc;
+}
+
 template <typename T>
 __global__ void k_normalize_by(size_t count, const double* __restrict__ nrm2, const T* __restrict__ w,
                                T* __restrict__ v) {
@@ -862,6 +903,18 @@ int count_nonfinite(long count, const double* v, double* work, hipStream_t st) {
   PHZ_HIP(hipStreamSynchronize(st));
   return (int)h;
 }
+void reinit_step(int N, const double* phi, const double* phi0, double dt, double* out, hipStream_t st) {
+  const size_t nn = (size_t)N * N * N;
+  hipLaunchKernelGGL(k_reinit_step, dim3(blocks_for(nn, 256)), dim3(256), 0, st, (unsigned)N, phi, phi0, dt, out);
+  PHZ_LAUNCH_CHECK();
+}
+
+void const_stencil_apply(int N, int K, const double* w, const double* x, double* y, hipStream_t st) {
+  const size_t nn = (size_t)N * N * N;
+  hipLaunchKernelGGL(k_const_stencil, dim3(blocks_for(nn, 256), K), dim3(256), 0, st, (unsigned)N, w, x, y);
+  PHZ_LAUNCH_CHECK();
+}
+
 void hj_step(int N, const double* phi, const double* v, const double* vmax, double dt, double* out, hipStream_t st) {
   const size_t nn = (size_t)N * N * N;
   hipLaunchKernelGGL(k_hj_step, dim3(blocks_for(nn, 256)), dim3(256), 0, st, (unsigned)N, phi, v, vmax, dt, out);

@@ -1,0 +1,97 @@
+"""Level-set optimisation loop of the paper's results (Sec. 2.1, Sec. 3): maximise an effective figure
+of merit subject to equality constraints on the volume and a second effective property.
+
+The loop only sequences the library's calls and keeps the scalar history; every field operation (the
+homogenisation, the sensitivities, the chain rule to the level set, the Hilbertian extension and
+projection of the velocity, the HJ step and the reinitialisation) runs in the library's kernels.
+
+Per iteration q:
+  1. reinitialise at the start and every `reinit_every` iterations (the paper: every five);
+  2. solve the cell problems; figures of merit from the effective tensors;
+  3. for the objective and each constraint: its gradient with respect to the tensors, the backward
+     pass to dJ/dphi (the volume's is the chain rule of 1/N^3), j = -dJ/dphi;
+  4. the projected velocity (phz_hpm_velocity) with the constraints' relative violations;
+  5. one HJ step.
+It stops by the paper's rule (at q >= 10: the objective changed by less than 0.2 h relative to each of
+the five previous iterations and every relative violation is below 1e-3) or after `max_iters`.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import PHZ_OK, foms
+
+PROPERTIES = ("B_voigt", "B_reuss", "d_h", "g_h", "k_h", "C_zzzz", "vol")
+
+
+def _value_and_tensor_grads(name, CH, eH, kH):
+    """Value of an effective property and its gradient with respect to (C^H, e^H, kappa^H)."""
+    if name == "C_zzzz":
+        gC = np.zeros((6, 6))
+        gC[2, 2] = 1.0
+        return float(CH[2, 2]), (gC, np.zeros((3, 6)), np.zeros((3, 3)))
+    f, grads = foms(CH, eH, kH, grad_of=name)
+    return float(f[name]), grads
+
+
+def _sensitivity(ctx, name, CH, eH, kH, void_scale):
+    """(value, dValue/dphi) of a property at the context's solved geometry."""
+    n3 = ctx.nn
+    if name == "vol":
+        rho = (ctx.scale() - void_scale) / (1.0 - void_scale)
+        return float(np.mean(rho)), ctx.levelset_gradient(np.full(n3, 1.0 / n3))
+    val, (gC, ge, gk) = _value_and_tensor_grads(name, CH, eH, kH)
+    _, gphi = ctx.backward(gC, ge, gk, want_phi=True)
+    return val, gphi
+
+
+def should_stop(J_hist, viol_hist, h):
+    """The paper's stopping rule on the objective and relative-violation histories."""
+    q = len(J_hist) - 1
+    if q < 10:
+        return False
+    Jq = J_hist[q]
+    if any(abs(Jq - J_hist[q - j]) >= 0.2 * h * abs(Jq) for j in range(1, 6)):
+        return False
+    return all(abs(c) < 1e-3 for c in viol_hist[q])
+
+
+def optimise(ctx, material, phi0, objective, constraints, max_iters=200, cfl=0.5, gamma=0.5, alpha=0.0,
+             reinit_every=5, reinit_steps=20, callback=None):
+    """Maximise `objective` subject to [(property, target), ...] equality constraints from the level set
+    phi0 (nodes, x fastest).  Returns a dict with the histories and the final level set."""
+    if objective not in PROPERTIES or objective == "vol":
+        raise ValueError(f"objective must be one of {PROPERTIES[:-1]}")
+    for name, target in constraints:
+        if name not in PROPERTIES or not target:
+            raise ValueError(f"bad constraint {(name, target)}")
+    h = 1.0 / ctx.n
+    ctx.set_levelset(np.ascontiguousarray(phi0, dtype=np.float64).ravel())
+    hist = {"J": [], "constraints": [], "violations": [], "status": []}
+    phi = None
+    for q in range(max_iters):
+        if reinit_every and q % reinit_every == 0:
+            ctx.reinit(reinit_steps, cfl, return_phi=False)
+        status = ctx.solve()
+        CH, eH, kH = ctx.effective()
+        J, dJ = _sensitivity(ctx, objective, CH, eH, kH, material.void_scale)
+        vals, viol, jc = [], [], []
+        for name, target in constraints:
+            val, dC = _sensitivity(ctx, name, CH, eH, kH, material.void_scale)
+            vals.append(val)
+            viol.append((val - target) / abs(target))
+            jc.append(-dC / abs(target))
+        hist["J"].append(J)
+        hist["constraints"].append(vals)
+        hist["violations"].append(viol)
+        hist["status"].append(status)
+        if callback:
+            callback(q, J, vals, viol)
+        if should_stop(hist["J"], hist["violations"], h):
+            break
+        v = ctx.hpm_velocity(-dJ, jc, viol, alpha=alpha, cfl=cfl, gamma=gamma)
+        phi = ctx.hj_step(v, cfl=cfl, return_phi=True)
+    hist["phi"] = phi
+    hist["iterations"] = len(hist["J"])
+    hist["converged"] = should_stop(hist["J"], hist["violations"], h)
+    return hist
