@@ -177,6 +177,11 @@ typedef struct {
                                graphs)                                        */
     double inner_eps;       /* inner = 1: relative tolerance, default 1e-2     */
     int inner_maxit;        /* inner = 1: iterations per map, default 200      */
+    int warm_start;         /* 1: a solve with no phz_set_initial_guess guess
+                               starts from the last successful solve's
+                               solution, kept on the device across geometry
+                               changes (an optimisation loop's next cell is
+                               close to the last); 0 (default) from zero     */
 } phz_options;
 
 typedef struct {
@@ -215,7 +220,11 @@ typedef struct {
 void phz_default_options(phz_options* o);
 
 /* Create a context for an N x N x N periodic cell.  N must be even and
- * >= 2 (multigrid halves N).  stream is a hipStream_t (NULL: the library
+ * >= 2 (multigrid halves N), and halving N while it is even and above 4
+ * (at most mg_levels - 1 times when mg_levels > 0) must end at a side of at
+ * most 10: the coarsest level is inverted densely on the host.  So N = m 2^k
+ * with m <= 10 (96 and 128 qualify, 100 does not); otherwise PHZ_E_INVALID.
+ * phz_set_options applies the same rule to a new mg_levels.  stream is a hipStream_t (NULL: the library
  * creates its own).  On success *out owns device workspaces sized for N,
  * nine loads and the chosen restart length. */
 int phz_create(int n, const phz_material* mat, const phz_options* opt,

@@ -144,6 +144,7 @@ struct phz_ctx {
   phz::DevBuf<double> phi, rho, s, grad_rho, tmp_nodes;
   phz::DevBuf<float> s32;
   bool have_phi = false, have_s = false, have_solution = false, have_grad = false;
+  bool x_valid = false;   // X holds the finite result of the last solve (any geometry)
   bool precond_ready = false;
   bool have_guess = false;
 
@@ -256,6 +257,20 @@ static void upload_reference(phz_ctx* c) {
     c->kop[op].upload(ops.data(), ops.size(), st);
     sync(c);
   }
+}
+
+// Side of the coarsest level under the halving rule of build_levels.  Its
+// dense inverse is formed on the host, so the side is bounded by
+// kMaxCoarsestN (at most 3 * 10^3 rows).
+static const int kMaxCoarsestN = 10;
+static int coarsest_side(int N, int mg_levels) {
+  const int maxl = mg_levels > 0 ? mg_levels : 64;
+  int levels = 1;
+  while (N % 2 == 0 && N > 4 && levels < maxl) {
+    N /= 2;
+    ++levels;
+  }
+  return N;
 }
 
 // Level sizes N, N/2, ... while N is even and above 4 (or mg_levels levels).
@@ -1401,9 +1416,11 @@ static int do_solve(phz_ctx* c) {
   setup_preconditioner(c);
   c->stats.setup_ms = ms_since(ts);
   prepare_rhs(c);
+  const bool warm = !c->have_guess && c->opt.warm_start && c->x_valid;
+  c->x_valid = false;
   if (c->have_guess)
     PHZ_HIP(hipMemcpyAsync(c->X.p, c->guess.p, nn * 36 * sizeof(double), hipMemcpyDeviceToDevice, st));
-  else
+  else if (!warm)
     fill<double>(nn * 36, 0.0, c->X.p, st);
   const double rtol = c->opt.rtol;
   bool conv = true;
@@ -1442,6 +1459,7 @@ static int do_solve(phz_ctx* c) {
   sync(c);
   collect_timing(c);
   c->have_solution = true;
+  c->x_valid = true;
   c->have_grad = false;
   c->stats.solve_ms = ms_since(t0);
   if (c->opt.verbose) {
@@ -1532,6 +1550,7 @@ void phz_default_options(phz_options* o) {
   o->inner = 0;
   o->inner_eps = 1e-2;
   o->inner_maxit = 200;
+  o->warm_start = 0;
 }
 
 const char* phz_strerror(int status) {
@@ -1555,6 +1574,7 @@ static int check_options(const phz_options* o, std::string& err) {
   if (o->inner != 0 && o->inner != 1) { err = "inner must be 0 or 1"; return PHZ_E_INVALID; }
   if (!(o->inner_eps > 0 && o->inner_eps < 1)) { err = "inner_eps must be in (0, 1)"; return PHZ_E_INVALID; }
   if (o->inner_maxit < 1) { err = "inner_maxit must be positive"; return PHZ_E_INVALID; }
+  if (o->warm_start != 0 && o->warm_start != 1) { err = "warm_start must be 0 or 1"; return PHZ_E_INVALID; }
   for (int op = 0; op < 4; ++op) {
     if (o->block_kernel[op] < -1 || o->block_kernel[op] > 2) { err = "block_kernel entries must be -1, 0, 1 or 2"; return PHZ_E_INVALID; }
     if (o->block_tile[op] < -1 || o->block_tile[op] >= elem_tile_count()) {
@@ -1594,6 +1614,7 @@ int phz_create(int n, const phz_material* mat, const phz_options* opt, void* str
   std::string err;
   int rc = check_options(&c->opt, err);
   if (rc) return rc;
+  if (coarsest_side(n, c->opt.mg_levels) > kMaxCoarsestN) return PHZ_E_INVALID;
   if (stream) {
     c->stream = (hipStream_t)stream;
   } else {
@@ -1633,6 +1654,10 @@ int phz_set_options(phz_ctx* c, const phz_options* opt) {
   if (!c || !opt) return PHZ_E_INVALID;
   int rc = check_options(opt, c->err);
   if (rc) return rc;
+  if (coarsest_side(c->N, opt->mg_levels) > kMaxCoarsestN) {
+    c->err = "mg_levels leaves a coarsest level above 10^3 nodes";
+    return PHZ_E_INVALID;
+  }
   PHZ_GUARD_BEGIN
   const bool hier_change = opt->mg_levels != c->opt.mg_levels || opt->precision != c->opt.precision;
   if (opt->restart != c->opt.restart) {

@@ -17,6 +17,8 @@ the five previous iterations and every relative violation is below 1e-3) or afte
 """
 from __future__ import annotations
 
+import time
+
 import numpy as np
 
 from . import PHZ_OK, foms
@@ -59,7 +61,9 @@ def should_stop(J_hist, viol_hist, h):
 def optimise(ctx, material, phi0, objective, constraints, max_iters=200, cfl=0.5, gamma=0.5, alpha=0.0,
              reinit_every=5, reinit_steps=20, callback=None):
     """Maximise `objective` subject to [(property, target), ...] equality constraints from the level set
-    phi0 (nodes, x fastest).  Returns a dict with the histories and the final level set."""
+    phi0 (nodes, x fastest).  Returns a dict with the histories, the final level set and the wall time of
+    each phase in ms per iteration (every library call returns after its device work).  A context
+    created with warm_start=1 starts each solve from the last iteration's solution."""
     if objective not in PROPERTIES or objective == "vol":
         raise ValueError(f"objective must be one of {PROPERTIES[:-1]}")
     for name, target in constraints:
@@ -67,13 +71,24 @@ def optimise(ctx, material, phi0, objective, constraints, max_iters=200, cfl=0.5
             raise ValueError(f"bad constraint {(name, target)}")
     h = 1.0 / ctx.n
     ctx.set_levelset(np.ascontiguousarray(phi0, dtype=np.float64).ravel())
-    hist = {"J": [], "constraints": [], "violations": [], "status": []}
+    hist = {"J": [], "constraints": [], "violations": [], "status": [], "iter_ms": []}
+    phases = {"reinit": 0.0, "solve": 0.0, "sensitivities": 0.0, "velocity": 0.0, "hj": 0.0}
     phi = None
+    clock = time.perf_counter
+
+    def lap(name, t0):
+        t1 = clock()
+        phases[name] += 1e3 * (t1 - t0)
+        return t1
+
     for q in range(max_iters):
+        t = t_iter = clock()
         if reinit_every and q % reinit_every == 0:
             ctx.reinit(reinit_steps, cfl, return_phi=False)
+            t = lap("reinit", t)
         status = ctx.solve()
         CH, eH, kH = ctx.effective()
+        t = lap("solve", t)
         J, dJ = _sensitivity(ctx, objective, CH, eH, kH, material.void_scale)
         vals, viol, jc = [], [], []
         for name, target in constraints:
@@ -81,6 +96,7 @@ def optimise(ctx, material, phi0, objective, constraints, max_iters=200, cfl=0.5
             vals.append(val)
             viol.append((val - target) / abs(target))
             jc.append(-dC / abs(target))
+        t = lap("sensitivities", t)
         hist["J"].append(J)
         hist["constraints"].append(vals)
         hist["violations"].append(viol)
@@ -88,9 +104,14 @@ def optimise(ctx, material, phi0, objective, constraints, max_iters=200, cfl=0.5
         if callback:
             callback(q, J, vals, viol)
         if should_stop(hist["J"], hist["violations"], h):
+            hist["iter_ms"].append(1e3 * (clock() - t_iter))
             break
         v = ctx.hpm_velocity(-dJ, jc, viol, alpha=alpha, cfl=cfl, gamma=gamma)
+        t = lap("velocity", t)
         phi = ctx.hj_step(v, cfl=cfl, return_phi=True)
+        lap("hj", t)
+        hist["iter_ms"].append(1e3 * (clock() - t_iter))
+    hist["phase_ms"] = {k: v / max(len(hist["J"]), 1) for k, v in phases.items()}
     hist["phi"] = phi
     hist["iterations"] = len(hist["J"])
     hist["converged"] = should_stop(hist["J"], hist["violations"], h)

@@ -41,6 +41,11 @@ def test_create_rejects_bad_sizes_and_materials():
     h = C.c_void_p()
     for n in (0, 1, 3, 7, 2048):
         assert P._lib.phz_create(n, C.byref(m), None, None, C.byref(h)) == -1
+    # halving must end at a side of at most 10 (dense coarsest inverse)
+    for n in (22, 100, 120):
+        assert P._lib.phz_create(n, C.byref(m), None, None, C.byref(h)) == -1
+    o = P.default_options(mg_levels=2)
+    assert P._lib.phz_create(64, C.byref(m), C.byref(o), None, C.byref(h)) == -1
     bad = P.make_material(synth.material_workload())
     bad.C[0] = float("nan")
     assert P._lib.phz_create(8, C.byref(bad), None, None, C.byref(h)) == -2
@@ -69,7 +74,8 @@ def test_options_rejected_before_device_use():
     h = C.c_void_p()
     for field, val in (("block_kernel", [0, 3, -1, -1]), ("block_kernel", [-2, 0, 0, 0]),
                        ("block_tile", [0, 0, 0, 3]), ("fine_kernel", 5), ("elem_tile", 7), ("solver", 2),
-                       ("inner", 2), ("inner_eps", 0.0), ("inner_eps", 1.0), ("inner_maxit", 0)):
+                       ("inner", 2), ("inner_eps", 0.0), ("inner_eps", 1.0), ("inner_maxit", 0),
+                       ("warm_start", 2)):
         o = P.default_options(**{field: val})
         assert P._lib.phz_create(16, C.byref(m), C.byref(o), None, C.byref(h)) == -1, field
         assert not h.value

@@ -145,3 +145,27 @@ def test_short_run_restores_constraints(torch_cuda, P):
     print("objective", [f"{x:.3e}" for x in out["J"]])
     assert all(np.isfinite(out["J"]))
     assert abs(vol[-1]) < 0.5 * abs(vol[0])
+
+
+def test_warm_start_matches_cold_solve(P):
+    """warm_start = 1: the solve on a moved interface starts from the last solution, reaches the same
+    tensors as a solve from zero, in fewer iterations."""
+    n = 16
+    say("warm start", n)
+    phi = synth.grf_levelset(n, seed=2410, solid_fraction=0.5)
+    phi2 = phi + 0.01 * np.cos(2 * np.pi * synth.node_coords(n)[0])
+    with P.Context(n, MAT, precision=P.PHZ_FP32_IR, rtol=1e-10) as ctx:
+        ctx.set_levelset(phi2)
+        assert ctx.solve() == P.PHZ_OK
+        cold = sum(ctx.stats()["iterations"])
+        MHc, _ = ctx.effective_nd()
+    with P.Context(n, MAT, precision=P.PHZ_FP32_IR, rtol=1e-10, warm_start=1) as ctx:
+        ctx.set_levelset(phi)
+        assert ctx.solve() == P.PHZ_OK
+        ctx.set_levelset(phi2)
+        assert ctx.solve() == P.PHZ_OK
+        warm = sum(ctx.stats()["iterations"])
+        MHw, _ = ctx.effective_nd()
+    print("iterations cold", cold, "warm", warm)
+    assert warm < cold
+    assert np.abs(MHw - MHc).max() / np.abs(MHc).max() < 1e-8
