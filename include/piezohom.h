@@ -290,10 +290,17 @@ int phz_hj_step(phz_ctx* ctx, const double* velocity, double cfl,
 
 /* Reinitialise the context's level set towards a signed distance (Sec. 3:
  * a standard first-order scheme): `steps` pseudo-time steps of
- * phi_t + S(phi0) (|grad phi| - 1) = 0, S = phi0 / sqrt(phi0^2 + h^2), with the
- * HJ step's first-order Godunov upwinding, dtau = cfl * h.  The result becomes
- * the geometry and is written to phi_out ([N^3], may be NULL). */
-int phz_reinit(phz_ctx* ctx, int steps, double cfl, double* phi_out, int on_device);
+ * phi_t + S(phi0) (|grad phi| - 1) = 0 with the HJ step's first-order Godunov
+ * upwinding, dtau = cfl * h.  subcell = 0: S = phi0 / sqrt(phi0^2 + h^2)
+ * everywhere.  subcell = 1: the subcell fix of Russo and Smereka (J. Comput.
+ * Phys. 163, 2000): S = sign(phi0), and a node whose phi0 changes sign towards
+ * one of its six neighbours (or is 0) relaxes towards D = phi0 / |grad phi0|,
+ * phi <- phi - (dtau / h)(sign(phi0) |phi| - D), |grad phi0| taking per
+ * direction the largest of the central and one-sided differences; the zero
+ * level set then stays in place instead of moving by a fraction of h per call.
+ * The result becomes the geometry and is written to phi_out ([N^3], may be
+ * NULL).  steps < 0, cfl <= 0 or subcell outside {0, 1}: PHZ_E_INVALID. */
+int phz_reinit(phz_ctx* ctx, int steps, double cfl, int subcell, double* phi_out, int on_device);
 /* Chain rule of the density map rho_e = 1 - H(mean of phi over element e)
  * (Sec. 2.1, Sec. 3 smoothing): grad_phi[N^3] = dJ/dphi from any element
  * gradient grad_rho[N^3] (e.g. 1/N^3 for the volume). */

@@ -11,6 +11,12 @@ library.  Readings, all shared with the GPU path:
 
 * reinitialisation: pseudo-time steps of phi_t + S(phi0) (|grad phi| - 1) = 0 with the smoothed sign
   S = phi0 / sqrt(phi0^2 + h^2), the same first-order Godunov upwinding as the HJ step, dtau = cfl h;
+  or, with the subcell fix of Russo and Smereka (J. Comput. Phys. 163, 2000), still first order: the
+  exact sign elsewhere, and nodes with a sign change of phi0 towards one of their six neighbours (or
+  phi0 = 0) relax towards D = phi0 / |grad phi0| instead, phi <- phi - (dtau / h)(sign(phi0)|phi| - D),
+  with |grad phi0| from, per direction, the largest of the central and the two one-sided differences.
+  The zero level set then stays where phi0 puts it; the plain scheme moves it by a fraction of h per
+  reinitialisation, which erodes features a few elements thick;
 * sensitivities: j = -dJ/dphi, the exact derivative of the discrete functional with respect to the
   nodal level set (positive where lowering phi, i.e. growing solid, increases J); the HJ step lowers
   phi by cfl h v |grad phi|, so to first order J changes by cfl h (j . v) for |grad phi| = 1;
@@ -36,12 +42,24 @@ from . import fe
 from .cell import element_nodes
 
 
-def reinit(n, phi, steps=20, cfl=0.5):
-    """`steps` first-order pseudo-time steps of the reinitialisation equation."""
+def reinit(n, phi, steps=20, cfl=0.5, subcell=False):
+    """`steps` first-order pseudo-time steps of the reinitialisation equation (plain, or with the
+    subcell fix at the interface nodes)."""
     h = 1.0 / n
     dt = cfl * h
     f0 = np.asarray(phi, dtype=np.float64).reshape(n, n, n)
-    S = f0 / np.sqrt(f0 * f0 + h * h)
+    if subcell:
+        S = np.sign(f0)
+        iface = f0 == 0.0
+        grad2 = np.zeros_like(f0)
+        for ax in (2, 1, 0):
+            lo, hi = np.roll(f0, 1, axis=ax), np.roll(f0, -1, axis=ax)
+            iface |= (f0 * lo < 0.0) | (f0 * hi < 0.0)
+            d = np.maximum(np.abs(hi - lo) / 2.0, np.maximum(np.abs(hi - f0), np.abs(f0 - lo)))
+            grad2 += d * d
+        D = np.where(grad2 > 0.0, h * f0 / np.sqrt(np.where(grad2 > 0.0, grad2, 1.0)), 0.0)
+    else:
+        S = f0 / np.sqrt(f0 * f0 + h * h)
     f = f0.copy()
     for _ in range(steps):
         gp2 = np.zeros_like(f)
@@ -51,7 +69,10 @@ def reinit(n, phi, steps=20, cfl=0.5):
             dp = (np.roll(f, -1, axis=ax) - f) / h
             gp2 += np.maximum(dm, 0.0) ** 2 + np.minimum(dp, 0.0) ** 2
             gm2 += np.minimum(dm, 0.0) ** 2 + np.maximum(dp, 0.0) ** 2
-        f = f - dt * (np.maximum(S, 0.0) * np.sqrt(gp2) + np.minimum(S, 0.0) * np.sqrt(gm2) - S)
+        upd = f - dt * (np.maximum(S, 0.0) * np.sqrt(gp2) + np.minimum(S, 0.0) * np.sqrt(gm2) - S)
+        if subcell:
+            upd = np.where(iface, f - (dt / h) * (S * np.abs(f) - D), upd)
+        f = upd
     return f.ravel()
 
 

@@ -110,7 +110,7 @@ def _load():
         "phz_apply": (ip, [vp, ip, ip, ip, vp, vp]),
         "phz_precondition": (ip, [vp, ip, vp, vp]),
         "phz_coarse_apply": (ip, [vp, ip, ip, ip, ip, vp, vp]),
-        "phz_reinit": (ip, [vp, ip, C.c_double, vp, ip]),
+        "phz_reinit": (ip, [vp, ip, C.c_double, ip, vp, ip]),
         "phz_levelset_gradient": (ip, [vp, vp, vp, ip]),
         "phz_riesz": (ip, [vp, ip, C.c_double, vp, vp, C.POINTER(ip)]),
         "phz_hpm_velocity": (ip, [vp, ip, vp, C.POINTER(C.c_void_p), vp, C.c_double, C.c_double, C.c_double,
@@ -321,11 +321,11 @@ class Context:
         self._check(st, "phz_hj_step")
         return out
 
-    def reinit(self, steps=20, cfl=0.5, return_phi=True):
-        """Reinitialise the level set towards a signed distance (phz_reinit)."""
+    def reinit(self, steps=20, cfl=0.5, subcell=False, return_phi=True):
+        """Reinitialise the level set towards a signed distance (phz_reinit; subcell: Russo-Smereka fix)."""
         out = np.zeros(self.nn) if return_phi else None
-        self._check(_lib.phz_reinit(self._h, steps, cfl, C.c_void_p(out.ctypes.data) if return_phi else None, 0),
-                    "phz_reinit")
+        self._check(_lib.phz_reinit(self._h, steps, cfl, 1 if subcell else 0,
+                                    C.c_void_p(out.ctypes.data) if return_phi else None, 0), "phz_reinit")
         return out
 
     def levelset_gradient(self, grad_rho):

@@ -221,7 +221,8 @@ void hj_step(int N, const double* phi, const double* v, const double* vmax, doub
              double* out, hipStream_t st);
 // one pseudo-time step of the reinitialisation equation towards a signed
 // distance, smoothed sign taken from phi0
-void reinit_step(int N, const double* phi, const double* phi0, double dt, double* out, hipStream_t st);
+void reinit_step(int N, const double* phi, const double* phi0, double dt, int subcell, double* out,
+                 hipStream_t st);
 // y = W x, a constant 27-point stencil w[dx + 3 dy + 9 dz] (offsets -1..1), K node columns
 void const_stencil_apply(int N, int K, const double* w, const double* x, double* y, hipStream_t st);
 int count_nonfinite(long count, const double* v, double* work, hipStream_t st);

@@ -2120,18 +2120,20 @@ static double device_dot(phz_ctx* c, const double* a, const double* b) {
 
 }  // namespace phz
 
-int phz_reinit(phz_ctx* c, int steps, double cfl, double* phi_out, int on_device) {
-  if (!c || steps < 0 || !(cfl > 0)) return PHZ_E_INVALID;
+int phz_reinit(phz_ctx* c, int steps, double cfl, int subcell, double* phi_out, int on_device) {
+  if (!c || steps < 0 || !(cfl > 0) || (subcell != 0 && subcell != 1)) return PHZ_E_INVALID;
   if (!c->have_phi) { c->err = "reinitialisation needs a level set"; return PHZ_E_STATE; }
   PHZ_GUARD_BEGIN
-  DevBuf<double> phi0, tmp;
-  phi0.alloc(c->nn);
-  tmp.alloc(c->nn);
-  PHZ_HIP(hipMemcpyAsync(phi0.p, c->phi.p, c->nn * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
-  for (int i = 0; i < steps; ++i) {
-    reinit_step(c->N, c->phi.p, phi0.p, cfl / c->N, tmp.p, c->stream);
-    PHZ_HIP(hipMemcpyAsync(c->phi.p, tmp.p, c->nn * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
-  }
+  // phi0 stays fixed; the steps alternate between the geometry and rz_r
+  for (DevBuf<double>* v : {&c->rz_p, &c->rz_r})
+    if (v->n < (size_t)c->nn) v->alloc(c->nn);
+  double* phi0 = c->rz_p.p;
+  double* buf[2] = {c->phi.p, c->rz_r.p};
+  PHZ_HIP(hipMemcpyAsync(phi0, c->phi.p, c->nn * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+  for (int i = 0; i < steps; ++i)
+    reinit_step(c->N, buf[i & 1], phi0, cfl / c->N, subcell, buf[(i + 1) & 1], c->stream);
+  if (steps & 1)
+    PHZ_HIP(hipMemcpyAsync(c->phi.p, buf[1], c->nn * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
   levelset_to_scale(c->N, c->phi.p, c->opt.smooth_width / c->N, c->mat.void_scale, c->rho.p, c->s.p, c->s32.p,
                     c->stream);
   if (phi_out)

@@ -650,13 +650,38 @@ __global__ void k_hj_step(unsigned N, const double* __restrict__ phi, const doub
 // phi_t + S(phi0) (|grad phi| - 1) = 0, S = phi0 / sqrt(phi0^2 + h^2), with the
 // first-order Godunov upwinding of the HJ step
 __global__ void k_reinit_step(unsigned N, const double* __restrict__ phi, const double* __restrict__ phi0, double dt,
-                              double* __restrict__ out) {
+                              int subcell, double* __restrict__ out) {
   const unsigned nn = N * N * N;
   const unsigned n = blockIdx.x * blockDim.x + threadIdx.x;
   if (n >= nn) return;
   const Nb q = nbr(n, N);
   const double h = 1.0 / N;
   const double f0 = phi[n];
+  const double p0 = phi0[n];
+  double S;
+  if (subcell) {
+    // subcell fix: a node with a sign change of phi0 towards a neighbour
+    // relaxes towards its distance estimate phi0 / |grad phi0|
+    const double gx[2] = {phi0[at(N, q.im, q.j, q.k)], phi0[at(N, q.ip, q.j, q.k)]};
+    const double gy[2] = {phi0[at(N, q.i, q.jm, q.k)], phi0[at(N, q.i, q.jp, q.k)]};
+    const double gz[2] = {phi0[at(N, q.i, q.j, q.km)], phi0[at(N, q.i, q.j, q.kp)]};
+    const double* g[3] = {gx, gy, gz};
+    bool iface = p0 == 0.0;
+    double grad2 = 0.0;
+    for (int a = 0; a < 3; ++a) {
+      iface = iface || p0 * g[a][0] < 0.0 || p0 * g[a][1] < 0.0;
+      const double d = fmax(fabs(g[a][1] - g[a][0]) / 2.0, fmax(fabs(g[a][1] - p0), fabs(p0 - g[a][0])));
+      grad2 += d * d;
+    }
+    S = p0 > 0.0 ? 1.0 : (p0 < 0.0 ? -1.0 : 0.0);
+    if (iface) {
+      const double D = grad2 > 0.0 ? h * p0 / sqrt(grad2) : 0.0;
+      out[n] = f0 - (dt / h) * (S * fabs(f0) - D);
+      return;
+    }
+  } else {
+    S = p0 / sqrt(p0 * p0 + h * h);
+  }
   const double fx[2] = {phi[at(N, q.im, q.j, q.k)], phi[at(N, q.ip, q.j, q.k)]};
   const double fy[2] = {phi[at(N, q.i, q.jm, q.k)], phi[at(N, q.i, q.jp, q.k)]};
   const double fz[2] = {phi[at(N, q.i, q.j, q.km)], phi[at(N, q.i, q.j, q.kp)]};
@@ -667,8 +692,6 @@ __global__ void k_reinit_step(unsigned N, const double* __restrict__ phi, const 
     gp += fmax(dm, 0.0) * fmax(dm, 0.0) + fmin(dp, 0.0) * fmin(dp, 0.0);
     gm += fmin(dm, 0.0) * fmin(dm, 0.0) + fmax(dp, 0.0) * fmax(dp, 0.0);
   }
-  const double p0 = phi0[n];
-  const double S = p0 / sqrt(p0 * p0 + h * h);
   out[n] = f0 - dt * (fmax(S, 0.0) * sqrt(gp) + fmin(S, 0.0) * sqrt(gm) - S);
 }
 
@@ -903,9 +926,9 @@ int count_nonfinite(long count, const double* v, double* work, hipStream_t st) {
   PHZ_HIP(hipStreamSynchronize(st));
   return (int)h;
 }
-void reinit_step(int N, const double* phi, const double* phi0, double dt, double* out, hipStream_t st) {
+void reinit_step(int N, const double* phi, const double* phi0, double dt, int subcell, double* out, hipStream_t st) {
   const size_t nn = (size_t)N * N * N;
-  hipLaunchKernelGGL(k_reinit_step, dim3(blocks_for(nn, 256)), dim3(256), 0, st, (unsigned)N, phi, phi0, dt, out);
+  hipLaunchKernelGGL(k_reinit_step, dim3(blocks_for(nn, 256)), dim3(256), 0, st, (unsigned)N, phi, phi0, dt, subcell, out);
   PHZ_LAUNCH_CHECK();
 }
 

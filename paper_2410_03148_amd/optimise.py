@@ -6,7 +6,9 @@ homogenisation, the sensitivities, the chain rule to the level set, the Hilberti
 projection of the velocity, the HJ step and the reinitialisation) runs in the library's kernels.
 
 Per iteration q:
-  1. reinitialise at the start and every `reinit_every` iterations (the paper: every five);
+  1. reinitialise at the start and every `reinit_every` iterations (the paper: every five), by default
+     with the subcell fix, which keeps the zero level set in place (the plain first-order scheme moves
+     it by a fraction of h per call and erodes members a few elements thick);
   2. solve the cell problems; figures of merit from the effective tensors;
   3. for the objective and each constraint: its gradient with respect to the tensors, the backward
      pass to dJ/dphi (the volume's is the chain rule of 1/N^3), j = -dJ/dphi;
@@ -59,10 +61,11 @@ def should_stop(J_hist, viol_hist, h):
 
 
 def optimise(ctx, material, phi0, objective, constraints, max_iters=200, cfl=0.5, gamma=0.5, alpha=0.0,
-             reinit_every=5, reinit_steps=20, callback=None):
+             reinit_every=5, reinit_steps=20, reinit_subcell=True, callback=None):
     """Maximise `objective` subject to [(property, target), ...] equality constraints from the level set
-    phi0 (nodes, x fastest).  Returns a dict with the histories, the final level set and the wall time of
-    each phase in ms per iteration (every library call returns after its device work).  A context
+    phi0 (nodes, x fastest).  Returns a dict with the histories, the final level set, the effective
+    tensors of the last solved geometry and the wall time of each phase in ms per iteration (every
+    library call returns after its device work).  A context
     created with warm_start=1 starts each solve from the last iteration's solution."""
     if objective not in PROPERTIES or objective == "vol":
         raise ValueError(f"objective must be one of {PROPERTIES[:-1]}")
@@ -84,7 +87,7 @@ def optimise(ctx, material, phi0, objective, constraints, max_iters=200, cfl=0.5
     for q in range(max_iters):
         t = t_iter = clock()
         if reinit_every and q % reinit_every == 0:
-            ctx.reinit(reinit_steps, cfl, return_phi=False)
+            ctx.reinit(reinit_steps, cfl, subcell=reinit_subcell, return_phi=False)
             t = lap("reinit", t)
         status = ctx.solve()
         CH, eH, kH = ctx.effective()
@@ -101,6 +104,7 @@ def optimise(ctx, material, phi0, objective, constraints, max_iters=200, cfl=0.5
         hist["constraints"].append(vals)
         hist["violations"].append(viol)
         hist["status"].append(status)
+        hist["effective"] = (CH, eH, kH)
         if callback:
             callback(q, J, vals, viol)
         if should_stop(hist["J"], hist["violations"], h):

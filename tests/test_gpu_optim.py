@@ -35,16 +35,22 @@ def relmax(a, b):
     return np.abs(np.asarray(a) - np.asarray(b)).max() / max(np.abs(np.asarray(b)).max(), 1e-300)
 
 
-def test_reinit_vs_oracle(torch_cuda, P):
+@pytest.mark.parametrize("subcell", [False, True])
+@pytest.mark.parametrize("steps", [20, 7])
+def test_reinit_vs_oracle(torch_cuda, P, subcell, steps):
     n = 16
-    say("reinit", n)
+    say("reinit", n, "subcell", subcell, "steps", steps)
     phi = synth.grf_levelset(n, seed=2410, solid_fraction=0.5) * 2.5
     with P.Context(n, MAT) as ctx:
         ctx.set_levelset(phi)
-        r = ctx.reinit(steps=20, cfl=0.5)
-    ref = optim.reinit(n, phi, steps=20, cfl=0.5)
-    print("reinit error", relmax(r, ref))
+        r = ctx.reinit(steps=steps, cfl=0.5, subcell=subcell)
+        # a second call starts from the first one's result
+        r2 = ctx.reinit(steps=steps, cfl=0.5, subcell=subcell)
+    ref = optim.reinit(n, phi, steps=steps, cfl=0.5, subcell=subcell)
+    ref2 = optim.reinit(n, ref, steps=steps, cfl=0.5, subcell=subcell)
+    print("reinit error", relmax(r, ref), relmax(r2, ref2))
     assert relmax(r, ref) < 1e-12
+    assert relmax(r2, ref2) < 1e-12
 
 
 def test_levelset_gradient_vs_oracle(torch_cuda, P):
@@ -102,7 +108,7 @@ def test_one_optimisation_iteration_vs_oracle(torch_cuda, P):
     say("one optimisation iteration", n)
     phi0 = synth.grf_levelset(n, seed=2410, solid_fraction=0.5)
     # oracle
-    phi_r = optim.reinit(n, phi0, steps=20, cfl=0.5)
+    phi_r = optim.reinit(n, phi0, steps=20, cfl=0.5, subcell=True)
     res = cell.homogenise(n, MAT, phi=phi_r)
     dh0 = ofoms.foms(res.C, res.e, res.kappa)["d_h"]
     target = 1.2 * dh0
