@@ -308,8 +308,11 @@ int phz_levelset_gradient(phz_ctx* ctx, const double* grad_rho, double* grad_phi
 /* Riesz representatives in the Hilbert space of the velocity extension:
  * g = H^-1 j for ncol (<= 9) device node columns [ncol][N^3], with
  * H = alpha^2 K + M the trilinear finite-element Laplace and mass matrices of
- * the periodic grid (alpha: length scale, cell units).  Conjugate gradients
- * to a relative residual of 1e-12; *iters (may be NULL) gets the count. */
+ * the periodic grid (alpha: length scale, cell units).  Chebyshev iteration
+ * on H's exact extreme eigenvalues (constant coefficients: the extremes of its
+ * symbol over the grid frequencies), run for the step count whose bound
+ * 2 rho^k reaches a relative residual of 1e-12, with no host synchronisation
+ * inside; *iters (may be NULL) gets the count.  j and g must not overlap. */
 int phz_riesz(phz_ctx* ctx, int ncol, double alpha, const double* j, double* g, int* iters);
 /* Velocity of one constrained optimisation step by projection in that
  * Hilbert space (the paper uses a Hilbertian projection method for its

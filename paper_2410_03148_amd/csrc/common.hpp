@@ -224,7 +224,10 @@ void hj_step(int N, const double* phi, const double* v, const double* vmax, doub
 void reinit_step(int N, const double* phi, const double* phi0, double dt, int subcell, double* out,
                  hipStream_t st);
 // y = W x, a constant 27-point stencil w[dx + 3 dy + 9 dz] (offsets -1..1), K node columns
-void const_stencil_apply(int N, int K, const double* w, const double* x, double* y, hipStream_t st);
+// one Chebyshev step for a constant 27-point stencil (K columns):
+// x += d, r -= W d, dn = c1 d + c2 r
+void stencil_cheb_step(int N, int K, const double* w, const double* d, double* x, double* r, double* dn, double c1,
+                       double c2, hipStream_t st);
 int count_nonfinite(long count, const double* v, double* work, hipStream_t st);
 // power iteration helper: v = w / sqrt(nrm2[0])
 template <typename T>

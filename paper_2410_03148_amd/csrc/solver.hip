@@ -166,7 +166,8 @@ struct phz_ctx {
   phz::DevBuf<double> negone;  // nine copies of -1.0 (block-diagonal preconditioner)
   // optimisation step: Helmholtz stencil, conjugate-gradient vectors and
   // scalars of the Riesz solves, the velocity's direction vectors
-  phz::DevBuf<double> helm_w, rz_r, rz_z, rz_p, rz_q, rz_g, rz_j, rz_dev;
+  phz::DevBuf<double> helm_w, rz_r, rz_z, rz_p, rz_g, rz_j, rz_dev;
+  double rz_host[40] = {};  // staged stencil weights and column scales (outlive their async copies)
   phz::DevBuf<double> pcg_dev; // per-column scalars of the inexact block maps
 
   // optional per-kernel timing with HIP events on the context stream
@@ -2023,73 +2024,56 @@ static void helmholtz_weights(int N, double alpha, double* w) {
   }
 }
 
-// g = H^-1 j for K node columns (device), conjugate gradients with the
-// (constant) diagonal as preconditioner, to a relative residual of 1e-12
-// per column; returns the iterations
+// g = H^-1 j for K node columns (device) by Chebyshev iteration.  H is
+// periodic with constant coefficients, so its eigenvalues are its symbol at
+// the grid frequencies.  Per direction, with c = cos t, the symbols
+// m = h (2 + c) / 3 and k = 2 (1 - c) / h are affine in c, so the symbol
+// alpha^2 (k1 m2 m3 + m1 k2 m3 + m1 m2 k3) + m1 m2 m3 is multilinear in
+// (c1, c2, c3) and takes its extremes at the vertices c = +-1, which are grid
+// frequencies for even N: the bounds are exact.  After k steps the residual is
+// at most 2 rho^k times the initial one, rho = (sqrt(kappa) - 1) /
+// (sqrt(kappa) + 1), so the step count for a relative residual of 1e-12 is
+// known in advance and the iteration takes no inner products (no host round
+// trip).  Returns the step count.
 static int riesz_solve(phz_ctx* c, int K, double alpha, const double* j, double* g) {
   const long nn = c->nn;
   hipStream_t st = c->stream;
-  double w[27];
-  helmholtz_weights(c->N, alpha, w);
-  c->helm_w.upload(w, 27, st);
-  for (DevBuf<double>* v : {&c->rz_r, &c->rz_z, &c->rz_p, &c->rz_q})
+  const double h = 1.0 / c->N;
+  double lmin = HUGE_VAL, lmax = 0.0;
+  for (int v = 0; v < 8; ++v) {
+    double m[3], k[3];
+    for (int a = 0; a < 3; ++a) {
+      const double cs = (v >> a) & 1 ? -1.0 : 1.0;
+      m[a] = h * (2.0 + cs) / 3.0;
+      k[a] = 2.0 * (1.0 - cs) / h;
+    }
+    const double lam =
+        alpha * alpha * (k[0] * m[1] * m[2] + m[0] * k[1] * m[2] + m[0] * m[1] * k[2]) + m[0] * m[1] * m[2];
+    lmin = std::min(lmin, lam);
+    lmax = std::max(lmax, lam);
+  }
+  // the mass part alone spans a factor 27, so lmax > lmin
+  const double theta = 0.5 * (lmax + lmin), delta = 0.5 * (lmax - lmin), sigma = theta / delta;
+  const double sk = std::sqrt(lmax / lmin);
+  const int steps = (int)std::ceil(std::log(2.0 / 1e-12) / std::log((sk + 1.0) / (sk - 1.0)));
+  helmholtz_weights(c->N, alpha, c->rz_host);
+  for (int k = 0; k < K; ++k) c->rz_host[27 + k] = 1.0 / theta;
+  c->helm_w.upload(c->rz_host, 27, st);
+  c->rz_dev.upload(c->rz_host + 27, K, st);
+  for (DevBuf<double>* v : {&c->rz_r, &c->rz_z, &c->rz_p})
     if (v->n < (size_t)nn * K) v->alloc((size_t)nn * K);
-  c->rz_dev.alloc(4 * 9);
-  double* dv = c->rz_dev.p;  // [0, K) alpha, [K, 2K) -alpha, [2K, 3K) beta, [3K, 4K) reductions
-  double* red = dv + 27;
-  const double dinv = 1.0 / w[13];
-  std::vector<double> dsc(K, dinv), bn(K), rz(K), h(K), al(2 * K), be(K);
-  std::vector<int> act(K);
-  auto to_host = [&](std::vector<double>& out) {
-    PHZ_HIP(hipMemcpyAsync(out.data(), red, K * sizeof(double), hipMemcpyDeviceToHost, st));
-    sync(c);
-  };
-  double *r = c->rz_r.p, *z = c->rz_z.p, *p = c->rz_p.p, *q = c->rz_q.p;
+  double *r = c->rz_r.p, *d = c->rz_z.p, *dn = c->rz_p.p;
   PHZ_HIP(hipMemcpyAsync(r, j, (size_t)nn * K * sizeof(double), hipMemcpyDeviceToDevice, st));
   fill<double>(nn * K, 0.0, g, st);
-  col_norm2<double>(nn, 1, K, r, red, c->red_work.p, st);
-  to_host(bn);
-  for (int k = 0; k < K; ++k) {
-    bn[k] = std::sqrt(bn[k]);
-    act[k] = bn[k] > 0.0;
+  scale_cols<double>(nn, 1, K, r, c->rz_dev.p, d, st);  // d0 = r0 / theta
+  double rho = 1.0 / sigma;
+  for (int it = 0; it < steps; ++it) {
+    const double rho1 = 1.0 / (2.0 * sigma - rho);
+    stencil_cheb_step(c->N, K, c->helm_w.p, d, g, r, dn, rho1 * rho, 2.0 * rho1 / delta, st);
+    std::swap(d, dn);
+    rho = rho1;
   }
-  PHZ_HIP(hipMemcpyAsync(dv + 2 * K, dsc.data(), K * sizeof(double), hipMemcpyHostToDevice, st));
-  scale_cols<double>(nn, 1, K, r, dv + 2 * K, z, st);
-  PHZ_HIP(hipMemcpyAsync(p, z, (size_t)nn * K * sizeof(double), hipMemcpyDeviceToDevice, st));
-  col_dot<double>(nn, 1, K, r, z, red, c->red_work.p, st);
-  to_host(rz);
-  int it = 0;
-  for (; it < 2000; ++it) {
-    int nact = 0;
-    for (int k = 0; k < K; ++k) nact += act[k];
-    if (nact == 0) break;
-    const_stencil_apply(c->N, K, c->helm_w.p, p, q, st);
-    col_dot<double>(nn, 1, K, p, q, red, c->red_work.p, st);
-    to_host(h);
-    for (int k = 0; k < K; ++k) {
-      const double a = act[k] && h[k] > 0.0 ? rz[k] / h[k] : 0.0;
-      al[k] = a;
-      al[K + k] = -a;
-    }
-    PHZ_HIP(hipMemcpyAsync(dv, al.data(), 2 * K * sizeof(double), hipMemcpyHostToDevice, st));
-    axpy_cols<double, double>(nn, 1, K, dv, p, g, st);
-    axpy_cols<double, double>(nn, 1, K, dv + K, q, r, st);
-    col_norm2<double>(nn, 1, K, r, red, c->red_work.p, st);
-    to_host(h);
-    for (int k = 0; k < K; ++k)
-      if (act[k] && !(std::sqrt(h[k]) > 1e-12 * bn[k])) act[k] = 0;
-    PHZ_HIP(hipMemcpyAsync(dv + 2 * K, dsc.data(), K * sizeof(double), hipMemcpyHostToDevice, st));
-    scale_cols<double>(nn, 1, K, r, dv + 2 * K, z, st);
-    col_dot<double>(nn, 1, K, r, z, red, c->red_work.p, st);
-    to_host(h);
-    for (int k = 0; k < K; ++k) {
-      be[k] = act[k] && rz[k] != 0.0 ? h[k] / rz[k] : 0.0;
-      rz[k] = h[k];
-    }
-    PHZ_HIP(hipMemcpyAsync(dv + 2 * K, be.data(), K * sizeof(double), hipMemcpyHostToDevice, st));
-    xpby_cols<double>(nn, 1, K, dv + 2 * K, z, p, st);
-  }
-  return it;
+  return steps;
 }
 
 // copies K host or device node vectors into one device block of K columns

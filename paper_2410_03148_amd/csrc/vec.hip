@@ -695,10 +695,14 @@ __global__ void k_reinit_step(unsigned N, const double* __restrict__ phi, const 
   out[n] = f0 - dt * (fmax(S, 0.0) * sqrt(gp) + fmin(S, 0.0) * sqrt(gm) - S);
 }
 
-// y = W x for a constant 27-point node stencil w[d] (d = dx + 3 dy + 9 dz,
-// offsets -1..1), K columns
-__global__ __launch_bounds__(256) void k_const_stencil(unsigned N, const double* __restrict__ w,
-                                                       const double* __restrict__ x, double* __restrict__ y) {
+// One Chebyshev step on K columns for a constant 27-point node stencil w[d]
+// (d = dx + 3 dy + 9 dz, offsets -1..1): q = W d at the node, then
+// x += d, r -= q, dn = c1 d + c2 r.  dn is a separate buffer because the
+// stencil reads d at the neighbours.
+__global__ __launch_bounds__(256) void k_stencil_cheb(unsigned N, const double* __restrict__ w,
+                                                      const double* __restrict__ d, double* __restrict__ x,
+                                                      double* __restrict__ r, double* __restrict__ dn, double c1,
+                                                      double c2) {
   const unsigned nn = N * N * N;
   const unsigned n = blockIdx.x * blockDim.x + threadIdx.x;
   if (n >= nn) return;
@@ -706,8 +710,12 @@ __global__ __launch_bounds__(256) void k_const_stencil(unsigned N, const double*
   const Nb q = nbr(n, N);
   const unsigned xs[3] = {q.im, q.i, q.ip}, ys[3] = {q.jm, q.j, q.jp}, zs[3] = {q.km, q.k, q.kp};
   double acc = 0.0;
-  for (int d = 0; d < 27; ++d) acc += w[d] * x[co + at(N, xs[d % 3], ys[(d / 3) % 3], zs[d / 9])];
-  y[co + n] = acc;
+  for (int e = 0; e < 27; ++e) acc += w[e] * d[co + at(N, xs[e % 3], ys[(e / 3) % 3], zs[e / 9])];
+  const double dv = d[co + n];
+  const double rv = r[co + n] - acc;
+  x[co + n] += dv;
+  r[co + n] = rv;
+  dn[co + n] = c1 * dv + c2 * rv;
 }
 
 template <typename T>
@@ -932,9 +940,11 @@ void reinit_step(int N, const double* phi, const double* phi0, double dt, int su
   PHZ_LAUNCH_CHECK();
 }
 
-void const_stencil_apply(int N, int K, const double* w, const double* x, double* y, hipStream_t st) {
+void stencil_cheb_step(int N, int K, const double* w, const double* d, double* x, double* r, double* dn, double c1,
+                       double c2, hipStream_t st) {
   const size_t nn = (size_t)N * N * N;
-  hipLaunchKernelGGL(k_const_stencil, dim3(blocks_for(nn, 256), K), dim3(256), 0, st, (unsigned)N, w, x, y);
+  hipLaunchKernelGGL(k_stencil_cheb, dim3(blocks_for(nn, 256), K), dim3(256), 0, st, (unsigned)N, w, d, x, r, dn,
+                     c1, c2);
   PHZ_LAUNCH_CHECK();
 }
 

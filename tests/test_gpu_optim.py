@@ -65,11 +65,11 @@ def test_levelset_gradient_vs_oracle(torch_cuda, P):
     assert relmax(gp, ref) < 1e-13
 
 
-def test_riesz_vs_oracle(torch_cuda, P):
+@pytest.mark.parametrize("n,alpha_h", [(16, 4.0), (24, 4.0), (16, 0.0)])
+def test_riesz_vs_oracle(torch_cuda, P, n, alpha_h):
     torch = torch_cuda
-    n = 16
-    say("riesz", n)
-    alpha = 4.0 / n
+    say("riesz", n, alpha_h)
+    alpha = alpha_h / n
     j = np.random.default_rng(9).standard_normal((3, n ** 3))
     with P.Context(n, MAT) as ctx:
         jd = torch.tensor(j, dtype=torch.float64, device="cuda").contiguous()
