@@ -139,23 +139,23 @@ def solver_study(P, torch, synth, mat, dev):
 
 
 # The paper's optimisation problems: (objective, constraints, what the paper reports for the result).
-# bvoigt: its worked example (Sec. 4.1); dh_a/b/c: Eq. (optim prob 2) with the three stiffness targets
-# of its Table 2, whose volume target is not printed: it is read as the volume that Table 2 reports.
+# bvoigt: its worked example (Sec. 3.1); dh_a/b/c: Eq. (optim prob 2) with the three stiffness targets
+# of its Table 3, whose volume target is not printed: it is read as the volume that Table 3 reports.
 OPT_PROBLEMS = {
     "bvoigt": ("B_voigt", [("vol", 0.5), ("d_h", 2.9e-10)],
                "converges after about 180 iterations at 100^3; about 9x the base d_h at about 20% of the "
-               "base B_Voigt (Sec. 4.1)"),
+               "base B_Voigt (Sec. 3.1)"),
     "dh_a": ("d_h", [("vol", 0.599), ("C_zzzz", 5e9)],
-             "Table 2 (a): d_h 3.5e-10, B_Voigt 1.75e10, B_Reuss 4.85e9, g_h 0.197, k_h 0.578"),
+             "Table 3 (a): d_h 3.5e-10, B_Voigt 1.75e10, B_Reuss 4.85e9, g_h 0.197, k_h 0.578"),
     "dh_b": ("d_h", [("vol", 0.586), ("C_zzzz", 2.5e9)],
-             "Table 2 (b): d_h 3.89e-10, B_Voigt 1.63e10, B_Reuss 2.45e9, g_h 0.357, k_h 0.584"),
+             "Table 3 (b): d_h 3.89e-10, B_Voigt 1.63e10, B_Reuss 2.45e9, g_h 0.357, k_h 0.584"),
     "dh_c": ("d_h", [("vol", 0.581), ("C_zzzz", 1e9)],
-             "Table 2 (c): d_h 4.45e-10, B_Voigt 1.58e10, B_Reuss 9.77e8, g_h 0.889, k_h 0.622"),
+             "Table 3 (c): d_h 4.45e-10, B_Voigt 1.58e10, B_Reuss 9.77e8, g_h 0.889, k_h 0.622"),
 }
 
 
 def optimisation_run(P, torch, synth, n, max_iters, precision, problem="bvoigt", reinit_every=5):
-    """One of the paper's optimisation problems (Sec. 3): z-poled PZT-5A, from the level set
+    """One of the paper's optimisation problems (Sec. 2.3, Sec. 2.6): z-poled PZT-5A, from the level set
     -prod cos(2 pi x_i) - 0.2 reinitialised, reinitialisation every five iterations, the paper's
     stopping rule.  The paper runs them on a 100^3 mesh; the multigrid hierarchy here needs N = m 2^k
     with m <= 10, so the nearest cell is 96^3.  Reports the wall time per iteration and per phase and

@@ -286,9 +286,9 @@ int phz_backward(phz_ctx* ctx, const double gC[36], const double ge[18],
 int phz_hj_step(phz_ctx* ctx, const double* velocity, double cfl,
                 double* phi_out, int on_device);
 
-/* ---- the optimisation loop around the solve (Sec. 2.1, Sec. 3) ---- */
+/* ---- the optimisation loop around the solve (Sec. 2.1, Sec. 2.6) ---- */
 
-/* Reinitialise the context's level set towards a signed distance (Sec. 3:
+/* Reinitialise the context's level set towards a signed distance (Sec. 2.6:
  * a standard first-order scheme): `steps` pseudo-time steps of
  * phi_t + S(phi0) (|grad phi| - 1) = 0 with the HJ step's first-order Godunov
  * upwinding, dtau = cfl * h.  subcell = 0: S = phi0 / sqrt(phi0^2 + h^2)
@@ -302,7 +302,7 @@ int phz_hj_step(phz_ctx* ctx, const double* velocity, double cfl,
  * NULL).  steps < 0, cfl <= 0 or subcell outside {0, 1}: PHZ_E_INVALID. */
 int phz_reinit(phz_ctx* ctx, int steps, double cfl, int subcell, double* phi_out, int on_device);
 /* Chain rule of the density map rho_e = 1 - H(mean of phi over element e)
- * (Sec. 2.1, Sec. 3 smoothing): grad_phi[N^3] = dJ/dphi from any element
+ * (Sec. 2.1, Sec. 2.6 smoothing): grad_phi[N^3] = dJ/dphi from any element
  * gradient grad_rho[N^3] (e.g. 1/N^3 for the volume). */
 int phz_levelset_gradient(phz_ctx* ctx, const double* grad_rho, double* grad_phi, int on_device);
 /* Riesz representatives in the Hilbert space of the velocity extension:

@@ -1,4 +1,4 @@
-"""The level-set optimisation loop around the homogenisation (Sec. 2.1, Sec. 2.4, Sec. 3): reinitialisation
+"""The level-set optimisation loop around the homogenisation (Sec. 2.1, Sec. 2.3, Sec. 2.6): reinitialisation
 to a signed distance, the extension of the discrete sensitivities into a velocity by a Hilbert-space
 projection onto the constraints' null space, and the stopping rule.
 
@@ -134,7 +134,7 @@ def volume(n, phi, width_elems=2.0):
 
 
 def should_stop(J_hist, viol_hist, h):
-    """The paper's stopping rule (Sec. 3) on the objective and relative-violation histories."""
+    """The paper's stopping rule (Sec. 2.6) on the objective and relative-violation histories."""
     q = len(J_hist) - 1
     if q < 10:
         return False

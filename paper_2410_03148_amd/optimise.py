@@ -1,4 +1,4 @@
-"""Level-set optimisation loop of the paper's results (Sec. 2.1, Sec. 3): maximise an effective figure
+"""Level-set optimisation loop of the paper's results (Sec. 2.1, Sec. 2.3, Sec. 2.6): maximise an effective figure
 of merit subject to equality constraints on the volume and a second effective property.
 
 The loop only sequences the library's calls and keeps the scalar history; every field operation (the
