@@ -82,11 +82,24 @@ extern "C" {
                             float32; refinement, residuals, Hessenberg/Givens,
                             coarse solve and reductions stay float64. */
 
-/* preconditioners of phz_options.solver (Sec. 2.5): both right-precondition
+/* solvers of phz_options.solver (Sec. 2.5): the first two right-precondition
  * GMRES on calA */
 #define PHZ_SOLVER_SCP 0 /* approximate Schur complement, lower block-triangular
                             [[A, 0], [-B, S_bar]] (SCP-GMRES, the default)   */
 #define PHZ_SOLVER_DBP 1 /* block diagonal [[A, 0], [0, -C]] (DBP-GMRES)     */
+#define PHZ_SOLVER_TRICG 2 /* TriCG (Sec. 2.5.2) on the quasi-definite calA:
+                            orthogonal tridiagonalisation in the A- and
+                            C-inner products, block LDL^T short recurrences;
+                            A^-1 and C^-1 by conjugate gradients to inner_eps
+                            (one V-cycle per iteration).  PHZ_FP64 only.
+                            Each cycle starts from the true residual; a
+                            residual block below 1e-12 of the other, or
+                            below min(1e-13, rtol / 10) of ||b||, starts
+                            from a shifted point (c = 0: y0 = C^-1 B A^-1 b;
+                            b = 0: x0 = -A^-1 B^T C^-1 c), and a breakdown
+                            (beta or gamma below 1e-10 of its largest value)
+                            ends the cycle.  stats: iterations = TriCG
+                            iterations, restarts = cycles                    */
 
 /* operator blocks for phz_apply (Sec. 2.5 block structure) */
 #define PHZ_OP_FULL 0    /* calA = [[A, B^T], [B, -C]] on [n][4][k]        */
@@ -95,6 +108,8 @@ extern "C" {
 #define PHZ_OP_SBAR 3    /* element-wise approximate Schur S_bar on [n][1][k] */
 #define PHZ_OP_C 4       /* C (dielectric; calA's (phi, phi) block is -C) on
                             [n][1][k]                                       */
+#define PHZ_OP_BT 5      /* B^T [n][1][k] -> [n][3][k] (PHZ_FP64 and
+                            PHZ_FP32_IR only)                                */
 
 typedef struct phz_ctx phz_ctx;
 
@@ -165,7 +180,8 @@ typedef struct {
                                and 1 the apply with the input tile staged in
                                LDS (levels with N a multiple of 16); 0 or 1
                                forces that kernel where it applies           */
-    int solver;             /* PHZ_SOLVER_SCP (default) or PHZ_SOLVER_DBP     */
+    int solver;             /* PHZ_SOLVER_SCP (default), PHZ_SOLVER_DBP or
+                               PHZ_SOLVER_TRICG                               */
     int inner;              /* block maps v -> A^-1 v and the potential block's
                                inverse (S_bar or C): 0 (default) fixed V-cycle
                                counts (vcycles_a, vcycles_s), a fixed linear

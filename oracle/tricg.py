@@ -34,8 +34,9 @@ The method, as written here:
 * Breakdown: when beta_{k+1} or gamma_{k+1} falls below 1e-10 of the largest one so far, one of the
   two Krylov spaces is exhausted and the process cannot continue (it happens right after the start
   above).  The cycle stops at its last iterate, and the solve restarts from the true residual of the
-  accumulated solution.  A residual block below 1e-12 of the other counts as zero there and takes the
-  start above (on the cell, the in-plane shear load's potential residual is exact after a cycle).
+  accumulated solution.  A residual block below 1e-12 of the other, or below min(1e-13, rtol / 10) of
+  the right-hand side (rounding noise, negligible against the target), counts as zero there and takes
+  the start above (on the cell, the in-plane shear load's potential residual is exact after a cycle).
   Cycles also end when the recurrence's residual reaches the tolerance; the solve ends when the true
   residual does.
 """
@@ -201,9 +202,10 @@ def solve_restarted(Kop, Aop, Atop, Einv, Finv, b, c, rtol=1e-10, maxit=500, max
         if rn <= rtol * n0:
             break
         cycles += 1
-        if ny <= 1e-12 * nx:
+        tiny = min(1e-13, 0.1 * rtol) * n0
+        if ny <= 1e-12 * nx or ny <= tiny:
             ry = np.zeros_like(ry)
-        elif nx <= 1e-12 * ny:
+        elif nx <= 1e-12 * ny or nx <= tiny:
             rx = np.zeros_like(rx)
         x0, y0, done = start(rx, ry, Aop, Atop, Einv, Finv)
         if done or np.any(x0) or np.any(y0):

@@ -23,8 +23,8 @@ PHZ_NOT_CONVERGED = 1
 PHZ_FP64 = 0
 PHZ_FP32_IR = 1
 PHZ_BF16X3_IR = 2
-PHZ_SOLVER_SCP, PHZ_SOLVER_DBP = 0, 1
-OP_FULL, OP_A, OP_B, OP_SBAR, OP_C = 0, 1, 2, 3, 4
+PHZ_SOLVER_SCP, PHZ_SOLVER_DBP, PHZ_SOLVER_TRICG = 0, 1, 2
+OP_FULL, OP_A, OP_B, OP_SBAR, OP_C, OP_BT = 0, 1, 2, 3, 4, 5
 
 
 class phz_material(C.Structure):

@@ -224,6 +224,11 @@ void hj_step(int N, const double* phi, const double* v, const double* vmax, doub
 void reinit_step(int N, const double* phi, const double* phi0, double dt, int subcell, double* out,
                  hipStream_t st);
 // y = W x, a constant 27-point stencil w[dx + 3 dy + 9 dz] (offsets -1..1), K node columns
+// TriCG update of one block (F fields, K loads) with per-load coefficients
+// cf[6k..6k+5] = (L00, L01, L10, L11, z0, z1): g1 <- [side 0] w - (L00 g1 +
+// L01 g2), g2 <- [side 1] w - (L10 g1 + L11 g2), x += z0 g1 + z1 g2
+void tricg_update(long nn, int F, int K, const double* cf, const double* w, int side, double* g1, double* g2,
+                  double* x, hipStream_t st);
 // one Chebyshev step for a constant 27-point stencil (K columns):
 // x += d, r -= W d, dn = c1 d + c2 r
 void stencil_cheb_step(int N, int K, const double* w, const double* d, double* x, double* r, double* dn, double c1,

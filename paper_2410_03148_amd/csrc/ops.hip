@@ -66,6 +66,7 @@ template <> struct OpFields<0> { static constexpr int FO = 4, FI = 4; };
 template <> struct OpFields<1> { static constexpr int FO = 3, FI = 3; };
 template <> struct OpFields<2> { static constexpr int FO = 1, FI = 3; };
 template <> struct OpFields<3> { static constexpr int FO = 1, FI = 1; };
+template <> struct OpFields<5> { static constexpr int FO = 3, FI = 1; };  // B^T
 
 // Contribution of the neighbour m = n + (dx, dy, dz) to the FO x K outputs of
 // node n: its FO x FI stencil block (the reference element blocks of the
@@ -734,6 +735,7 @@ void fine_apply(int op, int nrhs, int N, const T* s, const T* kref, const T* x, 
       case 1: PHZ_FA(1, 1); break;
       case 2: PHZ_FA(2, 1); break;
       case 3: PHZ_FA(3, 1); break;
+      case 5: PHZ_FA(5, 1); break;
       default: throw std::invalid_argument("fine_apply op");
     }
   } else if (nrhs == 9) {
@@ -742,6 +744,7 @@ void fine_apply(int op, int nrhs, int N, const T* s, const T* kref, const T* x, 
       case 1: PHZ_FA(1, 9); break;
       case 2: PHZ_FA(2, 9); break;
       case 3: PHZ_FA(3, 9); break;
+      case 5: PHZ_FA(5, 9); break;
       default: throw std::invalid_argument("fine_apply op");
     }
   } else {

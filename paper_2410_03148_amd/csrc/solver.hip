@@ -132,8 +132,8 @@ struct phz_ctx {
   // reference blocks: 0 full, 1 A, 2 B, 3 S_bar, and 4 C (the dielectric
   // block, a 1 -> 1 block like S_bar, used by the block-diagonal
   // preconditioner)
-  phz::DevBuf<double> kref_full, kref_A, kref_B, kref_S, kref_C, F0d;
-  phz::DevBuf<float> kref32_full, kref32_A, kref32_B, kref32_S, kref32_C;
+  phz::DevBuf<double> kref_full, kref_A, kref_B, kref_S, kref_C, kref_BT, F0d;
+  phz::DevBuf<float> kref32_full, kref32_A, kref32_B, kref32_S, kref32_C, kref32_BT;
   // split-BF16 MFMA operands of the five fine blocks, the tile choice of the
   // four block shapes (-1 not yet chosen, -2 none divides N), and the kernel
   // chosen for each shape's float32 nine-column launches
@@ -169,6 +169,10 @@ struct phz_ctx {
   phz::DevBuf<double> helm_w, rz_r, rz_z, rz_p, rz_g, rz_j, rz_dev;
   double rz_host[40] = {};  // staged stencil weights and column scales (outlive their async copies)
   phz::DevBuf<double> pcg_dev; // per-column scalars of the inexact block maps
+  // TriCG vectors: displacement block [3][K][nn], potential block [K][nn]
+  phz::DevBuf<double> tri_u, tri_Eu, tri_Eup, tri_q, tri_Eq, tri_g1x, tri_g2x;
+  phz::DevBuf<double> tri_v, tri_Fv, tri_Fvp, tri_p, tri_Fp, tri_g1y, tri_g2y;
+  phz::DevBuf<double> tri_dev;  // per-load coefficients and reductions
 
   // optional per-kernel timing with HIP events on the context stream
   bool ktime = false;
@@ -239,6 +243,13 @@ static void upload_reference(phz_ctx* c) {
   c->kref_B.upload(R.B0, 8 * 24, st);
   c->kref_S.upload(R.S0, 8 * 8, st);
   c->kref_C.upload(R.C0, 8 * 8, st);
+  // B^T in the 3 <- 1 block layout [(corner c, field f)][corner m]
+  double BT[24 * 8];
+  for (int cn = 0; cn < 8; ++cn)
+    for (int f = 0; f < 3; ++f)
+      for (int m = 0; m < 8; ++m) BT[(cn * 3 + f) * 8 + m] = R.B0[m * 24 + cn * 3 + f];
+  c->kref_BT.upload(BT, 24 * 8, st);
+  sync(c);
   c->F0d.upload(R.F0, 32 * 9, st);
   std::vector<float> f(32 * 32);
   auto up32 = [&](DevBuf<float>& d, const double* h, int n) {
@@ -251,6 +262,7 @@ static void upload_reference(phz_ctx* c) {
   up32(c->kref32_B, R.B0, 8 * 24);
   up32(c->kref32_S, R.S0, 8 * 8);
   up32(c->kref32_C, R.C0, 8 * 8);
+  up32(c->kref32_BT, BT, 24 * 8);
   std::vector<unsigned short> ops(2048);
   const double* krefs[5] = {R.K0, R.A0, R.B0, R.S0, R.C0};
   for (int op = 0; op < 5; ++op) {
@@ -376,13 +388,15 @@ static GmresState gm_state(phz_ctx* c) {
 // ---------------------------------------------------------- level operators
 template <typename T> static const T* kref_of(phz_ctx* c, int op);
 template <> const double* kref_of<double>(phz_ctx* c, int op) {
-  return op == 0 ? c->kref_full.p : op == 1 ? c->kref_A.p : op == 2 ? c->kref_B.p : op == 3 ? c->kref_S.p : c->kref_C.p;
+  return op == 0 ? c->kref_full.p : op == 1 ? c->kref_A.p : op == 2 ? c->kref_B.p : op == 3 ? c->kref_S.p
+       : op == 4 ? c->kref_C.p : c->kref_BT.p;
 }
 template <> const float* kref_of<float>(phz_ctx* c, int op) {
   return op == 0 ? c->kref32_full.p : op == 1 ? c->kref32_A.p : op == 2 ? c->kref32_B.p
-       : op == 3 ? c->kref32_S.p : c->kref32_C.p;
+       : op == 3 ? c->kref32_S.p : op == 4 ? c->kref32_C.p : c->kref32_BT.p;
 }
-// launch shape (fields in and out) of a reference block: C is shaped like S_bar
+// launch shape (fields in and out) of a reference block: C is shaped like
+// S_bar; B^T (block 5, 3 <- 1) has its own shape and only the direct gather
 static int shape_of(int op) { return op == 4 ? 3 : op; }
 template <typename T> static const T* s_of(phz_ctx* c);
 template <> const double* s_of<double>(phz_ctx* c) { return c->s.p; }
@@ -573,7 +587,7 @@ template <typename T>
 static void op_apply_args(phz_ctx* c, int blk, int K, const T* x, const OpArgs<T>& a, bool cheby) {
   const int op = shape_of(blk);
   if constexpr (std::is_same<T, float>::value) {
-    if (K == 9) {
+    if (K == 9 && op <= 3) {
       const int kind = fine_kind_of(c, op);
       if (kind == kFineElem) {
         const long slot = time_begin(c, elem_op_name(op, c->opt.bf16_terms == 3, cheby));
@@ -792,8 +806,8 @@ static void setup_preconditioner(phz_ctx* c) {
   }
   build_levels(c, c->hA, 3, 1);
   build_levels(c, c->hS, 1, 3);
-  // the C hierarchy only exists for the block-diagonal preconditioner
-  if (c->opt.solver == PHZ_SOLVER_DBP) {
+  // the C hierarchy only exists for the block-diagonal preconditioner and TriCG
+  if (c->opt.solver == PHZ_SOLVER_DBP || c->opt.solver == PHZ_SOLVER_TRICG) {
     build_levels(c, c->hC, 1, 4);
   } else if (!c->hC.lv.empty()) {
     c->hC.lv.clear();
@@ -1325,6 +1339,293 @@ static int solve_ir(phz_ctx* c, int K, const double* b, double* x, double rtol, 
   return steps;
 }
 
+// TriCG (Sec. 2.5.2) on calA x = b in float64 for K loads in lockstep.  With
+// E = A, F = C and the coupling B^T, calA = [[E, B^T], [B, -F]] is
+// quasi-definite.  Per iteration: the tridiagonalisation step
+//   q = B^T v_k - gamma_k E u_{k-1},  p = B u_k - beta_k F v_{k-1},
+//   alpha_k = u_k . q,  q -= alpha_k E u_k,  p -= alpha_k F v_k,
+//   beta_{k+1} = sqrt(q . E^-1 q),  gamma_{k+1} = sqrt(p . F^-1 p),
+// (E^-1, F^-1 by conjugate gradients to inner_eps), then the block LDL^T
+// step of the Galerkin system [[I, T], [T^T, -I]] on the host (2 x 2 per
+// load), and one fused update of the two direction columns and the iterate
+// per block.  The residual norm after step k is
+// sqrt((z_1 ||q||)^2 + (z_0 ||p||)^2) with z the step's last solution block.
+// Cycles start from the true residual; see the header for the zero-block
+// start and the breakdown rule.
+static void solve_tricg(phz_ctx* c, int K, const double* b, double* x, double rtol, int hist_base,
+                        GmresResult& out) {
+  alloc_work<double>(c, c->w64, K, 1);
+  Work<double>& W = c->w64;
+  const long nn = c->nn;
+  hipStream_t st = c->stream;
+  const size_t nu = (size_t)nn * 3 * K, np = (size_t)nn * K;
+  for (DevBuf<double>* v : {&c->tri_u, &c->tri_Eu, &c->tri_Eup, &c->tri_q, &c->tri_Eq, &c->tri_g1x, &c->tri_g2x})
+    if (v->n < nu) v->alloc(nu);
+  for (DevBuf<double>* v : {&c->tri_v, &c->tri_Fv, &c->tri_Fvp, &c->tri_p, &c->tri_Fp, &c->tri_g1y, &c->tri_g2y})
+    if (v->n < np) v->alloc(np);
+  if (c->tri_dev.n < (size_t)(20 * K)) c->tri_dev.alloc(20 * 9);
+  double* cf = c->tri_dev.p;              // [0, 6K) update coefficients
+  double* sc = c->tri_dev.p + 6 * K;      // [6K, 8K) two per-load scale vectors
+  double* red = c->tri_dev.p + 8 * K;     // [8K, 12K) four reductions
+  // raw pointers so the rotations below are pointer swaps
+  double *u = c->tri_u.p, *Eu = c->tri_Eu.p, *Eup = c->tri_Eup.p, *q = c->tri_q.p, *Eq = c->tri_Eq.p;
+  double *v = c->tri_v.p, *Fv = c->tri_Fv.p, *Fvp = c->tri_Fvp.p, *p = c->tri_p.p, *Fp = c->tri_Fp.p;
+  double *g1x = c->tri_g1x.p, *g2x = c->tri_g2x.p, *g1y = c->tri_g1y.p, *g2y = c->tri_g2y.p;
+  double* r = c->R64.p;
+  const double* bu = b;
+  const double* bp = b + nu;
+  double* xu = x;
+  double* xp = x + nu;
+  std::vector<double> h4(4 * K), s1(K), s2(K), cfh(6 * K);
+  auto fetch = [&](int slots) {
+    PHZ_HIP(hipMemcpyAsync(h4.data(), red, (size_t)slots * K * sizeof(double), hipMemcpyDeviceToHost, st));
+    sync(c);
+  };
+  auto put = [&](double* dst, const std::vector<double>& src) {
+    PHZ_HIP(hipMemcpyAsync(dst, src.data(), src.size() * sizeof(double), hipMemcpyHostToDevice, st));
+  };
+  auto emap = [&](const double* rhs, double* sol) {
+    c->stats.inner_iters[0] += pcg_block<double>(c, c->hA, W.A, K, rhs, sol);
+    c->stats.inner_calls[0] += 1;
+  };
+  auto fmap = [&](const double* rhs, double* sol) {
+    c->stats.inner_iters[1] += pcg_block<double>(c, c->hC, W.C, K, rhs, sol);
+    c->stats.inner_calls[1] += 1;
+  };
+  col_norm2<double>(nn, 4, K, b, red, c->red_work.p, st);
+  fetch(1);
+  std::vector<double> bn(K), ru(K), rp(K);
+  for (int k = 0; k < K; ++k) bn[k] = std::sqrt(h4[k]);
+  std::vector<int> done(K, 0);
+  // r = b - calA x, per-load block norms; marks converged loads
+  auto residual = [&]() {
+    op_apply<double>(c, 0, K, x, b, r, -1.0, 1.0);
+    col_norm2<double>(nn, 3, K, r, red, c->red_work.p, st);
+    col_norm2<double>(nn, 1, K, r + nu, red + K, c->red_work.p, st);
+    fetch(2);
+    bool all = true;
+    for (int k = 0; k < K; ++k) {
+      ru[k] = std::sqrt(h4[k]);
+      rp[k] = std::sqrt(h4[K + k]);
+      out.true_rel[k] = bn[k] > 0 ? std::hypot(ru[k], rp[k]) / bn[k] : 0.0;
+      if (!std::isfinite(out.true_rel[k])) throw std::runtime_error("non-finite residual in TriCG");
+      done[k] = bn[k] == 0.0 || out.true_rel[k] <= rtol;
+      all = all && done[k];
+    }
+    return all;
+  };
+  const int max_cycles = 100;
+  int used = 0;
+  out.converged = residual();
+  for (int cyc = 0; cyc < max_cycles && !out.converged && used < c->opt.max_iters; ++cyc) {
+    for (int k = 0; k < K; ++k) out.restarts[k] += !done[k];
+    // loads whose residual has a (relatively) zero block take the shifted start
+    std::vector<double> zc(K, 0.0), zb(K, 0.0);
+    bool any_zc = false, any_zb = false;
+    const double tiny = std::min(1e-13, 0.1 * rtol);
+    for (int k = 0; k < K; ++k) {
+      if (done[k]) continue;
+      if (rp[k] <= 1e-12 * ru[k] || rp[k] <= tiny * bn[k]) zc[k] = 1.0, any_zc = true;
+      else if (ru[k] <= 1e-12 * rp[k] || ru[k] <= tiny * bn[k]) zb[k] = 1.0, any_zb = true;
+    }
+    if (any_zc) {
+      // xh = E^-1 r_u, w = B xh, y0 = F^-1 w; y += y0, or x += xh where w = 0
+      put(sc, zc);
+      scale_cols<double>(nn, 3, K, r, sc, q, st);
+      emap(q, Eq);
+      op_apply<double>(c, 2, K, Eq, (const double*)nullptr, p, 1.0, 0.0);
+      col_norm2<double>(nn, 1, K, p, red, c->red_work.p, st);
+      fetch(1);
+      for (int k = 0; k < K; ++k) {
+        s1[k] = zc[k] != 0.0 && h4[k] == 0.0 ? 1.0 : 0.0;
+        s2[k] = zc[k] != 0.0 && h4[k] != 0.0 ? 1.0 : 0.0;
+      }
+      fmap(p, Fp);
+      put(sc, s1);
+      put(sc + K, s2);
+      axpy_cols<double, double>(nn, 3, K, sc, Eq, xu, st);
+      axpy_cols<double, double>(nn, 1, K, sc + K, Fp, xp, st);
+      sync(c);
+    }
+    if (any_zb) {
+      // yh = F^-1 r_p, t = B^T yh, x0 = -E^-1 t; x += x0, or y -= yh where t = 0
+      put(sc, zb);
+      scale_cols<double>(nn, 1, K, r + nu, sc, p, st);
+      fmap(p, Fp);
+      op_apply<double>(c, 5, K, Fp, (const double*)nullptr, q, 1.0, 0.0);
+      col_norm2<double>(nn, 3, K, q, red, c->red_work.p, st);
+      fetch(1);
+      for (int k = 0; k < K; ++k) {
+        s1[k] = zb[k] != 0.0 && h4[k] != 0.0 ? -1.0 : 0.0;
+        s2[k] = zb[k] != 0.0 && h4[k] == 0.0 ? -1.0 : 0.0;
+      }
+      emap(q, Eq);
+      put(sc, s1);
+      put(sc + K, s2);
+      axpy_cols<double, double>(nn, 3, K, sc, Eq, xu, st);
+      axpy_cols<double, double>(nn, 1, K, sc + K, Fp, xp, st);
+      sync(c);
+    }
+    if (any_zc || any_zb) {
+      out.converged = residual();
+      continue;
+    }
+    // a TriCG cycle from zero on the masked residual (converged loads idle)
+    for (int k = 0; k < K; ++k) s1[k] = done[k] ? 0.0 : 1.0;
+    put(sc, s1);
+    scale_cols<double>(nn, 3, K, r, sc, Eu, st);
+    scale_cols<double>(nn, 1, K, r + nu, sc, Fv, st);
+    emap(Eu, u);
+    fmap(Fv, v);
+    col_dot<double>(nn, 3, K, Eu, u, red, c->red_work.p, st);
+    col_dot<double>(nn, 1, K, Fv, v, red + K, c->red_work.p, st);
+    fetch(2);
+    std::vector<double> beta(K), gamma(K), bmax(K), gmax(K), d(2 * K), D(4 * K), alpha(K);
+    std::vector<int> act(K, 0), first(K, 1);
+    int nact = 0;
+    for (int k = 0; k < K; ++k) {
+      beta[k] = std::sqrt(std::max(h4[k], 0.0));
+      gamma[k] = std::sqrt(std::max(h4[K + k], 0.0));
+      act[k] = !done[k] && beta[k] > 0.0 && gamma[k] > 0.0;
+      nact += act[k];
+      bmax[k] = beta[k];
+      gmax[k] = gamma[k];
+      d[2 * k] = beta[k];
+      d[2 * k + 1] = gamma[k];
+      s1[k] = act[k] ? 1.0 / beta[k] : 0.0;
+      s2[k] = act[k] ? 1.0 / gamma[k] : 0.0;
+    }
+    if (nact == 0) break;
+    put(sc, s1);
+    put(sc + K, s2);
+    scale_cols<double>(nn, 3, K, Eu, sc, Eu, st);
+    scale_cols<double>(nn, 3, K, u, sc, u, st);
+    scale_cols<double>(nn, 1, K, Fv, sc + K, Fv, st);
+    scale_cols<double>(nn, 1, K, v, sc + K, v, st);
+    fill<double>((long)nu, 0.0, Eup, st);
+    fill<double>((long)np, 0.0, Fvp, st);
+    fill<double>((long)nu, 0.0, g1x, st);
+    fill<double>((long)nu, 0.0, g2x, st);
+    fill<double>((long)np, 0.0, g1y, st);
+    fill<double>((long)np, 0.0, g2y, st);
+    sync(c);  // the host staging vectors are rewritten below
+    while (nact > 0 && used < c->opt.max_iters) {
+      // q = B^T v - gamma E u_prev, p = B u - beta F v_prev
+      for (int k = 0; k < K; ++k) {
+        s1[k] = act[k] ? -gamma[k] : 0.0;
+        s2[k] = act[k] ? -beta[k] : 0.0;
+      }
+      put(sc, s1);
+      put(sc + K, s2);
+      op_apply<double>(c, 5, K, v, (const double*)nullptr, q, 1.0, 0.0);
+      axpy_cols<double, double>(nn, 3, K, sc, Eup, q, st);
+      op_apply<double>(c, 2, K, u, (const double*)nullptr, p, 1.0, 0.0);
+      axpy_cols<double, double>(nn, 1, K, sc + K, Fvp, p, st);
+      col_dot<double>(nn, 3, K, u, q, red, c->red_work.p, st);
+      fetch(1);
+      for (int k = 0; k < K; ++k) {
+        alpha[k] = act[k] ? h4[k] : 0.0;
+        s1[k] = -alpha[k];
+      }
+      put(sc, s1);
+      axpy_cols<double, double>(nn, 3, K, sc, Eu, q, st);
+      axpy_cols<double, double>(nn, 1, K, sc, Fv, p, st);
+      emap(q, Eq);
+      fmap(p, Fp);
+      col_dot<double>(nn, 3, K, q, Eq, red, c->red_work.p, st);
+      col_dot<double>(nn, 1, K, p, Fp, red + K, c->red_work.p, st);
+      col_norm2<double>(nn, 3, K, q, red + 2 * K, c->red_work.p, st);
+      col_norm2<double>(nn, 1, K, p, red + 3 * K, c->red_work.p, st);
+      fetch(4);
+      ++used;
+      // block LDL^T step and the update coefficients, per load
+      std::vector<int> cont(K, 0);
+      for (int k = 0; k < K; ++k) {
+        double* ck = &cfh[6 * k];
+        for (int i = 0; i < 6; ++i) ck[i] = 0.0;
+        s1[k] = s2[k] = 0.0;
+        if (!act[k]) continue;
+        const double a = alpha[k];
+        double L[4] = {0.0, 0.0, 0.0, 0.0};
+        double Dn[4] = {1.0, a, a, -1.0};
+        double* dk = &d[2 * k];
+        if (!first[k]) {
+          // L = Gamma D^-1, D_new = Delta - L Gamma^T, d = -L d;  Gamma = [[0, beta], [gamma, 0]]
+          const double* Dk = &D[4 * k];
+          const double det = Dk[0] * Dk[3] - Dk[1] * Dk[2];
+          const double Di[4] = {Dk[3] / det, -Dk[1] / det, -Dk[2] / det, Dk[0] / det};
+          const double G[4] = {0.0, beta[k], gamma[k], 0.0};
+          L[0] = G[0] * Di[0] + G[1] * Di[2];
+          L[1] = G[0] * Di[1] + G[1] * Di[3];
+          L[2] = G[2] * Di[0] + G[3] * Di[2];
+          L[3] = G[2] * Di[1] + G[3] * Di[3];
+          // (L Gamma^T)_ij = sum_l L_il G_jl
+          Dn[0] -= L[0] * G[0] + L[1] * G[1];
+          Dn[1] -= L[0] * G[2] + L[1] * G[3];
+          Dn[2] -= L[2] * G[0] + L[3] * G[1];
+          Dn[3] -= L[2] * G[2] + L[3] * G[3];
+          const double d0 = -(L[0] * dk[0] + L[1] * dk[1]);
+          const double d1 = -(L[2] * dk[0] + L[3] * dk[1]);
+          dk[0] = d0;
+          dk[1] = d1;
+        }
+        first[k] = 0;
+        for (int i = 0; i < 4; ++i) D[4 * k + i] = Dn[i];
+        const double det = Dn[0] * Dn[3] - Dn[1] * Dn[2];
+        const double z0 = (Dn[3] * dk[0] - Dn[1] * dk[1]) / det;
+        const double z1 = (-Dn[2] * dk[0] + Dn[0] * dk[1]) / det;
+        ck[0] = L[0];
+        ck[1] = L[1];
+        ck[2] = L[2];
+        ck[3] = L[3];
+        ck[4] = z0;
+        ck[5] = z1;
+        out.iters[k] += 1;
+        const double est = std::hypot(z1 * std::sqrt(std::max(h4[2 * K + k], 0.0)),
+                                      z0 * std::sqrt(std::max(h4[3 * K + k], 0.0)));
+        c->hist[hist_base + k].push_back(bn[k] > 0 ? est / bn[k] : 0.0);
+        const double bnext = std::sqrt(std::max(h4[k], 0.0)), gnext = std::sqrt(std::max(h4[K + k], 0.0));
+        if (!(std::isfinite(est) && std::isfinite(z0) && std::isfinite(z1)))
+          throw std::runtime_error("TriCG: non-finite recurrence");
+        if (est <= rtol * bn[k]) continue;
+        bmax[k] = std::max(bmax[k], bnext);
+        gmax[k] = std::max(gmax[k], gnext);
+        if (!(bnext > 1e-10 * bmax[k] && gnext > 1e-10 * gmax[k])) continue;  // breakdown: the cycle ends
+        cont[k] = 1;
+        beta[k] = bnext;
+        gamma[k] = gnext;
+        s1[k] = 1.0 / bnext;
+        s2[k] = 1.0 / gnext;
+      }
+      put(cf, cfh);
+      tricg_update(nn, 3, K, cf, u, 0, g1x, g2x, xu, st);
+      tricg_update(nn, 1, K, cf, v, 1, g1y, g2y, xp, st);
+      // next basis vectors: E u_prev <- E u, E u <- q / beta, u <- E^-1 q / beta (and the same for v)
+      put(sc, s1);
+      put(sc + K, s2);
+      std::swap(Eu, Eup);
+      scale_cols<double>(nn, 3, K, q, sc, Eu, st);
+      scale_cols<double>(nn, 3, K, Eq, sc, Eq, st);
+      std::swap(u, Eq);
+      std::swap(Fv, Fvp);
+      scale_cols<double>(nn, 1, K, p, sc + K, Fv, st);
+      scale_cols<double>(nn, 1, K, Fp, sc + K, Fp, st);
+      std::swap(v, Fp);
+      sync(c);  // the host staging vectors are rewritten next iteration
+      nact = 0;
+      for (int k = 0; k < K; ++k) {
+        act[k] = cont[k];
+        nact += act[k];
+      }
+    }
+    out.converged = residual();
+  }
+  // hand the rotated buffers back to their owners
+  c->tri_u.p = u; c->tri_Eu.p = Eu; c->tri_Eup.p = Eup; c->tri_q.p = q; c->tri_Eq.p = Eq;
+  c->tri_v.p = v; c->tri_Fv.p = Fv; c->tri_Fvp.p = Fvp; c->tri_p.p = p; c->tri_Fp.p = Fp;
+  sync(c);
+}
+
 static void compute_effective(phz_ctx* c) {
   hipStream_t st = c->stream;
   const long nn = c->nn;
@@ -1425,9 +1726,11 @@ static int do_solve(phz_ctx* c) {
     fill<double>(nn * 36, 0.0, c->X.p, st);
   const double rtol = c->opt.rtol;
   bool conv = true;
+  const bool tri = c->opt.solver == PHZ_SOLVER_TRICG;
   if (c->opt.batched) {
     GmresResult g;
-    if (c->opt.precision != PHZ_FP64) c->stats.refinements = solve_ir(c, 9, c->Bvec.p, c->X.p, rtol, 0, g);
+    if (tri) solve_tricg(c, 9, c->Bvec.p, c->X.p, rtol, 0, g);
+    else if (c->opt.precision != PHZ_FP64) c->stats.refinements = solve_ir(c, 9, c->Bvec.p, c->X.p, rtol, 0, g);
     else solve_fp64(c, 9, c->Bvec.p, c->X.p, rtol, 0, g);
     for (int k = 0; k < 9; ++k) {
       c->stats.iterations[k] = g.iters[k];
@@ -1442,7 +1745,8 @@ static int do_solve(phz_ctx* c) {
       extract_column(nn, L, c->Bvec.p, c->col_b.p, st);
       extract_column(nn, L, c->X.p, c->col_x.p, st);
       GmresResult g;
-      if (c->opt.precision != PHZ_FP64) c->stats.refinements += solve_ir(c, 1, c->col_b.p, c->col_x.p, rtol, L, g);
+      if (tri) solve_tricg(c, 1, c->col_b.p, c->col_x.p, rtol, L, g);
+      else if (c->opt.precision != PHZ_FP64) c->stats.refinements += solve_ir(c, 1, c->col_b.p, c->col_x.p, rtol, L, g);
       else solve_fp64(c, 1, c->col_b.p, c->col_x.p, rtol, L, g);
       insert_column(nn, L, c->col_x.p, c->X.p, st);
       c->stats.iterations[L] = g.iters[0];
@@ -1571,7 +1875,8 @@ static int check_options(const phz_options* o, std::string& err) {
   if (o->use_graph != 0 && o->use_graph != 1) { err = "use_graph must be 0 or 1"; return PHZ_E_INVALID; }
   if (o->fine_kernel < -1 || o->fine_kernel > 2) { err = "fine_kernel must be -1, 0, 1 or 2"; return PHZ_E_INVALID; }
   if (o->coarse_kernel < -1 || o->coarse_kernel > 1) { err = "coarse_kernel must be -1, 0 or 1"; return PHZ_E_INVALID; }
-  if (o->solver != PHZ_SOLVER_SCP && o->solver != PHZ_SOLVER_DBP) { err = "solver must be PHZ_SOLVER_SCP or PHZ_SOLVER_DBP"; return PHZ_E_INVALID; }
+  if (o->solver != PHZ_SOLVER_SCP && o->solver != PHZ_SOLVER_DBP && o->solver != PHZ_SOLVER_TRICG) { err = "solver must be PHZ_SOLVER_SCP, PHZ_SOLVER_DBP or PHZ_SOLVER_TRICG"; return PHZ_E_INVALID; }
+  if (o->solver == PHZ_SOLVER_TRICG && o->precision != PHZ_FP64) { err = "TriCG runs in float64 (precision PHZ_FP64)"; return PHZ_E_INVALID; }
   if (o->inner != 0 && o->inner != 1) { err = "inner must be 0 or 1"; return PHZ_E_INVALID; }
   if (!(o->inner_eps > 0 && o->inner_eps < 1)) { err = "inner_eps must be in (0, 1)"; return PHZ_E_INVALID; }
   if (o->inner_maxit < 1) { err = "inner_maxit must be positive"; return PHZ_E_INVALID; }
@@ -2288,8 +2593,12 @@ int phz_get_kernel_timing(phz_ctx* c, char* buf, int cap, int* len) {
 }
 
 int phz_apply(phz_ctx* c, int op, int nrhs, int precision, const void* x, void* y) {
-  if (!c || !x || !y || op < 0 || op > 4 || (nrhs != 1 && nrhs != 9)) return PHZ_E_INVALID;
+  if (!c || !x || !y || op < 0 || op > 5 || (nrhs != 1 && nrhs != 9)) return PHZ_E_INVALID;
   if (!c->have_s) return PHZ_E_STATE;
+  if (op == 5 && precision == PHZ_BF16X3_IR) {
+    c->err = "B^T has no split-BF16 form";
+    return PHZ_E_INVALID;
+  }
   PHZ_GUARD_BEGIN
   if (precision == PHZ_FP64)
     op_apply<double>(c, op, nrhs, (const double*)x, (const double*)nullptr, (double*)y, 1.0, 0.0);

@@ -718,6 +718,26 @@ __global__ __launch_bounds__(256) void k_stencil_cheb(unsigned N, const double* 
   dn[co + n] = c1 * dv + c2 * rv;
 }
 
+// TriCG direction and iterate update on one block (F fields, K loads,
+// column f K + k): with the load's coefficients cf[6k..6k+5] =
+// (L00, L01, L10, L11, z0, z1) and the block's basis vector w entering the
+// first (side 0) or the second (side 1) direction column,
+//   g1 <- [side 0] w - (L00 g1 + L01 g2),  g2 <- [side 1] w - (L10 g1 + L11 g2),
+//   x  += z0 g1 + z1 g2.
+__global__ void k_tricg_update(size_t nn, size_t count, int K, const double* __restrict__ cf,
+                               const double* __restrict__ w, int side, double* __restrict__ g1,
+                               double* __restrict__ g2, double* __restrict__ x) {
+  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= count) return;
+  const double* c = cf + 6 * ((idx / nn) % K);
+  const double o1 = g1[idx], o2 = g2[idx], wv = w[idx];
+  const double n1 = (side == 0 ? wv : 0.0) - (c[0] * o1 + c[1] * o2);
+  const double n2 = (side == 1 ? wv : 0.0) - (c[2] * o1 + c[3] * o2);
+  g1[idx] = n1;
+  g2[idx] = n2;
+  x[idx] += c[4] * n1 + c[5] * n2;
+}
+
 template <typename T>
 __global__ void k_normalize_by(size_t count, const double* __restrict__ nrm2, const T* __restrict__ w,
                                T* __restrict__ v) {
@@ -937,6 +957,14 @@ int count_nonfinite(long count, const double* v, double* work, hipStream_t st) {
 void reinit_step(int N, const double* phi, const double* phi0, double dt, int subcell, double* out, hipStream_t st) {
   const size_t nn = (size_t)N * N * N;
   hipLaunchKernelGGL(k_reinit_step, dim3(blocks_for(nn, 256)), dim3(256), 0, st, (unsigned)N, phi, phi0, dt, subcell, out);
+  PHZ_LAUNCH_CHECK();
+}
+
+void tricg_update(long nn, int F, int K, const double* cf, const double* w, int side, double* g1, double* g2,
+                  double* x, hipStream_t st) {
+  const size_t count = (size_t)nn * F * K;
+  hipLaunchKernelGGL(k_tricg_update, dim3(blocks_for(count, 256)), dim3(256), 0, st, (size_t)nn, count, K, cf, w,
+                     side, g1, g2, x);
   PHZ_LAUNCH_CHECK();
 }
 

@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
 
 import synth  # noqa: E402
-from oracle import cell, foms  # noqa: E402
+from oracle import cell, fe, foms, tricg  # noqa: E402
 
 
 def case(name, n, phi=None, rho=None, mat=None):
@@ -33,8 +33,27 @@ def case(name, n, phi=None, rho=None, mat=None):
     print(name, f"{dt:.1f}s")
 
 
+def tricg_counts(cases, rtol=1e-10):
+    """TriCG iterations per load (exact block inverses, zero-block start, restarts) on the golden cells."""
+    mat = synth.material_workload()
+    M = fe.nondim_matrix(mat)
+    out = {"rtol": rtol}
+    for name, n, phi in cases:
+        t = time.perf_counter()
+        s = fe.ersatz_scale(fe.density_from_levelset(n, phi), mat.void_scale)
+        K, F = cell.assemble(n, s, M)
+        X, its = tricg.solve_tricg(K, -F, rtol=rtol)
+        MH = cell.effective_flux(n, s, M, X)
+        out[name] = {"iterations": its, "MH": MH.tolist()}
+        print(name, "tricg", its, f"{time.perf_counter() - t:.1f}s")
+    with open(os.path.join(HERE, "tricg16.json"), "w") as f:
+        json.dump(out, f, indent=1)
+
+
 if __name__ == "__main__":
     # 16^3 void sphere of radius 0.3 (signed distance), workload material
     case("sphere16", 16, phi=synth.sphere_levelset(16))
     # 16^3 Gaussian random field, seed 2410, 50% solid
     case("grf16", 16, phi=synth.grf_levelset(16, seed=2410, solid_fraction=0.5))
+    tricg_counts([("grf16", 16, synth.grf_levelset(16, seed=2410, solid_fraction=0.5)),
+                  ("sphere16", 16, synth.sphere_levelset(16))])

@@ -128,3 +128,76 @@ def test_tight_inner_maps_cut_outer_iterations(P):
             its[eps] = max(ctx.stats()["iterations"])
     print("outer iterations", its)
     assert its[1e-8] < its[1e-2]
+
+
+def test_bt_block_operator(torch_cuda, P):
+    """B^T (block 5, potential -> displacements) against the oracle's assembled coupling block, float64
+    and float32."""
+    torch = torch_cuda
+    n = 16
+    say("B^T block operator")
+    rho = synth.random_density(n, seed=93)
+    s = fe.ersatz_scale(rho, MAT.void_scale)
+    K, _ = cell.assemble(n, s, MND)
+    d = np.arange(4 * n ** 3)
+    iu, ip = d[d % 4 < 3], d[d % 4 == 3]
+    Bt = K[iu][:, ip]
+    nn = n ** 3
+    x = np.random.default_rng(6).standard_normal((nn, 9))
+    with P.Context(n, MAT, precision=P.PHZ_FP64) as ctx:
+        ctx.set_density(rho)
+        for prec, dt, tol in ((P.PHZ_FP64, torch.float64, 1e-13), (P.PHZ_FP32_IR, torch.float32, 2e-6)):
+            for nrhs in (1, 9):
+                xs = x[:, :nrhs]
+                xd = torch.tensor(to_soa(xs, nn, 1, nrhs), dtype=dt, device="cuda").contiguous()
+                xr = from_soa(xd.cpu().double().numpy(), nn, 1, nrhs)
+                yd = torch.zeros((3, nrhs, nn), dtype=dt, device="cuda")
+                ctx.apply(P.OP_BT, nrhs, prec, xd.data_ptr(), yd.data_ptr())
+                torch.cuda.synchronize()
+                y = from_soa(yd.cpu().double().numpy(), nn, 3, nrhs)
+                err = (np.abs(y - Bt @ xr) / np.maximum(abs(Bt) @ abs(xr), 1e-300)).max()
+                print("precision", prec, "columns", nrhs, "max error / term magnitude", err)
+                assert err < tol, (prec, nrhs, err)
+
+
+TRICG = json.load(open(os.path.join(HERE, "golden", "tricg16.json")))
+
+
+@pytest.mark.parametrize("name", ["grf16", "sphere16"])
+@pytest.mark.parametrize("batched", [1, 0])
+def test_tricg_solve(P, name, batched):
+    """TriCG (float64, block maps by conjugate gradients to 1e-10) reaches the oracle's direct-solve
+    tensors.  Its iterations per load are those of the oracle's TriCG with exact block inverses, up to
+    a short extra cycle: inexact maps can leave the true residual above the recurrence's at the end of
+    a cycle, and the solve then restarts from it (-2 to +5 iterations)."""
+    g = json.load(open(os.path.join(HERE, "golden", f"{name}.json")))
+    phi = synth.grf_levelset(16, seed=2410, solid_fraction=0.5) if name == "grf16" else synth.sphere_levelset(16)
+    say("TriCG", name, "batched", batched)
+    with P.Context(16, MAT, precision=P.PHZ_FP64, solver=P.PHZ_SOLVER_TRICG, inner_eps=1e-10, rtol=1e-10,
+                   batched=batched) as ctx:
+        ctx.set_levelset(phi)
+        assert ctx.solve() == P.PHZ_OK
+        st = ctx.stats()
+        print("iterations", st["iterations"], "cycles", st["restarts"], "oracle", TRICG[name]["iterations"],
+              "CG per map", [st["inner_iters"][i] / max(st["inner_calls"][i], 1) for i in range(2)])
+        MH, _ = ctx.effective_nd()
+        ref = np.array(g["MH"])
+        assert relmax(MH, ref) < 1e-8
+        assert max(st["true_residual"]) <= 1e-10
+        for got, want in zip(st["iterations"], TRICG[name]["iterations"]):
+            assert -2 <= got - want <= 5, (st["iterations"], TRICG[name]["iterations"])
+
+
+def test_tricg_loose_inner_maps(P):
+    """With block maps only to 1e-4 the cycles restart from the true residual until it reaches the
+    tolerance: the tensors still match the direct solve."""
+    g = json.load(open(os.path.join(HERE, "golden", "grf16.json")))
+    say("TriCG, inner 1e-4")
+    with P.Context(16, MAT, precision=P.PHZ_FP64, solver=P.PHZ_SOLVER_TRICG, inner_eps=1e-4, rtol=1e-10,
+                   max_iters=2000) as ctx:
+        ctx.set_levelset(synth.grf_levelset(16, seed=2410, solid_fraction=0.5))
+        assert ctx.solve() == P.PHZ_OK
+        st = ctx.stats()
+        print("iterations", st["iterations"], "cycles", st["restarts"])
+        MH, _ = ctx.effective_nd()
+        assert relmax(MH, np.array(g["MH"])) < 1e-8

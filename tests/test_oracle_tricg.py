@@ -104,3 +104,17 @@ def test_piezo_cell_matches_the_direct_solve():
     MHd = cell.effective_flux(n, s, M, Xd)
     assert np.abs(MH - MHd).max() < 1e-10 * np.abs(MHd).max()
     print("iterations per load", its)
+
+
+def test_stored_tricg_cases_match_the_direct_goldens():
+    """The stored TriCG runs (tests/golden/tricg16.json, written by make_golden.py) reach the direct
+    solves' tensors on both 16^3 cells, within at most 25 iterations per load."""
+    import json
+    import os
+    here = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+    tc = json.load(open(os.path.join(here, "tricg16.json")))
+    for name in ("grf16", "sphere16"):
+        ref = np.array(json.load(open(os.path.join(here, f"{name}.json")))["MH"])
+        MH = np.array(tc[name]["MH"])
+        assert np.abs(MH - ref).max() < 1e-9 * np.abs(ref).max(), name
+        assert max(tc[name]["iterations"]) <= 25
