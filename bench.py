@@ -97,7 +97,7 @@ def cpu_baseline(n_sample=16):
     return float(out.stdout.strip().splitlines()[-1])
 
 
-def solver_study(P, torch, synth, mat, dev):
+def solver_study(P, torch, synth, mat, dev, only=None):
     """Outer GMRES iterations, inner conjugate-gradient iterations per block
     map and times of the preconditioner forms (the analogue of the paper's
     Table 1 on one GPU: multigrid instead of algebraic multigrid inside the
@@ -106,7 +106,11 @@ def solver_study(P, torch, synth, mat, dev):
     forms = [("SCP-GMRES", P.PHZ_SOLVER_SCP, 0, None), ("SCP-GMRES", P.PHZ_SOLVER_SCP, 1, 1e-8),
              ("SCP-GMRES", P.PHZ_SOLVER_SCP, 1, 1e-4), ("SCP-GMRES", P.PHZ_SOLVER_SCP, 1, 1e-2),
              ("DBP-GMRES", P.PHZ_SOLVER_DBP, 0, None), ("DBP-GMRES", P.PHZ_SOLVER_DBP, 1, 1e-8),
-             ("DBP-GMRES", P.PHZ_SOLVER_DBP, 1, 1e-4), ("DBP-GMRES", P.PHZ_SOLVER_DBP, 1, 1e-2)]
+             ("DBP-GMRES", P.PHZ_SOLVER_DBP, 1, 1e-4), ("DBP-GMRES", P.PHZ_SOLVER_DBP, 1, 1e-2),
+             ("TriCG", P.PHZ_SOLVER_TRICG, 1, 1e-8), ("TriCG", P.PHZ_SOLVER_TRICG, 1, 1e-4),
+             ("TriCG", P.PHZ_SOLVER_TRICG, 1, 1e-2)]
+    if only:
+        forms = [f for f in forms if f[0] in only]
     rows = []
     for n in (64, 128):
         phi = torch.tensor(synth.paper_levelset(n), device=dev)
@@ -129,6 +133,7 @@ def solver_study(P, torch, synth, mat, dev):
             rows.append({"n": n, "dofs": 4 * n ** 3, "solver": name,
                          "block_maps": "V-cycles (A 2, potential 1)" if not inner else f"CG to {eps:g}",
                          "status": status, "outer_iters_load0": st["iterations"][0],
+                         "cycles_max": max(st["restarts"]) if solver == P.PHZ_SOLVER_TRICG else None,
                          "outer_iters_max": max(st["iterations"]),
                          "cg_iters_per_A_map": st["inner_iters"][0] / calls[0] if calls[0] else None,
                          "cg_iters_per_potential_map": st["inner_iters"][1] / calls[1] if calls[1] else None,
@@ -223,6 +228,8 @@ def main():
                          "(-1 = timed choice); for profiling runs whose timing would change the choice")
     ap.add_argument("--block-tiles", default=None, metavar="T0,T1,T2,T3",
                     help="pin the element-contraction tile per fine block (-1 = timed choice)")
+    ap.add_argument("--solver-study-only", default=None, metavar="NAMES",
+                    help="comma-separated subset of SCP-GMRES, DBP-GMRES, TriCG for --solver-study")
     ap.add_argument("--solver-study", action="store_true",
                     help="instead of the step benchmark: the solver comparison of Sec. 2.5 (SCP-GMRES and DBP-GMRES, "
                          "fixed V-cycle block maps or conjugate-gradient maps to 1e-8, 1e-4, 1e-2) on the paper's test "
@@ -311,7 +318,8 @@ def main():
         return dt / steps, st, tens, f
 
     if args.solver_study:
-        print(json.dumps(solver_study(P, torch, synth, mat, dev)))
+        only = args.solver_study_only.split(",") if args.solver_study_only else None
+        print(json.dumps(solver_study(P, torch, synth, mat, dev, only)))
         return
     if args.optimise:
         print(json.dumps(optimisation_run(P, torch, synth, args.opt_n, args.optimise, prec, args.optimise_problem,
