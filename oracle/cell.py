@@ -40,19 +40,26 @@ def element_dofs(n):
 
 
 def assemble(n, s, M, npts=2):
-    """Global K (CSR, 4n^3 square) and F (dense 4n^3 x 9) for scales s."""
+    """Global K (CSR, 4n^3 square) and F (dense 4n^3 x 9) for scales s: one per element (n^3,), or
+    one per element and Gauss point (n^3, npts^3) for the quadrature-point material."""
     h = 1.0 / n
-    Ke, Fe = fe.element_matrices(M, h, npts)
+    s = np.asarray(s, dtype=np.float64)
     dofs = element_dofs(n)
     ne = n ** 3
     nd = 4 * ne
     rows = np.repeat(dofs, 32, axis=1).ravel()
     cols = np.tile(dofs, (1, 32)).ravel()
-    vals = (np.asarray(s)[:, None] * Ke.ravel()[None, :]).ravel()
+    if s.ndim == 1:
+        Ke, Fe = fe.element_matrices(M, h, npts)
+        vals = (s[:, None] * Ke.ravel()[None, :]).ravel()
+        contrib = s[:, None, None] * Fe[None, :, :]
+    else:
+        Kq, Fq = fe.element_matrices_qp(M, h, npts)
+        vals = np.einsum("eq,qij->eij", s, Kq).ravel()
+        contrib = np.einsum("eq,qil->eil", s, Fq)
     K = sp.coo_matrix((vals, (rows, cols)), shape=(nd, nd)).tocsr()
     K.sum_duplicates()
     F = np.zeros((nd, 9))
-    contrib = np.asarray(s)[:, None, None] * Fe[None, :, :]
     np.add.at(F, dofs.ravel(), contrib.reshape(-1, 9))
     return K, F
 
@@ -114,17 +121,23 @@ def _gauss_g(n, X, npts=2):
     return g, w
 
 
+def _point_scales(s, nq):
+    """Scales per (element, Gauss point): per-element scales repeat at every point."""
+    s = np.asarray(s, dtype=np.float64)
+    return np.repeat(s[:, None], nq, axis=1) if s.ndim == 1 else s
+
+
 def effective_flux(n, s, M, X, npts=2):
-    """M^H[:, L] = sum_e s_e sum_q w_q M (e_L + B_q x_e^L)  (mean generalised stress)."""
+    """M^H[:, L] = sum_e sum_q w_q s_eq M (e_L + B_q x_e^L)  (mean generalised stress)."""
     g, w = _gauss_g(n, X, npts)
-    mean_g = np.einsum("q,e,qeal->al", w, np.asarray(s), g)
+    mean_g = np.einsum("q,eq,qeal->al", w, _point_scales(s, len(w)), g)
     return M @ mean_g
 
 
 def effective_energy(n, s, M, X, npts=2):
-    """M^H_en[K, L] = sum_e s_e sum_q w_q (e_K + B x^K) . M (e_L + B x^L)."""
+    """M^H_en[K, L] = sum_e sum_q w_q s_eq (e_K + B x^K) . M (e_L + B x^L)."""
     g, w = _gauss_g(n, X, npts)
-    return np.einsum("q,e,qeak,ab,qebl->kl", w, np.asarray(s), g, M, g, optimize=True)
+    return np.einsum("q,eq,qeak,ab,qebl->kl", w, _point_scales(s, len(w)), g, M, g, optimize=True)
 
 
 def element_energy_matrices(n, X, M, npts=2):
@@ -146,16 +159,18 @@ class Result(dict):
     __getattr__ = dict.__getitem__
 
 
-def homogenise(n, mat, phi=None, rho=None, width_elems=2.0, solver="lu", want_x=True):
+def homogenise(n, mat, phi=None, rho=None, width_elems=2.0, solver="lu", want_x=True, smoothing="element"):
     """Full oracle pipeline for one cell: density -> solve -> tensors.
 
-    Give either the nodal level set phi (length n^3) or per-element rho.
+    Give either the nodal level set phi (length n^3) or per-element rho.  smoothing = "qp" evaluates
+    the smoothed Heaviside at every Gauss point of the level set's trilinear interpolation (rho and s
+    then have one value per element and point).
     Returns a dict with s, rho, X (4n^3 x 9, node-major dofs 4*node + f),
     MH (non-dimensional flux form), MH_energy, and SI tensors C, e, kappa.
     """
     M = fe.nondim_matrix(mat)
     if rho is None:
-        rho = fe.density_from_levelset(n, phi, width_elems)
+        rho = fe.density_qp(n, phi, width_elems) if smoothing == "qp" else fe.density_from_levelset(n, phi, width_elems)
     s = fe.ersatz_scale(rho, mat.void_scale)
     K, F = assemble(n, s, M)
     if solver == "lu":

@@ -69,6 +69,11 @@ def shape_grads(xi):
     return G
 
 
+def shape_values(xi):
+    """Values (8,) of the trilinear shape functions on [0,1]^3 at xi."""
+    return np.array([np.prod([xi[d] if LOCAL[l, d] else 1.0 - xi[d] for d in range(3)]) for l in range(8)])
+
+
 def bmat(xi, h):
     """9x32 map from element dofs (4l + f, f = ux, uy, uz, phi) to g at xi."""
     G = shape_grads(xi) / h            # physical gradients
@@ -126,6 +131,16 @@ def element_matrices(M, h, npts=2):
     return K, F
 
 
+def element_matrices_qp(M, h, npts=2):
+    """The terms of element_matrices per Gauss point: K_q = w_q B_q^T M B_q (q, 32, 32) and
+    F_q = w_q B_q^T M (q, 32, 9), so that an element whose material is s_q M at point q has matrices
+    sum_q s_q K_q and sum_q s_q F_q (the quadrature-point interpolation of the material)."""
+    Bs, w = element_bmats(h, npts)
+    K = np.einsum("q,qai,ab,qbj->qij", w, Bs, M, Bs)
+    F = np.einsum("q,qai,ab->qib", w, Bs, M)
+    return K, F
+
+
 # ---------------------------------------------------------------- density
 def smoothed_heaviside(t, eta):
     """Sinusoidal smoothed Heaviside of half-width eta (Sec. 2.6 smoothing)."""
@@ -159,6 +174,22 @@ def density_from_levelset(n, phi, width_elems=2.0):
     """rho_e = 1 - H_eta(mean_e phi) with eta = width_elems * h (phi < 0 solid)."""
     eta = width_elems / n
     return 1.0 - smoothed_heaviside(element_mean(n, phi), eta)
+
+
+def levelset_at_gauss(n, phi, npts=2):
+    """Trilinear interpolation of the nodal level set at every element's Gauss points: (n^3, npts^3),
+    points in gauss_rule's order."""
+    pts, _ = gauss_rule(npts)
+    f = np.asarray(phi, dtype=np.float64).reshape(n, n, n)     # [k][j][i]
+    corner = [np.roll(f, shift=(-c, -b, -a), axis=(0, 1, 2)).ravel() for a, b, c in LOCAL]
+    Nv = np.array([shape_values(p) for p in pts])                # (q, 8)
+    return np.stack(corner, axis=1) @ Nv.T                        # (ne, q)
+
+
+def density_qp(n, phi, width_elems=2.0, npts=2):
+    """rho at each Gauss point, 1 - H_eta(phi interpolated there): the smoothing evaluated at the
+    quadrature points instead of once per element (phi < 0 solid)."""
+    return 1.0 - smoothed_heaviside(levelset_at_gauss(n, phi, npts), width_elems / n)
 
 
 def ersatz_scale(rho, void_scale):

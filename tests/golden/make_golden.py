@@ -17,10 +17,10 @@ import synth  # noqa: E402
 from oracle import cell, fe, foms, tricg  # noqa: E402
 
 
-def case(name, n, phi=None, rho=None, mat=None):
+def case(name, n, phi=None, rho=None, mat=None, smoothing="element"):
     mat = mat or synth.material_workload()
     t = time.perf_counter()
-    r = cell.homogenise(n, mat, phi=phi, rho=rho, want_x=False)
+    r = cell.homogenise(n, mat, phi=phi, rho=rho, want_x=False, smoothing=smoothing)
     dt = time.perf_counter() - t
     out = {
         "name": name, "n": n, "oracle_seconds": dt,
@@ -55,5 +55,8 @@ if __name__ == "__main__":
     case("sphere16", 16, phi=synth.sphere_levelset(16))
     # 16^3 Gaussian random field, seed 2410, 50% solid
     case("grf16", 16, phi=synth.grf_levelset(16, seed=2410, solid_fraction=0.5))
+    # the same two cells with the smoothing at the quadrature points
+    case("sphere16_qp", 16, phi=synth.sphere_levelset(16), smoothing="qp")
+    case("grf16_qp", 16, phi=synth.grf_levelset(16, seed=2410, solid_fraction=0.5), smoothing="qp")
     tricg_counts([("grf16", 16, synth.grf_levelset(16, seed=2410, solid_fraction=0.5)),
                   ("sphere16", 16, synth.sphere_levelset(16))])
