@@ -101,6 +101,20 @@ extern "C" {
                             ends the cycle.  stats: iterations = TriCG
                             iterations, restarts = cycles                    */
 
+/* smoothing of the material near the interface (phz_options.smoothing;
+ * Sec. 2.6: within two elements of the zero level set) */
+#define PHZ_SMOOTH_ELEMENT 0 /* once per element, at the mean of its 8 nodal
+                                phi (default)                               */
+#define PHZ_SMOOTH_QP 1      /* at each of the element's 8 Gauss points, on
+                                the trilinear interpolation of phi: the
+                                operator, loads and tensors use the point
+                                scales; the preconditioner (multigrid, S_bar,
+                                the split-BF16 blocks) their element means.
+                                Not with TriCG; phz_backward and
+                                phz_levelset_gradient return PHZ_E_INVALID.
+                                A cell given by densities has equal point
+                                scales (the element form)                   */
+
 /* operator blocks for phz_apply (Sec. 2.5 block structure) */
 #define PHZ_OP_FULL 0    /* calA = [[A, B^T], [B, -C]] on [n][4][k]        */
 #define PHZ_OP_A 1       /* A (elasticity) on [n][3][k]                    */
@@ -198,6 +212,9 @@ typedef struct {
                                solution, kept on the device across geometry
                                changes (an optimisation loop's next cell is
                                close to the last); 0 (default) from zero     */
+    int smoothing;          /* PHZ_SMOOTH_ELEMENT (default) or PHZ_SMOOTH_QP;
+                               a change recomputes the current geometry's
+                               scales                                        */
 } phz_options;
 
 typedef struct {
@@ -274,7 +291,8 @@ int phz_get_stats(phz_ctx* ctx, phz_stats* st);
 int phz_get_solution(phz_ctx* ctx, double* X, int on_device);
 /* Warm start for the next solve, same layout; NULL clears it. */
 int phz_set_initial_guess(phz_ctx* ctx, const double* X, int on_device);
-/* Load vectors b = -sum_e s_e F0 e_L, [N^3][4][9] non-dimensional. */
+/* Load vectors b = -sum_e s_e F0 e_L (with PHZ_SMOOTH_QP
+ * -sum_e sum_p s_ep F0_p e_L), [N^3][4][9] non-dimensional. */
 int phz_get_rhs(phz_ctx* ctx, double* b, int on_device);
 
 /* Figures of merit (Sec. 2.3) of SI tensors and their gradients with respect

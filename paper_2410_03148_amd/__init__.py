@@ -24,6 +24,7 @@ PHZ_FP64 = 0
 PHZ_FP32_IR = 1
 PHZ_BF16X3_IR = 2
 PHZ_SOLVER_SCP, PHZ_SOLVER_DBP, PHZ_SOLVER_TRICG = 0, 1, 2
+PHZ_SMOOTH_ELEMENT, PHZ_SMOOTH_QP = 0, 1
 OP_FULL, OP_A, OP_B, OP_SBAR, OP_C, OP_BT = 0, 1, 2, 3, 4, 5
 
 
@@ -41,7 +42,7 @@ class phz_options(C.Structure):
                 ("elem_tile", C.c_int), ("use_graph", C.c_int), ("fine_kernel", C.c_int),
                 ("block_kernel", C.c_int * 4), ("block_tile", C.c_int * 4), ("coarse_kernel", C.c_int),
                 ("solver", C.c_int), ("inner", C.c_int), ("inner_eps", C.c_double), ("inner_maxit", C.c_int),
-                ("warm_start", C.c_int)]
+                ("warm_start", C.c_int), ("smoothing", C.c_int)]
 
 
 def _set_option(o, k, v):

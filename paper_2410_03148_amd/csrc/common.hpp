@@ -56,6 +56,12 @@ template <typename T>
 void fine_apply(int op, int nrhs, int N, const T* s, const T* kref, const T* x, const OpArgs<T>& a,
                 bool cheby, hipStream_t st);
 
+// The full operator (4 x 4 fields) with the material interpolated at the
+// quadrature points: point scales sq[8 e + p], per-point reference terms
+// kq[p][32 x 32]; nrhs in {1, 9}
+template <typename T>
+void fine_apply_qp(int nrhs, int N, const T* sq, const T* kq, const T* x, const OpArgs<T>& a, hipStream_t st);
+
 // The float32 fine-level gather with the workgroup's input tile (16 x 4 x 4
 // nodes and a one-node halo, all columns) staged in LDS; nine columns, N a
 // multiple of 16 (fine_tiled_fits).
@@ -206,6 +212,16 @@ void density_to_scale(long nn, const double* rho, double void_scale, double* s, 
                       hipStream_t st);
 // b[(f*9 + L)][n] = -sum_e s_e F0 e_L; absval: sum_e s_e |F0| (a magnitude reference)
 void build_rhs(int N, const double* s, const double* F0, double* b, hipStream_t st, bool absval = false);
+// quadrature-point smoothing: point scales sq[8 e + p] (p = i + 2j + 4k) and
+// their element means; point scales from element scales; the load vectors
+// from point scales and the per-point terms F0q[p][32 x 9]
+void levelset_to_scale_qp(int N, const double* phi, double eta, double void_scale, double* rho, double* s,
+                          float* s32, double* sq, float* sq32, hipStream_t st);
+void point_scales(long nn, const double* s, double* sq, float* sq32, hipStream_t st);
+void build_rhs_qp(int N, const double* sq, const double* F0q, double* b, hipStream_t st, bool absval = false);
+// as reduce_effective (out[l*36 + col] only) with the scales of point p
+void reduce_effective_point(int N, const double* sq, int p, const double* X, double* out, double* work,
+                            hipStream_t st);
 // out[l*36 + f*9 + L] = sum_e s_e x_{node(e,l)}[f][L]; out[288] = sum_e s_e
 void reduce_effective(int N, const double* s, const double* X, double* out, double* work,
                       hipStream_t st);

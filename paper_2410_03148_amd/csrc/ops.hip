@@ -161,6 +161,59 @@ __global__ __launch_bounds__(128) void k_fine_apply(unsigned N, const T* __restr
   epilogue<T, FO, K, CHEBY>(n, nn, acc, a);
 }
 
+// The full operator with the material interpolated at the quadrature points:
+// the block of neighbour m sums, over the elements shared with node n and
+// their eight Gauss points p, sq[8 e + p] K0q[p] (the per-point reference
+// terms, read through the caches: every lane reads the same coefficient).
+template <typename T, int K>
+__global__ __launch_bounds__(128) void k_fine_apply_qp(unsigned N, const T* __restrict__ sq, const T* __restrict__ kq,
+                                                       const T* __restrict__ x, OpArgs<T> a) {
+  const unsigned nn = N * N * N;
+  const unsigned n = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+  if (n >= nn) return;
+  const NodeIdx q = node_idx(n, N);
+  unsigned ec[8];  // element whose corner c is this node (origin n - c)
+#pragma unroll
+  for (int c = 0; c < 8; ++c) ec[c] = nb_node(q, N, -(c & 1), -((c >> 1) & 1), -((c >> 2) & 1));
+  T acc[4 * K];
+#pragma unroll
+  for (int t = 0; t < 4 * K; ++t) acc[t] = T(0);
+#pragma unroll 1
+  for (int d = 0; d < 27; ++d) {
+    const int dx = d % 3 - 1, dy = (d / 3) % 3 - 1, dz = d / 9 - 1;
+    const unsigned m = nb_node(q, N, dx, dy, dz);
+    T xv[4 * K];
+#pragma unroll
+    for (int col = 0; col < 4 * K; ++col) xv[col] = x[(size_t)col * nn + m];
+    T blk[16];
+#pragma unroll
+    for (int t = 0; t < 16; ++t) blk[t] = T(0);
+#pragma unroll 1
+    for (int c = 0; c < 8; ++c) {
+      const int mx = (c & 1) + dx, my = ((c >> 1) & 1) + dy, mz = ((c >> 2) & 1) + dz;
+      if (mx < 0 || mx > 1 || my < 0 || my > 1 || mz < 0 || mz > 1) continue;
+      const int lm = mx + 2 * my + 4 * mz;
+      const T* sp = sq + (size_t)ec[c] * 8;
+#pragma unroll 1
+      for (int p = 0; p < 8; ++p) {
+        const T sv = sp[p];
+        const T* kr = kq + p * 1024 + (c * 4) * 32 + lm * 4;
+#pragma unroll
+        for (int fo = 0; fo < 4; ++fo)
+#pragma unroll
+          for (int fi = 0; fi < 4; ++fi) blk[fo * 4 + fi] += sv * kr[fo * 32 + fi];
+      }
+    }
+#pragma unroll
+    for (int fi = 0; fi < 4; ++fi)
+#pragma unroll
+      for (int kk = 0; kk < K; ++kk)
+#pragma unroll
+        for (int fo = 0; fo < 4; ++fo) acc[fo * K + kk] += blk[fo * 4 + fi] * xv[fi * K + kk];
+  }
+  epilogue<T, 4, K, false>(n, nn, acc, a);
+}
+
 // ---------------------------------------------------------------------------
 // LDS-tiled variant of the float32 gather (nine load columns).  A workgroup
 // owns a GTX x GTY x GTZ tile of 256 output nodes (one per thread) and first
@@ -754,6 +807,19 @@ void fine_apply(int op, int nrhs, int N, const T* s, const T* kref, const T* x, 
   PHZ_LAUNCH_CHECK();
 }
 
+template <typename T>
+void fine_apply_qp(int nrhs, int N, const T* sq, const T* kq, const T* x, const OpArgs<T>& a, hipStream_t st) {
+  const size_t nn = (size_t)N * N * N;
+  const unsigned g = blocks_for(nn, 128);
+  if (nrhs == 1)
+    hipLaunchKernelGGL((k_fine_apply_qp<T, 1>), dim3(g), dim3(128), 0, st, (unsigned)N, sq, kq, x, a);
+  else if (nrhs == 9)
+    hipLaunchKernelGGL((k_fine_apply_qp<T, 9>), dim3(g), dim3(128), 0, st, (unsigned)N, sq, kq, x, a);
+  else
+    throw std::invalid_argument("fine_apply_qp nrhs");
+  PHZ_LAUNCH_CHECK();
+}
+
 bool fine_tiled_fits(int N) { return N >= GTX && N % GTX == 0 && N % GTY == 0 && N % GTZ == 0; }
 
 void fine_apply_tiled(int op, int nrhs, int N, const float* s, const float* kref, const float* x,
@@ -864,6 +930,7 @@ void dense_apply(int F, int nc, int nrhs, const double* Minv, const T* r, T* z, 
 
 #define PHZ_INST(T)                                                                                            \
   template void fine_apply<T>(int, int, int, const T*, const T*, const T*, const OpArgs<T>&, bool, hipStream_t); \
+  template void fine_apply_qp<T>(int, int, const T*, const T*, const T*, const OpArgs<T>&, hipStream_t); \
   template void coarse_apply<T>(int, int, int, const T*, const T*, const OpArgs<T>&, bool, hipStream_t);         \
   template void cheby_first<T>(int, int, long, const T*, const T*, T*, T*, const T*, int, hipStream_t);               \
   template void restrict_fw<T>(int, int, int, const T*, T*, hipStream_t);                                     \

@@ -35,6 +35,11 @@ struct RefElement {
   double S0[8 * 8];      // (l, l')
   double C0[8 * 8];      // (l, l'): the dielectric block; the operator's (phi, phi) block is -C0
   double Kfull[32 * 32]; // same as K0 (4l+f, 4l'+f'), kept for clarity
+  // the quadrature terms of K0 and F0 per Gauss point q = i + 2j + 4k (points
+  // (g_i, g_j, g_k)): an element whose material is s_q M at point q has
+  // matrices sum_q s_q K0q[q] and sum_q s_q F0q[q]
+  double K0q[8][32 * 32];
+  double F0q[8][32 * 9];
 };
 
 inline void build_material_matrix(const phz_material& m, double* M) {
@@ -112,6 +117,10 @@ inline RefElement build_ref_element(const phz_material& mat, double h, double de
   const double w = h * h * h / 8.0;
   for (int i = 0; i < 32 * 32; ++i) R.K0[i] = 0.0;
   for (int i = 0; i < 32 * 9; ++i) R.F0[i] = 0.0;
+  for (int q = 0; q < 8; ++q) {
+    for (int i = 0; i < 32 * 32; ++i) R.K0q[q][i] = 0.0;
+    for (int i = 0; i < 32 * 9; ++i) R.F0q[q][i] = 0.0;
+  }
   double B[9 * 32], MB[9 * 32];
   for (int q = 0; q < 8; ++q) {
     double xi[3] = {gp[q & 1], gp[(q >> 1) & 1], gp[(q >> 2) & 1]};
@@ -127,11 +136,13 @@ inline RefElement build_ref_element(const phz_material& mat, double h, double de
         double v = 0.0;
         for (int a = 0; a < 9; ++a) v += B[a * 32 + i] * MB[a * 32 + j];
         R.K0[i * 32 + j] += w * v;
+        R.K0q[q][i * 32 + j] = w * v;
       }
       for (int L = 0; L < 9; ++L) {
         double v = 0.0;
         for (int a = 0; a < 9; ++a) v += B[a * 32 + i] * R.M[a * 9 + L];
         R.F0[i * 9 + L] += w * v;
+        R.F0q[q][i * 9 + L] = w * v;
       }
     }
   }
@@ -140,6 +151,10 @@ inline RefElement build_ref_element(const phz_material& mat, double h, double de
     for (int j = i + 1; j < 32; ++j) {
       double v = 0.5 * (R.K0[i * 32 + j] + R.K0[j * 32 + i]);
       R.K0[i * 32 + j] = R.K0[j * 32 + i] = v;
+      for (int q = 0; q < 8; ++q) {
+        double vq = 0.5 * (R.K0q[q][i * 32 + j] + R.K0q[q][j * 32 + i]);
+        R.K0q[q][i * 32 + j] = R.K0q[q][j * 32 + i] = vq;
+      }
     }
   for (int i = 0; i < 32 * 32; ++i) R.Kfull[i] = R.K0[i];
   for (int l = 0; l < 8; ++l)

@@ -133,6 +133,9 @@ struct phz_ctx {
   // block, a 1 -> 1 block like S_bar, used by the block-diagonal
   // preconditioner)
   phz::DevBuf<double> kref_full, kref_A, kref_B, kref_S, kref_C, kref_BT, F0d;
+  // quadrature-point smoothing: per-point reference terms and point scales
+  phz::DevBuf<double> kq64, f0q, sq;
+  phz::DevBuf<float> kq32, sq32;
   phz::DevBuf<float> kref32_full, kref32_A, kref32_B, kref32_S, kref32_C, kref32_BT;
   // split-BF16 MFMA operands of the five fine blocks, the tile choice of the
   // four block shapes (-1 not yet chosen, -2 none divides N), and the kernel
@@ -249,6 +252,8 @@ static void upload_reference(phz_ctx* c) {
     for (int f = 0; f < 3; ++f)
       for (int m = 0; m < 8; ++m) BT[(cn * 3 + f) * 8 + m] = R.B0[m * 24 + cn * 3 + f];
   c->kref_BT.upload(BT, 24 * 8, st);
+  c->kq64.upload(&R.K0q[0][0], 8 * 1024, st);
+  c->f0q.upload(&R.F0q[0][0], 8 * 288, st);
   sync(c);
   c->F0d.upload(R.F0, 32 * 9, st);
   std::vector<float> f(32 * 32);
@@ -263,6 +268,12 @@ static void upload_reference(phz_ctx* c) {
   up32(c->kref32_S, R.S0, 8 * 8);
   up32(c->kref32_C, R.C0, 8 * 8);
   up32(c->kref32_BT, BT, 24 * 8);
+  {
+    std::vector<float> kq(8 * 1024);
+    for (int i = 0; i < 8 * 1024; ++i) kq[i] = (float)(&R.K0q[0][0])[i];
+    c->kq32.upload(kq.data(), kq.size(), st);
+    sync(c);
+  }
   std::vector<unsigned short> ops(2048);
   const double* krefs[5] = {R.K0, R.A0, R.B0, R.S0, R.C0};
   for (int op = 0; op < 5; ++op) {
@@ -583,9 +594,26 @@ static int fine_kind_of(phz_ctx* c, int op) {
 // fine-level operator launch with optional timing
 // (blk: reference block 0..4; launches use its shape, whose kernel and tile
 // choices it shares)
+template <typename T> static const T* sq_of(phz_ctx* c);
+template <> const double* sq_of<double>(phz_ctx* c) { return c->sq.p; }
+template <> const float* sq_of<float>(phz_ctx* c) { return c->sq32.p; }
+template <typename T> static const T* kq_of(phz_ctx* c);
+template <> const double* kq_of<double>(phz_ctx* c) { return c->kq64.p; }
+template <> const float* kq_of<float>(phz_ctx* c) { return c->kq32.p; }
+
 template <typename T>
 static void op_apply_args(phz_ctx* c, int blk, int K, const T* x, const OpArgs<T>& a, bool cheby) {
   const int op = shape_of(blk);
+  if (blk == 0 && c->opt.smoothing == PHZ_SMOOTH_QP) {
+    // the full operator with the material at the quadrature points (the
+    // preconditioner's blocks keep the element means)
+    if (cheby) throw std::logic_error("no smoothing step on the full operator");
+    const long slot = time_begin(c, sizeof(T) == 4 ? (K == 9 ? "fineqp_full_k9_f32" : "fineqp_full_k1_f32")
+                                                   : (K == 9 ? "fineqp_full_k9_f64" : "fineqp_full_k1_f64"));
+    fine_apply_qp<T>(K, c->N, sq_of<T>(c), kq_of<T>(c), x, a, c->stream);
+    time_end(c, slot);
+    return;
+  }
   if constexpr (std::is_same<T, float>::value) {
     if (K == 9 && op <= 3) {
       const int kind = fine_kind_of(c, op);
@@ -1649,6 +1677,24 @@ static void compute_effective(phz_ctx* c) {
         for (int f = 0; f < 4; ++f) v += R.F0[(4 * l + f) * 9 + K] * red[l * 36 + f * 9 + L];
       FY[K * 9 + L] = v;
     }
+  if (c->opt.smoothing == PHZ_SMOOTH_QP) {
+    // F0^T sum_e s_e X_e becomes sum_p F0q[p]^T sum_e s_ep X_e (the <s> M term
+    // is unchanged: the element scale is the mean of the point scales)
+    for (int i = 0; i < 81; ++i) FY[i] = 0.0;
+    std::vector<double> rp(288);
+    for (int p = 0; p < 8; ++p) {
+      reduce_effective_point(c->N, c->sq.p, p, c->X.p, out, c->red_work.p, st);
+      PHZ_HIP(hipMemcpyAsync(rp.data(), out, 288 * sizeof(double), hipMemcpyDeviceToHost, st));
+      sync(c);
+      for (int K = 0; K < 9; ++K)
+        for (int L = 0; L < 9; ++L) {
+          double v = 0.0;
+          for (int l = 0; l < 8; ++l)
+            for (int f = 0; f < 4; ++f) v += R.F0q[p][(4 * l + f) * 9 + K] * rp[l * 36 + f * 9 + L];
+          FY[K * 9 + L] += v;
+        }
+    }
+  }
   for (int K = 0; K < 9; ++K)
     for (int L = 0; L < 9; ++L) c->MH[K * 9 + L] = h3 * ssum * R.M[K * 9 + L] + FY[K * 9 + L];
   // energy form: <s>M + FY + FY^T + X^T calA X
@@ -1679,11 +1725,14 @@ static void compute_effective(phz_ctx* c) {
 static void prepare_rhs(phz_ctx* c) {
   hipStream_t st = c->stream;
   const long nn = c->nn;
-  build_rhs(c->N, c->s.p, c->F0d.p, c->R64.p, st, true);
+  const bool qp = c->opt.smoothing == PHZ_SMOOTH_QP;
+  if (qp) build_rhs_qp(c->N, c->sq.p, c->f0q.p, c->R64.p, st, true);
+  else build_rhs(c->N, c->s.p, c->F0d.p, c->R64.p, st, true);
   double* nb = c->small.p;
   double* nref = c->small.p + 16;
   col_norm2<double>(nn, 4, 9, c->R64.p, nref, c->red_work.p, st);
-  build_rhs(c->N, c->s.p, c->F0d.p, c->Bvec.p, st, false);
+  if (qp) build_rhs_qp(c->N, c->sq.p, c->f0q.p, c->Bvec.p, st, false);
+  else build_rhs(c->N, c->s.p, c->F0d.p, c->Bvec.p, st, false);
   field_sums<double>(nn, 4, 9, c->Bvec.p, c->small.p + 32, c->red_work.p, st);
   subtract_mean<double>(nn, 4, 9, c->small.p + 32, c->Bvec.p, st);
   col_norm2<double>(nn, 4, 9, c->Bvec.p, nb, c->red_work.p, st);
@@ -1807,6 +1856,29 @@ static bool inv_general(int n, const double* A, double* out) {
   return true;
 }
 
+// Element scales from the level set, and with quadrature-point smoothing the
+// point scales (the element scales are then their means, used by the
+// preconditioner)
+static void update_scales(phz_ctx* c) {
+  const double eta = c->opt.smooth_width / c->N;
+  if (c->opt.smoothing == PHZ_SMOOTH_QP) {
+    if (c->sq.n < (size_t)c->nn * 8) c->sq.alloc((size_t)c->nn * 8);
+    if (c->sq32.n < (size_t)c->nn * 8) c->sq32.alloc((size_t)c->nn * 8);
+    levelset_to_scale_qp(c->N, c->phi.p, eta, c->mat.void_scale, c->rho.p, c->s.p, c->s32.p, c->sq.p, c->sq32.p,
+                         c->stream);
+  } else {
+    levelset_to_scale(c->N, c->phi.p, eta, c->mat.void_scale, c->rho.p, c->s.p, c->s32.p, c->stream);
+  }
+}
+
+// point scales equal to the element scales (a cell given by densities)
+static void fill_point_scales(phz_ctx* c) {
+  if (c->opt.smoothing != PHZ_SMOOTH_QP) return;
+  if (c->sq.n < (size_t)c->nn * 8) c->sq.alloc((size_t)c->nn * 8);
+  if (c->sq32.n < (size_t)c->nn * 8) c->sq32.alloc((size_t)c->nn * 8);
+  point_scales(c->nn, c->s.p, c->sq.p, c->sq32.p, c->stream);
+}
+
 }  // namespace phz
 
 using namespace phz;
@@ -1856,6 +1928,7 @@ void phz_default_options(phz_options* o) {
   o->inner_eps = 1e-2;
   o->inner_maxit = 200;
   o->warm_start = 0;
+  o->smoothing = PHZ_SMOOTH_ELEMENT;
 }
 
 const char* phz_strerror(int status) {
@@ -1881,6 +1954,8 @@ static int check_options(const phz_options* o, std::string& err) {
   if (!(o->inner_eps > 0 && o->inner_eps < 1)) { err = "inner_eps must be in (0, 1)"; return PHZ_E_INVALID; }
   if (o->inner_maxit < 1) { err = "inner_maxit must be positive"; return PHZ_E_INVALID; }
   if (o->warm_start != 0 && o->warm_start != 1) { err = "warm_start must be 0 or 1"; return PHZ_E_INVALID; }
+  if (o->smoothing != PHZ_SMOOTH_ELEMENT && o->smoothing != PHZ_SMOOTH_QP) { err = "smoothing must be PHZ_SMOOTH_ELEMENT or PHZ_SMOOTH_QP"; return PHZ_E_INVALID; }
+  if (o->smoothing == PHZ_SMOOTH_QP && o->solver == PHZ_SOLVER_TRICG) { err = "TriCG applies the element-smoothed blocks; use SCP or DBP with smoothing = PHZ_SMOOTH_QP"; return PHZ_E_INVALID; }
   for (int op = 0; op < 4; ++op) {
     if (o->block_kernel[op] < -1 || o->block_kernel[op] > 2) { err = "block_kernel entries must be -1, 0, 1 or 2"; return PHZ_E_INVALID; }
     if (o->block_tile[op] < -1 || o->block_tile[op] >= elem_tile_count()) {
@@ -1981,9 +2056,19 @@ int phz_set_options(phz_ctx* c, const phz_options* opt) {
     for (auto& L : c->hS.lv) L->ckind = -1;
     c->precond_ready = false;
   }
+  const bool smooth_change = opt->smoothing != c->opt.smoothing || opt->smooth_width != c->opt.smooth_width;
   c->opt = *opt;
   ++c->graph_epoch;
   if (hier_change) c->precond_ready = false;
+  if (smooth_change && c->have_s) {
+    // the current geometry's scales under the new smoothing
+    if (c->have_phi) update_scales(c);
+    else fill_point_scales(c);
+    sync(c);
+    c->precond_ready = false;
+    c->have_solution = false;
+    c->have_grad = false;
+  }
   ensure_state_buffers(c);
   return PHZ_OK;
   PHZ_GUARD_END(c)
@@ -2004,8 +2089,7 @@ int phz_set_levelset(phz_ctx* c, const double* phi, int on_device) {
   PHZ_GUARD_BEGIN
   int rc = set_input(c, phi, on_device, c->phi);
   if (rc) return rc;
-  levelset_to_scale(c->N, c->phi.p, c->opt.smooth_width / c->N, c->mat.void_scale, c->rho.p, c->s.p, c->s32.p,
-                    c->stream);
+  update_scales(c);
   sync(c);
   c->have_phi = true;
   c->have_s = true;
@@ -2021,6 +2105,7 @@ int phz_set_density(phz_ctx* c, const double* rho, int on_device) {
   int rc = set_input(c, rho, on_device, c->rho);
   if (rc) return rc;
   density_to_scale(c->nn, c->rho.p, c->mat.void_scale, c->s.p, c->s32.p, c->stream);
+  fill_point_scales(c);
   sync(c);
   c->have_phi = false;
   c->have_s = true;
@@ -2238,6 +2323,10 @@ int phz_foms(const double CH[36], const double eH[18], const double kH[9], phz_f
 int phz_backward(phz_ctx* c, const double gC[36], const double ge[18], const double gk[9], double* grad_rho,
                  double* grad_phi_out, int on_device) {
   if (!c || !grad_rho) return PHZ_E_INVALID;
+  if (c->opt.smoothing == PHZ_SMOOTH_QP) {
+    c->err = "sensitivities are implemented for element smoothing only";
+    return PHZ_E_INVALID;
+  }
   if (!c->have_solution) { c->err = "backward needs a solve"; return PHZ_E_STATE; }
   if (grad_phi_out && !c->have_phi) { c->err = "grad_phi needs a level set"; return PHZ_E_STATE; }
   PHZ_GUARD_BEGIN
@@ -2298,8 +2387,7 @@ int phz_hj_step(phz_ctx* c, const double* velocity, double cfl, double* phi_out,
     hj_step(c->N, c->phi.p, v.p, vmax, cfl / c->N, out.p, c->stream);
   }
   PHZ_HIP(hipMemcpyAsync(c->phi.p, out.p, c->nn * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
-  levelset_to_scale(c->N, c->phi.p, c->opt.smooth_width / c->N, c->mat.void_scale, c->rho.p, c->s.p, c->s32.p,
-                    c->stream);
+  update_scales(c);
   if (phi_out)
     PHZ_HIP(hipMemcpyAsync(phi_out, c->phi.p, c->nn * sizeof(double),
                            on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, c->stream));
@@ -2423,8 +2511,7 @@ int phz_reinit(phz_ctx* c, int steps, double cfl, int subcell, double* phi_out, 
     reinit_step(c->N, buf[i & 1], phi0, cfl / c->N, subcell, buf[(i + 1) & 1], c->stream);
   if (steps & 1)
     PHZ_HIP(hipMemcpyAsync(c->phi.p, buf[1], c->nn * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
-  levelset_to_scale(c->N, c->phi.p, c->opt.smooth_width / c->N, c->mat.void_scale, c->rho.p, c->s.p, c->s32.p,
-                    c->stream);
+  update_scales(c);
   if (phi_out)
     PHZ_HIP(hipMemcpyAsync(phi_out, c->phi.p, c->nn * sizeof(double),
                            on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, c->stream));
@@ -2438,6 +2525,10 @@ int phz_reinit(phz_ctx* c, int steps, double cfl, int subcell, double* phi_out, 
 
 int phz_levelset_gradient(phz_ctx* c, const double* grad_rho, double* grad_phi, int on_device) {
   if (!c || !grad_rho || !grad_phi) return PHZ_E_INVALID;
+  if (c->opt.smoothing == PHZ_SMOOTH_QP) {
+    c->err = "the chain rule is implemented for element smoothing only";
+    return PHZ_E_INVALID;
+  }
   if (!c->have_phi) { c->err = "the chain rule needs a level set"; return PHZ_E_STATE; }
   PHZ_GUARD_BEGIN
   DevBuf<double> g, out;
@@ -2597,6 +2688,10 @@ int phz_apply(phz_ctx* c, int op, int nrhs, int precision, const void* x, void* 
   if (!c->have_s) return PHZ_E_STATE;
   if (op == 5 && precision == PHZ_BF16X3_IR) {
     c->err = "B^T has no split-BF16 form";
+    return PHZ_E_INVALID;
+  }
+  if (op == 0 && precision == PHZ_BF16X3_IR && c->opt.smoothing == PHZ_SMOOTH_QP) {
+    c->err = "the split-BF16 full operator has no quadrature-point form";
     return PHZ_E_INVALID;
   }
   PHZ_GUARD_BEGIN

@@ -457,6 +457,48 @@ __global__ void k_levelset_to_scale(unsigned N, const double* __restrict__ phi, 
   s32[e] = (float)sv;
 }
 
+// Quadrature-point smoothing: the level set interpolated trilinearly at the
+// element's eight Gauss points p = i + 2j + 4k (points (g_i, g_j, g_k)),
+// smoothed there; sq[8e + p] the point scales, s and rho their element means.
+__global__ void k_levelset_to_scale_qp(unsigned N, const double* __restrict__ phi, double eta, double ev,
+                                       double* __restrict__ rho, double* __restrict__ s, float* __restrict__ s32,
+                                       double* __restrict__ sq, float* __restrict__ sq32) {
+  const unsigned nn = N * N * N;
+  const unsigned e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nn) return;
+  const Nb q = nbr(e, N);
+  double pc[8];
+  for (int c = 0; c < 8; ++c) pc[c] = phi[corner_node(q, N, c)];
+  const double g[2] = {0.5 - 0.5 / sqrt(3.0), 0.5 + 0.5 / sqrt(3.0)};
+  double rsum = 0.0, ssum = 0.0;
+  for (int p = 0; p < 8; ++p) {
+    const double xi = g[p & 1], yi = g[(p >> 1) & 1], zi = g[(p >> 2) & 1];
+    double v = 0.0;
+    for (int c = 0; c < 8; ++c)
+      v += ((c & 1) ? xi : 1.0 - xi) * ((c & 2) ? yi : 1.0 - yi) * ((c & 4) ? zi : 1.0 - zi) * pc[c];
+    const double r = 1.0 - sheaviside(v, eta);
+    const double sv = ev + (1.0 - ev) * r;
+    sq[(size_t)e * 8 + p] = sv;
+    sq32[(size_t)e * 8 + p] = (float)sv;
+    rsum += r;
+    ssum += sv;
+  }
+  rho[e] = 0.125 * rsum;
+  s[e] = 0.125 * ssum;
+  s32[e] = (float)(0.125 * ssum);
+}
+
+// point scales equal to the element scale (a cell given by its densities)
+__global__ void k_point_scales(unsigned nn, const double* __restrict__ s, double* __restrict__ sq,
+                               float* __restrict__ sq32) {
+  const unsigned e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nn) return;
+  for (int p = 0; p < 8; ++p) {
+    sq[(size_t)e * 8 + p] = s[e];
+    sq32[(size_t)e * 8 + p] = (float)s[e];
+  }
+}
+
 __global__ void k_density_to_scale(unsigned nn, const double* __restrict__ rho, double ev, double* __restrict__ s,
                                    float* __restrict__ s32) {
   const unsigned e = blockIdx.x * blockDim.x + threadIdx.x;
@@ -486,9 +528,34 @@ __global__ __launch_bounds__(128) void k_build_rhs(unsigned N, const double* __r
     }
 }
 
-// partial Y[(l, col)] = sum_n s_{n - c(l)} X[col][n] for column blockIdx.y
-__global__ __launch_bounds__(256) void k_reduce_effective(unsigned N, const double* __restrict__ s,
-                                                          const double* __restrict__ X, double* __restrict__ part) {
+// b[(f*9 + L)][n] = -sum_c sum_p sq[8 e_c + p] F0q[p][4c + f][L], e_c the
+// element whose corner c is n (absval: the magnitudes of the terms)
+__global__ __launch_bounds__(128) void k_build_rhs_qp(unsigned N, const double* __restrict__ sq,
+                                                      const double* __restrict__ F0q, double* __restrict__ b,
+                                                      int absval) {
+  const unsigned nn = N * N * N;
+  const unsigned n = blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= nn) return;
+  const Nb q = nbr(n, N);
+  unsigned ec[8];
+  for (int c = 0; c < 8; ++c) ec[c] = elem_of_corner(q, N, c);
+  for (int f = 0; f < 4; ++f)
+    for (int L = 0; L < 9; ++L) {
+      double acc = 0.0;
+      for (int c = 0; c < 8; ++c)
+        for (int p = 0; p < 8; ++p) {
+          const double v = F0q[p * 288 + (4 * c + f) * 9 + L];
+          acc -= sq[(size_t)ec[c] * 8 + p] * (absval ? -fabs(v) : v);
+        }
+      b[(size_t)(f * 9 + L) * nn + n] = acc;
+    }
+}
+
+// partial Y[(l, col)] = sum_n s_{n - c(l)} X[col][n] for column blockIdx.y,
+// the scale of element e read at s[stride e + off]
+__global__ __launch_bounds__(256) void k_reduce_effective(unsigned N, const double* __restrict__ s, int stride,
+                                                          int off, const double* __restrict__ X,
+                                                          double* __restrict__ part) {
   __shared__ double lds4[4];
   const unsigned nn = N * N * N;
   const double* col = X + (size_t)blockIdx.y * nn;
@@ -497,7 +564,7 @@ __global__ __launch_bounds__(256) void k_reduce_effective(unsigned N, const doub
   for (unsigned n = blockIdx.x * 256 + threadIdx.x; n < nn; n += gridDim.x * 256) {
     const Nb q = nbr(n, N);
     const double xv = col[n];
-    for (int l = 0; l < 8; ++l) acc[l] += s[elem_of_corner(q, N, l)] * xv;
+    for (int l = 0; l < 8; ++l) acc[l] += s[(size_t)elem_of_corner(q, N, l) * stride + off] * xv;
   }
   const size_t base = ((size_t)blockIdx.y * gridDim.x + blockIdx.x) * 8;
   for (int l = 0; l < 8; ++l) {
@@ -897,6 +964,23 @@ void density_to_scale(long nn, const double* rho, double void_scale, double* s, 
                      s32);
   PHZ_LAUNCH_CHECK();
 }
+void levelset_to_scale_qp(int N, const double* phi, double eta, double void_scale, double* rho, double* s,
+                          float* s32, double* sq, float* sq32, hipStream_t st) {
+  const size_t nn = (size_t)N * N * N;
+  hipLaunchKernelGGL(k_levelset_to_scale_qp, dim3(blocks_for(nn, 256)), dim3(256), 0, st, (unsigned)N, phi, eta,
+                     void_scale, rho, s, s32, sq, sq32);
+  PHZ_LAUNCH_CHECK();
+}
+void point_scales(long nn, const double* s, double* sq, float* sq32, hipStream_t st) {
+  hipLaunchKernelGGL(k_point_scales, dim3(blocks_for(nn, 256)), dim3(256), 0, st, (unsigned)nn, s, sq, sq32);
+  PHZ_LAUNCH_CHECK();
+}
+void build_rhs_qp(int N, const double* sq, const double* F0q, double* b, hipStream_t st, bool absval) {
+  const size_t nn = (size_t)N * N * N;
+  hipLaunchKernelGGL(k_build_rhs_qp, dim3(blocks_for(nn, 128)), dim3(128), 0, st, (unsigned)N, sq, F0q, b,
+                     (int)absval);
+  PHZ_LAUNCH_CHECK();
+}
 void build_rhs(int N, const double* s, const double* F0, double* b, hipStream_t st, bool absval) {
   const size_t nn = (size_t)N * N * N;
   hipLaunchKernelGGL(k_build_rhs, dim3(blocks_for(nn, 128)), dim3(128), 0, st, (unsigned)N, s, F0, b, (int)absval);
@@ -905,11 +989,18 @@ void build_rhs(int N, const double* s, const double* F0, double* b, hipStream_t 
 void reduce_effective(int N, const double* s, const double* X, double* out, double* work, hipStream_t st) {
   const size_t nn = (size_t)N * N * N;
   const unsigned G = slices_for(nn, 36);
-  hipLaunchKernelGGL(k_reduce_effective, dim3(G, 36), dim3(256), 0, st, (unsigned)N, s, X, work);
+  hipLaunchKernelGGL(k_reduce_effective, dim3(G, 36), dim3(256), 0, st, (unsigned)N, s, 1, 0, X, work);
   // out[l*36 + col] = sum over slices
   reduce_cols((int)G, 1, 36, 8, 0, 8, work, out, st);
   // out[288] = sum_e s_e
   col_reduce<double, false>(nn, 1, 1, s, out + 288, work, st);
+}
+void reduce_effective_point(int N, const double* sq, int p, const double* X, double* out, double* work,
+                            hipStream_t st) {
+  const size_t nn = (size_t)N * N * N;
+  const unsigned G = slices_for(nn, 36);
+  hipLaunchKernelGGL(k_reduce_effective, dim3(G, 36), dim3(256), 0, st, (unsigned)N, sq, 8, p, X, work);
+  reduce_cols((int)G, 1, 36, 8, 0, 8, work, out, st);
 }
 void cross_dots(long nn, const double* X, const double* Y, double* out, double* work, hipStream_t st) {
   const unsigned G = slices_for((size_t)nn, 36);

@@ -75,12 +75,14 @@ def test_options_rejected_before_device_use():
     for field, val in (("block_kernel", [0, 3, -1, -1]), ("block_kernel", [-2, 0, 0, 0]),
                        ("block_tile", [0, 0, 0, 3]), ("fine_kernel", 5), ("elem_tile", 7), ("solver", -1),
                        ("inner", 2), ("inner_eps", 0.0), ("inner_eps", 1.0), ("inner_maxit", 0),
-                       ("warm_start", 2), ("solver", 3)):
+                       ("warm_start", 2), ("solver", 3), ("smoothing", 2)):
         o = P.default_options(**{field: val})
         assert P._lib.phz_create(16, C.byref(m), C.byref(o), None, C.byref(h)) == -1, field
         assert not h.value
-    # TriCG runs in float64 only
+    # TriCG runs in float64 only, and with element smoothing
     o = P.default_options(solver=P.PHZ_SOLVER_TRICG, precision=P.PHZ_FP32_IR)
+    assert P._lib.phz_create(16, C.byref(m), C.byref(o), None, C.byref(h)) == -1
+    o = P.default_options(solver=P.PHZ_SOLVER_TRICG, precision=P.PHZ_FP64, smoothing=P.PHZ_SMOOTH_QP)
     assert P._lib.phz_create(16, C.byref(m), C.byref(o), None, C.byref(h)) == -1
     with pytest.raises(ValueError):
         P.default_options(block_tile=[0, 1])
