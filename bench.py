@@ -207,6 +207,38 @@ def optimisation_run(P, torch, synth, n, max_iters, precision, problem="bvoigt",
             "history_every_5": [[q, out["J"][q], *out["constraints"][q]] for q in range(0, it, 5)]}
 
 
+def smoothing_study(P, torch, synth, mat):
+    """Element smoothing against quadrature-point smoothing (Sec. 2.6) on the random-field workload at
+    64^3 and 128^3: solve time, iterations and the relative difference of the tensors, which shrinks
+    with h."""
+    rows = []
+    for n in (64, 128):
+        phi = synth.grf_levelset(n, seed=2410, solid_fraction=0.3)
+        out = {}
+        for name, sm in (("element", P.PHZ_SMOOTH_ELEMENT), ("qp", P.PHZ_SMOOTH_QP)):
+            with P.Context(n, mat, stream=torch.cuda.current_stream().cuda_stream, precision=P.PHZ_BF16X3_IR,
+                           rtol=1e-10, restart=12, vcycles_a=2, inner_rtol=1e-4, smoothing=sm) as ctx:
+                ctx.set_levelset(phi)
+                ctx.solve()
+                ctx.set_levelset(phi)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                ctx.solve()
+                torch.cuda.synchronize()
+                dt = time.perf_counter() - t0
+                st = ctx.stats()
+                MH, _ = ctx.effective_nd()
+            out[name] = (MH, dt, max(st["iterations"]), st["refinements"])
+            print(f"[bench] smoothing {name} {n}^3: {dt:.3f} s, {max(st['iterations'])} iterations", file=sys.stderr,
+                  flush=True)
+        d = np.abs(out["qp"][0] - out["element"][0]).max() / np.abs(out["element"][0]).max()
+        rows.append({"n": n, "solve_s_element": out["element"][1], "solve_s_qp": out["qp"][1],
+                     "iters_element": out["element"][2], "iters_qp": out["qp"][2],
+                     "refinements": [out["element"][3], out["qp"][3]], "tensor_rel_difference": d})
+    return {"study": "element vs quadrature-point smoothing, GRF seed 2410 solid 0.3, split-BF16 form, rtol 1e-10",
+            "rows": rows}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -237,6 +269,8 @@ def main():
     ap.add_argument("--optimise", type=int, default=0, metavar="ITERS",
                     help="run the paper's optimisation example (at most ITERS iterations) at --opt-n and "
                          "print its timing instead of the solve benchmark")
+    ap.add_argument("--smoothing-study", action="store_true",
+                    help="compare element and quadrature-point smoothing at 64^3 and 128^3")
     ap.add_argument("--opt-n", type=int, default=96)
     ap.add_argument("--optimise-problem", default="bvoigt", choices=sorted(OPT_PROBLEMS))
     ap.add_argument("--reinit-every", type=int, default=5,
@@ -320,6 +354,9 @@ def main():
     if args.solver_study:
         only = args.solver_study_only.split(",") if args.solver_study_only else None
         print(json.dumps(solver_study(P, torch, synth, mat, dev, only)))
+        return
+    if args.smoothing_study:
+        print(json.dumps(smoothing_study(P, torch, synth, mat)))
         return
     if args.optimise:
         print(json.dumps(optimisation_run(P, torch, synth, args.opt_n, args.optimise, prec, args.optimise_problem,
