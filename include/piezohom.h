@@ -110,10 +110,14 @@ extern "C" {
                                 operator, loads and tensors use the point
                                 scales; the preconditioner (multigrid, S_bar,
                                 the split-BF16 blocks) their element means.
-                                Not with TriCG; phz_backward and
-                                phz_levelset_gradient return PHZ_E_INVALID.
-                                A cell given by densities has equal point
-                                scales (the element form)                   */
+                                Not with TriCG.  phz_backward
+                                differentiates the point densities (its
+                                grad_rho[e] is their sum over the element,
+                                the derivative for a uniform change of the
+                                element's points); phz_levelset_gradient
+                                spreads an element gradient evenly over its
+                                points.  A cell given by densities has equal
+                                point scales (the element form)             */
 
 /* operator blocks for phz_apply (Sec. 2.5 block structure) */
 #define PHZ_OP_FULL 0    /* calA = [[A, B^T], [B, -C]] on [n][4][k]        */
@@ -307,7 +311,9 @@ int phz_foms(const double CH[36], const double eH[18], const double kH[9],
  * dJ/drho_e = (1 - eps_v) <W, G_e>, G_e[K, L] = element energy of the
  * fields e_K + B x^K and e_L + B x^L.  grad_rho: [N^3].  grad_phi (may be
  * NULL): [N^3] chain rule through the smoothed Heaviside (requires a level
- * set given by phz_set_levelset). */
+ * set given by phz_set_levelset).  With PHZ_SMOOTH_QP the same per Gauss
+ * point (G_ep, the point's share of the element energy): grad_rho[e] is the
+ * sum over the element's points, grad_phi goes through the point densities. */
 int phz_backward(phz_ctx* ctx, const double gC[36], const double ge[18],
                  const double gk[9], double* grad_rho, double* grad_phi,
                  int on_device);

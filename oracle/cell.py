@@ -210,6 +210,36 @@ def grad_phi_from_rho(n, phi, g_rho, width_elems=2.0):
     return out
 
 
+def element_energy_matrices_qp(n, X, M, npts=2):
+    """Per element and Gauss point, G_ep[K, L] = w_p (e_K + B_p x_e^K) . M (e_L + B_p x_e^L):
+    (ne, q, 9, 9).  With the material at the points, M^H = sum_e sum_p s_ep G_ep at the discrete
+    solution, so dM^H/ds_ep = G_ep."""
+    g, w = _gauss_g(n, X, npts)
+    return np.einsum("q,qeak,ab,qebl->eqkl", w, g, M, g, optimize=True)
+
+
+def grad_rho_qp(n, mat, X, W_nd):
+    """dJ/drho_ep = (1 - eps_v) <W, G_ep> (ne, q) for W = dJ/dM^H."""
+    M = fe.nondim_matrix(mat)
+    G = element_energy_matrices_qp(n, X, M)
+    return (1.0 - mat.void_scale) * np.einsum("eqkl,kl->eq", G, W_nd)
+
+
+def grad_phi_from_rho_qp(n, phi, g_rho, width_elems=2.0, npts=2):
+    """Chain rule of the point densities rho_ep = 1 - H(phi(x_p)), phi(x_p) = sum_l N_l(xi_p) phi_l:
+    dJ/dphi_n = -sum over (e, p) with n = corner l of e of H'(phi(x_p)) N_l(xi_p) dJ/drho_ep."""
+    eta = width_elems / n
+    pts, _ = fe.gauss_rule(npts)
+    Nv = np.array([fe.shape_values(p) for p in pts])                 # (q, 8)
+    gp = -fe.smoothed_heaviside_deriv(fe.levelset_at_gauss(n, phi, npts), eta) * g_rho     # (ne, q)
+    contrib = gp @ Nv                                                  # (ne, 8 corners)
+    en = element_nodes(n)
+    out = np.zeros(n ** 3)
+    for l in range(8):
+        np.add.at(out, en[:, l], contrib[:, l])
+    return out
+
+
 def W_from_tensor_grads(gC, ge, gk):
     """Map gradients w.r.t. SI (C^H, e^H, kappa^H) to W = dJ/dM^H (non-dim).
 

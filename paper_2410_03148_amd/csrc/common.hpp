@@ -227,10 +227,16 @@ void reduce_effective(int N, const double* s, const double* X, double* out, doub
                       hipStream_t st);
 // out[b*9 + a] = sum_{f, n} X[(f, a)][n] Y[(f, b)][n]  (9-load blocks)
 void cross_dots(long nn, const double* X, const double* Y, double* out, double* work, hipStream_t st);
+// grad[stride e + off] = factor (cterm + <X_e, FW> + <K0-weighted cross terms of X_e and W>)
 void backward_elem(int N, const double* X, const double* K0, const double* FW, double cterm,
-                   double factor, double* grad, hipStream_t st);
+                   double factor, double* grad, hipStream_t st, int stride = 1, int off = 0);
 void grad_phi(int N, const double* phi, double eta, const double* grad_rho, double* out,
               hipStream_t st);
+// chain rule of the point densities to the nodes: g per point (stride 8) or
+// per element spread evenly over its points (stride 1)
+void grad_phi_qp(int N, const double* phi, double eta, const double* g, int stride, double* out, hipStream_t st);
+// ge[e] = sum_p gq[8 e + p]
+void sum_points(long nn, const double* gq, double* ge, hipStream_t st);
 void nodal_mean_of_elements(int N, const double* ge, double* vn, hipStream_t st);
 void max_abs(long count, const double* v, double* out, double* work, hipStream_t st);
 void hj_step(int N, const double* phi, const double* v, const double* vmax, double dt,

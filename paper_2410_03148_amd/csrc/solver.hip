@@ -145,6 +145,7 @@ struct phz_ctx {
   int fkind[4] = {-1, -1, -1, -1};   // kernel of the float32 nine-column launches, -1 not yet chosen
 
   phz::DevBuf<double> phi, rho, s, grad_rho, tmp_nodes;
+  phz::DevBuf<double> grad_q;  // per-point density gradient (quadrature-point smoothing)
   phz::DevBuf<float> s32;
   bool have_phi = false, have_s = false, have_solution = false, have_grad = false;
   bool x_valid = false;   // X holds the finite result of the last solve (any geometry)
@@ -2323,10 +2324,6 @@ int phz_foms(const double CH[36], const double eH[18], const double kH[9], phz_f
 int phz_backward(phz_ctx* c, const double gC[36], const double ge[18], const double gk[9], double* grad_rho,
                  double* grad_phi_out, int on_device) {
   if (!c || !grad_rho) return PHZ_E_INVALID;
-  if (c->opt.smoothing == PHZ_SMOOTH_QP) {
-    c->err = "sensitivities are implemented for element smoothing only";
-    return PHZ_E_INVALID;
-  }
   if (!c->have_solution) { c->err = "backward needs a solve"; return PHZ_E_STATE; }
   if (grad_phi_out && !c->have_phi) { c->err = "grad_phi needs a level set"; return PHZ_E_STATE; }
   PHZ_GUARD_BEGIN
@@ -2340,26 +2337,44 @@ int phz_backward(phz_ctx* c, const double gC[36], const double ge[18], const dou
   for (int i = 0; i < 81; ++i)
     if (!std::isfinite(W[i])) { c->err = "non-finite upstream gradient"; return PHZ_E_NAN; }
   const RefElement& R = c->ref;
-  std::vector<double> buf(288 + 81);
-  for (int i = 0; i < 32; ++i)
-    for (int L = 0; L < 9; ++L) {
-      double v = 0.0;
-      for (int K = 0; K < 9; ++K) v += R.F0[i * 9 + K] * (W[K * 9 + L] + W[L * 9 + K]);
-      buf[i * 9 + L] = v;
-    }
-  for (int i = 0; i < 81; ++i) buf[288 + i] = W[i];
-  double cterm = 0.0;
-  for (int i = 0; i < 81; ++i) cterm += W[i] * R.M[i];
-  cterm *= std::pow(1.0 / c->N, 3);
+  const bool qp = c->opt.smoothing == PHZ_SMOOTH_QP;
+  // per element, or per Gauss point p (K0 -> K0q[p], F0 -> F0q[p], the
+  // constant term's weight h^3 -> h^3 / 8)
+  const int nterms = qp ? 8 : 1;
+  std::vector<double> buf((size_t)nterms * 369);
+  double cw = 0.0;
+  for (int i = 0; i < 81; ++i) cw += W[i] * R.M[i];
+  for (int p = 0; p < nterms; ++p) {
+    const double* F0 = qp ? R.F0q[p] : R.F0;
+    double* b = buf.data() + (size_t)p * 369;
+    for (int i = 0; i < 32; ++i)
+      for (int L = 0; L < 9; ++L) {
+        double v = 0.0;
+        for (int K = 0; K < 9; ++K) v += F0[i * 9 + K] * (W[K * 9 + L] + W[L * 9 + K]);
+        b[i * 9 + L] = v;
+      }
+    for (int i = 0; i < 81; ++i) b[288 + i] = W[i];
+  }
+  const double cterm = cw * std::pow(1.0 / c->N, 3) / nterms;
   DevBuf<double> dbuf;
   dbuf.upload(buf.data(), buf.size(), c->stream);
   c->grad_rho.alloc(c->nn);
-  backward_elem(c->N, c->X.p, c->kref_full.p, dbuf.p, cterm, 1.0 - c->mat.void_scale, c->grad_rho.p, c->stream);
+  const double eta = c->opt.smooth_width / c->N;
+  if (qp) {
+    c->grad_q.alloc((size_t)c->nn * 8);
+    for (int p = 0; p < 8; ++p)
+      backward_elem(c->N, c->X.p, c->kq64.p + (size_t)p * 1024, dbuf.p + (size_t)p * 369, cterm,
+                    1.0 - c->mat.void_scale, c->grad_q.p, c->stream, 8, p);
+    sum_points(c->nn, c->grad_q.p, c->grad_rho.p, c->stream);
+  } else {
+    backward_elem(c->N, c->X.p, c->kref_full.p, dbuf.p, cterm, 1.0 - c->mat.void_scale, c->grad_rho.p, c->stream);
+  }
   const hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
   PHZ_HIP(hipMemcpyAsync(grad_rho, c->grad_rho.p, c->nn * sizeof(double), kind, c->stream));
   if (grad_phi_out) {
     c->tmp_nodes.alloc(c->nn);
-    grad_phi(c->N, c->phi.p, c->opt.smooth_width / c->N, c->grad_rho.p, c->tmp_nodes.p, c->stream);
+    if (qp) grad_phi_qp(c->N, c->phi.p, eta, c->grad_q.p, 8, c->tmp_nodes.p, c->stream);
+    else grad_phi(c->N, c->phi.p, eta, c->grad_rho.p, c->tmp_nodes.p, c->stream);
     PHZ_HIP(hipMemcpyAsync(grad_phi_out, c->tmp_nodes.p, c->nn * sizeof(double), kind, c->stream));
   }
   sync(c);
@@ -2525,10 +2540,6 @@ int phz_reinit(phz_ctx* c, int steps, double cfl, int subcell, double* phi_out, 
 
 int phz_levelset_gradient(phz_ctx* c, const double* grad_rho, double* grad_phi, int on_device) {
   if (!c || !grad_rho || !grad_phi) return PHZ_E_INVALID;
-  if (c->opt.smoothing == PHZ_SMOOTH_QP) {
-    c->err = "the chain rule is implemented for element smoothing only";
-    return PHZ_E_INVALID;
-  }
   if (!c->have_phi) { c->err = "the chain rule needs a level set"; return PHZ_E_STATE; }
   PHZ_GUARD_BEGIN
   DevBuf<double> g, out;
@@ -2542,7 +2553,10 @@ int phz_levelset_gradient(phz_ctx* c, const double* grad_rho, double* grad_phi, 
     out.alloc(c->nn);
     o = out.p;
   }
-  phz::grad_phi(c->N, c->phi.p, c->opt.smooth_width / c->N, gr, o, c->stream);
+  // with quadrature-point smoothing an element gradient is the derivative for
+  // the element's mean point density: each point takes an eighth
+  if (c->opt.smoothing == PHZ_SMOOTH_QP) phz::grad_phi_qp(c->N, c->phi.p, c->opt.smooth_width / c->N, gr, 1, o, c->stream);
+  else phz::grad_phi(c->N, c->phi.p, c->opt.smooth_width / c->N, gr, o, c->stream);
   if (!on_device) PHZ_HIP(hipMemcpyAsync(grad_phi, o, c->nn * sizeof(double), hipMemcpyDeviceToHost, c->stream));
   sync(c);
   return PHZ_OK;

@@ -576,7 +576,8 @@ __global__ __launch_bounds__(256) void k_reduce_effective(unsigned N, const doub
 // dJ/drho_e = factor * ( cterm + <X_e, FW> + sum_{l,l'} <K0[l,l'], (x_l W) x_l'^T> )
 __global__ __launch_bounds__(128) void k_backward(unsigned N, const double* __restrict__ X, const double* __restrict__ K0,
                                                   const double* __restrict__ FW, const double* __restrict__ W,
-                                                  double cterm, double factor, double* __restrict__ grad) {
+                                                  double cterm, double factor, int stride, int off,
+                                                  double* __restrict__ grad) {
   const unsigned nn = N * N * N;
   const unsigned e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= nn) return;
@@ -609,7 +610,48 @@ __global__ __launch_bounds__(128) void k_backward(unsigned N, const double* __re
       }
     }
   }
-  grad[e] = factor * total;
+  grad[(size_t)e * stride + off] = factor * total;
+}
+
+// Chain rule of the point densities rho_ep = 1 - H(phi(x_p)) to the nodes:
+// dJ/dphi_n = -sum over the 8 elements e with n = corner c of e, and their
+// Gauss points p, of H'(phi(x_p)) N_c(xi_p) g_ep, with g_ep = g[8e + p]
+// (stride 8) or g[e] / 8 (stride 1: an element gradient spread evenly)
+__global__ void k_grad_phi_qp(unsigned N, const double* __restrict__ phi, double eta, const double* __restrict__ g,
+                              int stride, double* __restrict__ out) {
+  const unsigned nn = N * N * N;
+  const unsigned n = blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= nn) return;
+  const Nb q = nbr(n, N);
+  const double gq[2] = {0.5 - 0.5 / sqrt(3.0), 0.5 + 0.5 / sqrt(3.0)};
+  double acc = 0.0;
+  for (int c = 0; c < 8; ++c) {
+    const unsigned e = elem_of_corner(q, N, c);
+    const Nb qe = nbr(e, N);
+    double pc[8];
+    for (int cc = 0; cc < 8; ++cc) pc[cc] = phi[corner_node(qe, N, cc)];
+    for (int p = 0; p < 8; ++p) {
+      const double xi = gq[p & 1], yi = gq[(p >> 1) & 1], zi = gq[(p >> 2) & 1];
+      double v = 0.0, nc = 0.0;
+      for (int cc = 0; cc < 8; ++cc) {
+        const double w = ((cc & 1) ? xi : 1.0 - xi) * ((cc & 2) ? yi : 1.0 - yi) * ((cc & 4) ? zi : 1.0 - zi);
+        v += w * pc[cc];
+        if (cc == c) nc = w;
+      }
+      const double ge = stride == 8 ? g[(size_t)e * 8 + p] : 0.125 * g[e];
+      acc -= sheaviside_d(v, eta) * nc * ge;
+    }
+  }
+  out[n] = acc;
+}
+
+// per element, the sum of its eight point values
+__global__ void k_sum_points(unsigned nn, const double* __restrict__ gq, double* __restrict__ ge) {
+  const unsigned e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nn) return;
+  double v = 0.0;
+  for (int p = 0; p < 8; ++p) v += gq[(size_t)e * 8 + p];
+  ge[e] = v;
 }
 
 // partial cross products sum_n X[(f, a)][n] * Y[(f, b)][n] for (f, a) = blockIdx.y
@@ -1010,11 +1052,21 @@ void cross_dots(long nn, const double* X, const double* Y, double* out, double* 
   PHZ_LAUNCH_CHECK();
 }
 void backward_elem(int N, const double* X, const double* K0, const double* FW, double cterm, double factor,
-                   double* grad, hipStream_t st) {
+                   double* grad, hipStream_t st, int stride, int off) {
   // W (9x9) is stored right after FW (32x9) in the same buffer
   const size_t nn = (size_t)N * N * N;
   hipLaunchKernelGGL(k_backward, dim3(blocks_for(nn, 128)), dim3(128), 0, st, (unsigned)N, X, K0, FW, FW + 288, cterm,
-                     factor, grad);
+                     factor, stride, off, grad);
+  PHZ_LAUNCH_CHECK();
+}
+void grad_phi_qp(int N, const double* phi, double eta, const double* g, int stride, double* out, hipStream_t st) {
+  const size_t nn = (size_t)N * N * N;
+  hipLaunchKernelGGL(k_grad_phi_qp, dim3(blocks_for(nn, 256)), dim3(256), 0, st, (unsigned)N, phi, eta, g, stride,
+                     out);
+  PHZ_LAUNCH_CHECK();
+}
+void sum_points(long nn, const double* gq, double* ge, hipStream_t st) {
+  hipLaunchKernelGGL(k_sum_points, dim3(blocks_for(nn, 256)), dim3(256), 0, st, (unsigned)nn, gq, ge);
   PHZ_LAUNCH_CHECK();
 }
 void grad_phi(int N, const double* phi, double eta, const double* grad_rho, double* out, hipStream_t st) {

@@ -102,9 +102,35 @@ def test_qp_solve_vs_oracle(P, name, precision):
         assert relmax(MH, ge["MH"]) > 1e-5
 
 
-def test_qp_switch_density_input_and_rejections(P):
+def test_qp_sensitivities_vs_oracle(P):
+    """The point-form backward (d_h's density gradient summed per element, and its level-set gradient)
+    and the chain rule of an element gradient spread over the points, against the oracle's direct
+    solve of the 12^3 cell."""
+    n = 12
+    say("quadrature-point sensitivities", n)
+    phi = synth.grf_levelset(n, seed=2410, solid_fraction=0.5)
+    r = cell.homogenise(n, MAT, phi=phi, smoothing="qp")
+    from oracle import foms as ofoms
+    gC, ge_, gk = ofoms.fom_grads(r.C, r.e, r.kappa, "d_h")
+    W = cell.W_from_tensor_grads(gC, ge_, gk)
+    grq = cell.grad_rho_qp(n, MAT, r.X, W)
+    gphi = cell.grad_phi_from_rho_qp(n, phi, grq)
+    with P.Context(n, MAT, precision=P.PHZ_FP64, rtol=1e-12, smoothing=P.PHZ_SMOOTH_QP) as ctx:
+        ctx.set_levelset(phi)
+        assert ctx.solve() == P.PHZ_OK
+        f, (gC2, ge2, gk2) = P.foms(*ctx.effective(), grad_of="d_h")
+        grho, gp = ctx.backward(gC2, ge2, gk2, want_phi=True)
+        print("grad_rho error", relmax(grho, grq.sum(axis=1)), "grad_phi error", relmax(gp, gphi))
+        assert relmax(grho, grq.sum(axis=1)) < 1e-8
+        assert relmax(gp, gphi) < 1e-8
+        g = np.random.default_rng(3).standard_normal(n ** 3)
+        ref = cell.grad_phi_from_rho_qp(n, phi, np.repeat(g[:, None] / 8.0, 8, axis=1))
+        assert relmax(ctx.levelset_gradient(g), ref) < 1e-13
+
+
+def test_qp_switch_and_density_input(P):
     """Switching the smoothing on a set geometry recomputes its scales both ways; a cell given by
-    densities has equal point scales (the element form); sensitivities are refused in this mode."""
+    densities has equal point scales (the element form)."""
     g = json.load(open(os.path.join(HERE, "golden", "grf16_qp.json")))
     ge = json.load(open(os.path.join(HERE, "golden", "grf16.json")))
     say("smoothing switch")
@@ -116,8 +142,6 @@ def test_qp_switch_density_input_and_rejections(P):
         ctx.set_options(smoothing=P.PHZ_SMOOTH_QP)
         ctx.solve()
         assert relmax(ctx.effective_nd()[0], g["MH"]) < 1e-8
-        with pytest.raises(P.PiezoError):
-            ctx.backward(np.eye(6), want_phi=True)
         ctx.set_options(smoothing=P.PHZ_SMOOTH_ELEMENT)
         ctx.solve()
         assert relmax(ctx.effective_nd()[0], ge["MH"]) < 1e-8
