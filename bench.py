@@ -162,7 +162,8 @@ OPT_PROBLEMS = {
 }
 
 
-def optimisation_run(P, torch, synth, n, max_iters, precision, problem="bvoigt", reinit_every=5, smoothing="element"):
+def optimisation_run(P, torch, synth, n, max_iters, precision, problem="bvoigt", reinit_every=5, smoothing="element",
+                     step_control=True):
     """One of the paper's optimisation problems (Sec. 2.3, Sec. 2.6): z-poled PZT-5A, from the level set
     -prod cos(2 pi x_i) - 0.2 reinitialised, reinitialisation every five iterations, the paper's
     stopping rule.  The paper runs them on a 100^3 mesh; the multigrid hierarchy here needs N = m 2^k
@@ -185,7 +186,7 @@ def optimisation_run(P, torch, synth, n, max_iters, precision, problem="bvoigt",
                 smoothing=P.PHZ_SMOOTH_QP if smoothing == "qp" else P.PHZ_SMOOTH_ELEMENT)
     with P.Context(n, mat, stream=torch.cuda.current_stream().cuda_stream, **opts) as ctx:
         out = optimise(ctx, mat, synth.paper_levelset(n), objective, constraints, max_iters=max_iters,
-                       reinit_every=reinit_every, callback=progress)
+                       reinit_every=reinit_every, step_control=step_control, callback=progress)
         st = ctx.stats()
     CH, eH, kH = out["effective"]
     wall = time.perf_counter() - t0
@@ -198,6 +199,7 @@ def optimisation_run(P, torch, synth, n, max_iters, precision, problem="bvoigt",
                      + ", ".join(f"{c} = {v:g}" for c, v in constraints)
                      + ", PZT-5A, phi0 = -prod cos(2 pi x_i) - 0.2 reinitialised",
             "problem": problem, "n": n, "reinit_every": reinit_every, "smoothing": smoothing,
+            "step_control": step_control, "tau_last": out["tau"][-1] if out["tau"] else None,
             "precision": {P.PHZ_BF16X3_IR: "bf16x3ir", P.PHZ_FP32_IR: "fp32ir", P.PHZ_FP64: "fp64"}[precision],
             "solve": "SCP-GMRES, outer rtol 1e-12, warm start from the last iteration",
             "iterations": it, "converged": out["converged"], "wall_s": wall,
@@ -277,6 +279,8 @@ def main():
                     help="compare element and quadrature-point smoothing at 64^3 and 128^3")
     ap.add_argument("--opt-n", type=int, default=96)
     ap.add_argument("--optimise-problem", default="bvoigt", choices=sorted(OPT_PROBLEMS))
+    ap.add_argument("--opt-no-step-control", action="store_true",
+                    help="keep the objective's full step (no step control)")
     ap.add_argument("--opt-smoothing", default="element", choices=["element", "qp"],
                     help="material smoothing of the optimisation run (element mean or quadrature points)")
     ap.add_argument("--reinit-every", type=int, default=5,
@@ -366,7 +370,7 @@ def main():
         return
     if args.optimise:
         print(json.dumps(optimisation_run(P, torch, synth, args.opt_n, args.optimise, prec, args.optimise_problem,
-                                          args.reinit_every, args.opt_smoothing)))
+                                          args.reinit_every, args.opt_smoothing, not args.opt_no_step_control)))
         return
 
     if args.copy_calibration:

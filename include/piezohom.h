@@ -361,14 +361,16 @@ int phz_riesz(phz_ctx* ctx, int ncol, double alpha, const double* j, double* g, 
  * (host), i < m <= 8.  With g = H^-1 j, G_ik = j_i . g_k:
  *   theta_J = g_0 - sum_i g_i (G^-1 b)_i,  b_k = j_k . g_0,
  *   theta_C = -sum_i g_i (G^-1 viol)_i,
- *   v = theta_J / max|theta_J| + gamma / (cfl h) theta_C, scaled to max|v| <= 1,
- * so that an HJ step of cfl moves the boundary by up to cfl h along the
+ *   v = w theta_J / max|theta_J| + gamma / (cfl h) theta_C, scaled to
+ *   max|v| <= 1,
+ * so that an HJ step of cfl moves the boundary by up to w cfl h along the
  * objective's direction with the constraints' first-order changes removed,
- * and removes a fraction gamma of each violation to first order.
+ * and removes a fraction gamma of each violation to first order.  w =
+ * obj_weight in [0, 1] (1: the full step; a step control may lower it).
  * alpha <= 0 selects 4h.  Vectors on the host or (on_device) the device. */
 int phz_hpm_velocity(phz_ctx* ctx, int m, const double* j_obj, const double* const* j_cons,
-                     const double* viol, double alpha, double cfl, double gamma, double* v_out,
-                     int on_device);
+                     const double* viol, double alpha, double cfl, double gamma, double obj_weight,
+                     double* v_out, int on_device);
 
 /* Low-level operator apply on the current geometry: y = calA_block x for
  * nrhs in {1, 9} columns, device pointers.  These low-level entry points use

@@ -26,8 +26,8 @@ library.  Readings, all shared with the GPU path:
   theta_J = g_0 - sum_i g_i (G^-1 b)_i, b_k = j_k . g_0 (the objective direction with the constraint
   directions removed), and theta_C = -sum_i g_i (G^-1 c)_i for the relative violations c_i (to first
   order it removes them: <g_k, theta_C>_H = -c_k);
-* velocity: v = theta_J / max|theta_J| + (gamma / (cfl h)) theta_C, scaled down to max|v| = 1 when
-  larger (the objective part moves the boundary by cfl h per step, the constraint part removes a
+* velocity: v = w theta_J / max|theta_J| + (gamma / (cfl h)) theta_C, scaled down to max|v| = 1 when
+  larger (w = 1 unless a step control lowers it) (the objective part moves the boundary by cfl h per step, the constraint part removes a
   fraction gamma of each violation per step to first order);
 * stopping: at iteration q >= 10, |J_q - J_{q-j}| / |J_q| < 0.2 h for j = 1..5 and every relative
   violation below 1e-3 (h, the element side, is the paper's epsilon_m).
@@ -107,7 +107,7 @@ def riesz(n, j, alpha):
     return spla.spsolve(helmholtz_matrix(n, alpha).tocsc(), np.asarray(j, dtype=np.float64))
 
 
-def hpm_velocity(n, j_obj, j_cons, viol, alpha=None, cfl=0.5, gamma=0.5):
+def hpm_velocity(n, j_obj, j_cons, viol, alpha=None, cfl=0.5, gamma=0.5, obj_weight=1.0):
     """Velocity of one optimisation step (readings in the module docstring)."""
     h = 1.0 / n
     alpha = 4.0 * h if alpha is None else alpha
@@ -123,7 +123,7 @@ def hpm_velocity(n, j_obj, j_cons, viol, alpha=None, cfl=0.5, gamma=0.5):
         thC = -sum(lam_c[i] * gs[i] for i in range(m))
     else:
         thJ, thC = g0, np.zeros_like(g0)
-    v = thJ / np.max(np.abs(thJ)) + (gamma / (cfl * h)) * thC
+    v = obj_weight * thJ / np.max(np.abs(thJ)) + (gamma / (cfl * h)) * thC
     vm = np.max(np.abs(v))
     return v / vm if vm > 1.0 else v
 

@@ -115,7 +115,7 @@ def _load():
         "phz_levelset_gradient": (ip, [vp, vp, vp, ip]),
         "phz_riesz": (ip, [vp, ip, C.c_double, vp, vp, C.POINTER(ip)]),
         "phz_hpm_velocity": (ip, [vp, ip, vp, C.POINTER(C.c_void_p), vp, C.c_double, C.c_double, C.c_double,
-                                  vp, ip]),
+                                  C.c_double, vp, ip]),
         "phz_kernel_timing": (ip, [vp, ip]),
         "phz_get_kernel_timing": (ip, [vp, C.c_char_p, ip, C.POINTER(ip)]),
     }
@@ -344,7 +344,7 @@ class Context:
                     "phz_riesz")
         return it.value
 
-    def hpm_velocity(self, j_obj, j_cons=(), viol=(), alpha=0.0, cfl=0.5, gamma=0.5):
+    def hpm_velocity(self, j_obj, j_cons=(), viol=(), alpha=0.0, cfl=0.5, gamma=0.5, obj_weight=1.0):
         """Velocity of one constrained step (phz_hpm_velocity), host arrays."""
         jo = np.ascontiguousarray(j_obj, dtype=np.float64).ravel()
         jc = [np.ascontiguousarray(j, dtype=np.float64).ravel() for j in j_cons]
@@ -352,7 +352,8 @@ class Context:
         ptrs = (C.c_void_p * max(len(jc), 1))(*[j.ctypes.data for j in jc])
         out = np.zeros(self.nn)
         self._check(_lib.phz_hpm_velocity(self._h, len(jc), _dptr(jo), ptrs, _dptr(vi) if len(jc) else None,
-                                          alpha, cfl, gamma, C.c_void_p(out.ctypes.data), 0), "phz_hpm_velocity")
+                                          alpha, cfl, gamma, obj_weight, C.c_void_p(out.ctypes.data), 0),
+                    "phz_hpm_velocity")
         return out
 
     def kernel_timing(self, enable=True):

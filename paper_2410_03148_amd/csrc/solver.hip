@@ -2574,8 +2574,9 @@ int phz_riesz(phz_ctx* c, int ncol, double alpha, const double* j, double* g, in
 }
 
 int phz_hpm_velocity(phz_ctx* c, int m, const double* j_obj, const double* const* j_cons, const double* viol,
-                     double alpha, double cfl, double gamma, double* v_out, int on_device) {
-  if (!c || !j_obj || !v_out || m < 0 || m > 8 || (m > 0 && (!j_cons || !viol)) || !(cfl > 0) || !(gamma >= 0))
+                     double alpha, double cfl, double gamma, double obj_weight, double* v_out, int on_device) {
+  if (!c || !j_obj || !v_out || m < 0 || m > 8 || (m > 0 && (!j_cons || !viol)) || !(cfl > 0) || !(gamma >= 0) ||
+      !(obj_weight >= 0.0 && obj_weight <= 1.0))
     return PHZ_E_INVALID;
   for (int i = 0; i < m; ++i)
     if (!j_cons[i] || !std::isfinite(viol[i])) return PHZ_E_INVALID;
@@ -2646,8 +2647,8 @@ int phz_hpm_velocity(phz_ctx* c, int m, const double* j_obj, const double* const
   for (int i = 0; i < m; ++i) add(-lb[i], col(gv, 1 + i));
   const double mj = device_max_abs(c, v);
   if (!(mj > 0)) throw std::runtime_error("the objective direction vanishes");
-  // v = theta_J / max|theta_J| + (gamma / (cfl h)) theta_C, theta_C = -sum_i lc_i g_i
-  std::vector<double> one{1.0 / mj};
+  // v = w theta_J / max|theta_J| + (gamma / (cfl h)) theta_C, theta_C = -sum_i lc_i g_i
+  std::vector<double> one{obj_weight / mj};
   PHZ_HIP(hipMemcpyAsync(cf, one.data(), sizeof(double), hipMemcpyHostToDevice, c->stream));
   scale_cols<double>(nn, 1, 1, v, cf, v, c->stream);
   sync(c);

@@ -16,6 +16,12 @@ Per iteration q:
   5. one HJ step.
 It stops by the paper's rule (at q >= 10: the objective changed by less than 0.2 h relative to each of
 the five previous iterations and every relative violation is below 1e-3) or after `max_iters`.
+
+Step control (on by default; a reading, since the paper leaves it to its library): a factor tau in [0.05, 1] scales
+the objective part of the velocity.  It halves when the largest relative violation is above 1e-3 and has
+not fallen by 10% over the last five iterations, and otherwise grows by 1.1.  The objective's step moves the
+interface by up to cfl h per iteration, and its second-order effect on the constraints does not fade
+with a fixed step; the constraint part, first order, then holds them only at a nonzero violation.
 """
 from __future__ import annotations
 
@@ -61,7 +67,7 @@ def should_stop(J_hist, viol_hist, h):
 
 
 def optimise(ctx, material, phi0, objective, constraints, max_iters=200, cfl=0.5, gamma=0.5, alpha=0.0,
-             reinit_every=5, reinit_steps=20, reinit_subcell=True, callback=None):
+             reinit_every=5, reinit_steps=20, reinit_subcell=True, step_control=True, callback=None):
     """Maximise `objective` subject to [(property, target), ...] equality constraints from the level set
     phi0 (nodes, x fastest).  Returns a dict with the histories, the final level set, the effective
     tensors of the last solved geometry and the wall time of each phase in ms per iteration (every
@@ -74,7 +80,8 @@ def optimise(ctx, material, phi0, objective, constraints, max_iters=200, cfl=0.5
             raise ValueError(f"bad constraint {(name, target)}")
     h = 1.0 / ctx.n
     ctx.set_levelset(np.ascontiguousarray(phi0, dtype=np.float64).ravel())
-    hist = {"J": [], "constraints": [], "violations": [], "status": [], "iter_ms": []}
+    hist = {"J": [], "constraints": [], "violations": [], "status": [], "iter_ms": [], "tau": []}
+    tau = 1.0
     phases = {"reinit": 0.0, "solve": 0.0, "sensitivities": 0.0, "velocity": 0.0, "hj": 0.0}
     phi = None
     clock = time.perf_counter
@@ -110,7 +117,12 @@ def optimise(ctx, material, phi0, objective, constraints, max_iters=200, cfl=0.5
         if should_stop(hist["J"], hist["violations"], h):
             hist["iter_ms"].append(1e3 * (clock() - t_iter))
             break
-        v = ctx.hpm_velocity(-dJ, jc, viol, alpha=alpha, cfl=cfl, gamma=gamma)
+        if step_control and q >= 5:
+            now = max(map(abs, viol), default=0.0)
+            before = max(map(abs, hist["violations"][-6]), default=0.0)
+            tau = max(0.05, 0.5 * tau) if now > 1e-3 and now > 0.9 * before else min(1.0, 1.1 * tau)
+        hist["tau"].append(tau)
+        v = ctx.hpm_velocity(-dJ, jc, viol, alpha=alpha, cfl=cfl, gamma=gamma, obj_weight=tau)
         t = lap("velocity", t)
         phi = ctx.hj_step(v, cfl=cfl, return_phi=True)
         lap("hj", t)

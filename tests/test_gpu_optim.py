@@ -97,6 +97,9 @@ def test_hpm_velocity_vs_oracle(torch_cuda, P):
             assert relmax(v, ref) < 1e-9
         v = ctx.hpm_velocity(j0)
         assert relmax(v, optim.hpm_velocity(n, j0, [], [])) < 1e-9
+        # a reduced objective weight (step control)
+        v = ctx.hpm_velocity(j0, jc, [0.01, -0.02], obj_weight=0.3)
+        assert relmax(v, optim.hpm_velocity(n, j0, jc, [0.01, -0.02], obj_weight=0.3)) < 1e-9
 
 
 def test_one_optimisation_iteration_vs_oracle(torch_cuda, P):

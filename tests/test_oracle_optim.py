@@ -155,3 +155,18 @@ def test_reinit_subcell_keeps_a_thin_member():
         b = optim.reinit(n, b, steps=20)
     assert abs(optim.volume(n, a) / v0 - 1.0) < 0.2
     assert optim.volume(n, b) < 0.05 * v0
+
+
+def test_objective_weight_scales_only_the_objective_part():
+    """With the objective weight w the velocity is w times the objective part plus the unchanged
+    constraint part (while no rescaling to max|v| = 1 occurs)."""
+    n = 6
+    rng = np.random.default_rng(8)
+    j0 = rng.standard_normal(n ** 3)
+    jc = [rng.standard_normal(n ** 3)]
+    c = [1e-4]
+    v1 = optim.hpm_velocity(n, j0, jc, c)
+    vw = optim.hpm_velocity(n, j0, jc, c, obj_weight=0.25)
+    v0 = optim.hpm_velocity(n, j0, jc, [0.0])
+    assert np.abs(v1).max() <= 1.0 + 1e-12
+    assert np.abs((vw - (v1 - v0)) - 0.25 * v0).max() < 1e-12
