@@ -573,31 +573,46 @@ __global__ __launch_bounds__(256) void k_reduce_effective(unsigned N, const doub
   }
 }
 
-// dJ/drho_e = factor * ( cterm + <X_e, FW> + sum_{l,l'} <K0[l,l'], (x_l W) x_l'^T> )
-__global__ __launch_bounds__(128) void k_backward(unsigned N, const double* __restrict__ X, const double* __restrict__ K0,
+// dJ/drho_e = factor * ( cterm + <X_e, FW> + sum_{l,l'} <K0[l,l'], (x_l W) x_l'^T> ).
+// Eight threads per element, one per corner l: each forms u = x_l W from its
+// corner's 36 values and sums its row of the K0-weighted cross terms over the
+// eight corners l' (and its part of <X_e, FW>); the element's eight lanes
+// then add their partial sums by shuffles.  K0 and FW sit in LDS.
+__global__ __launch_bounds__(256) void k_backward(unsigned N, const double* __restrict__ X, const double* __restrict__ K0,
                                                   const double* __restrict__ FW, const double* __restrict__ W,
                                                   double cterm, double factor, int stride, int off,
                                                   double* __restrict__ grad) {
+  __shared__ double k0s[32 * 32];
+  __shared__ double fws[32 * 9];
+  __shared__ double ws[81];
+  for (int t = threadIdx.x; t < 32 * 32; t += blockDim.x) k0s[t] = K0[t];
+  for (int t = threadIdx.x; t < 32 * 9; t += blockDim.x) fws[t] = FW[t];
+  for (int t = threadIdx.x; t < 81; t += blockDim.x) ws[t] = W[t];
+  __syncthreads();
   const unsigned nn = N * N * N;
-  const unsigned e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= nn) return;
-  const Nb q = nbr(e, N);
-  unsigned cn[8];
-  for (int l = 0; l < 8; ++l) cn[l] = corner_node(q, N, l);
-  double total = cterm;
-  for (int l = 0; l < 8; ++l) {
+  const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const unsigned e = (unsigned)(gid >> 3);
+  const int l = (int)(gid & 7);
+  // every lane of an element's group takes part in the shuffles below; a
+  // group past the last element (only in the last block) adds zeros
+  const bool live = e < nn;
+  double part = 0.0;
+  if (live) {
+    const Nb q = nbr(e, N);
+    unsigned cn[8];
+    for (int c = 0; c < 8; ++c) cn[c] = corner_node(q, N, c);
     double xl[36];
     for (int t = 0; t < 36; ++t) xl[t] = X[(size_t)t * nn + cn[l]];
     double u[36];  // u = x_l W  (4 x 9)
-    for (int f = 0; f < 4; ++f) {
+    for (int f = 0; f < 4; ++f)
       for (int L = 0; L < 9; ++L) {
         double v = 0.0;
-        for (int Kk = 0; Kk < 9; ++Kk) v += xl[f * 9 + Kk] * W[Kk * 9 + L];
+        for (int Kk = 0; Kk < 9; ++Kk) v += xl[f * 9 + Kk] * ws[Kk * 9 + L];
         u[f * 9 + L] = v;
       }
-    }
+    if (l == 0) part = cterm;
     for (int f = 0; f < 4; ++f)
-      for (int L = 0; L < 9; ++L) total += xl[f * 9 + L] * FW[(4 * l + f) * 9 + L];
+      for (int L = 0; L < 9; ++L) part += xl[f * 9 + L] * fws[(4 * l + f) * 9 + L];
     for (int lp = 0; lp < 8; ++lp) {
       for (int fp = 0; fp < 4; ++fp) {
         double xm[9];
@@ -605,12 +620,15 @@ __global__ __launch_bounds__(128) void k_backward(unsigned N, const double* __re
         for (int f = 0; f < 4; ++f) {
           double v = 0.0;
           for (int L = 0; L < 9; ++L) v += u[f * 9 + L] * xm[L];
-          total += K0[(4 * l + f) * 32 + 4 * lp + fp] * v;
+          part += k0s[(4 * l + f) * 32 + 4 * lp + fp] * v;
         }
       }
     }
   }
-  grad[(size_t)e * stride + off] = factor * total;
+  part += __shfl_xor(part, 1, 8);
+  part += __shfl_xor(part, 2, 8);
+  part += __shfl_xor(part, 4, 8);
+  if (live && l == 0) grad[(size_t)e * stride + off] = factor * part;
 }
 
 // Chain rule of the point densities rho_ep = 1 - H(phi(x_p)) to the nodes:
@@ -1055,8 +1073,8 @@ void backward_elem(int N, const double* X, const double* K0, const double* FW, d
                    double* grad, hipStream_t st, int stride, int off) {
   // W (9x9) is stored right after FW (32x9) in the same buffer
   const size_t nn = (size_t)N * N * N;
-  hipLaunchKernelGGL(k_backward, dim3(blocks_for(nn, 128)), dim3(128), 0, st, (unsigned)N, X, K0, FW, FW + 288, cterm,
-                     factor, stride, off, grad);
+  hipLaunchKernelGGL(k_backward, dim3(blocks_for(nn * 8, 256)), dim3(256), 0, st, (unsigned)N, X, K0, FW, FW + 288,
+                     cterm, factor, stride, off, grad);
   PHZ_LAUNCH_CHECK();
 }
 void grad_phi_qp(int N, const double* phi, double eta, const double* g, int stride, double* out, hipStream_t st) {
