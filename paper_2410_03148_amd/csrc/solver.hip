@@ -146,6 +146,9 @@ struct phz_ctx {
 
   phz::DevBuf<double> phi, rho, s, grad_rho, tmp_nodes;
   phz::DevBuf<double> grad_q;  // per-point density gradient (quadrature-point smoothing)
+  // node-sized staging of the optimisation entry points and the backward's
+  // per-term block, kept so repeated calls do not allocate
+  phz::DevBuf<double> node_a, node_b, bw_terms;
   phz::DevBuf<float> s32;
   bool have_phi = false, have_s = false, have_solution = false, have_grad = false;
   bool x_valid = false;   // X holds the finite result of the last solve (any geometry)
@@ -2356,7 +2359,7 @@ int phz_backward(phz_ctx* c, const double gC[36], const double ge[18], const dou
     for (int i = 0; i < 81; ++i) b[288 + i] = W[i];
   }
   const double cterm = cw * std::pow(1.0 / c->N, 3) / nterms;
-  DevBuf<double> dbuf;
+  DevBuf<double>& dbuf = c->bw_terms;
   dbuf.upload(buf.data(), buf.size(), c->stream);
   c->grad_rho.alloc(c->nn);
   const double eta = c->opt.smooth_width / c->N;
@@ -2388,7 +2391,8 @@ int phz_hj_step(phz_ctx* c, const double* velocity, double cfl, double* phi_out,
   if (!c->have_phi) { c->err = "HJ step needs a level set"; return PHZ_E_STATE; }
   if (!velocity && !c->have_grad) { c->err = "no velocity and no backward result"; return PHZ_E_STATE; }
   PHZ_GUARD_BEGIN
-  DevBuf<double> v, out;
+  DevBuf<double>& v = c->node_a;
+  DevBuf<double>& out = c->node_b;
   v.alloc(c->nn);
   out.alloc(c->nn);
   double* vmax = c->small.p + 500;
@@ -2542,7 +2546,8 @@ int phz_levelset_gradient(phz_ctx* c, const double* grad_rho, double* grad_phi, 
   if (!c || !grad_rho || !grad_phi) return PHZ_E_INVALID;
   if (!c->have_phi) { c->err = "the chain rule needs a level set"; return PHZ_E_STATE; }
   PHZ_GUARD_BEGIN
-  DevBuf<double> g, out;
+  DevBuf<double>& g = c->node_a;
+  DevBuf<double>& out = c->node_b;
   const double* gr = grad_rho;
   if (!on_device) {
     g.upload(grad_rho, c->nn, c->stream);
@@ -2631,11 +2636,10 @@ int phz_hpm_velocity(phz_ctx* c, int m, const double* j_obj, const double* const
     }
   }
   // theta_J = g_0 - sum_i lb_i g_i into the output
-  DevBuf<double> vdev;
   double* v = v_out;
   if (!on_device) {
-    vdev.alloc(nn);
-    v = vdev.p;
+    c->node_a.alloc(nn);
+    v = c->node_a.p;
   }
   PHZ_HIP(hipMemcpyAsync(v, col(gv, 0), nn * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
   double* cf = c->small.p + 502;
