@@ -1894,6 +1894,10 @@ using namespace phz;
     if (ctx) (ctx)->err = ex.what();                                 \
     return std::strstr(ex.what(), "hipMalloc") ? PHZ_E_OOM : PHZ_E_HIP; \
   }                                                                  \
+  catch (const std::invalid_argument& ex) {                          \
+    if (ctx) (ctx)->err = ex.what();                                 \
+    return PHZ_E_INVALID;                                            \
+  }                                                                  \
   catch (const std::exception& ex) {                                 \
     if (ctx) (ctx)->err = ex.what();                                 \
     return PHZ_E_INTERNAL;                                           \
@@ -2467,7 +2471,11 @@ static int riesz_solve(phz_ctx* c, int K, double alpha, const double* j, double*
   // the mass part alone spans a factor 27, so lmax > lmin
   const double theta = 0.5 * (lmax + lmin), delta = 0.5 * (lmax - lmin), sigma = theta / delta;
   const double sk = std::sqrt(lmax / lmin);
-  const int steps = (int)std::ceil(std::log(2.0 / 1e-12) / std::log((sk + 1.0) / (sk - 1.0)));
+  const double nsteps = std::ceil(std::log(2.0 / 1e-12) / std::log((sk + 1.0) / (sk - 1.0)));
+  // the step count grows with alpha / h (kappa ~ 1 + 36 (alpha / h)^2): refuse
+  // length scales that would take more than 20000 steps
+  if (!(nsteps <= 20000.0)) throw std::invalid_argument("alpha too large for the extension (too many steps)");
+  const int steps = (int)nsteps;
   helmholtz_weights(c->N, alpha, c->rz_host);
   for (int k = 0; k < K; ++k) c->rz_host[27 + k] = 1.0 / theta;
   c->helm_w.upload(c->rz_host, 27, st);
