@@ -352,9 +352,10 @@ int phz_levelset_gradient(phz_ctx* ctx, const double* grad_rho, double* grad_phi
  * on H's exact extreme eigenvalues (constant coefficients: the extremes of its
  * symbol over the grid frequencies), run for the step count whose bound
  * 2 rho^k reaches a relative residual of 1e-12, with no host synchronisation
- * inside; *iters (may be NULL) gets the count (114 for alpha = 4h).  An
- * alpha needing more than 20000 steps (alpha above about 240 h) returns
- * PHZ_E_INVALID.  j and g must not overlap. */
+ * inside; *iters (may be NULL) gets the count (114 for alpha = 4h; about
+ * 28 alpha / h for large alpha).  An alpha needing more than 20000 steps
+ * (alpha above about 700 h) returns PHZ_E_INVALID.  j and g must not
+ * overlap. */
 int phz_riesz(phz_ctx* ctx, int ncol, double alpha, const double* j, double* g, int* iters);
 /* Velocity of one constrained optimisation step by projection in that
  * Hilbert space (the paper uses a Hilbertian projection method for its

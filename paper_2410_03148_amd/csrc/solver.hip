@@ -2472,8 +2472,8 @@ static int riesz_solve(phz_ctx* c, int K, double alpha, const double* j, double*
   const double theta = 0.5 * (lmax + lmin), delta = 0.5 * (lmax - lmin), sigma = theta / delta;
   const double sk = std::sqrt(lmax / lmin);
   const double nsteps = std::ceil(std::log(2.0 / 1e-12) / std::log((sk + 1.0) / (sk - 1.0)));
-  // the step count grows with alpha / h (kappa ~ 1 + 36 (alpha / h)^2): refuse
-  // length scales that would take more than 20000 steps
+  // the step count grows with alpha / h (kappa ~ 4 (alpha / h)^2, about
+  // 28 alpha / h steps): refuse length scales that would take more than 20000
   if (!(nsteps <= 20000.0)) throw std::invalid_argument("alpha too large for the extension (too many steps)");
   const int steps = (int)nsteps;
   helmholtz_weights(c->N, alpha, c->rz_host);

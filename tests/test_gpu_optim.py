@@ -80,7 +80,7 @@ def test_riesz_vs_oracle(torch_cuda, P, n, alpha_h):
         if alpha_h == 4.0 and n == 16:
             # a length scale needing more than 20000 Chebyshev steps is refused before any work
             with pytest.raises(P.PiezoError):
-                ctx.riesz(3, 20.0, jd.data_ptr(), gd.data_ptr())
+                ctx.riesz(3, 50.0, jd.data_ptr(), gd.data_ptr())
     print("Chebyshev steps", it)
     for k in range(3):
         ref = optim.riesz(n, j[k], alpha)
