@@ -116,24 +116,43 @@ template <typename T> struct Vec2;
 template <> struct Vec2<float> { using type = float2; };
 template <> struct Vec2<double> { using type = double2; };
 
-// Two consecutive nodes per thread and load (nn is even: N is even), which
-// doubles the bytes in flight per instruction.
+// Four consecutive values per thread as 16-byte accesses (one float4, or two
+// double2), widened to double; the pointer must be 16-byte aligned.
+__device__ __forceinline__ void ld4(const float* p, double (&v)[4]) {
+  const float4 q = *reinterpret_cast<const float4*>(p);
+  v[0] = q.x; v[1] = q.y; v[2] = q.z; v[3] = q.w;
+}
+__device__ __forceinline__ void ld4(const double* p, double (&v)[4]) {
+  const double2 a = reinterpret_cast<const double2*>(p)[0], b = reinterpret_cast<const double2*>(p)[1];
+  v[0] = a.x; v[1] = a.y; v[2] = b.x; v[3] = b.y;
+}
+__device__ __forceinline__ void st4(float* p, const double (&v)[4]) {
+  *reinterpret_cast<float4*>(p) = float4{(float)v[0], (float)v[1], (float)v[2], (float)v[3]};
+}
+__device__ __forceinline__ void st4(double* p, const double (&v)[4]) {
+  reinterpret_cast<double2*>(p)[0] = double2{v[0], v[1]};
+  reinterpret_cast<double2*>(p)[1] = double2{v[2], v[3]};
+}
+
+// Four consecutive nodes per thread and load (nn is a multiple of 8: N is
+// even), 16-byte accesses.
 template <typename T, int J>
 __global__ __launch_bounds__(256) void k_arnoldi_dots(unsigned nn, const T* __restrict__ V, size_t vstride,
                                                       const T* __restrict__ w, double* __restrict__ part) {
-  using V2 = typename Vec2<T>::type;
   __shared__ double lds4[4];
   const size_t co = (size_t)blockIdx.y * nn;
-  const unsigned nh = nn / 2;
+  const unsigned nq = nn / 4;
   double acc[J];
 #pragma unroll
   for (int i = 0; i < J; ++i) acc[i] = 0.0;
-  for (unsigned h = blockIdx.x * 256 + threadIdx.x; h < nh; h += gridDim.x * 256) {
-    const V2 wv = reinterpret_cast<const V2*>(w + co)[h];
+  for (unsigned h = blockIdx.x * 256 + threadIdx.x; h < nq; h += gridDim.x * 256) {
+    double wv[4];
+    ld4(w + co + 4 * (size_t)h, wv);
 #pragma unroll
     for (int i = 0; i < J; ++i) {
-      const V2 v = reinterpret_cast<const V2*>(V + i * vstride + co)[h];
-      acc[i] += (double)v.x * (double)wv.x + (double)v.y * (double)wv.y;
+      double v[4];
+      ld4(V + i * vstride + co + 4 * (size_t)h, v);
+      acc[i] += v[0] * wv[0] + v[1] * wv[1] + v[2] * wv[2] + v[3] * wv[3];
     }
   }
   const size_t base = ((size_t)blockIdx.y * gridDim.x + blockIdx.x) * J;
@@ -149,11 +168,10 @@ template <typename T, int J, bool DOTS>
 __global__ __launch_bounds__(256) void k_arnoldi_update(unsigned nn, int K, const T* __restrict__ V, size_t vstride,
                                                         T* __restrict__ w, const double* __restrict__ hin,
                                                         double* __restrict__ part) {
-  using V2 = typename Vec2<T>::type;
   __shared__ double lds4[4];
   const int kk = blockIdx.y % K;
   const size_t co = (size_t)blockIdx.y * nn;
-  const unsigned nh = nn / 2;
+  const unsigned nq = nn / 4;
   double h[J];
 #pragma unroll
   for (int i = 0; i < J; ++i) h[i] = hin[i * K + kk];
@@ -161,27 +179,30 @@ __global__ __launch_bounds__(256) void k_arnoldi_update(unsigned nn, int K, cons
 #pragma unroll
   for (int i = 0; i < (DOTS ? J : 1); ++i) acc[i] = 0.0;
   double nrm = 0.0;
-  V2* w2 = reinterpret_cast<V2*>(w + co);
-  for (unsigned hh = blockIdx.x * 256 + threadIdx.x; hh < nh; hh += gridDim.x * 256) {
-    V2 vv[DOTS ? J : 1];
-    const V2 w0 = w2[hh];
-    double wx = (double)w0.x, wy = (double)w0.y;
+  for (unsigned hh = blockIdx.x * 256 + threadIdx.x; hh < nq; hh += gridDim.x * 256) {
+    T* wp = w + co + 4 * (size_t)hh;
+    double vv[DOTS ? J : 1][4];
+    double wv[4];
+    ld4(wp, wv);
 #pragma unroll
     for (int i = 0; i < J; ++i) {
-      const V2 v = reinterpret_cast<const V2*>(V + i * vstride + co)[hh];
-      if constexpr (DOTS) vv[i] = v;
-      wx -= h[i] * (double)v.x;
-      wy -= h[i] * (double)v.y;
+      double v[4];
+      ld4(V + i * vstride + co + 4 * (size_t)hh, v);
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        if constexpr (DOTS) vv[i][c] = v[c];
+        wv[c] -= h[i] * v[c];
+      }
     }
-    V2 wt;
-    wt.x = (T)wx;
-    wt.y = (T)wy;
-    w2[hh] = wt;
-    const double rx = (double)wt.x, ry = (double)wt.y;
-    nrm += rx * rx + ry * ry;
+    // round to the vector's type once, and use the rounded values below
+#pragma unroll
+    for (int c = 0; c < 4; ++c) wv[c] = (double)(T)wv[c];
+    st4(wp, wv);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) nrm += wv[c] * wv[c];
     if constexpr (DOTS) {
 #pragma unroll
-      for (int i = 0; i < J; ++i) acc[i] += (double)vv[i].x * rx + (double)vv[i].y * ry;
+      for (int i = 0; i < J; ++i) acc[i] += vv[i][0] * wv[0] + vv[i][1] * wv[1] + vv[i][2] * wv[2] + vv[i][3] * wv[3];
     }
   }
   constexpr int NV = (DOTS ? J : 0) + 1;
@@ -235,6 +256,67 @@ __global__ void k_scale_cols(unsigned nn, int K, const T* __restrict__ w, const 
   if (n >= nn) return;
   const size_t o = (size_t)blockIdx.y * nn + n;
   v[o] = (T)((double)w[o] * scale[blockIdx.y % K]);
+}
+
+// four-wide forms of the column kernels below (nn a multiple of 4)
+template <typename T>
+__global__ void k_scale_cols4(unsigned nn, int K, const T* __restrict__ w, const double* __restrict__ scale,
+                              T* __restrict__ v) {
+  const unsigned n = (blockIdx.x * blockDim.x + threadIdx.x) * 4;
+  if (n >= nn) return;
+  const size_t o = (size_t)blockIdx.y * nn + n;
+  const double sc = scale[blockIdx.y % K];
+  double a[4];
+  ld4(w + o, a);
+#pragma unroll
+  for (int c = 0; c < 4; ++c) a[c] *= sc;
+  st4(v + o, a);
+}
+template <typename T>
+__global__ void k_combine4(unsigned nn, int K, const T* __restrict__ V, size_t vstride, const double* __restrict__ y,
+                           const int* __restrict__ kused, T* __restrict__ t) {
+  const unsigned n = (blockIdx.x * blockDim.x + threadIdx.x) * 4;
+  if (n >= nn) return;
+  const int kk = blockIdx.y % K;
+  const int ku = kused[kk];
+  const size_t o = (size_t)blockIdx.y * nn + n;
+  double s[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int i = 0; i < ku; ++i) {
+    double v[4];
+    ld4(V + i * vstride + o, v);
+    const double yi = y[i * K + kk];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) s[c] += yi * v[c];
+  }
+  st4(t + o, s);
+}
+template <typename Tx, typename Tz>
+__global__ void k_axpy_cols4(unsigned nn, int K, const double* __restrict__ a, const Tz* __restrict__ z,
+                             Tx* __restrict__ x) {
+  const unsigned n = (blockIdx.x * blockDim.x + threadIdx.x) * 4;
+  if (n >= nn) return;
+  const size_t o = (size_t)blockIdx.y * nn + n;
+  const double av = a ? a[blockIdx.y % K] : 1.0;
+  double xv[4], zv[4];
+  ld4(x + o, xv);
+  ld4(z + o, zv);
+#pragma unroll
+  for (int c = 0; c < 4; ++c) xv[c] += av * zv[c];
+  st4(x + o, xv);
+}
+template <typename T>
+__global__ void k_xpby_cols4(unsigned nn, int K, const double* __restrict__ beta, const T* __restrict__ z,
+                             T* __restrict__ p) {
+  const unsigned n = (blockIdx.x * blockDim.x + threadIdx.x) * 4;
+  if (n >= nn) return;
+  const size_t o = (size_t)blockIdx.y * nn + n;
+  const double b = beta[blockIdx.y % K];
+  double zv[4], pv[4];
+  ld4(z + o, zv);
+  ld4(p + o, pv);
+#pragma unroll
+  for (int c = 0; c < 4; ++c) pv[c] = zv[c] + b * pv[c];
+  st4(p + o, pv);
 }
 
 template <typename T>
@@ -919,8 +1001,12 @@ void col_dot(long nn, int F, int K, const T* a, const T* b, double* out, double*
 
 template <typename T>
 void xpby_cols(long nn, int F, int K, const double* beta, const T* z, T* p, hipStream_t st) {
-  hipLaunchKernelGGL((k_xpby_cols<T>), dim3(blocks_for(nn, 256), F * K), dim3(256), 0, st, (unsigned)nn, K, beta, z,
-                     p);
+  if (nn % 4 == 0)
+    hipLaunchKernelGGL((k_xpby_cols4<T>), dim3(blocks_for(nn / 4, 256), F * K), dim3(256), 0, st, (unsigned)nn, K,
+                       beta, z, p);
+  else
+    hipLaunchKernelGGL((k_xpby_cols<T>), dim3(blocks_for(nn, 256), F * K), dim3(256), 0, st, (unsigned)nn, K, beta,
+                       z, p);
   PHZ_LAUNCH_CHECK();
 }
 
@@ -939,6 +1025,7 @@ template <typename T>
 void arnoldi_dots(long nn, int F, int K, int j, const T* V, long vstride, const T* w, double* hout, double* work,
                   hipStream_t st) {
   static constexpr auto table = dots_table<T>(std::make_integer_sequence<int, kMaxRestart + 1>{});
+  if (nn % 4 != 0 || vstride % 4 != 0) throw std::logic_error("Arnoldi vectors: length and stride multiples of 4");
   const unsigned G = slices_for((size_t)nn, F * K);
   table[j](dim3(G, F * K), st, (unsigned)nn, V, (size_t)vstride, w, work);
   reduce_cols((int)G, F, K, j + 1, 0, j + 1, work, hout, st);
@@ -949,6 +1036,7 @@ template <typename T>
 void arnoldi_update(long nn, int F, int K, int j, const T* V, long vstride, T* w, const double* hin, double* hout,
                     double* nrm2out, double* work, hipStream_t st) {
   static constexpr auto table = upd_table<T>(std::make_integer_sequence<int, kMaxRestart + 1>{});
+  if (nn % 4 != 0 || vstride % 4 != 0) throw std::logic_error("Arnoldi vectors: length and stride multiples of 4");
   const unsigned G = slices_for((size_t)nn, F * K);
   const bool fused = hout && j + 1 <= kFusedMaxJ;
   const int NV = (fused ? j + 1 : 0) + 1;
@@ -961,21 +1049,34 @@ void arnoldi_update(long nn, int F, int K, int j, const T* V, long vstride, T* w
 
 template <typename T>
 void scale_cols(long nn, int F, int K, const T* w, const double* scale, T* v, hipStream_t st) {
-  hipLaunchKernelGGL((k_scale_cols<T>), dim3(blocks_for(nn, 256), F * K), dim3(256), 0, st, (unsigned)nn, K, w, scale, v);
+  if (nn % 4 == 0)
+    hipLaunchKernelGGL((k_scale_cols4<T>), dim3(blocks_for(nn / 4, 256), F * K), dim3(256), 0, st, (unsigned)nn, K,
+                       w, scale, v);
+  else
+    hipLaunchKernelGGL((k_scale_cols<T>), dim3(blocks_for(nn, 256), F * K), dim3(256), 0, st, (unsigned)nn, K, w,
+                       scale, v);
   PHZ_LAUNCH_CHECK();
 }
 
 template <typename T>
 void combine(long nn, int F, int K, const T* V, long vstride, const double* y, const int* kused, T* t, hipStream_t st) {
-  hipLaunchKernelGGL((k_combine<T>), dim3(blocks_for(nn, 256), F * K), dim3(256), 0, st, (unsigned)nn, K, V,
-                     (size_t)vstride, y, kused, t);
+  if (nn % 4 == 0 && vstride % 4 == 0)
+    hipLaunchKernelGGL((k_combine4<T>), dim3(blocks_for(nn / 4, 256), F * K), dim3(256), 0, st, (unsigned)nn, K, V,
+                       (size_t)vstride, y, kused, t);
+  else
+    hipLaunchKernelGGL((k_combine<T>), dim3(blocks_for(nn, 256), F * K), dim3(256), 0, st, (unsigned)nn, K, V,
+                       (size_t)vstride, y, kused, t);
   PHZ_LAUNCH_CHECK();
 }
 
 template <typename Tx, typename Tz>
 void axpy_cols(long nn, int F, int K, const double* a, const Tz* z, Tx* x, hipStream_t st) {
-  hipLaunchKernelGGL((k_axpy_cols<Tx, Tz>), dim3(blocks_for(nn, 256), F * K), dim3(256), 0, st, (unsigned)nn, K, a, z,
-                     x);
+  if (nn % 4 == 0)
+    hipLaunchKernelGGL((k_axpy_cols4<Tx, Tz>), dim3(blocks_for(nn / 4, 256), F * K), dim3(256), 0, st, (unsigned)nn,
+                       K, a, z, x);
+  else
+    hipLaunchKernelGGL((k_axpy_cols<Tx, Tz>), dim3(blocks_for(nn, 256), F * K), dim3(256), 0, st, (unsigned)nn, K, a,
+                       z, x);
   PHZ_LAUNCH_CHECK();
 }
 
