@@ -240,6 +240,26 @@ def test_live_oracle_grf(torch_cuda, P, n):
         assert np.linalg.norm(res, axis=0).max() <= 1e-9 * np.linalg.norm(r.F, axis=0).max()
 
 
+@pytest.mark.parametrize("n", [2, 4, 6])
+@pytest.mark.parametrize("precision", ["fp64", "fp32ir"])
+def test_smallest_cells(torch_cuda, P, n, precision):
+    """The smallest cells: N = 2 and 4 are a single multigrid level (the dense coarse solve alone), N = 6
+    coarsens to 3^3; at N = 2 a node's left and right neighbours are the same node, so the gather adds
+    two element blocks into one coupling.  Against the oracle's direct solve."""
+    say("smallest cell", n, precision)
+    rho = synth.random_density(n, seed=40 + n, low=0.1, high=1.0)
+    r = cell.homogenise(n, MAT, rho=rho)
+    prec = P.PHZ_FP64 if precision == "fp64" else P.PHZ_FP32_IR
+    with P.Context(n, MAT, precision=prec, rtol=1e-10) as ctx:
+        ctx.set_density(rho)
+        assert ctx.solve() == P.PHZ_OK
+        st = ctx.stats()
+        MH, _ = ctx.effective_nd()
+        print("levels", st["mg_levels"], "iterations", max(st["iterations"]), "error", relmax(MH, r.MH))
+        assert st["mg_levels"] == (1 if n <= 4 else 2)
+        assert relmax(MH, r.MH) < 1e-8
+
+
 def test_laminate_closed_form_on_gpu(torch_cuda, P):
     n = 16
     say("laminate", n)
