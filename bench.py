@@ -458,31 +458,35 @@ def main():
     }
 
     # dominant single kernel from the live event timing of the timed steps
-    single = {k: v for k, v in ktimes.items() if k.startswith(("fine_", "tiled_", "elem_", "coarse_"))}
-    if single:
-        name = max(single, key=lambda k: single[k][1])
-        cnt, tot = single[name]
+    def roofline_of(name):
+        cnt, tot = ktimes[name]
         avg_s = tot / cnt * 1e-3
-        if name.startswith(("fine_", "tiled_", "elem_")):
-            fl, by, p = per_node(name)
-            flops = fl * n ** 3
-            nbytes = by * n ** 3
-            ai = fl / by
-            # published MI355X peaks: fp64 78.6, fp32 vector 157.3, dense bf16 MFMA 2500 TFLOP/s
-            peak_tf = {"f64": 78.6, "f32": 157.3}.get(p, 2500.0)
-            ridge = peak_tf * 1e12 / 8e12
-            tile = stats["elem_tile"][list(OPS).index(name.split("_")[1])] if name.startswith("elem_") else None
-            traffic = measured_traffic(name, tile)
-            if ai > ridge:
-                result["roofline"] = {"bound": "mfma" if name.startswith("elem_") else "alu", "achieved": flops / avg_s / 1e12, "peak": peak_tf,
-                                      "unit": "TFLOP/s", "frac": flops / avg_s / 1e12 / peak_tf,
-                                      "traffic": traffic, "kernel": name, "avg_ms": avg_s * 1e3,
-                                      "algorithmic_bytes": nbytes, "algorithmic_flops": flops}
-            else:
-                result["roofline"] = {"bound": "hbm", "achieved": nbytes / avg_s / 1e9, "peak": 8000.0,
-                                      "unit": "GB/s", "frac": nbytes / avg_s / 8e12, "traffic": traffic,
-                                      "kernel": name, "avg_ms": avg_s * 1e3,
-                                      "algorithmic_bytes": nbytes, "algorithmic_flops": flops}
+        fl, by, p = per_node(name)
+        flops = fl * n ** 3
+        nbytes = by * n ** 3
+        ai = fl / by
+        # published MI355X peaks: fp64 78.6, fp32 vector 157.3, dense bf16 MFMA 2500 TFLOP/s
+        peak_tf = {"f64": 78.6, "f32": 157.3}.get(p, 2500.0)
+        ridge = peak_tf * 1e12 / 8e12
+        tile = stats["elem_tile"][list(OPS).index(name.split("_")[1])] if name.startswith("elem_") else None
+        traffic = measured_traffic(name, tile)
+        if ai > ridge:
+            return {"bound": "mfma" if name.startswith("elem_") else "alu", "achieved": flops / avg_s / 1e12,
+                    "peak": peak_tf, "unit": "TFLOP/s", "frac": flops / avg_s / 1e12 / peak_tf, "traffic": traffic,
+                    "kernel": name, "avg_ms": avg_s * 1e3, "algorithmic_bytes": nbytes, "algorithmic_flops": flops}
+        return {"bound": "hbm", "achieved": nbytes / avg_s / 1e9, "peak": 8000.0, "unit": "GB/s",
+                "frac": nbytes / avg_s / 8e12, "traffic": traffic, "kernel": name, "avg_ms": avg_s * 1e3,
+                "algorithmic_bytes": nbytes, "algorithmic_flops": flops}
+
+    single = {k: v for k, v in ktimes.items() if k.startswith(("fine_", "tiled_", "elem_"))}
+    if single:
+        order = sorted(single, key=lambda k: -single[k][1])
+        result["roofline"] = roofline_of(order[0])
+        # the A block's plain and Chebyshev element kernels take about the same
+        # total time per step, so either may lead: a runner-up within 5% is
+        # reported beside it
+        if len(order) > 1 and single[order[1]][1] >= 0.95 * single[order[0]][1]:
+            result["roofline_runner_up"] = roofline_of(order[1])
         result["kernel_ms_per_step"] = {k: v[1] / args.steps for k, v in sorted(ktimes.items())}
         # the outer operator apply (all four fields, nine loads) as achieved
         # algorithmic HBM bandwidth
