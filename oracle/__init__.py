@@ -17,6 +17,11 @@ homogenisation of three-dimensional piezoelectric materials":
 * laminate.py  closed-form laminate tensors (a pin, not the method)
 * krylov.py    textbook right-preconditioned GMRES with the block
                lower-triangular Schur preconditioner of Sec. 2.5.3
+* tricg.py     TriCG for the quasi-definite block system (Sec. 2.5.2)
+* optim.py     the optimisation step: reinitialisation, Hilbertian
+               extension and projection, stopping rule (Sec. 2.6)
+* fullsize.py  the operator, residual and tensors element by element, for
+               checks at sizes the direct solve cannot reach
 
 Where the paper is silent the readings are stated in the docstrings:
 standard Galerkin weak form with E = -grad(phi); scales C0 = 1e9 Pa,

@@ -1,5 +1,7 @@
 """Material matrix, units, trilinear hex8 element and density map (FP64).
 
+TEST INFRASTRUCTURE: part of the oracle the GPU path is checked against; used by tests/ only.
+
 Sec. 2.2 (constitutive laws): sigma = C eps - e^T E, D = e eps + kappa E,
 eps = sym grad u, E = -grad phi.  With the generalised strain
 g = (eps_xx, eps_yy, eps_zz, gamma_yz, gamma_xz, gamma_xy, E_x, E_y, E_z)

@@ -1,5 +1,7 @@
 """Figures of merit of the effective tensors (Sec. 2.3) and their gradients.
 
+TEST INFRASTRUCTURE: part of the oracle the GPU path is checked against; used by tests/ only.
+
 Definitions (SI units, Voigt notation with engineering shear):
 * S = (C^H)^-1, d = e^H S (3x6, strain coefficients),
 * d_h = d_31 + d_32 + d_33 (sum over the z row of the first three columns),

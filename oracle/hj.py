@@ -1,5 +1,7 @@
 """One explicit step of the Hamilton-Jacobi equation of Sec. 2.1.
 
+TEST INFRASTRUCTURE: part of the oracle the GPU path is checked against; used by tests/ only.
+
 phi_t + v |grad phi| = 0 on the periodic node grid, first-order Godunov
 upwinding (Osher-Sethian).  The paper leaves the discretisation to its
 library; the reading here: nodal velocity v = mean of dJ/drho over the eight
