@@ -1,6 +1,7 @@
 """Periodic cell problem: assembly, pinned direct solve, effective tensors.
 
-TEST INFRASTRUCTURE: part of the oracle the GPU path is checked against; used by tests/ only.
+TEST INFRASTRUCTURE: part of the oracle the GPU path is checked against; used only by the tests, the
+smoke check and the benchmark's CPU baseline.
 
 Sec. 2.2: for each of the nine unit macroscopic fields g_L (six engineering
 strains, three electric fields) find the periodic fluctuation x^L with

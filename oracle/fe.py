@@ -1,6 +1,7 @@
 """Material matrix, units, trilinear hex8 element and density map (FP64).
 
-TEST INFRASTRUCTURE: part of the oracle the GPU path is checked against; used by tests/ only.
+TEST INFRASTRUCTURE: part of the oracle the GPU path is checked against; used only by the tests, the
+smoke check and the benchmark's CPU baseline.
 
 Sec. 2.2 (constitutive laws): sigma = C eps - e^T E, D = e eps + kappa E,
 eps = sym grad u, E = -grad phi.  With the generalised strain

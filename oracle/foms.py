@@ -1,6 +1,7 @@
 """Figures of merit of the effective tensors (Sec. 2.3) and their gradients.
 
-TEST INFRASTRUCTURE: part of the oracle the GPU path is checked against; used by tests/ only.
+TEST INFRASTRUCTURE: part of the oracle the GPU path is checked against; used only by the tests, the
+smoke check and the benchmark's CPU baseline.
 
 Definitions (SI units, Voigt notation with engineering shear):
 * S = (C^H)^-1, d = e^H S (3x6, strain coefficients),

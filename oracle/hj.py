@@ -1,6 +1,7 @@
 """One explicit step of the Hamilton-Jacobi equation of Sec. 2.1.
 
-TEST INFRASTRUCTURE: part of the oracle the GPU path is checked against; used by tests/ only.
+TEST INFRASTRUCTURE: part of the oracle the GPU path is checked against; used only by the tests, the
+smoke check and the benchmark's CPU baseline.
 
 phi_t + v |grad phi| = 0 on the periodic node grid, first-order Godunov
 upwinding (Osher-Sethian).  The paper leaves the discretisation to its

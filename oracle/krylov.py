@@ -1,6 +1,7 @@
 """Textbook right-preconditioned GMRES with the Schur preconditioner of Sec. 2.5.3.
 
-TEST INFRASTRUCTURE: part of the oracle the GPU path is checked against; used by tests/ only.
+TEST INFRASTRUCTURE: part of the oracle the GPU path is checked against; used only by the tests, the
+smoke check and the benchmark's CPU baseline.
 
 The block system of Sec. 2.5 orders unknowns as (x, y) = (displacements,
 potential):  calA = [[A, B^T], [B, -C]].  The preconditioner is the block

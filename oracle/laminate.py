@@ -1,6 +1,7 @@
 """Closed-form effective matrix of a layered cell (a pin for the whole solve).
 
-TEST INFRASTRUCTURE: part of the oracle the GPU path is checked against; used by tests/ only.
+TEST INFRASTRUCTURE: part of the oracle the GPU path is checked against; used only by the tests, the
+smoke check and the benchmark's CPU baseline.
 
 For a cell whose ersatz scale s depends only on the coordinate along one
 axis, the exact solution keeps the in-plane ("t") generalised strains equal

@@ -2,7 +2,7 @@
 to a signed distance, the extension of the discrete sensitivities into a velocity by a Hilbert-space
 projection onto the constraints' null space, and the stopping rule.
 
-TEST INFRASTRUCTURE: the oracle of the GPU path, used by tests/ only.
+TEST INFRASTRUCTURE: the oracle of the GPU path, used only by the tests.
 
 The paper states the problem (maximise a figure of merit under equality constraints on the volume and
 on a second effective property), reinitialisation every five iterations by a standard first-order

@@ -1,7 +1,7 @@
 """TriCG, the short-recurrence Krylov method the paper compares for its symmetric quasi-definite block
 system (Sec. 2.5, Sec. 2.5.2; Montoison and Orban, SIAM J. Sci. Comput. 43, 2021).
 
-TEST INFRASTRUCTURE: the oracle of the GPU path, used by tests/ only.
+TEST INFRASTRUCTURE: the oracle of the GPU path, used only by the tests.
 
 The system [[E, A], [A^T, -F]] [x; y] = [b; c] has E and F symmetric positive definite (on the periodic
 cell: on the subspace of zero field means).  For the piezoelectric block system of Sec. 2.5,
