@@ -182,3 +182,54 @@ def test_warm_start_matches_cold_solve(P):
     print("iterations cold", cold, "warm", warm)
     assert warm < cold
     assert np.abs(MHw - MHc).max() / np.abs(MHc).max() < 1e-8
+
+
+def _oracle_loop(n, phi0, target_dh, iters, cfl=0.5, gamma=0.5):
+    """The optimisation loop composed from the oracle's steps in the driver's order: reinitialisation
+    (subcell fix) at iterations 0, 5, ...; the direct solve; the objective's and constraints'
+    sensitivities; the step control (objective weight halved when the largest violation stays above
+    1e-3 without falling by 10% over five iterations, else grown by 1.1 up to 1); the projected
+    velocity and the HJ step.  Returns the objective and violation histories and the level set."""
+    phi = np.asarray(phi0, dtype=np.float64)
+    Js, viols, tau = [], [], 1.0
+    for q in range(iters):
+        if q % 5 == 0:
+            phi = optim.reinit(n, phi, steps=20, cfl=cfl, subcell=True)
+        res = cell.homogenise(n, MAT, phi=phi)
+        f = ofoms.foms(res.C, res.e, res.kappa)
+
+        def jvec(name):
+            W = cell.W_from_tensor_grads(*ofoms.fom_grads(res.C, res.e, res.kappa, name))
+            return -cell.grad_phi_from_rho(n, phi, cell.grad_rho(n, MAT, res.X, W))
+
+        rho = fe.density_from_levelset(n, phi)
+        viol = [(float(np.mean(rho)) - 0.5) / 0.5, (f["d_h"] - target_dh) / abs(target_dh)]
+        jc = [-cell.grad_phi_from_rho(n, phi, np.full(n ** 3, 1.0 / n ** 3)) / 0.5, jvec("d_h") / abs(target_dh)]
+        Js.append(f["B_voigt"])
+        viols.append(viol)
+        if q >= 5:
+            now, before = max(map(abs, viol)), max(map(abs, viols[-6]))
+            tau = max(0.05, 0.5 * tau) if now > 1e-3 and now > 0.9 * before else min(1.0, 1.1 * tau)
+        v = optim.hpm_velocity(n, jvec("B_voigt"), jc, viol, cfl=cfl, gamma=gamma, obj_weight=tau)
+        phi = ohj.hj_step(n, phi, v, cfl=cfl)
+    return Js, viols, phi
+
+
+def test_seven_optimisation_iterations_vs_oracle(torch_cuda, P):
+    """Seven iterations of the loop at 12^3 (two reinitialisations, the step control from iteration 5)
+    against the oracle's loop: objective, violations and the final level set."""
+    from paper_2410_03148_amd.optimise import optimise
+    n = 12
+    say("seven optimisation iterations", n)
+    phi0 = synth.grf_levelset(n, seed=2411, solid_fraction=0.55)
+    r0 = cell.homogenise(n, MAT, phi=optim.reinit(n, phi0, steps=20, cfl=0.5, subcell=True), want_x=False)
+    target = 1.3 * ofoms.foms(r0.C, r0.e, r0.kappa)["d_h"]
+    Js, viols, phi = _oracle_loop(n, phi0, target, 7)
+    with P.Context(n, MAT, precision=P.PHZ_FP64, rtol=1e-12) as ctx:
+        out = optimise(ctx, MAT, phi0, "B_voigt", [("vol", 0.5), ("d_h", target)], max_iters=7)
+    print("objective", ["%.6e" % v for v in out["J"]], "oracle", ["%.6e" % v for v in Js])
+    print("objective weights", out["tau"])
+    assert relmax(out["J"], Js) < 1e-8
+    assert np.allclose(out["violations"], viols, rtol=1e-7, atol=1e-10)
+    print("level set error", relmax(out["phi"], phi))
+    assert relmax(out["phi"], phi) < 1e-7
