@@ -156,8 +156,10 @@ typedef struct {
     int max_refine;         /* FP32_IR: cap on refinement steps, each one float
                                GMRES cycle of at most `restart` steps (default 50) */
     int verbose;            /* 0 silent; 1 per-solve summary on stderr          */
-    int bf16_terms;         /* PHZ_BF16X3_IR: 3 split products (default) or 1
-                               (hi*hi only, about 2^-8 relative)               */
+    int bf16_terms;         /* PHZ_BF16X3_IR: split products of the float GMRES
+                               operator's element contraction (bf16_outer) and
+                               of phz_apply: 3 (default) or 1 (hi*hi only,
+                               about 2^-8 relative)                            */
     int bf16_outer;         /* PHZ_BF16X3_IR: 1 (default) also runs the float
                                GMRES operator on the matrix cores, 0 only the
                                preconditioner's fine blocks                    */
@@ -219,6 +221,13 @@ typedef struct {
     int smoothing;          /* PHZ_SMOOTH_ELEMENT (default) or PHZ_SMOOTH_QP;
                                a change recomputes the current geometry's
                                scales                                        */
+    int bf16_terms_precond; /* PHZ_BF16X3_IR: split products of the element
+                               contractions inside the preconditioner (the A,
+                               B and S_bar blocks' smoothing steps and
+                               residuals): 1 (default) or 3.  The
+                               preconditioner's own accuracy sets only how
+                               fast GMRES converges; the operator and the FP64
+                               refinement set the result                     */
 } phz_options;
 
 typedef struct {

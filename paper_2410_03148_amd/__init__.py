@@ -42,7 +42,8 @@ class phz_options(C.Structure):
                 ("elem_tile", C.c_int), ("use_graph", C.c_int), ("fine_kernel", C.c_int),
                 ("block_kernel", C.c_int * 4), ("block_tile", C.c_int * 4), ("coarse_kernel", C.c_int),
                 ("solver", C.c_int), ("inner", C.c_int), ("inner_eps", C.c_double), ("inner_maxit", C.c_int),
-                ("warm_start", C.c_int), ("smoothing", C.c_int)]
+                ("warm_start", C.c_int), ("smoothing", C.c_int),
+                ("bf16_terms_precond", C.c_int)]
 
 
 def _set_option(o, k, v):

@@ -516,6 +516,13 @@ static bool elem_eligible(phz_ctx* c, int op) {
 // fixed candidate order instead of to launch-to-launch noise.
 static bool clearly_faster(float ms, float best_ms) { return ms < 0.97f * best_ms; }
 
+// Split products of the element contraction of block shape `op`: the full
+// block runs only as the GMRES operator, the others only inside the
+// preconditioner.
+static int elem_terms(const phz_ctx* c, int op) {
+  return op == 0 ? c->opt.bf16_terms : c->opt.bf16_terms_precond;
+}
+
 // Tile of the element contraction for block `op`: the option's choice, or
 // the fastest tile that divides N (timed once per context); -1 if none fits.
 static int elem_tile_of(phz_ctx* c, int op) {
@@ -531,7 +538,7 @@ static int elem_tile_of(phz_ctx* c, int op) {
       for (int t = 0; t < elem_tile_count(); ++t) {
         if (!elem_tile_fits(c->N, t)) continue;
         const float ms = time_launch(c, [&] {
-          elem_apply(op, 9, c->N, c->opt.bf16_terms, t, c->s32.p, c->kop[op].p, b.x.p, b.a, false, c->stream);
+          elem_apply(op, 9, c->N, elem_terms(c, op), t, c->s32.p, c->kop[op].p, b.x.p, b.a, false, c->stream);
         });
         if (best < 0 || clearly_faster(ms, best_ms)) {
           best = t;
@@ -581,7 +588,7 @@ static int fine_kind_of(phz_ctx* c, int op) {
     if (elem_ok && elem_tile_of(c, op) >= 0) {
       const int t = c->elem_tile[op];
       const float ms = time_launch(c, [&] {
-        elem_apply(op, 9, c->N, c->opt.bf16_terms, t, c->s32.p, c->kop[op].p, b.x.p, b.a, false, c->stream);
+        elem_apply(op, 9, c->N, elem_terms(c, op), t, c->s32.p, c->kop[op].p, b.x.p, b.a, false, c->stream);
       });
       if (clearly_faster(ms, best_ms)) {
         best_ms = ms;
@@ -622,8 +629,9 @@ static void op_apply_args(phz_ctx* c, int blk, int K, const T* x, const OpArgs<T
     if (K == 9 && op <= 3) {
       const int kind = fine_kind_of(c, op);
       if (kind == kFineElem) {
-        const long slot = time_begin(c, elem_op_name(op, c->opt.bf16_terms == 3, cheby));
-        elem_apply(op, K, c->N, c->opt.bf16_terms, c->elem_tile[op], c->s32.p, c->kop[blk].p, x, a, cheby, c->stream);
+        const int terms = elem_terms(c, op);
+        const long slot = time_begin(c, elem_op_name(op, terms == 3, cheby));
+        elem_apply(op, K, c->N, terms, c->elem_tile[op], c->s32.p, c->kop[blk].p, x, a, cheby, c->stream);
         time_end(c, slot);
         return;
       }
@@ -1937,6 +1945,7 @@ void phz_default_options(phz_options* o) {
   o->inner_maxit = 200;
   o->warm_start = 0;
   o->smoothing = PHZ_SMOOTH_ELEMENT;
+  o->bf16_terms_precond = 1;
 }
 
 const char* phz_strerror(int status) {
@@ -1951,6 +1960,7 @@ const char* phz_last_error(const phz_ctx* ctx) { return ctx ? ctx->err.c_str() :
 static int check_options(const phz_options* o, std::string& err) {
   if (o->precision != PHZ_FP64 && o->precision != PHZ_FP32_IR && o->precision != PHZ_BF16X3_IR) { err = "precision must be PHZ_FP64, PHZ_FP32_IR or PHZ_BF16X3_IR"; return PHZ_E_INVALID; }
   if (o->bf16_terms != 1 && o->bf16_terms != 3) { err = "bf16_terms must be 1 or 3"; return PHZ_E_INVALID; }
+  if (o->bf16_terms_precond != 1 && o->bf16_terms_precond != 3) { err = "bf16_terms_precond must be 1 or 3"; return PHZ_E_INVALID; }
   if (o->bf16_outer != 0 && o->bf16_outer != 1) { err = "bf16_outer must be 0 or 1"; return PHZ_E_INVALID; }
   if (o->elem_tile < -1 || o->elem_tile >= elem_tile_count()) { err = "elem_tile must be -1 or a tile index"; return PHZ_E_INVALID; }
   if (o->use_graph != 0 && o->use_graph != 1) { err = "use_graph must be 0 or 1"; return PHZ_E_INVALID; }

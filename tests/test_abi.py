@@ -62,6 +62,7 @@ def test_strerror_and_defaults():
     o = P.default_options()
     assert o.restart == 30 and o.rtol == 1e-10 and o.batched == 1 and o.cheby_degree == 2
     assert list(o.block_kernel) == [-1] * 4 and list(o.block_tile) == [-1] * 4
+    assert o.bf16_terms == 3 and o.bf16_terms_precond == 1
 
 
 def test_options_rejected_before_device_use():
@@ -75,7 +76,8 @@ def test_options_rejected_before_device_use():
     for field, val in (("block_kernel", [0, 3, -1, -1]), ("block_kernel", [-2, 0, 0, 0]),
                        ("block_tile", [0, 0, 0, 3]), ("fine_kernel", 5), ("elem_tile", 7), ("solver", -1),
                        ("inner", 2), ("inner_eps", 0.0), ("inner_eps", 1.0), ("inner_maxit", 0),
-                       ("warm_start", 2), ("solver", 3), ("smoothing", 2)):
+                       ("warm_start", 2), ("solver", 3), ("smoothing", 2), ("bf16_terms_precond", 2),
+                       ("bf16_terms_precond", 0)):
         o = P.default_options(**{field: val})
         assert P._lib.phz_create(16, C.byref(m), C.byref(o), None, C.byref(h)) == -1, field
         assert not h.value

@@ -138,17 +138,19 @@ def _golden(name):
     return json.load(open(os.path.join(HERE, "golden", f"{name}.json")))
 
 
-@pytest.mark.parametrize("outer,tile", [(1, 0), (0, 2), (1, -1)])
-def test_grf16_split_bf16_ir_vs_stored_oracle(torch_cuda, P, outer, tile):
+@pytest.mark.parametrize("outer,tile,pterms", [(1, 0, 1), (0, 2, 1), (1, -1, 1), (1, 0, 3), (0, -1, 3)])
+def test_grf16_split_bf16_ir_vs_stored_oracle(torch_cuda, P, outer, tile, pterms):
     """The mixed form with matrix-core operators still meets the FP64 residual
     target, so the tensors match the oracle to the plain-FP64 bar.  A fixed
     tile puts every block on the matrix cores; tile -1 lets the timed choice
-    keep a block on the float32 gather kernel.  (The single-product form,
-    bf16_terms = 1, is checked as an operator only: its 2^-8 error leaves some
-    cells short of a 1e-10 residual.)"""
+    keep a block on the float32 gather kernel.  The preconditioner's blocks
+    run with one split product (the default) or three.  (The single-product
+    GMRES operator, bf16_terms = 1, is checked as an operator only: its 2^-8
+    error leaves some cells short of a 1e-10 residual.)"""
     g = _golden("grf16")
-    say("grf16 bf16x3-ir outer", outer, "tile", tile)
-    with P.Context(16, MAT, precision=P.PHZ_BF16X3_IR, bf16_outer=outer, elem_tile=tile, rtol=1e-10) as ctx:
+    say("grf16 bf16x3-ir outer", outer, "tile", tile, "preconditioner terms", pterms)
+    with P.Context(16, MAT, precision=P.PHZ_BF16X3_IR, bf16_outer=outer, elem_tile=tile, rtol=1e-10,
+                   bf16_terms_precond=pterms) as ctx:
         ctx.set_levelset(synth.grf_levelset(16, seed=2410, solid_fraction=0.5))
         status = ctx.solve()
         st = ctx.stats()
