@@ -195,11 +195,18 @@ typedef struct {
                                else pins the element-contraction tile index  */
     int coarse_kernel;      /* float32 nine-column applies of the coarse
                                multigrid levels: -1 (default) per level the
-                               faster (timed once; the tiled one must be more
-                               than 3% faster) of 0 the direct stencil apply
-                               and 1 the apply with the input tile staged in
-                               LDS (levels with N a multiple of 16); 0 or 1
-                               forces that kernel where it applies           */
+                               fastest (timed once, in the order 0, 1, 2; a
+                               later one must be more than 3% faster) of
+                               0 the direct stencil apply, 1 the apply with
+                               the input tile staged in LDS, and 2 the same on
+                               compact stencils: the 26 off-centre blocks in
+                               bf16 and the centre block as minus their sum,
+                               so that rows still annihilate constants and
+                               the bf16 error scales with the differences
+                               across the stencil (1 and 2: levels with N a
+                               multiple of 16); 0, 1 or 2 forces that kernel
+                               where it applies.  The coarse operators serve
+                               the preconditioner only                        */
     int solver;             /* PHZ_SOLVER_SCP (default), PHZ_SOLVER_DBP or
                                PHZ_SOLVER_TRICG                               */
     int inner;              /* block maps v -> A^-1 v and the potential block's

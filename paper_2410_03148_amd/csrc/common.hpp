@@ -92,6 +92,12 @@ void coarse_apply(int F, int nrhs, int N, const T* S, const T* x, const OpArgs<T
 bool coarse_tiled_fits(int N);
 void coarse_apply_tiled(int F, int N, const float* S, const float* x, const OpArgs<float>& a, bool cheby,
                         hipStream_t st);
+// The same with the compact stencil form (compact_stencil): the 26
+// off-centre blocks in bf16 (S16, [d'][fo][fi][n], centre skipped) and the
+// centre block in float32 as minus their sum (Sc, [fo][fi][n]).
+void coarse_apply_tiled_compact(int F, int N, const unsigned short* S16, const float* Sc, const float* x,
+                                const OpArgs<float>& a, bool cheby, hipStream_t st);
+void compact_stencil(int F, long nn, const double* S, unsigned short* S16, float* Sc, hipStream_t st);
 // Node stencils of a coarse level from its Galerkin element matrices
 // (structure-of-arrays [corner L][row f][col][element]).
 void build_stencil(int F, int N, const double* Ae, double* S, hipStream_t st);

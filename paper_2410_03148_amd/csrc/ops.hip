@@ -358,8 +358,19 @@ void launch_tiled(unsigned N, const float* s, const float* kref, const float* x,
 // the tile's input nodes plus a one-node halo are staged once in LDS (rows of
 // CP floats as in the tiled fine gather) and each node's 27 stencil blocks
 // are streamed from HBM once.
-template <int F, bool CHEBY, bool BUF>
+//
+// COMPACT: the 26 off-centre blocks come as bf16 (S16, [d'][fo][fi][n] with
+// d' = d, or d - 1 past the centre d = 13) and the centre block as float32
+// minus their sum (Sc, [fo][fi][n]).  A Galerkin operator annihilates
+// constants per field pair (every block row sums to zero), and so does the
+// stored one, to float32 rounding: the apply equals
+// sum_{d != centre} S_d (x_{n+d} - x_n), whose bf16 coefficient error
+// (2^-9 relative) scales with the differences across the stencil rather than
+// with the values.  About half the stencil bytes per node.
+template <int F, bool CHEBY, bool BUF, bool COMPACT>
 __global__ __launch_bounds__(256) void k_stencil_tiled(unsigned N, const float* __restrict__ S,
+                                                       const unsigned short* __restrict__ S16,
+                                                       const float* __restrict__ Sc,
                                                        const float* __restrict__ x, OpArgs<float> a) {
   constexpr int K = 9, C = F * K, CP = (C + 3) / 4 * 4;
   __shared__ float4 xs[GNI * (CP / 4)];
@@ -382,8 +393,18 @@ __global__ __launch_bounds__(256) void k_stencil_tiled(unsigned N, const float* 
   auto load_block = [&](int d, float* sv) {
 #pragma unroll
     for (int t = 0; t < F * F; ++t) {
-      if constexpr (BUF) sv[t] = buf_load<float>(sr, n * (unsigned)sizeof(float), (unsigned)((d * F * F + t) * nn * sizeof(float)));
-      else sv[t] = S[(size_t)(d * F * F + t) * nn + n];
+      if constexpr (COMPACT) {
+        if (d == 13) {
+          sv[t] = Sc[(size_t)t * nn + n];
+        } else {
+          const int dd = d < 13 ? d : d - 1;
+          sv[t] = __builtin_bit_cast(float, (unsigned)S16[(size_t)(dd * F * F + t) * nn + n] << 16);
+        }
+      } else if constexpr (BUF) {
+        sv[t] = buf_load<float>(sr, n * (unsigned)sizeof(float), (unsigned)((d * F * F + t) * nn * sizeof(float)));
+      } else {
+        sv[t] = S[(size_t)(d * F * F + t) * nn + n];
+      }
     }
   };
   float sq[3][F * F];
@@ -419,10 +440,42 @@ void launch_stencil_tiled(unsigned N, const float* S, const float* x, const OpAr
                           hipStream_t st) {
   const unsigned g = (N / GTX) * (N / GTY) * (N / GTZ);
   const bool buf = (size_t)N * N * N * 27 * F * F * sizeof(float) < (size_t(1) << 32);
-#define PHZ_ST(CH, BUF) hipLaunchKernelGGL((k_stencil_tiled<F, CH, BUF>), dim3(g), dim3(256), 0, st, N, S, x, a)
+#define PHZ_ST(CH, BUF) \
+  hipLaunchKernelGGL((k_stencil_tiled<F, CH, BUF, false>), dim3(g), dim3(256), 0, st, N, S, nullptr, nullptr, x, a)
   if (cheby) { if (buf) PHZ_ST(true, true); else PHZ_ST(true, false); }
   else { if (buf) PHZ_ST(false, true); else PHZ_ST(false, false); }
 #undef PHZ_ST
+}
+
+template <int F>
+void launch_stencil_tiled_compact(unsigned N, const unsigned short* S16, const float* Sc, const float* x,
+                                  const OpArgs<float>& a, bool cheby, hipStream_t st) {
+  const unsigned g = (N / GTX) * (N / GTY) * (N / GTZ);
+  if (cheby)
+    hipLaunchKernelGGL((k_stencil_tiled<F, true, false, true>), dim3(g), dim3(256), 0, st, N, nullptr, S16, Sc, x, a);
+  else
+    hipLaunchKernelGGL((k_stencil_tiled<F, false, false, true>), dim3(g), dim3(256), 0, st, N, nullptr, S16, Sc, x, a);
+}
+
+// Compact form of a level's stencils: the off-centre blocks rounded to bf16
+// (nearest even), the centre block minus their rounded sum (accumulated in
+// float64, then rounded to float32).
+template <int F>
+__global__ void k_compact_stencil(unsigned nn, const double* __restrict__ S, unsigned short* __restrict__ S16,
+                                  float* __restrict__ Sc) {
+  const unsigned n = blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= nn) return;
+  for (int t = 0; t < F * F; ++t) {
+    double sum = 0.0;
+    for (int d = 0; d < 27; ++d) {
+      if (d == 13) continue;
+      const __bf16 h = (__bf16)(float)S[(size_t)(d * F * F + t) * nn + n];
+      const unsigned short hb = __builtin_bit_cast(unsigned short, h);
+      S16[(size_t)((d < 13 ? d : d - 1) * F * F + t) * nn + n] = hb;
+      sum += (double)__builtin_bit_cast(float, (unsigned)hb << 16);
+    }
+    Sc[(size_t)t * nn + n] = (float)(-sum);
+  }
 }
 
 // Coarse levels: assembled 27-point node stencils S[(d*F + fo)*F + fi][n]
@@ -853,6 +906,23 @@ void coarse_apply_tiled(int F, int N, const float* S, const float* x, const OpAr
   if (F == 3) launch_stencil_tiled<3>((unsigned)N, S, x, a, cheby, st);
   else if (F == 1) launch_stencil_tiled<1>((unsigned)N, S, x, a, cheby, st);
   else throw std::invalid_argument("coarse_apply_tiled F");
+  PHZ_LAUNCH_CHECK();
+}
+
+void coarse_apply_tiled_compact(int F, int N, const unsigned short* S16, const float* Sc, const float* x,
+                                const OpArgs<float>& a, bool cheby, hipStream_t st) {
+  if (!coarse_tiled_fits(N)) throw std::invalid_argument("coarse_apply_tiled_compact: N must be a multiple of 16");
+  if (F == 3) launch_stencil_tiled_compact<3>((unsigned)N, S16, Sc, x, a, cheby, st);
+  else if (F == 1) launch_stencil_tiled_compact<1>((unsigned)N, S16, Sc, x, a, cheby, st);
+  else throw std::invalid_argument("coarse_apply_tiled_compact F");
+  PHZ_LAUNCH_CHECK();
+}
+
+void compact_stencil(int F, long nn, const double* S, unsigned short* S16, float* Sc, hipStream_t st) {
+  const unsigned g = (unsigned)((nn + 255) / 256);
+  if (F == 3) hipLaunchKernelGGL((k_compact_stencil<3>), dim3(g), dim3(256), 0, st, (unsigned)nn, S, S16, Sc);
+  else if (F == 1) hipLaunchKernelGGL((k_compact_stencil<1>), dim3(g), dim3(256), 0, st, (unsigned)nn, S, S16, Sc);
+  else throw std::invalid_argument("compact_stencil F");
   PHZ_LAUNCH_CHECK();
 }
 

@@ -67,6 +67,10 @@ struct Level {
   DevBuf<double> Ae;      // Galerkin element matrices (levels >= 1)
   DevBuf<double> S;       // assembled 27-point node stencils (levels >= 1)
   DevBuf<float> S32;
+  // compact float form of S for the tiled apply: off-centre blocks in bf16,
+  // the centre block minus their sum (levels whose side is a multiple of 16)
+  DevBuf<unsigned short> S16;
+  DevBuf<float> Sc;
   DevBuf<double> Dinv;    // node-block diagonal inverse
   DevBuf<float> Dinv32;
   double lmax = 0.0;
@@ -78,7 +82,8 @@ struct Level {
   DevBuf<double> cheb;
   DevBuf<float> cheb32;
   // kernel of the float32 nine-column applies of this coarse level: 0 the
-  // direct stencil apply, 1 the LDS-tiled one, -1 not yet chosen
+  // direct stencil apply, 1 the LDS-tiled one, 2 the LDS-tiled one on the
+  // compact stencils, -1 not yet chosen
   int ckind = -1;
 };
 
@@ -667,6 +672,12 @@ static void level_apply_args(phz_ctx* c, Hierarchy& H, int l, int K, const T* x,
         time_end(c, slot);
         return;
       }
+      if (K == 9 && L.ckind == 2) {
+        const long slot = time_begin(c, H.F == 3 ? "coarse_tiledbf_A_f32" : "coarse_tiledbf_S_f32");
+        coarse_apply_tiled_compact(H.F, L.N, L.S16.p, L.Sc.p, x, a, cheby, c->stream);
+        time_end(c, slot);
+        return;
+      }
     }
     const long slot = time_begin(c, H.F == 3 ? (sizeof(T) == 4 ? "coarse_A_f32" : "coarse_A_f64")
                                              : (sizeof(T) == 4 ? "coarse_S_f32" : "coarse_S_f64"));
@@ -811,6 +822,11 @@ static void setup_hierarchy(phz_ctx* c, Hierarchy& H) {
       if (L.S.p) {
         L.S32.alloc(L.S.n);
         convert<double, float>((long)L.S.n, L.S.p, L.S32.p, c->stream);
+        if (coarse_tiled_fits(L.N)) {
+          L.S16.alloc((size_t)26 * H.F * H.F * L.nn);
+          L.Sc.alloc((size_t)H.F * H.F * L.nn);
+          compact_stencil(H.F, L.nn, L.S.p, L.S16.p, L.Sc.p, c->stream);
+        }
       }
       if (L.Dinv.p) {
         L.Dinv32.alloc(L.Dinv.n);
@@ -883,17 +899,24 @@ static int coarse_kind_of(phz_ctx* c, Hierarchy& H, int l) {
   if (L.ckind >= 0) return L.ckind;
   int kind = 0;
   if (coarse_tiled_fits(L.N) && c->opt.coarse_kernel != 0) {
-    if (c->opt.coarse_kernel == 1) {
-      kind = 1;
+    if (c->opt.coarse_kernel >= 1) {
+      kind = c->opt.coarse_kernel;
     } else {
       DevBuf<float> x, y;
       x.alloc((size_t)H.F * 9 * L.nn);
       y.alloc((size_t)H.F * 9 * L.nn);
       PHZ_HIP(hipMemsetAsync(x.p, 0, x.n * sizeof(float), c->stream));
       const OpArgs<float> a = plain_args<float>(nullptr, y.p, 1.0f, 0.0f);
-      const float direct = time_launch(c, [&] { coarse_apply<float>(H.F, 9, L.N, L.S32.p, x.p, a, false, c->stream); });
+      float best = time_launch(c, [&] { coarse_apply<float>(H.F, 9, L.N, L.S32.p, x.p, a, false, c->stream); });
       const float tiled = time_launch(c, [&] { coarse_apply_tiled(H.F, L.N, L.S32.p, x.p, a, false, c->stream); });
-      if (clearly_faster(tiled, direct)) kind = 1;
+      if (clearly_faster(tiled, best)) {
+        kind = 1;
+        best = tiled;
+      }
+      const float compact = time_launch(c, [&] {
+        coarse_apply_tiled_compact(H.F, L.N, L.S16.p, L.Sc.p, x.p, a, false, c->stream);
+      });
+      if (clearly_faster(compact, best)) kind = 2;
     }
   }
   L.ckind = kind;
@@ -1965,7 +1988,7 @@ static int check_options(const phz_options* o, std::string& err) {
   if (o->elem_tile < -1 || o->elem_tile >= elem_tile_count()) { err = "elem_tile must be -1 or a tile index"; return PHZ_E_INVALID; }
   if (o->use_graph != 0 && o->use_graph != 1) { err = "use_graph must be 0 or 1"; return PHZ_E_INVALID; }
   if (o->fine_kernel < -1 || o->fine_kernel > 2) { err = "fine_kernel must be -1, 0, 1 or 2"; return PHZ_E_INVALID; }
-  if (o->coarse_kernel < -1 || o->coarse_kernel > 1) { err = "coarse_kernel must be -1, 0 or 1"; return PHZ_E_INVALID; }
+  if (o->coarse_kernel < -1 || o->coarse_kernel > 2) { err = "coarse_kernel must be -1, 0, 1 or 2"; return PHZ_E_INVALID; }
   if (o->solver != PHZ_SOLVER_SCP && o->solver != PHZ_SOLVER_DBP && o->solver != PHZ_SOLVER_TRICG) { err = "solver must be PHZ_SOLVER_SCP, PHZ_SOLVER_DBP or PHZ_SOLVER_TRICG"; return PHZ_E_INVALID; }
   if (o->solver == PHZ_SOLVER_TRICG && o->precision != PHZ_FP64) { err = "TriCG runs in float64 (precision PHZ_FP64)"; return PHZ_E_INVALID; }
   if (o->inner != 0 && o->inner != 1) { err = "inner must be 0 or 1"; return PHZ_E_INVALID; }
@@ -2784,7 +2807,9 @@ int phz_coarse_apply(phz_ctx* c, int level, int op, int nrhs, int precision, con
   } else {
     if (!L.S32.p) { c->err = "float32 coarse operators exist only in the float forms"; return PHZ_E_STATE; }
     const OpArgs<float> a = plain_args<float>(nullptr, (float*)y, 1.0f, 0.0f);
-    if (nrhs == 9 && coarse_kind_of(c, H, level) == 1) coarse_apply_tiled(H.F, L.N, L.S32.p, (const float*)x, a, false, c->stream);
+    const int kind = nrhs == 9 ? coarse_kind_of(c, H, level) : 0;
+    if (kind == 1) coarse_apply_tiled(H.F, L.N, L.S32.p, (const float*)x, a, false, c->stream);
+    else if (kind == 2) coarse_apply_tiled_compact(H.F, L.N, L.S16.p, L.Sc.p, (const float*)x, a, false, c->stream);
     else coarse_apply<float>(H.F, nrhs, L.N, L.S32.p, (const float*)x, a, false, c->stream);
   }
   sync(c);

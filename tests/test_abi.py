@@ -77,7 +77,7 @@ def test_options_rejected_before_device_use():
                        ("block_tile", [0, 0, 0, 3]), ("fine_kernel", 5), ("elem_tile", 7), ("solver", -1),
                        ("inner", 2), ("inner_eps", 0.0), ("inner_eps", 1.0), ("inner_maxit", 0),
                        ("warm_start", 2), ("solver", 3), ("smoothing", 2), ("bf16_terms_precond", 2),
-                       ("bf16_terms_precond", 0)):
+                       ("bf16_terms_precond", 0), ("coarse_kernel", 3), ("coarse_kernel", -2)):
         o = P.default_options(**{field: val})
         assert P._lib.phz_create(16, C.byref(m), C.byref(o), None, C.byref(h)) == -1, field
         assert not h.value

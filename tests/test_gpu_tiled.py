@@ -117,6 +117,88 @@ def test_per_block_pins(P):
         assert np.abs(MH - ref).max() / np.abs(ref).max() < 1e-8
 
 
+def difference_magnitude(M, x, F):
+    """sum over off-node entries j of row i of |M_ij| |x_j - x_(node of i,
+    field of j)|, per column: the size of the stencil's difference form
+    (rows of M sum to zero per field pair)."""
+    C = M.tocoo()
+    off = (C.row // F) != (C.col // F)
+    r, c, v = C.row[off], C.col[off], np.abs(C.data[off])
+    own = (r // F) * F + c % F
+    out = np.zeros((M.shape[0], x.shape[1]))
+    np.add.at(out, r, v[:, None] * np.abs(x[c] - x[own]))
+    return out
+
+
+def test_compact_coarse_stencil_vs_oracle(torch_cuda, P):
+    """The tiled coarse apply on compact stencils (coarse_kernel = 2: the
+    off-centre blocks in bf16, the centre block minus their sum) against the
+    oracle's R A P at level 1 of a 32^3 cell.  Inputs are a large constant per
+    column (1e4 and up) plus unit noise: the error stays within 2^-8 of the
+    difference form's magnitude plus float32 rounding, about 300x below what
+    rounding all 27 blocks to bf16 would give (2^-9 of the values)."""
+    torch = torch_cuda
+    n = 32
+    say("compact coarse stencil", n)
+    rho = synth.random_density(n, seed=34)
+    s = fe.ersatz_scale(rho, MAT.void_scale)
+    K, _ = cell.assemble(n, s, MND)
+    iu = field_index(n, [0, 1, 2])
+    A = K[iu][:, iu].tocsr()
+    Sb = krylov.schur_elementwise(n, s, MND).tocsr()
+    rng = np.random.default_rng(5)
+    with P.Context(n, MAT, precision=P.PHZ_FP32_IR, coarse_kernel=2) as ctx:
+        ctx.set_density(rho)
+        for op, M0, F in ((P.OP_A, A, 3), (P.OP_SBAR, Sb, 1)):
+            nl = n // 2
+            Pm = prolongation_sparse(nl, F)
+            Ml = (Pm.T @ M0 @ Pm).tocsr()
+            x = 1e4 * (1.0 + 0.1 * np.arange(9))[None, :] + rng.standard_normal((nl ** 3 * F, 9))
+            xd = torch.tensor(to_soa(x, nl ** 3, F, 9), dtype=torch.float32, device="cuda").contiguous()
+            yd = torch.zeros_like(xd)
+            ctx.coarse_apply(1, op, 9, xd.data_ptr(), yd.data_ptr(), precision=P.PHZ_FP32_IR)
+            torch.cuda.synchronize()
+            # the float32 input the kernel saw
+            x32 = from_soa(xd.cpu().double().numpy(), nl ** 3, F, 9)
+            y = from_soa(yd.cpu().double().numpy(), nl ** 3, F, 9)
+            ref = Ml @ x32
+            bound = 2.0 ** -8 * difference_magnitude(Ml, x32, F) + 2.0 ** -22 * (abs(Ml) @ abs(x32))
+            worst = (np.abs(y - ref) / bound).max()
+            print("op", op, "max error / bound", worst, "error / value-form bf16 scale",
+                  (np.abs(y - ref) / (2.0 ** -9 * (abs(Ml) @ abs(x32)))).max())
+            assert worst < 1.0, (op, worst)
+        st = ctx.stats()
+        print("coarse kernels", st["coarse_kernel"])
+        assert st["coarse_kernel"][1] == 2 and st["coarse_kernel"][9] == 2
+
+
+def test_grf32_compact_coarse_solve_oracle_residual(P):
+    """A 32^3 split-BF16 solve with the compact coarse stencils forced at
+    level 1: the oracle's residual at every node meets the FP64 target, and
+    the tensors match the solve on the float32 tiled stencils."""
+    from oracle import fullsize
+    n = 32
+    say("grf32 compact coarse solve")
+    phi = synth.grf_levelset(n, seed=2410, solid_fraction=0.5)
+    MH = {}
+    for kind in (1, 2):
+        with P.Context(n, MAT, precision=P.PHZ_BF16X3_IR, coarse_kernel=kind, rtol=1e-10) as ctx:
+            ctx.set_levelset(phi)
+            assert ctx.solve() == P.PHZ_OK
+            st = ctx.stats()
+            print("coarse kernel", kind, "iterations", max(st["iterations"]), "refinements", st["refinements"],
+                  "residual", max(st["true_residual"]), "levels", st["coarse_kernel"])
+            assert st["coarse_kernel"][1] == kind
+            MH[kind] = ctx.effective_nd()[0]
+            if kind == 2:
+                X, s, b = ctx.solution(), ctx.scale(), ctx.rhs()
+    rows = fullsize.residual_rows(n, s, MND, X, np.arange(n ** 3))
+    rel = np.linalg.norm(rows.reshape(-1, 9), axis=0) / np.linalg.norm(b.reshape(-1, 9), axis=0)
+    print("oracle residual / ||b|| per load", rel.max())
+    assert rel.max() < 1e-9
+    assert np.abs(MH[2] - MH[1]).max() / np.abs(MH[1]).max() < 1e-8
+
+
 def prolongation_sparse(nc, F):
     """Periodic trilinear prolongation (fine (2nc)^3 F x nc^3 F), sparse: a
     fine node at an even index coincides with coarse node i/2, at an odd index
