@@ -285,9 +285,9 @@ def main():
                     help="material smoothing of the optimisation run (element mean or quadrature points)")
     ap.add_argument("--reinit-every", type=int, default=5,
                     help="reinitialise every this many optimisation iterations (the paper: 5)")
-    ap.add_argument("--coarse-kernel", type=int, default=-1, choices=[-1, 0, 1],
-                    help="pin the coarse levels' float kernel (0 direct, 1 LDS-tiled where N %% 16 == 0; "
-                         "-1 = timed choice per level)")
+    ap.add_argument("--coarse-kernel", type=int, default=-1, choices=[-1, 0, 1, 2],
+                    help="pin the coarse levels' float kernel (0 direct, 1 LDS-tiled, 2 LDS-tiled on the compact "
+                         "bf16 stencils; 1 and 2 where N %% 16 == 0; -1 = timed choice per level)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the solve runs on a single MI355X; "
