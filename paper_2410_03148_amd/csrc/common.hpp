@@ -104,9 +104,11 @@ void build_stencil(int F, int N, const double* Ae, double* S, hipStream_t st);
 
 // Galerkin coarsening of element matrices: coarse element E gets
 // sum_children Q_c^T K_c Q_c with trilinear Q_c.  From the fine level
-// (s != nullptr: K_c = s_c kref) or from stored matrices Afine.
+// (s != nullptr: K_c = s_c kref, so K_E = sum_c s_c M_c with the eight fixed
+// M_c = Q_c^T kref Q_c, built into mq: 8 (8F)^2 doubles of device memory) or
+// from stored matrices Afine (mq unused).
 void galerkin_build(int F, int Nf, const double* s, const double* kref, const double* Afine,
-                    double* Acoarse, hipStream_t st);
+                    double* Acoarse, double* mq, hipStream_t st);
 
 // Inverse node-block diagonal (F x F per node), fine or coarse level.
 void diag_inv_fine(int F, int N, const double* s, const double* kref, double* Dinv,

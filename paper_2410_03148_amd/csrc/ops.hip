@@ -607,6 +607,46 @@ __global__ __launch_bounds__(576) void k_galerkin(unsigned Nf, const double* __r
   Acoarse[((size_t)((L * F + f) * S + col)) * nec + E] = acc;
 }
 
+// The eight fixed blocks of the first coarsening, M_c = Q_c^T kref Q_c
+// (block c: child c of a coarse element), mq[c][r][col] with r, col in
+// (corner, field) order.  One workgroup per child, one thread per entry.
+template <int F>
+__global__ void k_galerkin_ref(const double* __restrict__ kref, double* __restrict__ mq) {
+  constexpr int S = 8 * F;
+  const int cp = blockIdx.x, t = threadIdx.x;
+  const int r = t / S, col = t % S;
+  const int L = r / F, f = r % F, Lp = col / F, g = col % F;
+  double v = 0.0;
+  for (int l = 0; l < 8; ++l) {
+    const double wl = qweight(cp, l, L);
+    for (int lp = 0; lp < 8; ++lp) v += wl * kref[(l * F + f) * S + lp * F + g] * qweight(cp, lp, Lp);
+  }
+  mq[cp * S * S + t] = v;
+}
+
+// First coarsening, one thread per coarse element E: K_E = sum_c s_c M_c
+// over its eight children, written entry by entry (coalesced over E).
+template <int F>
+__global__ __launch_bounds__(256) void k_galerkin_first(unsigned Nf, const double* __restrict__ s,
+                                                        const double* __restrict__ mq,
+                                                        double* __restrict__ Acoarse) {
+  constexpr int S = 8 * F;
+  const unsigned Nc = Nf / 2, nec = Nc * Nc * Nc;
+  const unsigned E = blockIdx.x * blockDim.x + threadIdx.x;
+  if (E >= nec) return;
+  const unsigned I = E % Nc, J = (E / Nc) % Nc, Kk = E / (Nc * Nc);
+  double sc[8];
+#pragma unroll
+  for (int cp = 0; cp < 8; ++cp)
+    sc[cp] = s[(2 * I + (cp & 1)) + Nf * ((2 * J + ((cp >> 1) & 1)) + Nf * (2 * Kk + ((cp >> 2) & 1)))];
+  for (int t = 0; t < S * S; ++t) {
+    double v = 0.0;
+#pragma unroll
+    for (int cp = 0; cp < 8; ++cp) v += sc[cp] * mq[cp * S * S + t];
+    Acoarse[(size_t)t * nec + E] = v;
+  }
+}
+
 __device__ __forceinline__ void inv3(const double* a, double* o) {
   const double c00 = a[4] * a[8] - a[5] * a[7];
   const double c01 = a[5] * a[6] - a[3] * a[8];
@@ -927,14 +967,28 @@ void compact_stencil(int F, long nn, const double* S, unsigned short* S16, float
 }
 
 void galerkin_build(int F, int Nf, const double* s, const double* kref, const double* Afine, double* Acoarse,
-                    hipStream_t st) {
+                    double* mq, hipStream_t st) {
   const unsigned nec = (unsigned)(Nf / 2) * (Nf / 2) * (Nf / 2);
-  if (F == 3)
+  if (s) {
+    // from the fine level: the children's blocks are s_c kref, so
+    // K_E = sum_c s_c M_c with the eight fixed M_c = Q_c^T kref Q_c
+    const unsigned g = (nec + 255) / 256;
+    if (F == 3) {
+      hipLaunchKernelGGL(k_galerkin_ref<3>, dim3(8), dim3(576), 0, st, kref, mq);
+      hipLaunchKernelGGL(k_galerkin_first<3>, dim3(g), dim3(256), 0, st, (unsigned)Nf, s, mq, Acoarse);
+    } else if (F == 1) {
+      hipLaunchKernelGGL(k_galerkin_ref<1>, dim3(8), dim3(64), 0, st, kref, mq);
+      hipLaunchKernelGGL(k_galerkin_first<1>, dim3(g), dim3(256), 0, st, (unsigned)Nf, s, mq, Acoarse);
+    } else {
+      throw std::invalid_argument("galerkin F");
+    }
+  } else if (F == 3) {
     hipLaunchKernelGGL(k_galerkin<3>, dim3(nec), dim3(576), 0, st, (unsigned)Nf, s, kref, Afine, Acoarse);
-  else if (F == 1)
+  } else if (F == 1) {
     hipLaunchKernelGGL(k_galerkin<1>, dim3(nec), dim3(64), 0, st, (unsigned)Nf, s, kref, Afine, Acoarse);
-  else
+  } else {
     throw std::invalid_argument("galerkin F");
+  }
   PHZ_LAUNCH_CHECK();
 }
 

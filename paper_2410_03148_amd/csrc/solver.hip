@@ -93,6 +93,7 @@ struct Hierarchy {
   std::vector<std::unique_ptr<Level>> lv;
   int rows = 0;           // coarsest dense size
   DevBuf<double> Minv;
+  DevBuf<double> Mq;      // the first coarsening's eight fixed child blocks
 };
 
 template <typename T>
@@ -780,10 +781,12 @@ static void setup_hierarchy(phz_ctx* c, Hierarchy& H) {
     Level& L = *H.lv[l];
     if (l > 0) {
       L.Ae.alloc((size_t)8 * L.nn * F * 8 * F);
-      if (l == 1)
-        galerkin_build(F, H.lv[0]->N, c->s.p, krefd, nullptr, L.Ae.p, c->stream);
-      else
-        galerkin_build(F, H.lv[l - 1]->N, nullptr, nullptr, H.lv[l - 1]->Ae.p, L.Ae.p, c->stream);
+      if (l == 1) {
+        H.Mq.alloc((size_t)8 * (8 * F) * (8 * F));
+        galerkin_build(F, H.lv[0]->N, c->s.p, krefd, nullptr, L.Ae.p, H.Mq.p, c->stream);
+      } else {
+        galerkin_build(F, H.lv[l - 1]->N, nullptr, nullptr, H.lv[l - 1]->Ae.p, L.Ae.p, nullptr, c->stream);
+      }
     }
     if (l > 0) {
       L.S.alloc((size_t)27 * F * F * L.nn);
