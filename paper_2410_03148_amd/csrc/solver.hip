@@ -71,6 +71,7 @@ struct Level {
   // the centre block minus their sum (levels whose side is a multiple of 16)
   DevBuf<unsigned short> S16;
   DevBuf<float> Sc;
+  DevBuf<double> pv, pw;  // power-iteration vectors, kept across set-ups
   DevBuf<double> Dinv;    // node-block diagonal inverse
   DevBuf<float> Dinv32;
   double lmax = 0.0;
@@ -753,7 +754,10 @@ static void build_coarsest(phz_ctx* c, Hierarchy& H) {
 static double power_lmax(phz_ctx* c, Hierarchy& H, int l) {
   Level& L = *H.lv[l];
   const long cnt = L.nn * H.F;
-  DevBuf<double> v, w;
+  // kept on the level: every set-up asks for the same sizes, so no
+  // allocation (and no implicit synchronisation of a free) after the first
+  DevBuf<double>& v = L.pv;
+  DevBuf<double>& w = L.pw;
   v.alloc(cnt);
   w.alloc(cnt);
   double* nrm = c->small.p;
