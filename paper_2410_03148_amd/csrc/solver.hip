@@ -71,7 +71,7 @@ struct Level {
   // the centre block minus their sum (levels whose side is a multiple of 16)
   DevBuf<unsigned short> S16;
   DevBuf<float> Sc;
-  DevBuf<double> pv, pw;  // power-iteration vectors, kept across set-ups
+  DevBuf<double> pv, pw, py;  // power-iteration vectors, kept across set-ups
   DevBuf<double> Dinv;    // node-block diagonal inverse
   DevBuf<float> Dinv32;
   double lmax = 0.0;
@@ -756,21 +756,36 @@ static double power_lmax(phz_ctx* c, Hierarchy& H, int l) {
   const long cnt = L.nn * H.F;
   // kept on the level: every set-up asks for the same sizes, so no
   // allocation (and no implicit synchronisation of a free) after the first
-  DevBuf<double>& v = L.pv;
-  DevBuf<double>& w = L.pw;
-  v.alloc(cnt);
-  w.alloc(cnt);
+  L.pv.alloc(cnt);
+  L.pw.alloc(cnt);
+  L.py.alloc(cnt);
+  double* v = L.pv.p;
+  double* w = L.pw.p;
   double* nrm = c->small.p;
-  hash_fill(cnt, 12345u + 7u * l + 101u * H.F, v.p, c->stream);
-  col_norm2<double>(L.nn, H.F, 1, v.p, nrm, c->red_work.p, c->stream);
-  normalize_by<double>(cnt, nrm, v.p, v.p, c->stream);
+  hash_fill(cnt, 12345u + 7u * l + 101u * H.F, v, c->stream);
+  col_norm2<double>(L.nn, H.F, 1, v, nrm, c->red_work.p, c->stream);
+  normalize_by<double>(cnt, nrm, v, v, c->stream);
+  // each step w = D^-1 A v is one pass: the plain apply with its first
+  // Chebyshev step at coefficient 1 (y = A v is a by-product).  The direction
+  // does not depend on scale, so the iterate is normalised only every fifth
+  // step (its norm grows by about lambda_max per step) and before the last,
+  // whose ||w|| is the estimate
   const int iters = 20;
   for (int it = 0; it < iters; ++it) {
-    level_apply<double>(c, H, l, 1, v.p, nullptr, w.p, 1.0, 0.0);
-    cheby_first<double>(H.F, 1, L.nn, L.Dinv.p, w.p, w.p, w.p, c->one64.p, kChebyXNone, c->stream);
-    col_norm2<double>(L.nn, H.F, 1, w.p, nrm, c->red_work.p, c->stream);
-    normalize_by<double>(cnt, nrm, w.p, v.p, c->stream);
+    OpArgs<double> a = plain_args<double>(nullptr, L.py.p, 1.0, 0.0);
+    a.dinv = L.Dinv.p;
+    a.cab = c->one64.p;
+    a.d1 = w;
+    level_apply_args<double>(c, H, l, 1, v, a, false);
+    if (it + 1 == iters) break;
+    if ((it + 1) % 5 == 0 || it + 2 == iters) {
+      col_norm2<double>(L.nn, H.F, 1, w, nrm, c->red_work.p, c->stream);
+      normalize_by<double>(cnt, nrm, w, v, c->stream);
+    } else {
+      std::swap(v, w);
+    }
   }
+  col_norm2<double>(L.nn, H.F, 1, w, nrm, c->red_work.p, c->stream);
   double h = 0.0;
   PHZ_HIP(hipMemcpyAsync(&h, nrm, sizeof(double), hipMemcpyDeviceToHost, c->stream));
   sync(c);
