@@ -607,6 +607,53 @@ __global__ __launch_bounds__(576) void k_galerkin(unsigned Nf, const double* __r
   Acoarse[((size_t)((L * F + f) * S + col)) * nec + E] = acc;
 }
 
+// Coarsening of stored element matrices, G coarse elements per workgroup
+// (consecutive in x; Nc a multiple of G): the children of neighbouring
+// coarse elements sit two elements apart, so a thread's G reads of one
+// entry share cache lines, where one element per workgroup read one line
+// per value.
+template <int F, int G>
+__global__ __launch_bounds__(64 * F * F) void k_galerkin_stored(unsigned Nf, const double* __restrict__ Afine,
+                                                                double* __restrict__ Acoarse) {
+  constexpr int S = 8 * F;
+  __shared__ double Kc[G][S * S];
+  __shared__ double T1[G][S * S];
+  const unsigned Nc = Nf / 2;
+  const unsigned nec = Nc * Nc * Nc;
+  const unsigned nef = Nf * Nf * Nf;
+  const unsigned E0 = blockIdx.x * G;  // G consecutive coarse elements along x
+  const unsigned I0 = E0 % Nc, J = (E0 / Nc) % Nc, Kk = E0 / (Nc * Nc);
+  const int t = threadIdx.x;  // blockDim == S*S
+  const int r = t / S, col = t % S;
+  const int L = r / F, f = r % F, Lp = col / F, gq = col % F;
+  double acc[G];
+#pragma unroll
+  for (int g = 0; g < G; ++g) acc[g] = 0.0;
+  for (int cp = 0; cp < 8; ++cp) {
+    const unsigned ef0 = (2 * I0 + (cp & 1)) + Nf * ((2 * J + ((cp >> 1) & 1)) + Nf * (2 * Kk + ((cp >> 2) & 1)));
+    const int l0 = r / F, f0 = r % F;
+#pragma unroll
+    for (int g = 0; g < G; ++g) Kc[g][t] = Afine[((size_t)((l0 * F + f0) * S + col)) * nef + ef0 + 2 * g];
+    __syncthreads();
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      double v = 0.0;
+      for (int lp = 0; lp < 8; ++lp) v += Kc[g][r * S + lp * F + gq] * qweight(cp, lp, Lp);
+      T1[g][t] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      double v = 0.0;
+      for (int l = 0; l < 8; ++l) v += qweight(cp, l, L) * T1[g][(l * F + f) * S + col];
+      acc[g] += v;
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int g = 0; g < G; ++g) Acoarse[((size_t)((L * F + f) * S + col)) * nec + E0 + g] = acc[g];
+}
+
 // The eight fixed blocks of the first coarsening, M_c = Q_c^T kref Q_c
 // (block c: child c of a coarse element), mq[c][r][col] with r, col in
 // (corner, field) order.  One workgroup per child, one thread per entry.
@@ -982,6 +1029,13 @@ void galerkin_build(int F, int Nf, const double* s, const double* kref, const do
     } else {
       throw std::invalid_argument("galerkin F");
     }
+  } else if ((Nf / 2) % 4 == 0) {
+    if (F == 3)
+      hipLaunchKernelGGL((k_galerkin_stored<3, 4>), dim3(nec / 4), dim3(576), 0, st, (unsigned)Nf, Afine, Acoarse);
+    else if (F == 1)
+      hipLaunchKernelGGL((k_galerkin_stored<1, 4>), dim3(nec / 4), dim3(64), 0, st, (unsigned)Nf, Afine, Acoarse);
+    else
+      throw std::invalid_argument("galerkin F");
   } else if (F == 3) {
     hipLaunchKernelGGL(k_galerkin<3>, dim3(nec), dim3(576), 0, st, (unsigned)Nf, s, kref, Afine, Acoarse);
   } else if (F == 1) {
