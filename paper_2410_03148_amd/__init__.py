@@ -5,7 +5,7 @@ Every step of the computation runs in the library's HIP kernels; this
 module only marshals arguments.  PyTorch is used, when present, for device
 memory and streams (device tensors are passed by pointer).
 
-The library must be built (``python -m paper_2410_03148_amd.build``);
+The library must be built (``python paper_2410_03148_amd/build.py``);
 importing the package without it raises ImportError.
 """
 from __future__ import annotations
@@ -85,7 +85,7 @@ EXPORTS = [
 
 def _load():
     if not os.path.exists(LIB_PATH):
-        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2410_03148_amd.build`")
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python paper_2410_03148_amd/build.py`")
     lib = C.CDLL(LIB_PATH)
     vp, dp, ip = C.c_void_p, C.POINTER(C.c_double), C.c_int
     sig = {

@@ -1,6 +1,6 @@
 """Build libpiezohom.so (HIP, gfx950) in-tree with hipcc.
 
-Usage: python -m paper_2410_03148_amd.build  (or build() from Python).
+Usage: python paper_2410_03148_amd/build.py  (or build() from __graft_entry__).
 Every call recompiles all sources; objects go to _build/ next to this file.
 """
 from __future__ import annotations
