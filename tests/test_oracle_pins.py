@@ -476,3 +476,160 @@ def test_galerkin_rows_annihilate_constants_and_compact_form():
             assert (np.abs(Mc @ x - ref) / bound).max() < 1.0, name
             Mp = sp.csr_matrix((_bf16(C.data), (C.row, C.col)), shape=Ml.shape)
             assert (np.abs(Mp @ x - ref) / bound).max() > 100.0, name
+
+
+# ------------------------------------------------ smoothing and density map
+# Sec. 2.6 smooths the interface over about two elements; the reading is a
+# sinusoidal H of half-width eta = 2h evaluated at each element's mean phi.
+# These pins fix the shape, the symmetry and the band width of that map from
+# properties any correct smoothed Heaviside of that width has.
+
+def test_smoothed_heaviside_end_values_and_symmetry():
+    eta = 0.3
+    H = lambda t: fe.smoothed_heaviside(np.asarray(t, dtype=float), eta)
+    dH = lambda t: fe.smoothed_heaviside_deriv(np.asarray(t, dtype=float), eta)
+    assert abs(H(-eta)) < 1e-15 and abs(H(eta) - 1.0) < 1e-15 and abs(H(0.0) - 0.5) < 1e-15
+    assert H(-2 * eta) == 0.0 and H(2 * eta) == 1.0
+    assert abs(dH(eta)) < 1e-15 and abs(dH(-eta)) < 1e-15
+    t = np.linspace(-1.5 * eta, 1.5 * eta, 2001)
+    # H - step is odd: H(t) + H(-t) = 1
+    assert np.abs(H(t) + H(-t) - 1.0).max() < 1e-15
+    # monotone, continuous at the band edges, derivative consistent with H
+    assert np.all(np.diff(H(t)) >= 0.0)
+    for edge in (-eta, eta):
+        assert abs(H(edge - 1e-12) - H(edge + 1e-12)) < 1e-10
+    tt = np.linspace(-0.99 * eta, 0.99 * eta, 37)
+    d = 1e-7
+    fd = (H(tt + d) - H(tt - d)) / (2 * d)
+    assert np.abs(fd - dH(tt)).max() < 1e-6 / eta
+    # the integral of H' over the band is one
+    q = np.linspace(-eta, eta, 200001)
+    assert abs(np.trapezoid(dH(q), q) - 1.0) < 1e-9
+
+
+@pytest.mark.parametrize("offset", [0.0, 0.5])
+def test_slab_density_band_width_and_exact_volume(offset):
+    """A slab |z - 1/2| < w as a signed distance phi = |z - 1/2| - w (phi < 0
+    solid).  Each element's mean phi is the distance at its mid-plane, so the
+    element layers sample the distance at spacing h.  With the interfaces on
+    node planes (offset 0) the mid-planes sit at +-h/2, +-3h/2, ...; with them
+    on element mid-planes (offset 0.5) at 0, +-h, +-2h.  A half-width of two
+    elements puts exactly four (three) layers per interface strictly inside
+    (0, 1), the rest exactly 0 or 1; and because H - step is odd the samples
+    cancel in pairs, so the mean density equals the slab's exact volume 2w."""
+    n = 32
+    h = 1.0 / n
+    w = 0.25 + offset * h
+    z = np.arange(n) * h
+    phi_z = np.abs(z - 0.5) - w
+    phi = np.broadcast_to(phi_z[:, None, None], (n, n, n)).ravel()     # [k][j][i]
+    rho = fe.density_from_levelset(n, phi).reshape(n, n, n)
+    layers = rho[:, 0, 0]
+    assert np.all(rho == layers[:, None, None])
+    tol = 1e-14   # sin(pi) rounds to about 1e-16 at the band edges
+    inside = (layers > tol) & (layers < 1.0 - tol)
+    assert inside.sum() == (8 if offset == 0.0 else 6)
+    # the fractional layers are the ones within 2h of an interface
+    mid = (np.arange(n) + 0.5) * h
+    dist = np.minimum(np.abs(mid - (0.5 - w)), np.abs(mid - (0.5 + w)))
+    assert np.array_equal(inside, dist < 2 * h - 1e-12)
+    # solid (phi < 0) maps to rho = 1
+    assert np.all(np.abs(layers[np.abs(mid - 0.5) < w - 2 * h + 1e-12] - 1.0) < tol)
+    assert np.all(np.abs(layers[np.abs(mid - 0.5) > w + 2 * h - 1e-12]) < tol)
+    assert abs(layers.mean() - 2 * w) < 1e-14
+    # the same slab turned to lie along x
+    phi_x = np.broadcast_to(phi_z[None, None, :], (n, n, n)).ravel()
+    rho_x = fe.density_from_levelset(n, phi_x).reshape(n, n, n)
+    assert np.array_equal(rho_x[0, 0, :], layers)
+
+
+def test_density_chain_rule_matches_finite_differences():
+    """The element-form chain rule dJ/dphi_n (Sec. 2.1, Sec. 2.6 smoothing)
+    against central differences of J(phi) = sum_e c_e rho_e(phi) at nodes in
+    and near the band, and through the whole solve at n = 4."""
+    n = 8
+    rng = np.random.default_rng(31)
+    phi = synth.grf_levelset(n, seed=5, solid_fraction=0.5)
+    c = rng.standard_normal(n ** 3)
+    g = cell.grad_phi_from_rho(n, phi, c)
+    J = lambda p: float(c @ fe.density_from_levelset(n, p))
+    rho = fe.density_from_levelset(n, phi)
+    band_nodes = np.unique(cell.element_nodes(n)[(rho > 0) & (rho < 1)])
+    assert band_nodes.size > 50
+    picks = list(rng.choice(band_nodes, 24, replace=False)) + [int(np.argmax(np.abs(phi)))]
+    d = 1e-6
+    for node in picks:
+        pp = phi.copy(); pp[node] += d
+        pm = phi.copy(); pm[node] -= d
+        fd = (J(pp) - J(pm)) / (2 * d)
+        assert abs(fd - g[node]) <= 1e-6 * np.abs(g).max(), (node, fd, g[node])
+    # and through the solve: J = <W, M^H(rho(phi))>
+    n = 4
+    phi = synth.grf_levelset(n, seed=8, solid_fraction=0.5) * 0.3
+    r = cell.homogenise(n, MAT, phi=phi)
+    W = rng.standard_normal((9, 9))
+    gphi = cell.grad_phi_from_rho(n, phi, cell.grad_rho(n, MAT, r.X, W))
+    d = 1e-6
+    for node in (0, 9, 27, 50):
+        pp = phi.copy(); pp[node] += d
+        pm = phi.copy(); pm[node] -= d
+        fd = np.sum(W * (cell.homogenise(n, MAT, phi=pp, want_x=False).MH
+                         - cell.homogenise(n, MAT, phi=pm, want_x=False).MH)) / (2 * d)
+        assert abs(fd - gphi[node]) <= 1e-5 * np.abs(gphi).max(), (node, fd, gphi[node])
+
+
+# ------------------------------------------------------- bulk moduli
+def test_voigt_and_reuss_bulk_moduli_isotropic_equality_and_order():
+    """Sec. 2.3: B_Reuss <= B_Voigt, with equality for isotropic stiffness.
+    For isotropic C (Lame lam, mu) both equal the bulk modulus lam + 2 mu / 3,
+    which fixes both normalisations and B_Reuss's compliance block."""
+    lam, mu = 61.0e9, 27.0e9
+    C = np.zeros((6, 6))
+    C[:3, :3] = lam
+    C[[0, 1, 2], [0, 1, 2]] = lam + 2 * mu
+    C[[3, 4, 5], [3, 4, 5]] = mu
+    e = np.zeros((3, 6)); e[2, :3] = 3.0
+    kap = np.eye(3) * 5e-9
+    f = foms.foms(C, e, kap)
+    K = lam + 2 * mu / 3
+    assert abs(f["B_voigt"] - K) < 1e-12 * K and abs(f["B_reuss"] - K) < 1e-12 * K
+    # anisotropic: random SPD stiffness matrices and the base material
+    rng = np.random.default_rng(3)
+    for _ in range(20):
+        A = rng.standard_normal((6, 6))
+        Cr = A @ A.T + 0.1 * np.eye(6)
+        fr = foms.foms(Cr, e, kap)
+        assert fr["B_reuss"] <= fr["B_voigt"] * (1 + 1e-14)
+    for m in (synth.material_workload(), synth.material_pzt5a()):
+        fm = foms.foms(m.C, m.e, m.kappa)
+        assert fm["B_reuss"] < fm["B_voigt"]
+    # and on solved cells
+    for seed in (1, 2):
+        r = cell.homogenise(6, MAT, phi=synth.grf_levelset(6, seed=seed), want_x=False)
+        fr = foms.foms(r.C, r.e, r.kappa)
+        assert 0 < fr["B_reuss"] < fr["B_voigt"]
+
+
+def test_table3_kh_through_the_oracle():
+    """P9 through oracle.foms: tensors built to have a Table 3 row's printed
+    d_h, g_h and B_Reuss give that row's printed k_h.  C is orthotropic with
+    normal stiffnesses (c1, c1, c3), c1 = 10 B_Reuss, c3 chosen to give the
+    row's B_Reuss, so that B_Voigt is about 2.4 B_Reuss (as for the paper's
+    soft-in-z designs); e has only e31 = e32 = e33 = a, so d_h = a / B_Reuss; kappa_33 is set so
+    that the stress-free permittivity gives g_h."""
+    pv = json.load(open(os.path.join(HERE, "golden", "paper_values.json")))
+    for row in pv["table3_rows"]["rows"]:
+        c1 = 10.0 * row["B_reuss"]
+        c3 = 1.0 / (1.0 / row["B_reuss"] - 2.0 / c1)
+        C = np.diag([c1, c1, c3, 0.3 * c1, 0.3 * c1, 0.3 * c1])
+        a = row["d_h"] * row["B_reuss"]
+        e = np.zeros((3, 6)); e[2, :3] = a
+        kap = np.eye(3) * 1e-9
+        kap[2, 2] = row["d_h"] / row["g_h"] - a * row["d_h"]
+        assert kap[2, 2] > 0
+        f = foms.foms(C, e, kap)
+        assert abs(f["d_h"] / row["d_h"] - 1) < 1e-12
+        assert abs(f["g_h"] / row["g_h"] - 1) < 1e-12
+        assert abs(f["B_reuss"] / row["B_reuss"] - 1) < 1e-12
+        assert f["B_voigt"] > 2.0 * f["B_reuss"]
+        assert abs(f["k_h"] - row["k_h"]) < 1.5e-3
