@@ -11,6 +11,7 @@ importing the package without it raises ImportError.
 from __future__ import annotations
 
 import ctypes as C
+import functools
 import os
 
 import numpy as np
@@ -130,6 +131,15 @@ def _load():
 _lib = _load()
 
 
+def _current_device():
+    """Index of the current HIP device as torch sees it, or None without torch or a GPU."""
+    try:
+        import torch
+    except ImportError:
+        return None
+    return torch.cuda.current_device() if torch.cuda.is_available() else None
+
+
 class PiezoError(RuntimeError):
     def __init__(self, status, msg):
         super().__init__(f"{_lib.phz_strerror(status).decode()} ({status}): {msg}")
@@ -158,15 +168,45 @@ def _dptr(a):
     return a.ctypes.data_as(C.POINTER(C.c_double))
 
 
-def _arg(buf, n, dtype=np.float64):
-    """(pointer, on_device, keepalive) for a host numpy array or a device tensor."""
-    if hasattr(buf, "data_ptr"):  # torch tensor
+def _is_tensor(buf):
+    return hasattr(buf, "data_ptr") and hasattr(buf, "is_cuda")
+
+
+def _arg(buf, n, device=None, out=False, what="array"):
+    """(pointer, on_device, keepalive) for a host array or a device tensor of n float64 values.
+
+    A device tensor passes by pointer, so it must be float64, contiguous, hold exactly n values and
+    live on the context's device (index `device`); anything else raises ValueError before the
+    library is called.  A host input is converted to a contiguous float64 copy; a host output
+    (out=True) must already be a contiguous float64 array (or CPU tensor) of n values, because the
+    library writes into its memory."""
+    if _is_tensor(buf):
         if buf.is_cuda:
-            assert buf.is_contiguous() and buf.numel() == n
+            import torch
+            if buf.dtype != torch.float64:
+                raise ValueError(f"{what}: device tensor must be float64, got {buf.dtype}")
+            if not buf.is_contiguous():
+                raise ValueError(f"{what}: device tensor must be contiguous")
+            if buf.numel() != n:
+                raise ValueError(f"{what}: device tensor must hold {n} values, got {buf.numel()}")
+            if device is not None and buf.device.index != device:
+                raise ValueError(f"{what}: tensor on cuda:{buf.device.index}, context on cuda:{device}")
             return C.c_void_p(buf.data_ptr()), 1, buf
-        buf = buf.detach().cpu().numpy()
-    a = np.ascontiguousarray(buf, dtype=dtype).ravel()
-    assert a.size == n, (a.size, n)
+        if out:
+            import torch
+            if buf.dtype != torch.float64 or not buf.is_contiguous() or buf.numel() != n:
+                raise ValueError(f"{what}: output tensor must be contiguous float64 with {n} values")
+            a = buf.numpy()
+            return C.c_void_p(a.ctypes.data), 0, a
+        buf = buf.detach().numpy()
+    if out:
+        if not isinstance(buf, np.ndarray) or buf.dtype != np.float64 or not buf.flags.c_contiguous \
+                or buf.size != n or not buf.flags.writeable:
+            raise ValueError(f"{what}: output array must be a writable contiguous float64 array of {n} values")
+        return C.c_void_p(buf.ctypes.data), 0, buf
+    a = np.ascontiguousarray(buf, dtype=np.float64).ravel()
+    if a.size != n:
+        raise ValueError(f"{what}: expected {n} values, got {a.size}")
     return C.c_void_p(a.ctypes.data), 0, a
 
 
@@ -195,6 +235,8 @@ class Context:
         self.nn = n ** 3
         self._mat = make_material(material)
         self._opt = default_options(**opts)
+        self.device = _current_device()
+        self._state = 0    # advances whenever the geometry or the solution may change
         h = C.c_void_p()
         st = _lib.phz_create(n, C.byref(self._mat), C.byref(self._opt),
                              C.c_void_p(stream) if stream else None, C.byref(h))
@@ -224,14 +266,17 @@ class Context:
     def set_options(self, **opts):
         for k, v in opts.items():
             _set_option(self._opt, k, v)
+        self._state += 1
         self._check(_lib.phz_set_options(self._h, C.byref(self._opt)), "phz_set_options")
 
     def set_levelset(self, phi):
-        p, dev, keep = _arg(phi, self.nn)
+        p, dev, keep = _arg(phi, self.nn, self.device, what="set_levelset")
+        self._state += 1
         self._check(_lib.phz_set_levelset(self._h, p, dev), "phz_set_levelset")
 
     def set_density(self, rho):
-        p, dev, keep = _arg(rho, self.nn)
+        p, dev, keep = _arg(rho, self.nn, self.device, what="set_density")
+        self._state += 1
         self._check(_lib.phz_set_density(self._h, p, dev), "phz_set_density")
 
     def scale(self):
@@ -241,6 +286,7 @@ class Context:
 
     def solve(self):
         """Solve the nine cell problems; returns PHZ_OK or PHZ_NOT_CONVERGED."""
+        self._state += 1
         return self._check(_lib.phz_solve(self._h), "phz_solve", allow_nc=True)
 
     def effective(self):
@@ -276,7 +322,7 @@ class Context:
     def solution(self, out=None):
         """X as [N^3, 4, 9] (host numpy, or into a device tensor `out`)."""
         if out is not None:
-            p, dev, keep = _arg(out, self.nn * 36)
+            p, dev, keep = _arg(out, self.nn * 36, self.device, out=True, what="solution(out=)")
             self._check(_lib.phz_get_solution(self._h, p, dev), "phz_get_solution")
             return out
         X = np.zeros(self.nn * 36)
@@ -287,7 +333,7 @@ class Context:
         if X is None:
             self._check(_lib.phz_set_initial_guess(self._h, None, 0), "phz_set_initial_guess")
             return
-        p, dev, keep = _arg(X, self.nn * 36)
+        p, dev, keep = _arg(X, self.nn * 36, self.device, what="set_initial_guess")
         self._check(_lib.phz_set_initial_guess(self._h, p, dev), "phz_set_initial_guess")
 
     def rhs(self):
@@ -299,11 +345,14 @@ class Context:
         """dJ/drho (and dJ/dphi) for upstream gradients w.r.t. (C^H, e^H, kappa^H)."""
         z = lambda a, n: np.ascontiguousarray(np.zeros(n) if a is None else a, dtype=np.float64).ravel()
         gC, ge, gk = z(gC, 36), z(ge, 18), z(gk, 9)
-        dev = out_rho is not None and hasattr(out_rho, "is_cuda") and out_rho.is_cuda
-        if dev:
-            prho = C.c_void_p(out_rho.data_ptr())
-            pphi = C.c_void_p(out_phi.data_ptr()) if out_phi is not None else None
-            self._check(_lib.phz_backward(self._h, _dptr(gC), _dptr(ge), _dptr(gk), prho, pphi, 1), "phz_backward")
+        if out_rho is not None:
+            prho, dev, _ = _arg(out_rho, self.nn, self.device, out=True, what="backward(out_rho=)")
+            pphi = None
+            if out_phi is not None:
+                pphi, dphi, _ = _arg(out_phi, self.nn, self.device, out=True, what="backward(out_phi=)")
+                if dphi != dev:
+                    raise ValueError("backward: out_rho and out_phi must both be on the host or both on the device")
+            self._check(_lib.phz_backward(self._h, _dptr(gC), _dptr(ge), _dptr(gk), prho, pphi, dev), "phz_backward")
             return out_rho, out_phi
         grho = np.zeros(self.nn)
         gphi = np.zeros(self.nn) if want_phi else None
@@ -319,13 +368,17 @@ class Context:
             st = _lib.phz_hj_step(self._h, None, cfl, optr, 0)
         else:
             v = np.ascontiguousarray(velocity, dtype=np.float64).ravel()
+            if v.size != self.nn:
+                raise ValueError(f"hj_step: velocity must hold {self.nn} values")
             st = _lib.phz_hj_step(self._h, C.c_void_p(v.ctypes.data), cfl, optr, 0)
+        self._state += 1
         self._check(st, "phz_hj_step")
         return out
 
     def reinit(self, steps=20, cfl=0.5, subcell=False, return_phi=True):
         """Reinitialise the level set towards a signed distance (phz_reinit; subcell: Russo-Smereka fix)."""
         out = np.zeros(self.nn) if return_phi else None
+        self._state += 1
         self._check(_lib.phz_reinit(self._h, steps, cfl, 1 if subcell else 0,
                                     C.c_void_p(out.ctypes.data) if return_phi else None, 0), "phz_reinit")
         return out
@@ -333,6 +386,8 @@ class Context:
     def levelset_gradient(self, grad_rho):
         """dJ/dphi from an element gradient dJ/drho (phz_levelset_gradient)."""
         g = np.ascontiguousarray(grad_rho, dtype=np.float64).ravel()
+        if g.size != self.nn:
+            raise ValueError(f"levelset_gradient: grad_rho must hold {self.nn} values")
         out = np.zeros(self.nn)
         self._check(_lib.phz_levelset_gradient(self._h, _dptr(g), C.c_void_p(out.ctypes.data), 0),
                     "phz_levelset_gradient")
@@ -350,6 +405,8 @@ class Context:
         jo = np.ascontiguousarray(j_obj, dtype=np.float64).ravel()
         jc = [np.ascontiguousarray(j, dtype=np.float64).ravel() for j in j_cons]
         vi = np.ascontiguousarray(viol, dtype=np.float64).ravel()
+        if jo.size != self.nn or any(j.size != self.nn for j in jc) or vi.size != len(jc):
+            raise ValueError(f"hpm_velocity: node columns of {self.nn} values and one violation per constraint")
         ptrs = (C.c_void_p * max(len(jc), 1))(*[j.ctypes.data for j in jc])
         out = np.zeros(self.nn)
         self._check(_lib.phz_hpm_velocity(self._h, len(jc), _dptr(jo), ptrs, _dptr(vi) if len(jc) else None,
@@ -400,31 +457,46 @@ def homogenise(n, material, phi=None, rho=None, **opts):
                 "status": status}
 
 
+@functools.lru_cache(maxsize=None)
 def _autograd():
     import torch
 
     class Homogenise(torch.autograd.Function):
         """(C^H, e^H, kappa^H) = F(rho) with a hand-written backward.
 
-        forward: rho (float64 tensor [N^3], any device) -> three float64 CPU
-        tensors; backward: phz_backward turns the upstream gradients into
-        dJ/drho on rho's device.
+        forward: rho (float64 tensor [N^3] on the context's device, or on
+        the host) -> three float64 CPU tensors (SI); it raises if the solve
+        does not converge.  backward: phz_backward turns the upstream
+        gradients into dJ/drho on rho's device.  The backward uses the
+        solution the context holds, so it raises if the context has been
+        given a new geometry, options or solve since this forward.
         """
 
         @staticmethod
         def forward(ctx_, rho, context):
-            context.set_density(rho.detach().contiguous())
-            context.solve()
+            context.set_density(rho.detach())
+            status = context.solve()
+            if status != PHZ_OK:
+                raise PiezoError(status, "Homogenise: the cell solve did not converge")
             Cm, e, k = context.effective()
             ctx_.context = context
+            ctx_.state = context._state
             ctx_.device = rho.device
             return (torch.from_numpy(Cm.copy()), torch.from_numpy(e.copy()), torch.from_numpy(k.copy()))
 
         @staticmethod
         def backward(ctx_, gC, ge, gk):
+            context = ctx_.context
+            if context._state != ctx_.state:
+                raise RuntimeError("Homogenise.backward: the context changed since this forward "
+                                   "(a new geometry, options or solve); run the forward again")
             cvt = lambda g: None if g is None else g.detach().cpu().double().numpy()
-            g = ctx_.context.backward(cvt(gC), cvt(ge), cvt(gk))
-            return torch.from_numpy(g).to(ctx_.device), None
+            if ctx_.device.type == "cuda":
+                out = torch.empty(context.nn, dtype=torch.float64, device=ctx_.device)
+                context.backward(cvt(gC), cvt(ge), cvt(gk), out_rho=out)
+                return out, None
+            g = context.backward(cvt(gC), cvt(ge), cvt(gk))
+            return torch.from_numpy(g), None
 
     return Homogenise
 
