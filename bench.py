@@ -81,20 +81,133 @@ def measured_traffic(label, tile=None):
     return k["bytes_per_launch"]
 
 
-def cpu_baseline(n_sample=16):
-    """Time the CPU oracle on a bounded sample in a single-threaded child."""
+_CPU_ENV = dict(OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
+
+
+def _cpu_child(code, timeout=3600):
+    """Run oracle timing code in a single-threaded child process; returns its
+    last stdout line parsed as JSON."""
+    env = dict(os.environ, **_CPU_ENV)
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env, timeout=timeout)
+    if out.returncode != 0:
+        raise RuntimeError(out.stderr[-2000:])
+    return json.loads(out.stdout.strip().splitlines()[-1])
+
+
+def cpu_solve_seconds(n, reps):
+    """Wall seconds of the oracle's whole homogenisation (assembly, sparse LU,
+    nine solves, reduction) of the n^3 random-field cell, one per repetition."""
     code = (
-        "import time,sys; sys.path.insert(0, %r)\n"
+        "import time,sys,json; sys.path.insert(0, %r)\n"
         "import synth\nfrom oracle import cell\n"
         "m = synth.material_workload()\n"
         "phi = synth.grf_levelset(%d, seed=2410, solid_fraction=0.3)\n"
-        "t = time.perf_counter(); cell.homogenise(%d, m, phi=phi, want_x=False)\n"
-        "print(time.perf_counter() - t)\n" % (ROOT, n_sample, n_sample))
-    env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
-    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env, timeout=600)
-    if out.returncode != 0:
-        raise RuntimeError(out.stderr)
-    return float(out.stdout.strip().splitlines()[-1])
+        "ts = []\n"
+        "for _ in range(%d):\n"
+        "    t = time.perf_counter(); cell.homogenise(%d, m, phi=phi, want_x=False)\n"
+        "    ts.append(time.perf_counter() - t)\n"
+        "print(json.dumps(ts))\n" % (ROOT, n, reps, n))
+    return _cpu_child(code)
+
+
+def cpu_apply_seconds(n, reps, csr=False):
+    """Wall seconds of one oracle operator apply K X on nine columns at n^3:
+    the matrix-free element form (oracle.fullsize), or with csr=True the
+    assembled CSR matrix (oracle.cell.assemble, assembly not timed).  The
+    second value is the CSR's stored nonzeros (0 for the element form)."""
+    code = (
+        "import time,sys,json; sys.path.insert(0, %r)\n"
+        "import numpy as np\nimport synth\nfrom oracle import cell, fe, fullsize\n"
+        "m = synth.material_workload(); M = fe.nondim_matrix(m); n = %d\n"
+        "s = fe.ersatz_scale(fe.density_from_levelset(n, synth.grf_levelset(n, seed=2410, solid_fraction=0.3)),"
+        " m.void_scale)\n"
+        "X = np.random.default_rng(0).standard_normal((4 * n ** 3, 9))\n"
+        "nnz = 0\n"
+        "if %r:\n"
+        "    K, _ = cell.assemble(n, s, M); nnz = int(K.nnz)\n"
+        "    f = lambda: K @ X\n"
+        "else:\n"
+        "    f = lambda: fullsize.element_apply(n, s, M, X)\n"
+        "ts = []\n"
+        "for _ in range(%d):\n"
+        "    t = time.perf_counter(); f(); ts.append(time.perf_counter() - t)\n"
+        "print(json.dumps([ts, nnz]))\n" % (ROOT, n, bool(csr), reps))
+    return _cpu_child(code)
+
+
+def cpu_baseline(n, iterations, fine_launches_per_iteration):
+    """The CPU oracle on bounded samples of the workload, timed on this host's
+    cores in single-threaded children: whole homogenisations at 12^3 and 16^3
+    (median of 3; their ratio gives the growth exponent of the direct solve),
+    the assembled CSR operator applied to nine columns at 32^3 (median of 3,
+    assembly not timed) and the matrix-free operator apply at the full size
+    (once).  No n^3 oracle solve is run (a direct one would take hours); two
+    labelled estimates stand in for it, and `value` is the one more
+    favourable to the CPU:
+      direct: the 16^3 time grown to n^3 with the measured exponent;
+      iterative: the CSR apply grown to n^3 in proportion to its nonzeros
+      (linear in the cell's nodes), times the GPU solve's operator-apply count
+      (iterations x fine-level applies per iteration): the oracle's fastest
+      operator running the GPU path's iteration count."""
+    t12 = float(np.median(cpu_solve_seconds(12, 3)))
+    t16 = float(np.median(cpu_solve_seconds(16, 3)))
+    p = float(np.log(t16 / t12) / np.log(16 ** 3 / 12 ** 3))
+    ts, nnz32 = cpu_apply_seconds(32, 3, csr=True)
+    t_csr32 = float(np.median(ts))
+    t_csr = t_csr32 * (n / 32) ** 3
+    ts, _ = cpu_apply_seconds(n, 1)
+    t_apply = float(ts[0])
+    t_direct = t16 * (n ** 3 / 16 ** 3) ** p
+    t_iter = min(t_csr, t_apply) * iterations * fine_launches_per_iteration
+    best = min(t_direct, t_iter)
+    return {
+        "value": 1.0 / best, "unit": "solves/s", "cores": 1, "kind": "oracle",
+        "sample": (f"oracle (numpy/scipy, one thread) timed on this host: nine-load homogenisations (sparse LU) at "
+                   f"12^3 {t12:.2f} s and 16^3 {t16:.2f} s (median of 3), growth exponent {p:.2f} in dofs; CSR "
+                   f"operator on nine columns at 32^3 {t_csr32 * 1e3:.1f} ms ({nnz32} nonzeros, median of 3), "
+                   f"{t_csr:.2f} s grown to {n}^3; matrix-free apply at {n}^3 {t_apply:.2f} s.  value is an "
+                   f"estimate, the more favourable to the CPU of: direct {t_direct:.0f} s per {n}^3 solve (16^3 "
+                   f"grown with the exponent) and iterative {t_iter:.0f} s ({iterations} iterations x "
+                   f"{fine_launches_per_iteration:.1f} operator applies per iteration x the faster apply)"),
+        "measured": {"solve_s_12": t12, "solve_s_16": t16, "exponent": p, "apply9_csr_s_32": t_csr32,
+                     "csr_nnz_32": nnz32, f"apply9_element_s_{n}": t_apply},
+        "estimates_s": {"direct": t_direct, "iterative": t_iter, f"apply9_csr_s_{n}_grown": t_csr},
+        "host_cores_available": len(os.sched_getaffinity(0)),
+    }
+
+
+def cpu_sweep():
+    """Longer oracle timings for the record (a few minutes and up to about 100
+    GB of host memory): direct solves at 12^3 to 24^3 and CSR applies at 64^3
+    and 128^3 next to the matrix-free ones."""
+    rows = {}
+    for n, reps in ((12, 3), (16, 3), (20, 1), (24, 1)):
+        rows[f"solve_s_{n}"] = cpu_solve_seconds(n, reps)
+        print(f"[bench] cpu sweep: solve {n}^3 {rows[f'solve_s_{n}']}", file=sys.stderr, flush=True)
+    for n in (64, 128):
+        rows[f"apply9_element_s_{n}"] = cpu_apply_seconds(n, 3)[0]
+        print(f"[bench] cpu sweep: element apply {n}^3 {rows[f'apply9_element_s_{n}']}", file=sys.stderr, flush=True)
+        ts, nnz = cpu_apply_seconds(n, 3, csr=True)
+        rows[f"apply9_csr_s_{n}"] = ts
+        rows[f"csr_nnz_{n}"] = nnz
+        print(f"[bench] cpu sweep: CSR apply {n}^3 {ts} (nnz {nnz})", file=sys.stderr, flush=True)
+    med = {k: float(np.median(v)) for k, v in rows.items() if k.startswith("solve_s_")}
+    ns = np.array([int(k.split("_")[-1]) for k in med])
+    ts = np.array(list(med.values()))
+    slope = float(np.polyfit(np.log(ns ** 3.0), np.log(ts), 1)[0])
+    return {"study": "CPU oracle timings, one thread", "cpu": _cpu_model(), "host_cores_available":
+            len(os.sched_getaffinity(0)), "raw": rows, "solve_median_s": med,
+            "solve_exponent_fit_12_to_24": slope}
+
+
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def solver_study(P, torch, synth, mat, dev, only=None):
@@ -285,6 +398,17 @@ def main():
                     help="material smoothing of the optimisation run (element mean or quadrature points)")
     ap.add_argument("--reinit-every", type=int, default=5,
                     help="reinitialise every this many optimisation iterations (the paper: 5)")
+    ap.add_argument("--graph", action="store_true",
+                    help="run the benchmarked form with every Arnoldi step replayed from a captured HIP graph "
+                         "(per-kernel event timing then covers the launches outside the graphs only)")
+    ap.add_argument("--no-kernel-timing", action="store_true",
+                    help="time the steps without per-kernel HIP events (no roofline figures)")
+    ap.add_argument("--full-kernel-timing", action="store_true",
+                    help="bracket every timed kernel class (coarse levels, preconditioner, Arnoldi) with HIP events, "
+                         "not only the fine-level operator launches (about 5%% slower steps)")
+    ap.add_argument("--cpu-sweep", action="store_true",
+                    help="instead of the step benchmark: longer CPU oracle timings (direct solves at 12^3..24^3, "
+                         "element and CSR applies at 64^3 and 128^3); prints one JSON line")
     ap.add_argument("--coarse-kernel", type=int, default=-1, choices=[-1, 0, 1, 2],
                     help="pin the coarse levels' float kernel (0 direct, 1 LDS-tiled, 2 LDS-tiled on the compact "
                          "bf16 stencils; 1 and 2 where N %% 16 == 0; -1 = timed choice per level)")
@@ -293,6 +417,10 @@ def main():
         print("bench.py measures one GPU: the solve runs on a single MI355X; "
               "multi-GPU sharding is not part of this build", file=sys.stderr)
         sys.exit(2)
+
+    if args.cpu_sweep:
+        print(json.dumps(cpu_sweep()))
+        return
 
     import torch
     import synth
@@ -319,6 +447,10 @@ def main():
         "fp64": dict(precision=P.PHZ_FP64, batched=1, restart=15, vcycles_a=2),
         "fp64_sequential": dict(precision=P.PHZ_FP64, batched=0, restart=30, vcycles_a=2),
     }
+    # the same float forms with every Arnoldi step replayed from a captured
+    # HIP graph
+    forms["bf16x3ir_graph"] = dict(forms["bf16x3ir"], use_graph=1)
+    forms["fp32ir_graph"] = dict(forms["fp32ir"], use_graph=1)
 
     pins = {}
     if args.block_kernels:
@@ -329,13 +461,16 @@ def main():
         pins["coarse_kernel"] = args.coarse_kernel
 
     def make_ctx(form):
-        return P.Context(n, mat, stream=stream.cuda_stream, rtol=1e-10, **forms[form],
-                         **(pins if form == args.precision else {}))
+        extra = dict(pins) if form == args.precision else {}
+        if form == args.precision and args.graph:
+            extra["use_graph"] = 1
+        return P.Context(n, mat, stream=stream.cuda_stream, rtol=1e-10, **forms[form], **extra)
 
     grad_d = torch.empty(n ** 3, dtype=torch.float64, device=dev)
+    geometry = {"phi": phi_d}
 
     def step(ctx):
-        ctx.set_levelset(phi_d)
+        ctx.set_levelset(geometry["phi"])
         st = ctx.solve()
         Cm, e, k = ctx.effective()
         f, (gC, ge, gk) = P.foms(Cm, e, k, grad_of="d_h")
@@ -352,7 +487,7 @@ def main():
             log(f"warmup step {i + 1}/{warmup} done")
         torch.cuda.synchronize()
         if timing:
-            ctx.kernel_timing(True)
+            ctx.kernel_timing(True, fine_only=not args.full_kernel_timing)
         t0 = time.perf_counter()
         for i in range(steps):
             st, tens, f = step(ctx)
@@ -384,7 +519,7 @@ def main():
         del src, dst
 
     ctx = make_ctx(args.precision)
-    ms, status, tens, f = run(ctx, args.warmup, args.steps, timing=True)
+    ms, status, tens, f = run(ctx, args.warmup, args.steps, timing=not args.no_kernel_timing)
     stats = ctx.stats()
     ktimes = ctx.kernel_times()
     ctx.kernel_timing(False)
@@ -454,7 +589,9 @@ def main():
                    "true_residual_max": max(stats["true_residual"]),
                    "setup_ms": stats["setup_ms"], "solve_ms": stats["solve_ms"],
                    "fine_kernels": stats["fine_kernel"], "mfma_tiles_full_A_B_S": stats["elem_tile"],
-                   "coarse_kernels_A_S": [stats["coarse_kernel"][1:8], stats["coarse_kernel"][9:16]]},
+                   "coarse_kernels_A_S": [stats["coarse_kernel"][1:8], stats["coarse_kernel"][9:16]],
+                   "split_products_operator_precond": ([3, 1] if args.precision == "bf16x3ir" else None),
+                   "final_precision": stats["final_precision"], "fallbacks": stats["fallbacks"]},
     }
 
     # dominant single kernel from the live event timing of the timed steps
@@ -503,35 +640,53 @@ def main():
         result.setdefault("operator", {})["apply_median"] = op_bench
     result["backward_ms"] = backward_ms
 
+    def compare_form(form, ref_tens, ref_ms, steps):
+        c64 = make_ctx(form)
+        ms64, st64, t64, f64 = run(c64, 1, steps)
+        s64 = c64.stats()
+        c64.close()
+        errs = {nm: float(np.linalg.norm(a - b) / np.linalg.norm(b)) for nm, a, b in zip(("C", "e", "kappa"), ref_tens, t64)}
+        return {"solves_per_s": 1.0 / ms64, "speedup_of_mixed": ms64 / ref_ms, "status": st64,
+                "iterations_max": max(s64["iterations"]), "refinements": s64["refinements"],
+                "true_residual_max": max(s64["true_residual"]), "restart": forms[form]["restart"],
+                "final_precision": s64["final_precision"], "fallbacks": s64["fallbacks"],
+                "use_graph": forms[form].get("use_graph", 0),
+                "rel_err_of_mixed": errs, "max_rel_err_of_mixed": max(errs.values()), "tensors": t64}
+
     if not args.no_compare and prec != P.PHZ_FP64:
         cmp = {}
-        for form in ("fp32ir", "fp64", "fp64_sequential"):
-            if form == args.precision:
+        for form in ("fp32ir", "fp64", "fp64_sequential", args.precision + "_graph"):
+            if form == args.precision or form not in forms:
                 continue
             if form == "fp64_sequential" and args.no_sequential:
                 continue
-            c64 = make_ctx(form)
-            ms64, st64, t64, f64 = run(c64, 1, 1 if form == "fp64_sequential" else 2)
-            s64 = c64.stats()
-            c64.close()
-            errs = {nm: float(np.linalg.norm(a - b) / np.linalg.norm(b)) for nm, a, b in zip(("C", "e", "kappa"), tens, t64)}
-            cmp[form] = {"solves_per_s": 1.0 / ms64, "speedup_of_mixed": ms64 / ms, "status": st64,
-                         "iterations_max": max(s64["iterations"]), "refinements": s64["refinements"],
-                         "true_residual_max": max(s64["true_residual"]), "restart": forms[form]["restart"],
-                         "rel_err_of_mixed": errs, "max_rel_err_of_mixed": max(errs.values())}
+            cmp[form] = compare_form(form, tens, ms, 1 if form == "fp64_sequential" else 2)
+            cmp[form].pop("tensors")
             log(f"{form} comparison done")
+        # the other solid fraction of the workload: the default form against
+        # FP64 batched on that cell
+        other = 0.7 if abs(args.solid_fraction - 0.3) < 1e-12 else 0.3
+        geometry["phi"] = torch.tensor(synth.grf_levelset(n, seed=2410, solid_fraction=other), device=dev)
+        mixed = compare_form(args.precision, tens, ms, 2)
+        ref64 = compare_form("fp64", mixed["tensors"], 1.0 / mixed["solves_per_s"], 2)
+        geometry["phi"] = phi_d
+        for d in (mixed, ref64):
+            d.pop("tensors")
+        cmp[f"solid_{other}"] = {"solves_per_s": mixed["solves_per_s"], "iterations_max": mixed["iterations_max"],
+                                 "refinements": mixed["refinements"], "true_residual_max": mixed["true_residual_max"],
+                                 "status": mixed["status"], "fp64_solves_per_s": ref64["solves_per_s"],
+                                 "fp64_iterations_max": ref64["iterations_max"],
+                                 "speedup_of_mixed_over_fp64": ref64["speedup_of_mixed"],
+                                 "rel_err_of_mixed": ref64["rel_err_of_mixed"],
+                                 "max_rel_err_of_mixed": ref64["max_rel_err_of_mixed"]}
+        log(f"solid fraction {other} comparison done")
         result["compare"] = cmp
 
     if not args.no_cpu:
-        log("cpu oracle baseline (16^3 sample, median of 3)")
-        t_cpu = float(np.median([cpu_baseline(16) for _ in range(3)]))
-        result["cpu_baseline"] = {
-            "value": (16 ** 3 / n ** 3) / t_cpu, "unit": "solves/s", "cores": 1, "kind": "oracle",
-            "sample": f"a 16^3 nine-load oracle homogenisation (sparse LU, 16,384 dofs; median of 3 runs) took "
-                      f"{t_cpu:.2f} s on one host core; value scales it linearly in dofs to {n}^3 (optimistic: "
-                      "LU cost grows faster than linearly)",
-            "host_cores_available": len(os.sched_getaffinity(0)),
-        }
+        log("cpu oracle baseline (12^3 and 16^3 solves, median of 3; one full-size operator apply)")
+        fine_launches = sum(v[0] for k, v in ktimes.items() if k.startswith(("fine_", "tiled_", "elem_"))) / args.steps
+        iters = max(stats["iterations"])
+        result["cpu_baseline"] = cpu_baseline(n, iters, fine_launches / max(iters, 1))
     print(json.dumps(result))
 
 

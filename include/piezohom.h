@@ -53,6 +53,8 @@
 #ifndef PIEZOHOM_H
 #define PIEZOHOM_H
 
+#include <stddef.h>
+
 #ifdef __cplusplus
 extern "C" {
 #endif
@@ -140,7 +142,8 @@ typedef struct {
 } phz_material;
 
 typedef struct {
-    int precision;          /* PHZ_FP64 or PHZ_FP32_IR                          */
+    int precision;          /* PHZ_FP64, PHZ_FP32_IR or PHZ_BF16X3_IR (default
+                               PHZ_FP64)                                        */
     int batched;            /* 1: the nine loads as one 9-column block;
                                0: one load at a time                            */
     int restart;            /* GMRES restart length m (default 30)              */
@@ -235,6 +238,17 @@ typedef struct {
                                preconditioner's own accuracy sets only how
                                fast GMRES converges; the operator and the FP64
                                refinement set the result                     */
+    int ir_fallback;        /* PHZ_FP32_IR and PHZ_BF16X3_IR: 1 (default) when
+                               a refinement step leaves a load above rtol
+                               without reducing its float64 residual tenfold
+                               (its float cycle having aimed at more), the
+                               float solve moves one form down for the rest
+                               of the solve: split-BF16 -> float32 kernels
+                               (float32 gathers and stencils) -> a float64
+                               GMRES from the current iterate to rtol; 0 never;
+                               2 treats every refinement step as stalled (a
+                               host-side switch that exercises the path).
+                               phz_stats reports the form that finished     */
 } phz_options;
 
 typedef struct {
@@ -263,56 +277,118 @@ typedef struct {
                                over the solve, [0] the A maps, [1] the
                                potential block's maps                          */
     long inner_calls[2];    /* inner = 1: number of those maps                 */
+    int final_precision;    /* form that finished the last solve: the option's
+                               precision, or after refinement-stall fallbacks
+                               PHZ_FP32_IR or PHZ_FP64 (ir_fallback)          */
+    int fallbacks;          /* refinement-stall fallbacks in the last solve   */
 } phz_stats;
 
 typedef struct {
     double d_h, g_h, B_voigt, B_reuss, k_h;
 } phz_foms_t;
 
+/* Device memory supplied by the caller (for instance a framework's caching
+ * allocator).  alloc(bytes, stream, user) returns device memory of the
+ * context's device usable on `stream` (the context's stream), or NULL on
+ * failure (the calling entry point then returns PHZ_E_OOM);
+ * free(ptr, stream, user) takes back a pointer alloc returned, after all work
+ * the library queued on `stream` that reads or writes it (the library calls
+ * free only for memory whose last use is ordered before the call on that
+ * stream).  The callbacks run on the thread that called the entry point, only
+ * during calls on the context that was created with them, and must not call
+ * back into the library. */
+typedef struct {
+    void* (*alloc)(size_t bytes, void* stream, void* user);
+    void (*free)(void* ptr, void* stream, void* user);
+    void* user;
+} phz_allocator;
+
 /* Fill *o with the defaults documented in phz_options. */
 void phz_default_options(phz_options* o);
 
-/* Create a context for an N x N x N periodic cell.  N must be even and
- * >= 2 (multigrid halves N), and halving N while it is even and above 4
+/* Create a context for a periodic cell of nx x ny x nz elements (the cell
+ * resolution of Sec. 2.6; Sec. 2.2's cell problems on the unit cube).  The
+ * cell must be cubic (nx = ny = nz = N, else PHZ_E_INVALID).  N must be even
+ * and >= 2 (multigrid halves N), and halving N while it is even and above 4
  * (at most mg_levels - 1 times when mg_levels > 0) must end at a side of at
  * most 10: the coarsest level is inverted densely on the host.  So N = m 2^k
  * with m <= 10 (96 and 128 qualify, 100 does not); otherwise PHZ_E_INVALID.
- * phz_set_options applies the same rule to a new mg_levels.  stream is a hipStream_t (NULL: the library
- * creates its own).  On success *out owns device workspaces sized for N,
- * nine loads and the chosen restart length. */
-int phz_create(int n, const phz_material* mat, const phz_options* opt,
-               void* stream, phz_ctx** out);
+ * phz_set_options applies the same rule to a new mg_levels.  mat: base
+ * material (Sec. 2.3), copied.  opt: NULL for the defaults, copied.  stream
+ * is a hipStream_t (NULL: the library creates its own and destroys it in
+ * phz_destroy).  alloc (may be NULL: hipMalloc and hipFree) supplies every
+ * device workspace of the context, copied; the callbacks' user pointer must
+ * stay valid until phz_destroy returns.  On success *out owns device
+ * workspaces sized for N, nine loads and the chosen restart length; on
+ * failure *out is NULL and everything allocated is returned. */
+int phz_create(int nx, int ny, int nz, const phz_material* mat, const phz_options* opt,
+               void* stream, const phz_allocator* alloc, phz_ctx** out);
+/* Wait for the context's stream, return every workspace (through the
+ * allocator given to phz_create, if any) and free the context.  NULL is a
+ * no-op. */
 void phz_destroy(phz_ctx* ctx);
+/* Text of the last error on ctx (owned by ctx, valid until its next call). */
 const char* phz_last_error(const phz_ctx* ctx);
+/* Static name of a status code. */
 const char* phz_strerror(int status);
 /* Replace the options of an existing context (workspaces are re-sized). */
 int phz_set_options(phz_ctx* ctx, const phz_options* opt);
 
-/* Geometry.  phi: [N^3] nodal level set (Sec. 2.1 sign convention).
- * rho: [N^3] per-element density in [0, 1].  NaN/Inf -> PHZ_E_NAN. */
+/* Geometry.  phi: [N^3] nodal level set (Sec. 2.1: phi < 0 solid, phi > 0
+ * void); the element densities follow by the smoothed Heaviside of Sec. 2.6
+ * (header comment).  rho: [N^3] per-element density in [0, 1] (Sec. 2.6's
+ * smoothed density given directly).  Host, or (on_device) device memory of
+ * the context's device; read before the call returns.  NaN/Inf ->
+ * PHZ_E_NAN; a density outside [0, 1] -> PHZ_E_INVALID. */
 int phz_set_levelset(phz_ctx* ctx, const double* phi, int on_device);
 int phz_set_density(phz_ctx* ctx, const double* rho, int on_device);
-/* Per-element ersatz scale s_e currently in use, [N^3]. */
+/* Per-element ersatz scale s_e = eps_v + (1 - eps_v) rho_e currently in use,
+ * [N^3], host or device as above. */
 int phz_get_scale(phz_ctx* ctx, double* s, int on_device);
 
-/* Solve the nine cell problems and reduce to the effective tensors. */
+/* Solve the nine cell problems of Sec. 2.2 for the current geometry with
+ * the configured solver (Sec. 2.5, default SCP-GMRES of Sec. 2.5.3) and
+ * precision form, and reduce to the effective tensors.  PHZ_NOT_CONVERGED:
+ * max_iters (or max_refine) ran out before every load reached rtol; the
+ * tensors, histories and stats are still written.  PHZ_E_STATE without a
+ * geometry. */
 int phz_solve(phz_ctx* ctx);
 
-/* Effective tensors of the last solve (SI, host). Any pointer may be NULL. */
+/* Effective tensors of the last solve (Sec. 2.2's homogenised C^H, e^H,
+ * kappa^H: cell averages of stress and electric displacement over the nine
+ * cell solutions), SI, host buffers.  Any pointer may be NULL.  PHZ_E_STATE
+ * before a solve. */
 int phz_get_effective(phz_ctx* ctx, double CH[36], double eH[18], double kH[9]);
-/* Non-dimensional 9x9 effective matrices (flux and energy forms, host). */
+/* The same as the non-dimensional 9x9 matrix M^H = [[C, -e^T], [-e, -kappa]]
+ * (row-major, host): flux form (cell average, Sec. 2.2) and energy form
+ * (the solutions' energy pairing, equal at convergence). */
 int phz_get_effective_nd(phz_ctx* ctx, double MH[81], double MH_energy[81]);
-/* Per-load residual history (relative GMRES estimates, then true
- * residuals at restarts).  Writes min(cap, available) values to buf and the
- * available count to *len. */
+/* Per-load convergence history of the last solve (the residual histories
+ * behind the iteration counts of Table 1): relative residual estimates of
+ * every GMRES iteration, with the true relative residual ||b - calA x|| /
+ * ||b|| at each restart and at exit.  load in [0, 9) (Voigt order, then the
+ * electric fields).  Writes min(cap, available) values to buf (host; may be
+ * NULL when cap = 0) and the available count to *len. */
 int phz_get_history(phz_ctx* ctx, int load, double* buf, int cap, int* len);
+/* Solver statistics of the last solve (Table 1's quantities: outer
+ * iterations, restarts, refinement steps, inner iterations of inexact block
+ * maps; final true residuals; set-up and solve times; the kernels chosen).
+ * st: host. */
 int phz_get_stats(phz_ctx* ctx, phz_stats* st);
-/* Fluctuation solution X, [N^3][4][9] non-dimensional (zero mean per field). */
+/* Fluctuation solution X of the nine cell problems of Sec. 2.2 (the
+ * periodic parts of displacement and potential), [N^3][4][9]
+ * non-dimensional, zero mean per field.  X: host or (on_device) device
+ * memory of 36 N^3 doubles, written (device: on the context's stream, then
+ * synchronised).  PHZ_E_STATE before a solve. */
 int phz_get_solution(phz_ctx* ctx, double* X, int on_device);
-/* Warm start for the next solve, same layout; NULL clears it. */
+/* Warm start for the next solve, same layout as phz_get_solution (read
+ * before the call returns); NULL clears it. */
 int phz_set_initial_guess(phz_ctx* ctx, const double* X, int on_device);
-/* Load vectors b = -sum_e s_e F0 e_L (with PHZ_SMOOTH_QP
- * -sum_e sum_p s_ep F0_p e_L), [N^3][4][9] non-dimensional. */
+/* Load vectors of the nine cell problems (Sec. 2.2: the weak form's
+ * right-hand side for unit macroscopic strains and fields)
+ * b = -sum_e s_e F0 e_L (with PHZ_SMOOTH_QP -sum_e sum_p s_ep F0_p e_L),
+ * [N^3][4][9] non-dimensional, host or device as phz_get_solution.
+ * PHZ_E_STATE without a geometry. */
 int phz_get_rhs(phz_ctx* ctx, double* b, int on_device);
 
 /* Figures of merit (Sec. 2.3) of SI tensors and their gradients with respect
@@ -413,10 +489,14 @@ int phz_precondition(phz_ctx* ctx, int nrhs, const double* r, double* z);
 int phz_coarse_apply(phz_ctx* ctx, int level, int op, int nrhs, int precision,
                      const void* x, void* y);
 
-/* Per-kernel timing.  With timing enabled, every operator launch (fine
+/* Per-kernel timing (measurement support, not part of the method).  With
+ * timing enabled (enable = 1), every operator launch (fine
  * blocks, coarse levels), every SCP preconditioner application and every
  * Arnoldi orthogonalisation of later calls is bracketed by HIP events on the
- * context's stream.  Enabling (or disabling) clears the totals.
+ * context's stream; enable = 2 brackets the fine-level operator launches
+ * only (fewer events, so less drain between launches).  Each bracket drains
+ * the stream between launches, so timed runs are a few per cent slower.
+ * Enabling (or disabling, enable = 0) clears the totals.
  * phz_get_kernel_timing writes one line "name count total_ms" per kernel
  * class into buf (NUL-terminated, truncated to cap) and the full length to
  * *len.  Names: fine_{full,A,B,S}_k{1,9}_f{64,32} (suffix _cheby for the

@@ -44,7 +44,7 @@ class phz_options(C.Structure):
                 ("block_kernel", C.c_int * 4), ("block_tile", C.c_int * 4), ("coarse_kernel", C.c_int),
                 ("solver", C.c_int), ("inner", C.c_int), ("inner_eps", C.c_double), ("inner_maxit", C.c_int),
                 ("warm_start", C.c_int), ("smoothing", C.c_int),
-                ("bf16_terms_precond", C.c_int)]
+                ("bf16_terms_precond", C.c_int), ("ir_fallback", C.c_int)]
 
 
 def _set_option(o, k, v):
@@ -65,7 +65,50 @@ class phz_stats(C.Structure):
                 ("setup_ms", C.c_double), ("solve_ms", C.c_double), ("mg_levels", C.c_int),
                 ("cheb_lambda", C.c_double * 16), ("elem_tile", C.c_int * 4),
                 ("fine_kernel", C.c_int * 4), ("coarse_kernel", C.c_int * 16), ("inner_iters", C.c_long * 2),
-                ("inner_calls", C.c_long * 2)]
+                ("inner_calls", C.c_long * 2), ("final_precision", C.c_int), ("fallbacks", C.c_int)]
+
+
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p, C.c_void_p)
+
+
+class phz_allocator(C.Structure):
+    _fields_ = [("alloc", ALLOC_FN), ("free", FREE_FN), ("user", C.c_void_p)]
+
+
+class TorchAllocator:
+    """Routes a context's device workspaces through PyTorch's caching allocator
+    (phz_allocator callbacks).  Keeps the callbacks alive while the context
+    lives; counts calls and bytes outstanding."""
+
+    def __init__(self, device=None):
+        import torch
+        self._torch = torch
+        self.device = torch.cuda.current_device() if device is None else device
+        self.allocs = 0
+        self.frees = 0
+        self.live = {}
+        self._alloc = ALLOC_FN(self._do_alloc)
+        self._free = FREE_FN(self._do_free)
+        self.struct = phz_allocator(self._alloc, self._free, None)
+
+    def _do_alloc(self, nbytes, stream, user):
+        try:
+            p = self._torch.cuda.caching_allocator_alloc(int(nbytes), device=self.device, stream=stream or 0)
+        except Exception:   # out of memory: the library reports PHZ_E_OOM
+            return None
+        self.allocs += 1
+        self.live[p] = int(nbytes)
+        return p
+
+    def _do_free(self, ptr, stream, user):
+        self.frees += 1
+        self.live.pop(ptr, None)
+        self._torch.cuda.caching_allocator_delete(ptr)
+
+    @property
+    def bytes_live(self):
+        return sum(self.live.values())
 
 
 class phz_foms_t(C.Structure):
@@ -91,7 +134,8 @@ def _load():
     vp, dp, ip = C.c_void_p, C.POINTER(C.c_double), C.c_int
     sig = {
         "phz_default_options": (None, [C.POINTER(phz_options)]),
-        "phz_create": (ip, [ip, C.POINTER(phz_material), C.POINTER(phz_options), vp, C.POINTER(vp)]),
+        "phz_create": (ip, [ip, ip, ip, C.POINTER(phz_material), C.POINTER(phz_options), vp,
+                            C.POINTER(phz_allocator), C.POINTER(vp)]),
         "phz_destroy": (None, [vp]),
         "phz_last_error": (C.c_char_p, [vp]),
         "phz_strerror": (C.c_char_p, [ip]),
@@ -230,16 +274,22 @@ def foms(CH, eH, kH, grad_of=None):
 class Context:
     """One periodic N^3 cell on the GPU (wraps phz_ctx)."""
 
-    def __init__(self, n, material, stream=None, **opts):
+    def __init__(self, n, material, stream=None, allocator=None, **opts):
+        """allocator: None (the library's hipMalloc), "torch" (PyTorch's caching
+        allocator, through TorchAllocator) or a TorchAllocator."""
         self.n = n
         self.nn = n ** 3
         self._mat = make_material(material)
         self._opt = default_options(**opts)
         self.device = _current_device()
         self._state = 0    # advances whenever the geometry or the solution may change
+        if allocator == "torch":
+            allocator = TorchAllocator(self.device)
+        self.allocator = allocator
         h = C.c_void_p()
-        st = _lib.phz_create(n, C.byref(self._mat), C.byref(self._opt),
-                             C.c_void_p(stream) if stream else None, C.byref(h))
+        st = _lib.phz_create(n, n, n, C.byref(self._mat), C.byref(self._opt),
+                             C.c_void_p(stream) if stream else None,
+                             C.byref(allocator.struct) if allocator is not None else None, C.byref(h))
         if st != PHZ_OK:
             raise PiezoError(st, "phz_create")
         self._h = h
@@ -310,6 +360,7 @@ class Context:
             "cheb_lambda": list(s.cheb_lambda), "elem_tile": list(s.elem_tile),
             "fine_kernel": list(s.fine_kernel), "coarse_kernel": list(s.coarse_kernel),
             "inner_iters": list(s.inner_iters), "inner_calls": list(s.inner_calls),
+            "final_precision": s.final_precision, "fallbacks": s.fallbacks,
         }
 
     def history(self, load):
@@ -414,9 +465,10 @@ class Context:
                     "phz_hpm_velocity")
         return out
 
-    def kernel_timing(self, enable=True):
-        """Enable (or disable) per-kernel HIP-event timing; clears the totals."""
-        self._check(_lib.phz_kernel_timing(self._h, 1 if enable else 0), "phz_kernel_timing")
+    def kernel_timing(self, enable=True, fine_only=False):
+        """Enable (or disable) per-kernel HIP-event timing; clears the totals.
+        fine_only: bracket the fine-level operator launches only."""
+        self._check(_lib.phz_kernel_timing(self._h, (2 if fine_only else 1) if enable else 0), "phz_kernel_timing")
 
     def kernel_times(self):
         """{name: (launches, total_ms)} recorded since timing was enabled."""

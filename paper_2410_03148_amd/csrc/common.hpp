@@ -264,6 +264,8 @@ void tricg_update(long nn, int F, int K, const double* cf, const double* w, int 
 void stencil_cheb_step(int N, int K, const double* w, const double* d, double* x, double* r, double* dn, double c1,
                        double c2, hipStream_t st);
 int count_nonfinite(long count, const double* v, double* work, hipStream_t st);
+// number of values that are not finite or lie outside [lo, hi]
+int count_outside(long count, const double* v, double lo, double hi, double* work, hipStream_t st);
 // power iteration helper: v = w / sqrt(nrm2[0])
 template <typename T>
 void normalize_by(long count, const double* nrm2, const T* w, T* v, hipStream_t st);

@@ -20,6 +20,7 @@
 #include <cstring>
 #include <map>
 #include <memory>
+#include <new>
 #include <string>
 #include <type_traits>
 #include <vector>
@@ -30,28 +31,58 @@
 
 namespace phz {
 
+// Device memory of a context: the caller's allocator (phz_create's
+// phz_allocator) when one was given, else hipMalloc.  Every entry point that
+// takes a context makes that context's hook current for the calling thread
+// (AllocScope); a buffer remembers the hook it was allocated with and returns
+// its memory through it.
+struct AllocHook {
+  phz_allocator a{};
+  hipStream_t stream = nullptr;
+  bool active = false;
+};
+static thread_local const AllocHook* g_alloc_hook = nullptr;
+struct AllocScope {
+  const AllocHook* prev;
+  explicit AllocScope(const AllocHook* h) : prev(g_alloc_hook) { g_alloc_hook = h; }
+  ~AllocScope() { g_alloc_hook = prev; }
+};
+
 template <typename T>
 struct DevBuf {
   T* p = nullptr;
   size_t n = 0;
+  const AllocHook* hook = nullptr;   // allocator the memory came from (null: hipMalloc)
   DevBuf() = default;
   DevBuf(const DevBuf&) = delete;
   DevBuf& operator=(const DevBuf&) = delete;
   ~DevBuf() { release(); }
   void release() {
-    if (p) hipFree(p);
+    if (p) {
+      if (hook) hook->a.free(p, hook->stream, hook->a.user);
+      else hipFree(p);
+    }
     p = nullptr;
     n = 0;
+    hook = nullptr;
   }
   void alloc(size_t count) {
     if (count == n && p) return;
     release();
     if (count == 0) return;
-    hipError_t e = hipMalloc(&p, count * sizeof(T));
-    if (e != hipSuccess) {
-      p = nullptr;
-      throw HipError(std::string("hipMalloc of ") + std::to_string(count * sizeof(T)) +
-                     " bytes: " + hipGetErrorString(e));
+    const AllocHook* h = g_alloc_hook && g_alloc_hook->active ? g_alloc_hook : nullptr;
+    if (h) {
+      p = static_cast<T*>(h->a.alloc(count * sizeof(T), h->stream, h->a.user));
+      if (!p) throw HipError(std::string("hipMalloc of ") + std::to_string(count * sizeof(T)) +
+                             " bytes: the caller's allocator returned NULL");
+      hook = h;
+    } else {
+      hipError_t e = hipMalloc(&p, count * sizeof(T));
+      if (e != hipSuccess) {
+        p = nullptr;
+        throw HipError(std::string("hipMalloc of ") + std::to_string(count * sizeof(T)) +
+                       " bytes: " + hipGetErrorString(e));
+      }
     }
     n = count;
   }
@@ -127,6 +158,7 @@ struct StepGraph {
 }  // namespace phz
 
 struct phz_ctx {
+  phz::AllocHook hook;   // first member: destroyed after every buffer that uses it
   int N = 0;
   long nn = 0;
   phz_material mat{};
@@ -161,6 +193,10 @@ struct phz_ctx {
   bool x_valid = false;   // X holds the finite result of the last solve (any geometry)
   bool precond_ready = false;
   bool have_guess = false;
+  // refinement-stall fallback of the current solve: 0 the configured form,
+  // 1 float32 kernels only (a split-BF16 context leaves its bf16 products
+  // and bf16 stencils), 2 a float64 inner GMRES
+  int ir_level = 0;
 
   phz::Hierarchy hA, hS, hC;   // hC: only for the block-diagonal preconditioner
   phz::Work<double> w64;
@@ -190,6 +226,7 @@ struct phz_ctx {
 
   // optional per-kernel timing with HIP events on the context stream
   bool ktime = false;
+  bool ktime_fine_only = false;   // timing mode 2: fine-level operator launches only
   std::vector<hipEvent_t> ev;           // start/stop pairs
   std::vector<std::string> ev_name;
   size_t ev_used = 0;
@@ -218,6 +255,9 @@ constexpr size_t kMaxTimedLaunches = 1 << 16;
 // Record a start event before a launch; returns the slot or -1.
 static long time_begin(phz_ctx* c, const char* name) {
   if (!c->ktime || c->ev_used >= kMaxTimedLaunches) return -1;
+  if (c->ktime_fine_only && std::strncmp(name, "fine", 4) != 0 && std::strncmp(name, "tiled_", 6) != 0 &&
+      std::strncmp(name, "elem_", 5) != 0)
+    return -1;
   const size_t i = c->ev_used++;
   if (c->ev.size() < 2 * (i + 1)) {
     hipEvent_t a, b;
@@ -634,7 +674,9 @@ static void op_apply_args(phz_ctx* c, int blk, int K, const T* x, const OpArgs<T
   }
   if constexpr (std::is_same<T, float>::value) {
     if (K == 9 && op <= 3) {
-      const int kind = fine_kind_of(c, op);
+      int kind = fine_kind_of(c, op);
+      // after a refinement stall the float solve leaves the bf16 products
+      if (kind == kFineElem && c->ir_level > 0) kind = fine_tiled_fits(c->N) ? kFineTiled : kFineDirect;
       if (kind == kFineElem) {
         const int terms = elem_terms(c, op);
         const long slot = time_begin(c, elem_op_name(op, terms == 3, cheby));
@@ -668,7 +710,7 @@ static void level_apply_args(phz_ctx* c, Hierarchy& H, int l, int K, const T* x,
     op_apply_args<T>(c, H.op, K, x, a, cheby);
   } else {
     if constexpr (sizeof(T) == 4) {
-      if (K == 9 && L.ckind == 1) {
+      if (K == 9 && (L.ckind == 1 || (L.ckind == 2 && c->ir_level > 0))) {
         const long slot = time_begin(c, H.F == 3 ? "coarse_tiled_A_f32" : "coarse_tiled_S_f32");
         coarse_apply_tiled(H.F, L.N, L.S32.p, x, a, cheby, c->stream);
         time_end(c, slot);
@@ -921,6 +963,10 @@ static int coarse_kind_of(phz_ctx* c, Hierarchy& H, int l) {
   if (L.ckind >= 0) return L.ckind;
   int kind = 0;
   if (coarse_tiled_fits(L.N) && c->opt.coarse_kernel != 0) {
+    // the bf16 compact stencils are a candidate of the automatic choice only
+    // in the split-BF16 form; the float32 form keeps float32 stencils unless
+    // coarse_kernel = 2 pins them
+    const bool compact_ok = c->opt.precision == PHZ_BF16X3_IR;
     if (c->opt.coarse_kernel >= 1) {
       kind = c->opt.coarse_kernel;
     } else {
@@ -935,10 +981,12 @@ static int coarse_kind_of(phz_ctx* c, Hierarchy& H, int l) {
         kind = 1;
         best = tiled;
       }
-      const float compact = time_launch(c, [&] {
-        coarse_apply_tiled_compact(H.F, L.N, L.S16.p, L.Sc.p, x.p, a, false, c->stream);
-      });
-      if (clearly_faster(compact, best)) kind = 2;
+      if (compact_ok) {
+        const float compact = time_launch(c, [&] {
+          coarse_apply_tiled_compact(H.F, L.N, L.S16.p, L.Sc.p, x.p, a, false, c->stream);
+        });
+        if (clearly_faster(compact, best)) kind = 2;
+      }
     }
   }
   L.ckind = kind;
@@ -1373,6 +1421,13 @@ static int solve_ir(phz_ctx* c, int K, const double* b, double* x, double rtol, 
   double* scp = c->gm_nrm.p + 18;
   int steps = 0;
   int used = 0;
+  // refinement-stall fallback: a refinement step that leaves a load above
+  // its target without reducing its float64 residual tenfold (when its
+  // cycle aimed at more than that) moves the float solve one form down:
+  // split-BF16 -> float32 kernels -> a float64 inner GMRES on the residual
+  // (ir_fallback = 2 treats every step as stalled, to exercise the path)
+  c->ir_level = 0;
+  std::vector<double> prev_rel(K, -1.0), prev_tol(K, 1.0);
   for (;;) {
     // r = b - calA x in float64
     op_apply<double>(c, 0, K, x, b, r64.p, -1.0, 1.0);
@@ -1392,6 +1447,34 @@ static int solve_ir(phz_ctx* c, int K, const double* b, double* x, double rtol, 
       break;
     }
     if (steps >= c->opt.max_refine || used >= c->opt.max_iters) break;
+    if (steps > 0 && c->opt.ir_fallback > 0) {
+      bool stalled = c->opt.ir_fallback == 2;
+      for (int k = 0; k < K; ++k)
+        if (bn[k] > 0 && !(out.true_rel[k] <= rtol) && prev_tol[k] <= 0.1 && out.true_rel[k] > 0.1 * prev_rel[k])
+          stalled = true;
+      if (stalled && c->ir_level < 2) {
+        c->ir_level = c->opt.precision == PHZ_BF16X3_IR ? c->ir_level + 1 : 2;
+        ++c->graph_epoch;   // captured steps hold the kernels of the form they were captured in
+        c->stats.fallbacks += 1;
+        if (c->opt.verbose)
+          std::fprintf(stderr, "[piezohom] refinement step %d stalled: float solve falls back to %s\n", steps,
+                       c->ir_level == 1 ? "float32 kernels" : "a float64 inner GMRES");
+      }
+    }
+    if (c->ir_level == 2) {
+      // float64 GMRES from the current iterate to the target
+      alloc_work<double>(c, c->w64, K, c->opt.restart);
+      GmresResult g = gmres<double>(c, K, b, x, rtol, std::max(c->opt.max_iters - used, 1), hist_base, true);
+      for (int k = 0; k < K; ++k) {
+        out.iters[k] += g.iters[k];
+        out.restarts[k] += g.restarts[k];
+        out.true_rel[k] = g.true_rel[k];
+      }
+      out.converged = g.converged;
+      ++steps;
+      break;
+    }
+    for (int k = 0; k < K; ++k) prev_rel[k] = out.true_rel[k];
     // solve calA d = r / ||r|| in float, x += ||r|| d.  A load's cycle aims
     // at inner_rtol, or, when less than that remains to its target, at what
     // remains (with a margin of 4 for the float estimate): the last cycle
@@ -1401,6 +1484,7 @@ static int solve_ir(phz_ctx* c, int K, const double* b, double* x, double rtol, 
       scale[k] = act ? rn[k] : 0.0;
       inv[k] = act ? 1.0 / rn[k] : 0.0;
       tol[k] = act ? std::max(c->opt.inner_rtol, 0.25 * rtol / out.true_rel[k]) : c->opt.inner_rtol;
+      prev_tol[k] = tol[k];
     }
     PHZ_HIP(hipMemcpyAsync(c->gm_tol.p, tol.data(), K * sizeof(double), hipMemcpyHostToDevice, st));
     PHZ_HIP(hipMemcpyAsync(scp, inv.data(), K * sizeof(double), hipMemcpyHostToDevice, st));
@@ -1421,6 +1505,11 @@ static int solve_ir(phz_ctx* c, int K, const double* b, double* x, double rtol, 
     used += std::max(mx, 1);
     ++steps;
   }
+  // the form that finished: the most precise one any column block needed
+  // (codes: PHZ_FP64 < PHZ_FP32_IR < PHZ_BF16X3_IR)
+  const int form = c->ir_level == 0 ? c->opt.precision : c->ir_level == 1 ? PHZ_FP32_IR : PHZ_FP64;
+  c->stats.final_precision = std::min(c->stats.final_precision, form);
+  c->ir_level = 0;
   return steps;
 }
 
@@ -1814,6 +1903,8 @@ static int do_solve(phz_ctx* c) {
   std::memset(c->stats.iterations, 0, sizeof(c->stats.iterations));
   std::memset(c->stats.restarts, 0, sizeof(c->stats.restarts));
   c->stats.refinements = 0;
+  c->stats.fallbacks = 0;
+  c->stats.final_precision = c->opt.precision;
   for (int i = 0; i < 2; ++i) c->stats.inner_iters[i] = c->stats.inner_calls[i] = 0;
   for (auto& h : c->hist) h.clear();
   ensure_state_buffers(c);
@@ -1940,7 +2031,11 @@ static void fill_point_scales(phz_ctx* c) {
 
 using namespace phz;
 
-#define PHZ_GUARD_BEGIN try {
+static const AllocHook* hook_of(phz_ctx* c) { return c ? &c->hook : nullptr; }
+
+#define PHZ_GUARD_BEGIN \
+  try {                 \
+    AllocScope alloc_scope_(hook_of(c));
 #define PHZ_GUARD_END(ctx)                                           \
   }                                                                  \
   catch (const HipError& ex) {                                       \
@@ -1991,6 +2086,7 @@ void phz_default_options(phz_options* o) {
   o->warm_start = 0;
   o->smoothing = PHZ_SMOOTH_ELEMENT;
   o->bf16_terms_precond = 1;
+  o->ir_fallback = 1;
 }
 
 const char* phz_strerror(int status) {
@@ -2035,37 +2131,61 @@ static int check_options(const phz_options* o, std::string& err) {
   if (o->vcycles_a < 1 || o->vcycles_s < 1) { err = "vcycles must be >= 1"; return PHZ_E_INVALID; }
   if (!(o->inner_rtol > 0 && o->inner_rtol < 1)) { err = "inner_rtol must be in (0, 1)"; return PHZ_E_INVALID; }
   if (o->max_refine < 1) { err = "max_refine must be >= 1"; return PHZ_E_INVALID; }
+  if (o->ir_fallback < 0 || o->ir_fallback > 2) { err = "ir_fallback must be 0, 1 or 2"; return PHZ_E_INVALID; }
   return PHZ_OK;
 }
 
-int phz_create(int n, const phz_material* mat, const phz_options* opt, void* stream, phz_ctx** out) {
+int phz_create(int nx, int ny, int nz, const phz_material* mat, const phz_options* opt, void* stream,
+               const phz_allocator* alloc, phz_ctx** out) {
   if (!out) return PHZ_E_INVALID;
   *out = nullptr;
+  if (nx != ny || ny != nz) return PHZ_E_INVALID;
+  const int n = nx;
   if (!mat || n < 2 || n % 2 != 0 || n > 1024) return PHZ_E_INVALID;
+  if (alloc && (!alloc->alloc || !alloc->free)) return PHZ_E_INVALID;
   for (int i = 0; i < 36; ++i) if (!std::isfinite(mat->C[i])) return PHZ_E_NAN;
   for (int i = 0; i < 18; ++i) if (!std::isfinite(mat->e[i])) return PHZ_E_NAN;
   for (int i = 0; i < 9; ++i) if (!std::isfinite(mat->kappa[i])) return PHZ_E_NAN;
   if (!(mat->void_scale > 0.0 && mat->void_scale <= 1.0)) return PHZ_E_INVALID;
-  std::unique_ptr<phz_ctx> c(new phz_ctx());
+  phz_options o;
+  if (opt) o = *opt;
+  else phz_default_options(&o);
+  {
+    std::string err;
+    const int rc = check_options(&o, err);
+    if (rc) return rc;
+  }
+  if (coarsest_side(n, o.mg_levels) > kMaxCoarsestN) return PHZ_E_INVALID;
+  // a context that fails part-way is torn down like any other (its buffers
+  // go back through the caller's allocator, its own stream is destroyed)
+  struct Pending {
+    phz_ctx* c;
+    ~Pending() { if (c) phz_destroy(c); }
+  } pending{new (std::nothrow) phz_ctx()};
+  phz_ctx* c = pending.c;
+  if (!c) return PHZ_E_OOM;
+  if (stream) {
+    c->stream = (hipStream_t)stream;
+  } else {
+    if (hipStreamCreate(&c->stream) != hipSuccess) {
+      c->stream = nullptr;
+      return PHZ_E_HIP;
+    }
+    c->own_stream = true;
+  }
+  if (alloc) {
+    c->hook.a = *alloc;
+    c->hook.stream = c->stream;
+    c->hook.active = true;
+  }
   PHZ_GUARD_BEGIN
   c->N = n;
   c->nn = (long)n * n * n;
   c->mat = *mat;
+  c->opt = o;
   for (int op = 0; op < 4; ++op) c->stats.elem_tile[op] = c->stats.fine_kernel[op] = -1;
   for (int q = 0; q < 16; ++q) c->stats.coarse_kernel[q] = -1;
-  if (opt) c->opt = *opt;
-  else phz_default_options(&c->opt);
-  std::string err;
-  int rc = check_options(&c->opt, err);
-  if (rc) return rc;
-  if (coarsest_side(n, c->opt.mg_levels) > kMaxCoarsestN) return PHZ_E_INVALID;
-  if (stream) {
-    c->stream = (hipStream_t)stream;
-  } else {
-    PHZ_HIP(hipStreamCreate(&c->stream));
-    c->own_stream = true;
-  }
-  upload_reference(c.get());
+  upload_reference(c);
   static const double kOne = 1.0;
   c->one64.upload(&kOne, 1, c->stream);
   const double neg[9] = {-1.0, -1.0, -1.0, -1.0, -1.0, -1.0, -1.0, -1.0, -1.0};
@@ -2075,11 +2195,12 @@ int phz_create(int n, const phz_material* mat, const phz_options* opt, void* str
   c->rho.alloc(c->nn);
   c->s.alloc(c->nn);
   c->s32.alloc(c->nn);
-  ensure_state_buffers(c.get());
-  sync(c.get());
-  *out = c.release();
+  ensure_state_buffers(c);
+  sync(c);
+  *out = c;
+  pending.c = nullptr;
   return PHZ_OK;
-  PHZ_GUARD_END(c.get())
+  PHZ_GUARD_END(c)
 }
 
 void phz_destroy(phz_ctx* ctx) {
@@ -2167,6 +2288,10 @@ int phz_set_density(phz_ctx* c, const double* rho, int on_device) {
   PHZ_GUARD_BEGIN
   int rc = set_input(c, rho, on_device, c->rho);
   if (rc) return rc;
+  if (count_outside(c->nn, c->rho.p, 0.0, 1.0, c->red_work.p, c->stream) > 0) {
+    c->err = "densities must lie in [0, 1]";
+    return PHZ_E_INVALID;
+  }
   density_to_scale(c->nn, c->rho.p, c->mat.void_scale, c->s.p, c->s32.p, c->stream);
   fill_point_scales(c);
   sync(c);
@@ -2734,11 +2859,12 @@ int phz_hpm_velocity(phz_ctx* c, int m, const double* j_obj, const double* const
 }
 
 int phz_kernel_timing(phz_ctx* c, int enable) {
-  if (!c) return PHZ_E_INVALID;
+  if (!c || enable < 0 || enable > 2) return PHZ_E_INVALID;
   PHZ_GUARD_BEGIN
   sync(c);
   collect_timing(c);
   c->ktime = enable != 0;
+  c->ktime_fine_only = enable == 2;
   c->ktotals.clear();
   return PHZ_OK;
   PHZ_GUARD_END(c)

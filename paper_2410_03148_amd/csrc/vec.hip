@@ -8,6 +8,7 @@
 #include <algorithm>
 #include <array>
 #include <cmath>
+#include <limits>
 #include <utility>
 
 #include "common.hpp"
@@ -823,11 +824,15 @@ __global__ void k_max_partials(int nb, const double* __restrict__ part, double* 
   }
 }
 
-__global__ void k_count_nonfinite(size_t count, const double* __restrict__ v, double* __restrict__ part) {
+// values that are not finite or lie outside [lo, hi]
+__global__ void k_count_outside(size_t count, const double* __restrict__ v, double lo, double hi,
+                                double* __restrict__ part) {
   __shared__ double lds4[4];
   double c = 0.0;
-  for (size_t idx = (size_t)blockIdx.x * 256 + threadIdx.x; idx < count; idx += (size_t)gridDim.x * 256)
-    c += isfinite(v[idx]) ? 0.0 : 1.0;
+  for (size_t idx = (size_t)blockIdx.x * 256 + threadIdx.x; idx < count; idx += (size_t)gridDim.x * 256) {
+    const double x = v[idx];
+    c += (isfinite(x) && x >= lo && x <= hi) ? 0.0 : 1.0;
+  }
   c = block_sum(c, lds4);
   if (threadIdx.x == 0) part[blockIdx.x] = c;
 }
@@ -1206,9 +1211,12 @@ void max_abs(long count, const double* v, double* out, double* work, hipStream_t
   PHZ_LAUNCH_CHECK();
 }
 int count_nonfinite(long count, const double* v, double* work, hipStream_t st) {
+  return count_outside(count, v, -std::numeric_limits<double>::max(), std::numeric_limits<double>::max(), work, st);
+}
+int count_outside(long count, const double* v, double lo, double hi, double* work, hipStream_t st) {
   unsigned g = blocks_for(count, 256);
   if (g > 512) g = 512;
-  hipLaunchKernelGGL(k_count_nonfinite, dim3(g), dim3(256), 0, st, (size_t)count, v, work);
+  hipLaunchKernelGGL(k_count_outside, dim3(g), dim3(256), 0, st, (size_t)count, v, lo, hi, work);
   reduce_cols((int)g, 1, 1, 1, 0, 1, work, work + 1024, st);
   PHZ_LAUNCH_CHECK();
   double h = 0.0;

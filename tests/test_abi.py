@@ -40,19 +40,26 @@ def test_create_rejects_bad_sizes_and_materials():
     m = P.make_material(synth.material_workload())
     h = C.c_void_p()
     for n in (0, 1, 3, 7, 2048):
-        assert P._lib.phz_create(n, C.byref(m), None, None, C.byref(h)) == -1
+        assert P._lib.phz_create(n, n, n, C.byref(m), None, None, None, C.byref(h)) == -1
     # halving must end at a side of at most 10 (dense coarsest inverse)
     for n in (22, 100, 120):
-        assert P._lib.phz_create(n, C.byref(m), None, None, C.byref(h)) == -1
+        assert P._lib.phz_create(n, n, n, C.byref(m), None, None, None, C.byref(h)) == -1
     o = P.default_options(mg_levels=2)
-    assert P._lib.phz_create(64, C.byref(m), C.byref(o), None, C.byref(h)) == -1
+    assert P._lib.phz_create(64, 64, 64, C.byref(m), C.byref(o), None, None, C.byref(h)) == -1
     bad = P.make_material(synth.material_workload())
     bad.C[0] = float("nan")
-    assert P._lib.phz_create(8, C.byref(bad), None, None, C.byref(h)) == -2
+    assert P._lib.phz_create(8, 8, 8, C.byref(bad), None, None, None, C.byref(h)) == -2
     bad2 = P.make_material(synth.material_workload())
     bad2.void_scale = 0.0
-    assert P._lib.phz_create(8, C.byref(bad2), None, None, C.byref(h)) == -1
-    assert P._lib.phz_create(8, C.byref(m), None, None, None) == -1
+    assert P._lib.phz_create(8, 8, 8, C.byref(bad2), None, None, None, C.byref(h)) == -1
+    assert P._lib.phz_create(8, 8, 8, C.byref(m), None, None, None, None) == -1
+    # the cell must be cubic
+    for dims in ((8, 8, 16), (8, 16, 8), (16, 8, 8)):
+        assert P._lib.phz_create(*dims, C.byref(m), None, None, None, C.byref(h)) == -1
+        assert not h.value
+    # an allocator needs both callbacks
+    half = P.phz_allocator()
+    assert P._lib.phz_create(8, 8, 8, C.byref(m), None, None, C.byref(half), C.byref(h)) == -1
 
 
 def test_strerror_and_defaults():
@@ -79,13 +86,13 @@ def test_options_rejected_before_device_use():
                        ("warm_start", 2), ("solver", 3), ("smoothing", 2), ("bf16_terms_precond", 2),
                        ("bf16_terms_precond", 0), ("coarse_kernel", 3), ("coarse_kernel", -2)):
         o = P.default_options(**{field: val})
-        assert P._lib.phz_create(16, C.byref(m), C.byref(o), None, C.byref(h)) == -1, field
+        assert P._lib.phz_create(16, 16, 16, C.byref(m), C.byref(o), None, None, C.byref(h)) == -1, field
         assert not h.value
     # TriCG runs in float64 only, and with element smoothing
     o = P.default_options(solver=P.PHZ_SOLVER_TRICG, precision=P.PHZ_FP32_IR)
-    assert P._lib.phz_create(16, C.byref(m), C.byref(o), None, C.byref(h)) == -1
+    assert P._lib.phz_create(16, 16, 16, C.byref(m), C.byref(o), None, None, C.byref(h)) == -1
     o = P.default_options(solver=P.PHZ_SOLVER_TRICG, precision=P.PHZ_FP64, smoothing=P.PHZ_SMOOTH_QP)
-    assert P._lib.phz_create(16, C.byref(m), C.byref(o), None, C.byref(h)) == -1
+    assert P._lib.phz_create(16, 16, 16, C.byref(m), C.byref(o), None, None, C.byref(h)) == -1
     with pytest.raises(ValueError):
         P.default_options(block_tile=[0, 1])
 

@@ -108,3 +108,49 @@ def test_homogenise_autograd_matches_oracle_gradient(torch_cuda, P, n):
         ctx.set_density(torch.tensor(np.clip(rho_np * 0.9, 0, 1), device="cuda"))
         with pytest.raises(RuntimeError):
             _dh_torch(torch, C3, e3).backward()
+
+
+def test_caller_allocator_receives_every_workspace(torch_cuda, P):
+    """phz_create's allocator: with PyTorch's caching allocator behind it, the
+    context's workspaces come from torch (counted), every one is returned at
+    destroy, and the tensors equal those of a context on hipMalloc."""
+    torch = torch_cuda
+    n = 16
+    say("caller allocator, n", n)
+    phi = torch.tensor(synth.grf_levelset(n, seed=2410, solid_fraction=0.5), device="cuda")
+    stream = torch.cuda.current_stream().cuda_stream
+    out = {}
+    # FP64 runs the same kernels in the same order whatever the memory (no
+    # timed kernel choice), so the tensors agree bit for bit; the split-BF16
+    # form times its kernel choices per context, so it agrees to its bar
+    for prec in (P.PHZ_FP64, P.PHZ_BF16X3_IR):
+        for name, alloc in (("hip", None), ("torch", P.TorchAllocator())):
+            before = torch.cuda.memory_allocated()
+            with P.Context(n, MAT, stream=stream, allocator=alloc, precision=prec) as ctx:
+                ctx.set_levelset(phi)
+                assert ctx.solve() == P.PHZ_OK
+                out[prec, name] = ctx.effective_nd()[0]
+                if alloc is not None:
+                    assert alloc.allocs > 20 and alloc.frees < alloc.allocs
+                    assert torch.cuda.memory_allocated() - before >= alloc.bytes_live > 0
+            if alloc is not None:
+                assert alloc.frees == alloc.allocs and alloc.bytes_live == 0
+                assert torch.cuda.memory_allocated() == before
+    assert np.array_equal(out[P.PHZ_FP64, "hip"], out[P.PHZ_FP64, "torch"])
+    a, b = out[P.PHZ_BF16X3_IR, "hip"], out[P.PHZ_BF16X3_IR, "torch"]
+    assert np.abs(a - b).max() <= 1e-8 * np.abs(a).max()
+    # an allocator that fails makes creation (or a later call) report out of memory, not crash
+    failing = P.TorchAllocator()
+    failing._do_alloc_orig = failing._do_alloc
+    calls = {"n": 0}
+
+    def refuse_late(nbytes, stream_, user):
+        calls["n"] += 1
+        return None if calls["n"] > 3 else failing._do_alloc_orig(nbytes, stream_, user)
+
+    failing._alloc = P.ALLOC_FN(refuse_late)
+    failing.struct.alloc = failing._alloc
+    with pytest.raises(P.PiezoError) as ei:
+        P.Context(n, MAT, stream=stream, allocator=failing)
+    assert ei.value.status == -4
+    assert failing.bytes_live == 0

@@ -111,9 +111,10 @@ def test_scale_and_rhs(torch_cuda, P):
 
 # ------------------------------------------------------------- multigrid
 def prolongation(nc, F):
-    """Dense periodic trilinear prolongation (fine (2nc)^3*F x nc^3*F), test-side."""
+    """Periodic trilinear prolongation (fine (2nc)^3*F x nc^3*F, sparse), test-side."""
+    import scipy.sparse as sps
     nf = 2 * nc
-    Pm = np.zeros((nf ** 3, nc ** 3))
+    Pm = sps.lil_matrix((nf ** 3, nc ** 3))
     for k in range(nf):
         for j in range(nf):
             for i in range(nf):
@@ -125,20 +126,23 @@ def prolongation(nc, F):
                     w = (0.5 if i % 2 else 1.0) * (0.5 if j % 2 else 1.0) * (0.5 if k % 2 else 1.0)
                     I = ((i // 2 + ax) % nc) + nc * (((j // 2 + ay) % nc) + nc * ((k // 2 + az) % nc))
                     Pm[row, I] += w
-    return np.kron(Pm, np.eye(F))
+    return sps.kron(Pm.tocsr(), sps.eye(F), format="csr")
 
 
-def test_galerkin_coarse_operators(torch_cuda, P):
-    """Coarse element matrices equal R A P with trilinear P (levels 1 and 2)."""
+@pytest.mark.parametrize("n", [12, 16])
+def test_galerkin_coarse_operators(torch_cuda, P, n):
+    """Coarse element matrices equal R A P with trilinear P (levels 1 and 2).
+    At n = 16 level 2 has a side of 4, which the Galerkin coarsening of stored
+    element matrices runs four coarse elements per workgroup; at n = 12 (side
+    3) it runs one per workgroup."""
     torch = torch_cuda
-    n = 12
     say("galerkin", n)
     rho = synth.random_density(n, seed=3)
     s = fe.ersatz_scale(rho, MAT.void_scale)
     K, _ = cell.assemble(n, s, MND)
     iu = field_index(n, [0, 1, 2])
-    A = K[iu][:, iu].toarray()
-    Sb = krylov.schur_elementwise(n, s, MND).toarray()
+    A = K[iu][:, iu].tocsr()
+    Sb = krylov.schur_elementwise(n, s, MND).tocsr()
     rng = np.random.default_rng(1)
     with P.Context(n, MAT) as ctx:
         ctx.set_density(rho)
@@ -147,7 +151,7 @@ def test_galerkin_coarse_operators(torch_cuda, P):
             nl = n
             for level in (1, 2):
                 Pm = prolongation(nl // 2, F)
-                Ml = Pm.T @ Ml @ Pm
+                Ml = (Pm.T @ Ml @ Pm).tocsr()
                 nl //= 2
                 x = rng.standard_normal((nl ** 3 * F, 9))
                 xd = torch.tensor(to_soa(x, nl ** 3, F, 9), device="cuda")

@@ -183,3 +183,37 @@ def test_laminate24_split_bf16_ir_closed_form(torch_cuda, P):
         MH, _ = ctx.effective_nd()
         assert ctx.stats()["elem_tile"] == [0, 0, 0, 0]
         assert relmax(MH, ref) < 1e-8
+
+
+@pytest.mark.parametrize("precision,batched", [("bf16x3", 1), ("fp32", 1), ("bf16x3", 0)])
+def test_refinement_stall_fallback_forced(torch_cuda, P, precision, batched):
+    """The refinement-stall fallback, forced from the host (ir_fallback = 2
+    treats every refinement step as stalled): split-BF16 moves to float32
+    kernels and then to a float64 inner GMRES, float32 directly to float64.
+    The form that finished is reported, and the tensors still reach the
+    stored oracle's to the plain-FP64 bar."""
+    g = _golden("grf16")
+    prec = {"bf16x3": P.PHZ_BF16X3_IR, "fp32": P.PHZ_FP32_IR}[precision]
+    say("grf16 forced refinement fallback", precision, "batched", batched)
+    phi = synth.grf_levelset(16, seed=2410, solid_fraction=0.5)
+    # float cycles aiming at 1e-2 need several refinement steps, so both
+    # fallbacks happen before the target is reached
+    with P.Context(16, MAT, precision=prec, batched=batched, elem_tile=1, rtol=1e-10, ir_fallback=2,
+                   inner_rtol=1e-2) as ctx:
+        ctx.set_levelset(phi)
+        assert ctx.solve() == P.PHZ_OK
+        st = ctx.stats()
+        print("fallbacks", st["fallbacks"], "final", st["final_precision"], "refinements", st["refinements"])
+        assert st["final_precision"] == P.PHZ_FP64
+        per_block = 2 if prec == P.PHZ_BF16X3_IR else 1
+        assert st["fallbacks"] == per_block * (1 if batched else 9)
+        assert max(st["true_residual"]) <= 1e-10
+        MH, _ = ctx.effective_nd()
+        assert relmax(MH, np.array(g["MH"])) < 1e-8
+        # the same context without the switch: no fallback, the configured form finishes
+        ctx.set_options(ir_fallback=1)
+        ctx.set_levelset(phi)
+        assert ctx.solve() == P.PHZ_OK
+        st = ctx.stats()
+        assert st["fallbacks"] == 0 and st["final_precision"] == prec
+        assert relmax(ctx.effective_nd()[0], np.array(g["MH"])) < 1e-8
