@@ -406,6 +406,9 @@ def main():
     ap.add_argument("--full-kernel-timing", action="store_true",
                     help="bracket every timed kernel class (coarse levels, preconditioner, Arnoldi) with HIP events, "
                          "not only the fine-level operator launches (about 5%% slower steps)")
+    ap.add_argument("--reorth-tol", type=float, default=None,
+                    help="Arnoldi second-pass rule of the benchmarked form (library option reorth_tol; "
+                         "-1 = always two passes)")
     ap.add_argument("--cpu-sweep", action="store_true",
                     help="instead of the step benchmark: longer CPU oracle timings (direct solves at 12^3..24^3, "
                          "element and CSR applies at 64^3 and 128^3); prints one JSON line")
@@ -459,6 +462,8 @@ def main():
         pins["block_tile"] = [int(v) for v in args.block_tiles.split(",")]
     if args.coarse_kernel >= 0:
         pins["coarse_kernel"] = args.coarse_kernel
+    if args.reorth_tol is not None:
+        pins["reorth_tol"] = args.reorth_tol
 
     def make_ctx(form):
         extra = dict(pins) if form == args.precision else {}
@@ -591,7 +596,8 @@ def main():
                    "fine_kernels": stats["fine_kernel"], "mfma_tiles_full_A_B_S": stats["elem_tile"],
                    "coarse_kernels_A_S": [stats["coarse_kernel"][1:8], stats["coarse_kernel"][9:16]],
                    "split_products_operator_precond": ([3, 1] if args.precision == "bf16x3ir" else None),
-                   "final_precision": stats["final_precision"], "fallbacks": stats["fallbacks"]},
+                   "final_precision": stats["final_precision"], "fallbacks": stats["fallbacks"],
+                   "reorth_passes_per_load_step": stats["reorth_passes"] / max(sum(stats["iterations"]), 1)},
     }
 
     # dominant single kernel from the live event timing of the timed steps

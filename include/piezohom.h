@@ -249,6 +249,15 @@ typedef struct {
                                2 treats every refinement step as stalled (a
                                host-side switch that exercises the path).
                                phz_stats reports the form that finished     */
+    double reorth_tol;      /* Arnoldi orthogonalisation: classical
+                               Gram-Schmidt, whose first pass also computes
+                               h2 = V^T w' of the projected vector w'; a load
+                               takes the second pass only where
+                               |h2| > reorth_tol |w'| (|h2| / |w'| is the new
+                               basis vector's departure from orthogonality).
+                               0 (default): 32 units of roundoff of the
+                               basis's type; > 0 that tolerance; < 0 the
+                               second pass always (CGS2)                      */
 } phz_options;
 
 typedef struct {
@@ -281,6 +290,8 @@ typedef struct {
                                precision, or after refinement-stall fallbacks
                                PHZ_FP32_IR or PHZ_FP64 (ir_fallback)          */
     int fallbacks;          /* refinement-stall fallbacks in the last solve   */
+    long reorth_passes;     /* second Gram-Schmidt passes taken, summed over
+                               loads and Arnoldi steps (reorth_tol)           */
 } phz_stats;
 
 typedef struct {
@@ -480,6 +491,17 @@ int phz_apply(phz_ctx* ctx, int op, int nrhs, int precision,
 /* Apply the SCP preconditioner z = P^-1 r (device, [4][nrhs][N^3], float64),
  * building it for the current geometry if needed. */
 int phz_precondition(phz_ctx* ctx, int nrhs, const double* r, double* z);
+/* One Arnoldi orthogonalisation of the GMRES step (Sec. 2.5's GMRES, its
+ * Gram-Schmidt kernels and the reorth_tol rule) on caller data: w (device,
+ * [4][9][N^3], float64 for PHZ_FP64, float32 for PHZ_FP32_IR) is
+ * orthogonalised in place against the nvec (1 .. 33) vectors of V (device,
+ * nvec x [4][9][N^3], contiguous), column by column of the nine loads.  h
+ * (host, [nvec][9]) gets the projection coefficients (both passes summed),
+ * nrm2 (host, [9]) |w|^2 of the result, second_pass (host, [9]) 1 where the
+ * second pass ran.  w is not normalised.  A test hook of the solver's
+ * internals. */
+int phz_orthogonalize(phz_ctx* ctx, int precision, int nvec, const void* V, void* w, double* h,
+                      double* nrm2, int* second_pass);
 /* Galerkin coarse operator of multigrid level >= 1 applied to x (device):
  * block PHZ_OP_A ([3][nrhs][nc]) or PHZ_OP_SBAR ([nrhs][nc]).  precision
  * PHZ_FP64 (double buffers, the FP64 stencils) or PHZ_FP32_IR (float buffers,

@@ -44,7 +44,8 @@ class phz_options(C.Structure):
                 ("block_kernel", C.c_int * 4), ("block_tile", C.c_int * 4), ("coarse_kernel", C.c_int),
                 ("solver", C.c_int), ("inner", C.c_int), ("inner_eps", C.c_double), ("inner_maxit", C.c_int),
                 ("warm_start", C.c_int), ("smoothing", C.c_int),
-                ("bf16_terms_precond", C.c_int), ("ir_fallback", C.c_int)]
+                ("bf16_terms_precond", C.c_int), ("ir_fallback", C.c_int),
+                ("reorth_tol", C.c_double)]
 
 
 def _set_option(o, k, v):
@@ -65,7 +66,8 @@ class phz_stats(C.Structure):
                 ("setup_ms", C.c_double), ("solve_ms", C.c_double), ("mg_levels", C.c_int),
                 ("cheb_lambda", C.c_double * 16), ("elem_tile", C.c_int * 4),
                 ("fine_kernel", C.c_int * 4), ("coarse_kernel", C.c_int * 16), ("inner_iters", C.c_long * 2),
-                ("inner_calls", C.c_long * 2), ("final_precision", C.c_int), ("fallbacks", C.c_int)]
+                ("inner_calls", C.c_long * 2), ("final_precision", C.c_int), ("fallbacks", C.c_int),
+                ("reorth_passes", C.c_long)]
 
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
@@ -123,7 +125,7 @@ EXPORTS = [
     "phz_get_solution", "phz_set_initial_guess", "phz_get_rhs", "phz_foms", "phz_backward",
     "phz_hj_step", "phz_apply", "phz_precondition", "phz_coarse_apply", "phz_reinit", "phz_levelset_gradient",
     "phz_riesz", "phz_hpm_velocity",
-    "phz_kernel_timing", "phz_get_kernel_timing",
+    "phz_kernel_timing", "phz_get_kernel_timing", "phz_orthogonalize",
 ]
 
 
@@ -163,6 +165,7 @@ def _load():
         "phz_hpm_velocity": (ip, [vp, ip, vp, C.POINTER(C.c_void_p), vp, C.c_double, C.c_double, C.c_double,
                                   C.c_double, vp, ip]),
         "phz_kernel_timing": (ip, [vp, ip]),
+        "phz_orthogonalize": (ip, [vp, ip, ip, vp, vp, dp, dp, C.POINTER(ip)]),
         "phz_get_kernel_timing": (ip, [vp, C.c_char_p, ip, C.POINTER(ip)]),
     }
     for name, (res, args) in sig.items():
@@ -360,7 +363,7 @@ class Context:
             "cheb_lambda": list(s.cheb_lambda), "elem_tile": list(s.elem_tile),
             "fine_kernel": list(s.fine_kernel), "coarse_kernel": list(s.coarse_kernel),
             "inner_iters": list(s.inner_iters), "inner_calls": list(s.inner_calls),
-            "final_precision": s.final_precision, "fallbacks": s.fallbacks,
+            "final_precision": s.final_precision, "fallbacks": s.fallbacks, "reorth_passes": s.reorth_passes,
         }
 
     def history(self, load):
@@ -490,6 +493,16 @@ class Context:
     def precondition(self, nrhs, r_ptr, z_ptr):
         self._check(_lib.phz_precondition(self._h, nrhs, C.c_void_p(r_ptr), C.c_void_p(z_ptr)),
                     "phz_precondition")
+
+    def orthogonalize(self, precision, nvec, V_ptr, w_ptr):
+        """One Arnoldi orthogonalisation of w (device) against nvec basis vectors V (device);
+        returns (h [nvec, 9], |w|^2 [9], second pass taken [9])."""
+        h = np.zeros(nvec * 9)
+        n2 = np.zeros(9)
+        sp = (C.c_int * 9)()
+        self._check(_lib.phz_orthogonalize(self._h, precision, nvec, C.c_void_p(V_ptr), C.c_void_p(w_ptr), _dptr(h),
+                                           _dptr(n2), sp), "phz_orthogonalize")
+        return h.reshape(nvec, 9), n2, np.array(list(sp))
 
     def coarse_apply(self, level, op, nrhs, x_ptr, y_ptr, precision=PHZ_FP64):
         self._check(_lib.phz_coarse_apply(self._h, level, op, nrhs, precision, C.c_void_p(x_ptr),

@@ -170,7 +170,12 @@ void arnoldi_dots(long nn, int F, int K, int j, const T* V, long vstride, const 
                   double* work, hipStream_t st);
 template <typename T>
 void arnoldi_update(long nn, int F, int K, int j, const T* V, long vstride, T* w, const double* hin,
-                    double* hout, double* nrm2out, double* work, hipStream_t st);
+                    double* hout, double* nrm2out, double* work, hipStream_t st, const int* flags = nullptr);
+// selective reorthogonalisation: flag[k] = active[k] and |h2_k|^2 > tau2
+// na2[k] (a second Gram-Schmidt pass is needed), h2 zeroed where not;
+// count[k] += flag[k]
+void reorth_decide(int K, int J, double tau2, double* h2, const double* na2, const int* active, int* flag,
+                   int* count, hipStream_t st);
 // v = w * scale[k] (in place allowed)
 template <typename T>
 void scale_cols(long nn, int F, int K, const T* w, const double* scale, T* v, hipStream_t st);
@@ -209,8 +214,11 @@ void gmres_start(int nrhs, const double* nrm2, double rtol, GmresState s, hipStr
 // Givens step j: a column stops at its tolerance, at the restart length, and,
 // with stall > 0, once its estimate fell by less than the factor `stall` over
 // two steps (a float cycle whose operator error floors it).
+// flag, na2 (may be null): where flag[k] = 0 the new vector's norm^2 is
+// na2[k] (no second Gram-Schmidt pass) instead of nrm2[k].
 void gmres_givens(int nrhs, int m, int j, const double* h1, const double* h2,
-                  const double* nrm2, double rtol, double stall, GmresState s, hipStream_t st);
+                  const double* nrm2, double rtol, double stall, GmresState s, hipStream_t st,
+                  const int* flag = nullptr, const double* na2 = nullptr);
 void gmres_solve_y(int nrhs, int m, GmresState s, hipStream_t st);
 
 // physics

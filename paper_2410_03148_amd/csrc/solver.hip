@@ -207,6 +207,8 @@ struct phz_ctx {
   phz::DevBuf<double> gm_H, gm_cs, gm_sn, gm_g, gm_y, gm_est, gm_bnorm, gm_scale, gm_h1, gm_h2, gm_nrm;
   phz::DevBuf<double> gm_tol;  // per-column relative targets of a float refinement cycle
   phz::DevBuf<int> gm_int;
+  phz::DevBuf<double> gm_na2;  // |w|^2 after the first Gram-Schmidt pass, per load
+  phz::DevBuf<int> gm_flag, gm_reorth;  // second pass needed per load; second passes counted per load
 
   // captured Arnoldi steps (use_graph), per precision and step index; the
   // epoch advances whenever a buffer they reference may have moved
@@ -426,6 +428,9 @@ static void ensure_state_buffers(phz_ctx* c) {
   c->gm_h2.alloc((size_t)(kMaxRestart + 1) * K);
   c->gm_nrm.alloc(4 * K);
   c->gm_int.alloc(3 * K + 1);
+  c->gm_na2.alloc(K);
+  c->gm_flag.alloc(K);
+  c->gm_reorth.alloc(K);
   c->gm_tol.alloc(K);
   c->red_work.alloc(reduce_work_size());
   c->small.alloc(512);
@@ -1287,6 +1292,11 @@ static GmresResult gmres(phz_ctx* c, int K, const T* b, T* x, double rtol, int m
   // (and so does every cycle whose block maps are conjugate-gradient solves,
   // a preconditioner that changes from one application to the next)
   const bool flexible = std::is_same<T, float>::value || c->opt.inner == 1;
+  // selective reorthogonalisation threshold: 32 units of roundoff of the
+  // basis's type by default
+  const bool selective = c->opt.reorth_tol >= 0.0;
+  const double tau = c->opt.reorth_tol > 0.0 ? c->opt.reorth_tol
+                                             : 32.0 * (std::is_same<T, float>::value ? 0x1p-24 : 0x1p-53);
   if (flexible && W.Z.n < (size_t)vs * m) W.Z.alloc((size_t)vs * m);
   GmresState S = gm_state(c);
   S.tol = coltol;
@@ -1347,13 +1357,18 @@ static GmresResult gmres(phz_ctx* c, int K, const T* b, T* x, double rtol, int m
         precond_apply<T>(c, K, Vj, Zj);
         time_end(c, tp);
         op_apply<T>(c, 0, K, Zj, (const T*)nullptr, W.w.p, T(1), T(0));
-        // classical Gram-Schmidt, twice
+        // classical Gram-Schmidt: the first pass fused with the inner
+        // products of the second; the second pass for the loads whose first
+        // left components above reorth_tol (every load with reorth_tol < 0)
         const long ts = time_begin(c, sizeof(T) == 4 ? "arnoldi_cgs2_f32" : "arnoldi_cgs2_f64");
         arnoldi_dots<T>(nn, 4, K, j, W.V.p, vs, W.w.p, c->gm_h1.p, c->red_work.p, st);
-        arnoldi_update<T>(nn, 4, K, j, W.V.p, vs, W.w.p, c->gm_h1.p, c->gm_h2.p, nullptr, c->red_work.p, st);
-        arnoldi_update<T>(nn, 4, K, j, W.V.p, vs, W.w.p, c->gm_h2.p, nullptr, nrm, c->red_work.p, st);
+        arnoldi_update<T>(nn, 4, K, j, W.V.p, vs, W.w.p, c->gm_h1.p, c->gm_h2.p, c->gm_na2.p, c->red_work.p, st);
+        // (tau2 < 0: every active load takes the second pass)
+        reorth_decide(K, j + 1, selective ? tau * tau : -1.0, c->gm_h2.p, c->gm_na2.p, S.active, c->gm_flag.p,
+                      c->gm_reorth.p, st);
+        arnoldi_update<T>(nn, 4, K, j, W.V.p, vs, W.w.p, c->gm_h2.p, nullptr, nrm, c->red_work.p, st, c->gm_flag.p);
         time_end(c, ts);
-        gmres_givens(K, m, j, c->gm_h1.p, c->gm_h2.p, nrm, rtol, stall, S, st);
+        gmres_givens(K, m, j, c->gm_h1.p, c->gm_h2.p, nrm, rtol, stall, S, st, c->gm_flag.p, c->gm_na2.p);
         scale_cols<T>(nn, 4, K, W.w.p, S.scale, W.V.p + (size_t)(j + 1) * vs, st);
       };
       // per-kernel timing needs eager launches
@@ -1905,9 +1920,11 @@ static int do_solve(phz_ctx* c) {
   c->stats.refinements = 0;
   c->stats.fallbacks = 0;
   c->stats.final_precision = c->opt.precision;
+  c->stats.reorth_passes = 0;
   for (int i = 0; i < 2; ++i) c->stats.inner_iters[i] = c->stats.inner_calls[i] = 0;
   for (auto& h : c->hist) h.clear();
   ensure_state_buffers(c);
+  PHZ_HIP(hipMemsetAsync(c->gm_reorth.p, 0, c->gm_reorth.n * sizeof(int), st));
   c->X.alloc(nn * 36);
   c->Bvec.alloc(nn * 36);
   c->R64.alloc(nn * 36);
@@ -1958,7 +1975,12 @@ static int do_solve(phz_ctx* c) {
       return PHZ_E_NAN;
     }
   compute_effective(c);
-  sync(c);
+  {
+    int cnt[9] = {0};
+    PHZ_HIP(hipMemcpyAsync(cnt, c->gm_reorth.p, 9 * sizeof(int), hipMemcpyDeviceToHost, st));
+    sync(c);
+    for (int k = 0; k < 9; ++k) c->stats.reorth_passes += cnt[k];
+  }
   collect_timing(c);
   c->have_solution = true;
   c->x_valid = true;
@@ -2087,6 +2109,7 @@ void phz_default_options(phz_options* o) {
   o->smoothing = PHZ_SMOOTH_ELEMENT;
   o->bf16_terms_precond = 1;
   o->ir_fallback = 1;
+  o->reorth_tol = 0.0;
 }
 
 const char* phz_strerror(int status) {
@@ -2132,6 +2155,7 @@ static int check_options(const phz_options* o, std::string& err) {
   if (!(o->inner_rtol > 0 && o->inner_rtol < 1)) { err = "inner_rtol must be in (0, 1)"; return PHZ_E_INVALID; }
   if (o->max_refine < 1) { err = "max_refine must be >= 1"; return PHZ_E_INVALID; }
   if (o->ir_fallback < 0 || o->ir_fallback > 2) { err = "ir_fallback must be 0, 1 or 2"; return PHZ_E_INVALID; }
+  if (!(o->reorth_tol < 1.0)) { err = "reorth_tol must be below 1"; return PHZ_E_INVALID; }
   return PHZ_OK;
 }
 
@@ -2917,6 +2941,56 @@ int phz_apply(phz_ctx* c, int op, int nrhs, int precision, const void* x, void* 
                plain_args<float>(nullptr, (float*)y, 1.0f, 0.0f), false, c->stream);
   } else
     return PHZ_E_INVALID;
+  return PHZ_OK;
+  PHZ_GUARD_END(c)
+}
+
+extern "C++" {
+template <typename T>
+static void orthogonalize_hook(phz_ctx* c, int j, const T* V, T* w, double* h, double* nrm2, int* second) {
+  const long nn = c->nn;
+  const int K = 9;
+  hipStream_t st = c->stream;
+  const long vs = 36 * nn;
+  const bool selective = c->opt.reorth_tol >= 0.0;
+  const double tau = c->opt.reorth_tol > 0.0 ? c->opt.reorth_tol
+                                             : 32.0 * (std::is_same<T, float>::value ? 0x1p-24 : 0x1p-53);
+  GmresState S = gm_state(c);
+  const int ones[9] = {1, 1, 1, 1, 1, 1, 1, 1, 1};
+  PHZ_HIP(hipMemcpyAsync(S.active, ones, sizeof(ones), hipMemcpyHostToDevice, st));
+  PHZ_HIP(hipMemsetAsync(c->gm_reorth.p, 0, K * sizeof(int), st));
+  double* nrm = c->gm_nrm.p;
+  arnoldi_dots<T>(nn, 4, K, j, V, vs, w, c->gm_h1.p, c->red_work.p, st);
+  arnoldi_update<T>(nn, 4, K, j, V, vs, w, c->gm_h1.p, c->gm_h2.p, c->gm_na2.p, c->red_work.p, st);
+  reorth_decide(K, j + 1, selective ? tau * tau : -1.0, c->gm_h2.p, c->gm_na2.p, S.active, c->gm_flag.p,
+                c->gm_reorth.p, st);
+  arnoldi_update<T>(nn, 4, K, j, V, vs, w, c->gm_h2.p, nullptr, nrm, c->red_work.p, st, c->gm_flag.p);
+  std::vector<double> h1((size_t)(j + 1) * K), h2((size_t)(j + 1) * K), n1(K), n2(K);
+  std::vector<int> fl(K);
+  PHZ_HIP(hipMemcpyAsync(h1.data(), c->gm_h1.p, h1.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+  PHZ_HIP(hipMemcpyAsync(h2.data(), c->gm_h2.p, h2.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+  PHZ_HIP(hipMemcpyAsync(n1.data(), c->gm_na2.p, K * sizeof(double), hipMemcpyDeviceToHost, st));
+  PHZ_HIP(hipMemcpyAsync(n2.data(), nrm, K * sizeof(double), hipMemcpyDeviceToHost, st));
+  PHZ_HIP(hipMemcpyAsync(fl.data(), c->gm_flag.p, K * sizeof(int), hipMemcpyDeviceToHost, st));
+  sync(c);
+  for (int k = 0; k < K; ++k) {
+    for (int i = 0; i <= j; ++i) h[i * K + k] = h1[i * K + k] + h2[i * K + k];
+    nrm2[k] = fl[k] ? n2[k] : n1[k];
+    second[k] = fl[k];
+  }
+}
+}  // extern "C++"
+
+int phz_orthogonalize(phz_ctx* c, int precision, int nvec, const void* V, void* w, double* h, double* nrm2,
+                      int* second_pass) {
+  if (!c || !V || !w || !h || !nrm2 || !second_pass || nvec < 1 || nvec > kMaxRestart + 1) return PHZ_E_INVALID;
+  if (precision != PHZ_FP64 && precision != PHZ_FP32_IR) return PHZ_E_INVALID;
+  PHZ_GUARD_BEGIN
+  ensure_state_buffers(c);
+  if (precision == PHZ_FP64)
+    orthogonalize_hook<double>(c, nvec - 1, (const double*)V, (double*)w, h, nrm2, second_pass);
+  else
+    orthogonalize_hook<float>(c, nvec - 1, (const float*)V, (float*)w, h, nrm2, second_pass);
   return PHZ_OK;
   PHZ_GUARD_END(c)
 }

@@ -164,15 +164,22 @@ __global__ __launch_bounds__(256) void k_arnoldi_dots(unsigned nn, const T* __re
   }
 }
 
-// w -= sum_i V_i h[i][k]; then (DOTS) V^T w_new, and ||w_new||^2 (last slot)
+// w -= sum_i V_i h[i][k]; then (DOTS) V^T w_new, and ||w_new||^2 (last slot).
+// flags (may be null): a load whose flag is 0 is left as it is (its blocks
+// only write zero partial sums).
 template <typename T, int J, bool DOTS>
 __global__ __launch_bounds__(256) void k_arnoldi_update(unsigned nn, int K, const T* __restrict__ V, size_t vstride,
                                                         T* __restrict__ w, const double* __restrict__ hin,
-                                                        double* __restrict__ part) {
+                                                        double* __restrict__ part, const int* __restrict__ flags) {
   __shared__ double lds4[4];
   const int kk = blockIdx.y % K;
   const size_t co = (size_t)blockIdx.y * nn;
   const unsigned nq = nn / 4;
+  constexpr int NV = (DOTS ? J : 0) + 1;
+  if (flags && !flags[kk]) {   // block-uniform
+    if (threadIdx.x < NV) part[((size_t)blockIdx.y * gridDim.x + blockIdx.x) * NV + threadIdx.x] = 0.0;
+    return;
+  }
   double h[J];
 #pragma unroll
   for (int i = 0; i < J; ++i) h[i] = hin[i * K + kk];
@@ -206,7 +213,6 @@ __global__ __launch_bounds__(256) void k_arnoldi_update(unsigned nn, int K, cons
       for (int i = 0; i < J; ++i) acc[i] += vv[i][0] * wv[0] + vv[i][1] * wv[1] + vv[i][2] * wv[2] + vv[i][3] * wv[3];
     }
   }
-  constexpr int NV = (DOTS ? J : 0) + 1;
   const size_t base = ((size_t)blockIdx.y * gridDim.x + blockIdx.x) * NV;
   if constexpr (DOTS) {
 #pragma unroll
@@ -227,19 +233,20 @@ void launch_dots_J(dim3 g, hipStream_t st, unsigned nn, const T* V, size_t vs, c
 }
 template <typename T, int J>
 void launch_update_J(dim3 g, hipStream_t st, unsigned nn, int K, const T* V, size_t vs, T* w, const double* hin,
-                     int want, double* part) {
+                     int want, double* part, const int* flags) {
   if constexpr (J <= kFusedMaxJ) {
     if (want) {
-      hipLaunchKernelGGL((k_arnoldi_update<T, J, true>), g, dim3(256), 0, st, nn, K, V, vs, w, hin, part);
+      hipLaunchKernelGGL((k_arnoldi_update<T, J, true>), g, dim3(256), 0, st, nn, K, V, vs, w, hin, part, flags);
       return;
     }
   }
-  hipLaunchKernelGGL((k_arnoldi_update<T, J, false>), g, dim3(256), 0, st, nn, K, V, vs, w, hin, part);
+  hipLaunchKernelGGL((k_arnoldi_update<T, J, false>), g, dim3(256), 0, st, nn, K, V, vs, w, hin, part, flags);
 }
 template <typename T>
 using DotsFn = void (*)(dim3, hipStream_t, unsigned, const T*, size_t, const T*, double*);
 template <typename T>
-using UpdFn = void (*)(dim3, hipStream_t, unsigned, int, const T*, size_t, T*, const double*, int, double*);
+using UpdFn = void (*)(dim3, hipStream_t, unsigned, int, const T*, size_t, T*, const double*, int, double*,
+                       const int*);
 template <typename T, int... Js>
 constexpr std::array<DotsFn<T>, sizeof...(Js)> dots_table(std::integer_sequence<int, Js...>) {
   return {&launch_dots_J<T, Js + 1>...};
@@ -422,8 +429,32 @@ __global__ void k_gmres_start(int K, const double* __restrict__ nrm2, double rto
   if (threadIdx.x == 0) s.nactive[0] = cnt;
 }
 
+// Selective reorthogonalisation.  After one classical Gram-Schmidt pass
+// w' = w - V h1, h2 = V^T w' are w''s remaining components along the basis,
+// so |h2| / |w'| is exactly how far v = w' / |w'| is from orthogonal to it.
+// A load needs the second pass only where |h2|^2 > tau2 |w'|^2; elsewhere
+// its h2 is zeroed (the Hessenberg column is then h1 and |w'|, which is the
+// Arnoldi relation of the vector actually kept) and flag[k] = 0.  tau2 < 0:
+// every active load takes the second pass (plain CGS2); inactive (converged)
+// loads never do.  count[k] accumulates the second passes taken.
+__global__ void k_reorth_decide(int K, int J, double tau2, double* __restrict__ h2, const double* __restrict__ na2,
+                                const int* __restrict__ active, int* __restrict__ flag, int* __restrict__ count) {
+  const int k = threadIdx.x;
+  if (k >= K) return;
+  double q = 0.0;
+  for (int i = 0; i < J; ++i) q += h2[i * K + k] * h2[i * K + k];
+  const int need = active[k] && (tau2 < 0.0 || q > tau2 * na2[k]) ? 1 : 0;
+  flag[k] = need;
+  count[k] += need;
+  if (!need)
+    for (int i = 0; i < J; ++i) h2[i * K + k] = 0.0;
+}
+
+// nrm2 is |w|^2 after the second pass where flag[k] (or flag is null), else
+// na2[k], the norm after the first
 __global__ void k_gmres_givens(int K, int m, int j, const double* __restrict__ h1, const double* __restrict__ h2,
-                               const double* __restrict__ nrm2, double rtol, double stall, GmresState s) {
+                               const double* __restrict__ nrm2, double rtol, double stall, GmresState s,
+                               const int* __restrict__ flag, const double* __restrict__ na2) {
   __shared__ int cnt;
   if (threadIdx.x == 0) cnt = 0;
   __syncthreads();
@@ -431,7 +462,7 @@ __global__ void k_gmres_givens(int K, int m, int j, const double* __restrict__ h
   if (k < K && s.active[k]) {
     double col[kMaxRestart + 1];
     for (int i = 0; i <= j; ++i) col[i] = h1[i * K + k] + (h2 ? h2[i * K + k] : 0.0);
-    const double hn = sqrt(nrm2[k]);
+    const double hn = sqrt(flag && !flag[k] ? na2[k] : nrm2[k]);
     col[j + 1] = hn;
     for (int i = 0; i < j; ++i) {
       const double c = s.cs[i * K + k], sn = s.sn[i * K + k];
@@ -1039,13 +1070,14 @@ void arnoldi_dots(long nn, int F, int K, int j, const T* V, long vstride, const 
 
 template <typename T>
 void arnoldi_update(long nn, int F, int K, int j, const T* V, long vstride, T* w, const double* hin, double* hout,
-                    double* nrm2out, double* work, hipStream_t st) {
+                    double* nrm2out, double* work, hipStream_t st, const int* flags) {
   static constexpr auto table = upd_table<T>(std::make_integer_sequence<int, kMaxRestart + 1>{});
   if (nn % 4 != 0 || vstride % 4 != 0) throw std::logic_error("Arnoldi vectors: length and stride multiples of 4");
+  if (flags && hout) throw std::logic_error("Arnoldi update: flags only on a pass without inner products");
   const unsigned G = slices_for((size_t)nn, F * K);
   const bool fused = hout && j + 1 <= kFusedMaxJ;
   const int NV = (fused ? j + 1 : 0) + 1;
-  table[j](dim3(G, F * K), st, (unsigned)nn, K, V, (size_t)vstride, w, hin, fused ? 1 : 0, work);
+  table[j](dim3(G, F * K), st, (unsigned)nn, K, V, (size_t)vstride, w, hin, fused ? 1 : 0, work, flags);
   if (fused) reduce_cols((int)G, F, K, NV, 0, j + 1, work, hout, st);
   if (nrm2out) reduce_cols((int)G, F, K, NV, NV - 1, 1, work, nrm2out, st);
   PHZ_LAUNCH_CHECK();
@@ -1109,8 +1141,13 @@ void gmres_start(int nrhs, const double* nrm2, double rtol, GmresState s, hipStr
   PHZ_LAUNCH_CHECK();
 }
 void gmres_givens(int nrhs, int m, int j, const double* h1, const double* h2, const double* nrm2, double rtol,
-                  double stall, GmresState s, hipStream_t st) {
-  hipLaunchKernelGGL(k_gmres_givens, dim3(1), dim3(64), 0, st, nrhs, m, j, h1, h2, nrm2, rtol, stall, s);
+                  double stall, GmresState s, hipStream_t st, const int* flag, const double* na2) {
+  hipLaunchKernelGGL(k_gmres_givens, dim3(1), dim3(64), 0, st, nrhs, m, j, h1, h2, nrm2, rtol, stall, s, flag, na2);
+  PHZ_LAUNCH_CHECK();
+}
+void reorth_decide(int K, int J, double tau2, double* h2, const double* na2, const int* active, int* flag, int* count,
+                   hipStream_t st) {
+  hipLaunchKernelGGL(k_reorth_decide, dim3(1), dim3(64), 0, st, K, J, tau2, h2, na2, active, flag, count);
   PHZ_LAUNCH_CHECK();
 }
 void gmres_solve_y(int nrhs, int m, GmresState s, hipStream_t st) {
@@ -1270,7 +1307,7 @@ void hash_fill(long count, unsigned seed, double* v, hipStream_t st) {
   template void subtract_mean<T>(long, int, int, const double*, T*, hipStream_t);                            \
   template void arnoldi_dots<T>(long, int, int, int, const T*, long, const T*, double*, double*, hipStream_t); \
   template void arnoldi_update<T>(long, int, int, int, const T*, long, T*, const double*, double*, double*,   \
-                                  double*, hipStream_t);                                                      \
+                                  double*, hipStream_t, const int*);                                          \
   template void scale_cols<T>(long, int, int, const T*, const double*, T*, hipStream_t);                     \
   template void combine<T>(long, int, int, const T*, long, const double*, const int*, T*, hipStream_t);      \
   template void normalize_by<T>(long, const double*, const T*, T*, hipStream_t);
