@@ -338,7 +338,9 @@ int phz_create(int nx, int ny, int nz, const phz_material* mat, const phz_option
  * allocator given to phz_create, if any) and free the context.  NULL is a
  * no-op. */
 void phz_destroy(phz_ctx* ctx);
-/* Text of the last error on ctx (owned by ctx, valid until its next call). */
+/* Text of the last error on ctx (owned by ctx, valid until its next call);
+ * with ctx = NULL, of the calling thread's last failing call that takes no
+ * context (phz_hj_step_noalloc). */
 const char* phz_last_error(const phz_ctx* ctx);
 /* Static name of a status code. */
 const char* phz_strerror(int status);
@@ -428,6 +430,24 @@ int phz_backward(phz_ctx* ctx, const double gC[36], const double ge[18],
  * is written to phi_out ([N^3], may be NULL). */
 int phz_hj_step(phz_ctx* ctx, const double* velocity, double cfl,
                 double* phi_out, int on_device);
+
+/* phz_hj_step's step from the last backward, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation): no context, nothing allocated, nothing
+ * synchronised.  phi (device, [N^3] nodal level set), grad_rho (device,
+ * [N^3], an element density gradient such as phz_backward's), phi_out
+ * (device, [N^3], not phi): phi_out = one Godunov step of phi with the nodal
+ * velocity v_n = mean of grad_rho over the 8 elements around node n,
+ * normalised to max |v| = 1, dt = cfl / n; the same kernels as phz_hj_step.
+ * Enqueued on `stream` (a hipStream_t, NULL the default stream) of the
+ * current device; the caller orders later work on it.  Working memory is a
+ * fixed per-device scratch array of the library (16 MiB plus 8 KiB, held
+ * until the process ends), so n is at most 128 (larger: PHZ_E_INVALID,
+ * described by phz_last_error(NULL)); calls that overlap on one GPU (other
+ * streams or threads) race on that scratch and must be serialised by the
+ * caller. */
+int phz_hj_step_noalloc(int n, const double* phi, const double* grad_rho, double cfl, double* phi_out,
+                        void* stream);
 
 /* ---- the optimisation loop around the solve (Sec. 2.1, Sec. 2.6) ---- */
 

@@ -125,7 +125,7 @@ EXPORTS = [
     "phz_get_solution", "phz_set_initial_guess", "phz_get_rhs", "phz_foms", "phz_backward",
     "phz_hj_step", "phz_apply", "phz_precondition", "phz_coarse_apply", "phz_reinit", "phz_levelset_gradient",
     "phz_riesz", "phz_hpm_velocity",
-    "phz_kernel_timing", "phz_get_kernel_timing", "phz_orthogonalize",
+    "phz_kernel_timing", "phz_get_kernel_timing", "phz_orthogonalize", "phz_hj_step_noalloc",
 ]
 
 
@@ -166,6 +166,7 @@ def _load():
                                   C.c_double, vp, ip]),
         "phz_kernel_timing": (ip, [vp, ip]),
         "phz_orthogonalize": (ip, [vp, ip, ip, vp, vp, dp, dp, C.POINTER(ip)]),
+        "phz_hj_step_noalloc": (ip, [ip, vp, vp, C.c_double, vp, vp]),
         "phz_get_kernel_timing": (ip, [vp, C.c_char_p, ip, C.POINTER(ip)]),
     }
     for name, (res, args) in sig.items():
@@ -507,6 +508,21 @@ class Context:
     def coarse_apply(self, level, op, nrhs, x_ptr, y_ptr, precision=PHZ_FP64):
         self._check(_lib.phz_coarse_apply(self._h, level, op, nrhs, precision, C.c_void_p(x_ptr),
                                           C.c_void_p(y_ptr)), "phz_coarse_apply")
+
+
+def hj_step_noalloc(n, phi, grad_rho, cfl, phi_out, stream=None):
+    """phz_hj_step_noalloc: one HJ step of the device level set phi driven by the
+    device element gradient grad_rho, into the device tensor phi_out, on `stream`
+    (a HIP stream handle; None the default stream).  Allocates nothing."""
+    nn = n ** 3
+    pp, dp_, _ = _arg(phi, nn, what="hj_step_noalloc(phi)")
+    pg, dg, _ = _arg(grad_rho, nn, what="hj_step_noalloc(grad_rho)")
+    po, do, _ = _arg(phi_out, nn, out=True, what="hj_step_noalloc(phi_out)")
+    if not (dp_ and dg and do):
+        raise ValueError("hj_step_noalloc: phi, grad_rho and phi_out must be device tensors")
+    st = _lib.phz_hj_step_noalloc(n, pp, pg, float(cfl), po, C.c_void_p(stream) if stream else None)
+    if st != PHZ_OK:
+        raise PiezoError(st, _lib.phz_last_error(None).decode())
 
 
 def homogenise(n, material, phi=None, rho=None, **opts):

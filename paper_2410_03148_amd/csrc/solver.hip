@@ -20,6 +20,7 @@
 #include <cstring>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <string>
 #include <type_traits>
@@ -2051,6 +2052,46 @@ static void fill_point_scales(phz_ctx* c) {
 
 }  // namespace phz
 
+namespace phz {
+
+// Device scratch of phz_hj_step_noalloc, one copy per GPU for the life of
+// the process: the nodal velocity (up to kNoAllocMaxNodes values) and the
+// partial maxima of its normalisation.  Host code never passes `scratch`
+// itself (on the host it names a stand-in, not device memory): each device's
+// address comes from hipGetSymbolAddress, taken once per device with that
+// device current.
+constexpr long kNoAllocMaxNodes = 128L * 128L * 128L;
+constexpr long kNoAllocPartials = 1024;
+__device__ __align__(256) double scratch[kNoAllocMaxNodes + kNoAllocPartials];
+
+static std::mutex g_scratch_mu;
+static double* g_scratch_ptr[64] = {};
+
+// Address of the current device's scratch, or nullptr (err set).
+static double* scratch_of_current_device(std::string& err) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) {
+    err = "no current HIP device (or device index above 63)";
+    return nullptr;
+  }
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+      err = std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e);
+      return nullptr;
+    }
+    g_scratch_ptr[dev] = static_cast<double*>(p);
+  }
+  return g_scratch_ptr[dev];
+}
+
+// error text of the last failing call that has no context
+static thread_local std::string g_free_err;
+
+}  // namespace phz
+
 using namespace phz;
 
 static const AllocHook* hook_of(phz_ctx* c) { return c ? &c->hook : nullptr; }
@@ -2119,7 +2160,7 @@ const char* phz_strerror(int status) {
   return "unknown status";
 }
 
-const char* phz_last_error(const phz_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+const char* phz_last_error(const phz_ctx* ctx) { return ctx ? ctx->err.c_str() : g_free_err.c_str(); }
 
 static int check_options(const phz_options* o, std::string& err) {
   if (o->precision != PHZ_FP64 && o->precision != PHZ_FP32_IR && o->precision != PHZ_BF16X3_IR) { err = "precision must be PHZ_FP64, PHZ_FP32_IR or PHZ_BF16X3_IR"; return PHZ_E_INVALID; }
@@ -2624,6 +2665,40 @@ int phz_hj_step(phz_ctx* c, const double* velocity, double cfl, double* phi_out,
   c->have_grad = false;
   return PHZ_OK;
   PHZ_GUARD_END(c)
+}
+
+int phz_hj_step_noalloc(int n, const double* phi, const double* grad_rho, double cfl, double* phi_out,
+                        void* stream) {
+  g_free_err.clear();
+  if (!phi || !grad_rho || !phi_out || !(cfl > 0) || n < 2) {
+    g_free_err = "phz_hj_step_noalloc: null buffer, n < 2 or cfl <= 0";
+    return PHZ_E_INVALID;
+  }
+  const long nn = (long)n * n * n;
+  if (nn > kNoAllocMaxNodes) {
+    g_free_err = "phz_hj_step_noalloc: n^3 = " + std::to_string(nn) + " exceeds the scratch maximum of " +
+                 std::to_string(kNoAllocMaxNodes) + " nodes (n <= 128)";
+    return PHZ_E_INVALID;
+  }
+  if (phi_out == phi) {
+    g_free_err = "phz_hj_step_noalloc: phi_out must not be phi (the step reads phi's neighbours)";
+    return PHZ_E_INVALID;
+  }
+  double* scr = scratch_of_current_device(g_free_err);
+  if (!scr) return PHZ_E_HIP;
+  try {
+    hipStream_t st = (hipStream_t)stream;
+    double* v = scr;                                  // nodal velocity, nn values
+    double* part = scr + kNoAllocMaxNodes;            // partial maxima (at most 512)
+    double* vmax = scr + kNoAllocMaxNodes + 512;      // max |v|
+    nodal_mean_of_elements(n, grad_rho, v, st);
+    max_abs(nn, v, vmax, part, st);
+    hj_step(n, phi, v, vmax, cfl / n, phi_out, st);
+  } catch (const std::exception& ex) {
+    g_free_err = ex.what();
+    return PHZ_E_HIP;
+  }
+  return PHZ_OK;
 }
 
 // ------------------------------------------------------- optimisation step
