@@ -783,6 +783,12 @@ __global__ __launch_bounds__(256) void k_cheby_first(unsigned nn, int K, const T
   }
 }
 
+// Two consecutive values of one column (the pair at an even index: 8- or
+// 16-byte aligned, one load or store instruction).
+template <typename T> struct Pair;
+template <> struct Pair<float> { using type = float2; };
+template <> struct Pair<double> { using type = double2; };
+
 // rc[I] = sum_{d in {-1,0,1}^3} prod(1 - |d|/2) rf[2I + d]: one thread per
 // (coarse node, chunk of CPT columns starting at CPT * blockIdx.y); the index
 // arithmetic is shared by the chunk, whose loads are independent
@@ -812,42 +818,51 @@ __global__ __launch_bounds__(256) void k_restrict(unsigned Nc, const T* __restri
   for (int q = 0; q < CPT; ++q) rc[((size_t)blockIdx.y * CPT + q) * nc + I] = acc[q];
 }
 
-// xf[i] += sum_I P[i, I] xc[I], fine node i = 2I + c: one thread per (fine
-// node, chunk of CPT columns starting at CPT * blockIdx.y)
+// xf[i] += sum_I P[i, I] xc[I] (trilinear, periodic): one thread per (coarse
+// cell, chunk of CPT columns starting at CPT * blockIdx.y).  The cell's eight
+// coarse corners give its 2 x 2 x 2 fine nodes by averaging along each axis
+// where the fine node is odd; each fine row pair is read and written as one
+// access.
 template <typename T, int CPT>
 __global__ __launch_bounds__(256) void k_prolong(unsigned Nc, const T* __restrict__ xc, T* __restrict__ xf) {
+  using P2 = typename Pair<T>::type;
   const unsigned Nf = 2 * Nc;
   const unsigned nc = Nc * Nc * Nc, nf = Nf * Nf * Nf;
   const unsigned i = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-  if (i >= nf) return;
-  const unsigned fi = i % Nf, fj = (i / Nf) % Nf, fk = i / (Nf * Nf);
-  const unsigned bi = fi >> 1, bj = fj >> 1, bk = fk >> 1;
-  const unsigned oi = fi & 1, oj = fj & 1, ok = fk & 1;
+  if (i >= nc) return;
+  const unsigned bi = i % Nc, bj = (i / Nc) % Nc, bk = i / (Nc * Nc);
   const unsigned bi1 = bi + 1 == Nc ? 0 : bi + 1, bj1 = bj + 1 == Nc ? 0 : bj + 1, bk1 = bk + 1 == Nc ? 0 : bk + 1;
-  const T w = T((oi ? 0.5 : 1.0) * (oj ? 0.5 : 1.0) * (ok ? 0.5 : 1.0));
-  // coarse corners that contribute (only along the axes where the fine node
-  // is odd); the others repeat corner 0 with weight 0
-  unsigned src_idx[8];
-  T cw[8];
+  unsigned ci[8];
 #pragma unroll
-  for (int c = 0; c < 8; ++c) {
-    const unsigned ax = c & 1, ay = (c >> 1) & 1, az = (c >> 2) & 1;
-    const bool use = !((ax && !oi) || (ay && !oj) || (az && !ok));
-    src_idx[c] = use ? (ax ? bi1 : bi) + Nc * ((ay ? bj1 : bj) + Nc * (az ? bk1 : bk)) : bi + Nc * (bj + Nc * bk);
-    cw[c] = use ? w : T(0);
-  }
+  for (int c = 0; c < 8; ++c)
+    ci[c] = ((c & 1) ? bi1 : bi) + Nc * (((c >> 1) & 1 ? bj1 : bj) + Nc * ((c >> 2) ? bk1 : bk));
+  const unsigned f0 = 2 * bi + Nf * (2 * bj + Nf * 2 * bk);
   const size_t c0 = (size_t)blockIdx.y * CPT;
-  T acc[CPT];
 #pragma unroll
   for (int q = 0; q < CPT; ++q) {
     const T* src = xc + (c0 + q) * nc;
-    T a = T(0);
+    T v[8];
 #pragma unroll
-    for (int c = 0; c < 8; ++c) a += cw[c] * src[src_idx[c]];
-    acc[q] = a;
+    for (int c = 0; c < 8; ++c) v[c] = src[ci[c]];
+    T* dst = xf + (c0 + q) * nf + f0;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {   // fine row (oj, ok) = (r & 1, r >> 1)
+      const int oj = r & 1, ok = r >> 1;
+      // coarse values of this row at x = bi and bi + 1
+      T e[2];
+#pragma unroll
+      for (int ax = 0; ax < 2; ++ax) {
+        const T z0 = oj ? T(0.5) * (v[ax] + v[ax + 2]) : v[ax];
+        const T z1 = oj ? T(0.5) * (v[ax + 4] + v[ax + 6]) : v[ax + 4];
+        e[ax] = ok ? T(0.5) * (z0 + z1) : z0;
+      }
+      P2* p = reinterpret_cast<P2*>(dst + Nf * (oj + Nf * ok));
+      P2 cur = *p;
+      cur.x += e[0];
+      cur.y += T(0.5) * (e[0] + e[1]);
+      *p = cur;
+    }
   }
-#pragma unroll
-  for (int q = 0; q < CPT; ++q) xf[(c0 + q) * nf + i] += acc[q];
 }
 
 // z[(f, k, n)] = sum_{(g, m)} Minv[(f*nc + n), (g*nc + m)] r[(g, k, m)]
@@ -1086,7 +1101,7 @@ void restrict_fw(int F, int nrhs, int Nc, const T* rf, T* rc, hipStream_t st) {
 template <typename T>
 void prolong_add(int F, int nrhs, int Nc, const T* xc, T* xf, hipStream_t st) {
   const int ncol = F * nrhs;
-  const unsigned g = blocks_for((size_t)8 * Nc * Nc * Nc, 256);
+  const unsigned g = blocks_for((size_t)Nc * Nc * Nc, 256);
   if (ncol % 9 == 0) hipLaunchKernelGGL((k_prolong<T, 9>), dim3(g, ncol / 9), dim3(256), 0, st, (unsigned)Nc, xc, xf);
   else if (ncol % 3 == 0) hipLaunchKernelGGL((k_prolong<T, 3>), dim3(g, ncol / 3), dim3(256), 0, st, (unsigned)Nc, xc, xf);
   else hipLaunchKernelGGL((k_prolong<T, 1>), dim3(g, ncol), dim3(256), 0, st, (unsigned)Nc, xc, xf);
