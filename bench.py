@@ -406,6 +406,10 @@ def main():
     ap.add_argument("--full-kernel-timing", action="store_true",
                     help="bracket every timed kernel class (coarse levels, preconditioner, Arnoldi) with HIP events, "
                          "not only the fine-level operator launches (about 5%% slower steps)")
+    ap.add_argument("--cheby-degree", type=int, default=None,
+                    help="Chebyshev smoothing degree of the benchmarked form (library option cheby_degree)")
+    ap.add_argument("--inner-rtol", type=float, default=None,
+                    help="relative target of each float refinement cycle of the benchmarked form")
     ap.add_argument("--reorth-tol", type=float, default=None,
                     help="Arnoldi second-pass rule of the benchmarked form (library option reorth_tol; "
                          "-1 = always two passes)")
@@ -445,7 +449,7 @@ def main():
     # at 1e-4); every form stops at a true FP64 residual of 1e-10 per load
     forms = {
         "bf16x3ir": dict(precision=P.PHZ_BF16X3_IR, batched=1, restart=args.restart, vcycles_a=args.vcycles_a,
-                         inner_rtol=1e-4),
+                         inner_rtol=1e-4 if args.inner_rtol is None else args.inner_rtol),
         "fp32ir": dict(precision=P.PHZ_FP32_IR, batched=1, restart=args.restart, vcycles_a=args.vcycles_a),
         "fp64": dict(precision=P.PHZ_FP64, batched=1, restart=15, vcycles_a=2),
         "fp64_sequential": dict(precision=P.PHZ_FP64, batched=0, restart=30, vcycles_a=2),
@@ -464,6 +468,8 @@ def main():
         pins["coarse_kernel"] = args.coarse_kernel
     if args.reorth_tol is not None:
         pins["reorth_tol"] = args.reorth_tol
+    if args.cheby_degree is not None:
+        pins["cheby_degree"] = args.cheby_degree
 
     def make_ctx(form):
         extra = dict(pins) if form == args.precision else {}

@@ -333,9 +333,12 @@ class Context:
         self._state += 1
         self._check(_lib.phz_set_density(self._h, p, dev), "phz_set_density")
 
-    def scale(self):
-        out = np.zeros(self.nn)
-        self._check(_lib.phz_get_scale(self._h, C.c_void_p(out.ctypes.data), 0), "phz_get_scale")
+    def scale(self, out=None):
+        """Element scales s_e (host array, or into `out`: a host array or a device tensor)."""
+        if out is None:
+            out = np.zeros(self.nn)
+        p, dev, _ = _arg(out, self.nn, self.device, out=True, what="scale(out=)")
+        self._check(_lib.phz_get_scale(self._h, p, dev), "phz_get_scale")
         return out
 
     def solve(self):
@@ -415,8 +418,27 @@ class Context:
                                       C.c_void_p(gphi.ctypes.data) if want_phi else None, 0), "phz_backward")
         return (grho, gphi) if want_phi else grho
 
-    def hj_step(self, velocity=None, cfl=0.5, return_phi=True):
-        """One HJ step; velocity None uses the last backward's dJ/drho."""
+    def hj_step(self, velocity=None, cfl=0.5, return_phi=True, out=None):
+        """One HJ step; velocity None uses the last backward's dJ/drho.  A device velocity
+        tensor keeps the step on the device; `out` (a device tensor) receives the new level set
+        there instead of a returned host copy."""
+        on_dev = (velocity is not None and _is_tensor(velocity) and velocity.is_cuda) or \
+            (out is not None and _is_tensor(out) and out.is_cuda)
+        if on_dev:
+            pv = None
+            if velocity is not None:
+                pv, dv, keep_v = _arg(velocity, self.nn, self.device, what="hj_step(velocity)")
+                if not dv:
+                    raise ValueError("hj_step: with a device output the velocity must be on the device too")
+            po = None
+            if out is not None:
+                po, do, _ = _arg(out, self.nn, self.device, out=True, what="hj_step(out=)")
+                if not do:
+                    raise ValueError("hj_step: out must be a device tensor when the velocity is one")
+            st = _lib.phz_hj_step(self._h, pv, cfl, po, 1)
+            self._state += 1
+            self._check(st, "phz_hj_step")
+            return out
         out = np.zeros(self.nn) if return_phi else None
         optr = C.c_void_p(out.ctypes.data) if return_phi else None
         if velocity is None:
@@ -438,8 +460,18 @@ class Context:
                                     C.c_void_p(out.ctypes.data) if return_phi else None, 0), "phz_reinit")
         return out
 
-    def levelset_gradient(self, grad_rho):
-        """dJ/dphi from an element gradient dJ/drho (phz_levelset_gradient)."""
+    def levelset_gradient(self, grad_rho, out=None):
+        """dJ/dphi from an element gradient dJ/drho (phz_levelset_gradient); with a device tensor
+        grad_rho, into the device tensor `out`."""
+        if _is_tensor(grad_rho) and grad_rho.is_cuda:
+            pg, _, _ = _arg(grad_rho, self.nn, self.device, what="levelset_gradient(grad_rho)")
+            if out is None:
+                raise ValueError("levelset_gradient: a device grad_rho needs a device `out`")
+            po, do, _ = _arg(out, self.nn, self.device, out=True, what="levelset_gradient(out=)")
+            if not do:
+                raise ValueError("levelset_gradient: `out` must be a device tensor")
+            self._check(_lib.phz_levelset_gradient(self._h, pg, po, 1), "phz_levelset_gradient")
+            return out
         g = np.ascontiguousarray(grad_rho, dtype=np.float64).ravel()
         if g.size != self.nn:
             raise ValueError(f"levelset_gradient: grad_rho must hold {self.nn} values")
@@ -455,8 +487,27 @@ class Context:
                     "phz_riesz")
         return it.value
 
-    def hpm_velocity(self, j_obj, j_cons=(), viol=(), alpha=0.0, cfl=0.5, gamma=0.5, obj_weight=1.0):
-        """Velocity of one constrained step (phz_hpm_velocity), host arrays."""
+    def hpm_velocity(self, j_obj, j_cons=(), viol=(), alpha=0.0, cfl=0.5, gamma=0.5, obj_weight=1.0, out=None):
+        """Velocity of one constrained step (phz_hpm_velocity): host arrays, or device tensors (j_obj,
+        every j_cons and `out`; the violations stay on the host)."""
+        if _is_tensor(j_obj) and j_obj.is_cuda:
+            pj, _, _ = _arg(j_obj, self.nn, self.device, what="hpm_velocity(j_obj)")
+            cons = [_arg(j, self.nn, self.device, what="hpm_velocity(j_cons)") for j in j_cons]
+            if any(not d for _, d, _ in cons):
+                raise ValueError("hpm_velocity: with a device j_obj every j_cons must be a device tensor")
+            vi = np.ascontiguousarray(viol, dtype=np.float64).ravel()
+            if vi.size != len(cons):
+                raise ValueError("hpm_velocity: one violation per constraint")
+            if out is None:
+                raise ValueError("hpm_velocity: device inputs need a device `out`")
+            po, do, _ = _arg(out, self.nn, self.device, out=True, what="hpm_velocity(out=)")
+            if not do:
+                raise ValueError("hpm_velocity: `out` must be a device tensor")
+            ptrs = (C.c_void_p * max(len(cons), 1))(*[p.value for p, _, _ in cons])
+            self._check(_lib.phz_hpm_velocity(self._h, len(cons), pj, ptrs,
+                                              _dptr(vi) if len(cons) else None, alpha, cfl, gamma, obj_weight, po, 1),
+                        "phz_hpm_velocity")
+            return out
         jo = np.ascontiguousarray(j_obj, dtype=np.float64).ravel()
         jc = [np.ascontiguousarray(j, dtype=np.float64).ravel() for j in j_cons]
         vi = np.ascontiguousarray(viol, dtype=np.float64).ravel()

@@ -44,9 +44,41 @@ def _value_and_tensor_grads(name, CH, eH, kH):
     return float(f[name]), grads
 
 
-def _sensitivity(ctx, name, CH, eH, kH, void_scale):
-    """(value, dValue/dphi) of a property at the context's solved geometry."""
+class _DeviceFields:
+    """Node-sized device tensors of one optimisation (the sensitivities, the velocity and the level set
+    stay on the device between the library's calls; only scalars come back to the host)."""
+
+    def __init__(self, ctx, m):
+        import torch
+        self.torch = torch
+        dev = torch.device("cuda", ctx.device)
+        self.new = lambda: torch.empty(ctx.nn, dtype=torch.float64, device=dev)
+        self.scale = self.new()
+        self.grad_rho = self.new()
+        self.const = torch.full((ctx.nn,), 1.0 / ctx.nn, dtype=torch.float64, device=dev)
+        self.gphi = [self.new() for _ in range(m + 1)]
+        self.v = self.new()
+        self.phi = self.new()
+        self.ready()
+
+    def ready(self):
+        """Wait for this thread's torch work on the fields: the library reads them on the context's
+        stream, which need not be torch's."""
+        self.torch.cuda.current_stream().synchronize()
+
+
+def _sensitivity(ctx, name, CH, eH, kH, void_scale, dev=None, slot=0):
+    """(value, dValue/dphi) of a property at the context's solved geometry; with device fields, dValue/dphi
+    is a device tensor (dev.gphi[slot])."""
     n3 = ctx.nn
+    if dev is not None:
+        if name == "vol":
+            ctx.scale(out=dev.scale)
+            vol = (float(dev.scale.mean()) - void_scale) / (1.0 - void_scale)
+            return vol, ctx.levelset_gradient(dev.const, out=dev.gphi[slot])
+        val, (gC, ge, gk) = _value_and_tensor_grads(name, CH, eH, kH)
+        ctx.backward(gC, ge, gk, out_rho=dev.grad_rho, out_phi=dev.gphi[slot])
+        return val, dev.gphi[slot]
     if name == "vol":
         rho = (ctx.scale() - void_scale) / (1.0 - void_scale)
         return float(np.mean(rho)), ctx.levelset_gradient(np.full(n3, 1.0 / n3))
@@ -80,6 +112,8 @@ def optimise(ctx, material, phi0, objective, constraints, max_iters=200, cfl=0.5
             raise ValueError(f"bad constraint {(name, target)}")
     h = 1.0 / ctx.n
     ctx.set_levelset(np.ascontiguousarray(phi0, dtype=np.float64).ravel())
+    # on a GPU context the node fields stay on the device
+    dev = _DeviceFields(ctx, len(constraints)) if ctx.device is not None else None
     hist = {"J": [], "constraints": [], "violations": [], "status": [], "iter_ms": [], "tau": []}
     tau = 1.0
     phases = {"reinit": 0.0, "solve": 0.0, "sensitivities": 0.0, "velocity": 0.0, "hj": 0.0}
@@ -99,13 +133,17 @@ def optimise(ctx, material, phi0, objective, constraints, max_iters=200, cfl=0.5
         status = ctx.solve()
         CH, eH, kH = ctx.effective()
         t = lap("solve", t)
-        J, dJ = _sensitivity(ctx, objective, CH, eH, kH, material.void_scale)
+        J, dJ = _sensitivity(ctx, objective, CH, eH, kH, material.void_scale, dev, 0)
         vals, viol, jc = [], [], []
-        for name, target in constraints:
-            val, dC = _sensitivity(ctx, name, CH, eH, kH, material.void_scale)
+        for i, (name, target) in enumerate(constraints):
+            val, dC = _sensitivity(ctx, name, CH, eH, kH, material.void_scale, dev, 1 + i)
             vals.append(val)
             viol.append((val - target) / abs(target))
-            jc.append(-dC / abs(target))
+            if dev is not None:
+                dC.mul_(-1.0 / abs(target))
+                jc.append(dC)
+            else:
+                jc.append(-dC / abs(target))
         t = lap("sensitivities", t)
         hist["J"].append(J)
         hist["constraints"].append(vals)
@@ -122,13 +160,21 @@ def optimise(ctx, material, phi0, objective, constraints, max_iters=200, cfl=0.5
             before = max(map(abs, hist["violations"][-6]), default=0.0)
             tau = max(0.05, 0.5 * tau) if now > 1e-3 and now > 0.9 * before else min(1.0, 1.1 * tau)
         hist["tau"].append(tau)
-        v = ctx.hpm_velocity(-dJ, jc, viol, alpha=alpha, cfl=cfl, gamma=gamma, obj_weight=tau)
-        t = lap("velocity", t)
-        phi = ctx.hj_step(v, cfl=cfl, return_phi=True)
+        if dev is not None:
+            dJ.neg_()
+            dev.ready()
+            v = ctx.hpm_velocity(dJ, jc, viol, alpha=alpha, cfl=cfl, gamma=gamma, obj_weight=tau, out=dev.v)
+            t = lap("velocity", t)
+            ctx.hj_step(v, cfl=cfl, out=dev.phi)
+            phi = dev.phi
+        else:
+            v = ctx.hpm_velocity(-dJ, jc, viol, alpha=alpha, cfl=cfl, gamma=gamma, obj_weight=tau)
+            t = lap("velocity", t)
+            phi = ctx.hj_step(v, cfl=cfl, return_phi=True)
         lap("hj", t)
         hist["iter_ms"].append(1e3 * (clock() - t_iter))
     hist["phase_ms"] = {k: v / max(len(hist["J"]), 1) for k, v in phases.items()}
-    hist["phi"] = phi
+    hist["phi"] = phi.cpu().numpy() if phi is not None and dev is not None else phi
     hist["iterations"] = len(hist["J"])
     hist["converged"] = should_stop(hist["J"], hist["violations"], h)
     return hist
