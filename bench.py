@@ -177,9 +177,10 @@ def cpu_baseline(n, iterations, fine_launches_per_iteration):
 
 
 def cpu_sweep():
-    """Longer oracle timings for the record (a few minutes and up to about 100
-    GB of host memory): direct solves at 12^3 to 24^3 and CSR applies at 64^3
-    and 128^3 next to the matrix-free ones."""
+    """Longer oracle timings for the record (a few minutes, about 30 GB of host
+    memory): direct solves at 12^3 to 24^3, CSR applies at 32^3 and 64^3 and
+    matrix-free applies at 64^3 and 128^3 (a 128^3 CSR matrix would hold 2^31
+    element entries before summation, about 100 GB to assemble)."""
     rows = {}
     for n, reps in ((12, 3), (16, 3), (20, 1), (24, 1)):
         rows[f"solve_s_{n}"] = cpu_solve_seconds(n, reps)
@@ -187,16 +188,21 @@ def cpu_sweep():
     for n in (64, 128):
         rows[f"apply9_element_s_{n}"] = cpu_apply_seconds(n, 3)[0]
         print(f"[bench] cpu sweep: element apply {n}^3 {rows[f'apply9_element_s_{n}']}", file=sys.stderr, flush=True)
+    for n in (32, 64):
         ts, nnz = cpu_apply_seconds(n, 3, csr=True)
         rows[f"apply9_csr_s_{n}"] = ts
         rows[f"csr_nnz_{n}"] = nnz
         print(f"[bench] cpu sweep: CSR apply {n}^3 {ts} (nnz {nnz})", file=sys.stderr, flush=True)
     med = {k: float(np.median(v)) for k, v in rows.items() if k.startswith("solve_s_")}
-    ns = np.array([int(k.split("_")[-1]) for k in med])
-    ts = np.array(list(med.values()))
+    for k, v in list(rows.items()):
+        if k.startswith("apply9_"):
+            med[k] = float(np.median(v))
+    solves = {k: v for k, v in med.items() if k.startswith("solve_s_")}
+    ns = np.array([int(k.split("_")[-1]) for k in solves])
+    ts = np.array(list(solves.values()))
     slope = float(np.polyfit(np.log(ns ** 3.0), np.log(ts), 1)[0])
     return {"study": "CPU oracle timings, one thread", "cpu": _cpu_model(), "host_cores_available":
-            len(os.sched_getaffinity(0)), "raw": rows, "solve_median_s": med,
+            len(os.sched_getaffinity(0)), "raw": rows, "median_s": med,
             "solve_exponent_fit_12_to_24": slope}
 
 
