@@ -243,8 +243,10 @@ void reduce_effective(int N, const double* s, const double* X, double* out, doub
                       hipStream_t st);
 // out[b*9 + a] = sum_{f, n} X[(f, a)][n] Y[(f, b)][n]  (9-load blocks)
 void cross_dots(long nn, const double* X, const double* Y, double* out, double* work, hipStream_t st);
-// grad[stride e + off] = factor (cterm + <X_e, FW> + <K0-weighted cross terms of X_e and W>)
-void backward_elem(int N, const double* X, const double* K0, const double* FW, double cterm,
+// U = X W per node (W 9 x 9 over the load columns, X and U [4][9][nn])
+void mix_cols(long nn, const double* X, const double* W, double* U, hipStream_t st);
+// grad[stride e + off] = factor (cterm + <X_e, FW> + sum_L U_e[:, L]^T K0 X_e[:, L]), U = X W
+void backward_elem(int N, const double* X, const double* U, const double* K0, const double* FW, double cterm,
                    double factor, double* grad, hipStream_t st, int stride = 1, int off = 0);
 void grad_phi(int N, const double* phi, double eta, const double* grad_rho, double* out,
               hipStream_t st);

@@ -186,6 +186,7 @@ struct phz_ctx {
 
   phz::DevBuf<double> phi, rho, s, grad_rho, tmp_nodes;
   phz::DevBuf<double> grad_q;  // per-point density gradient (quadrature-point smoothing)
+  phz::DevBuf<double> bw_u;    // U = X W of the backward pass (36 nn)
   // node-sized staging of the optimisation entry points and the backward's
   // per-term block, kept so repeated calls do not allocate
   phz::DevBuf<double> node_a, node_b, bw_terms;
@@ -2612,14 +2613,18 @@ int phz_backward(phz_ctx* c, const double gC[36], const double ge[18], const dou
   dbuf.upload(buf.data(), buf.size(), c->stream);
   c->grad_rho.alloc(c->nn);
   const double eta = c->opt.smooth_width / c->N;
+  // U = X W, the same for every term (W follows the first term's FW in dbuf)
+  c->bw_u.alloc((size_t)c->nn * 36);
+  mix_cols(c->nn, c->X.p, dbuf.p + 288, c->bw_u.p, c->stream);
   if (qp) {
     c->grad_q.alloc((size_t)c->nn * 8);
     for (int p = 0; p < 8; ++p)
-      backward_elem(c->N, c->X.p, c->kq64.p + (size_t)p * 1024, dbuf.p + (size_t)p * 369, cterm,
+      backward_elem(c->N, c->X.p, c->bw_u.p, c->kq64.p + (size_t)p * 1024, dbuf.p + (size_t)p * 369, cterm,
                     1.0 - c->mat.void_scale, c->grad_q.p, c->stream, 8, p);
     sum_points(c->nn, c->grad_q.p, c->grad_rho.p, c->stream);
   } else {
-    backward_elem(c->N, c->X.p, c->kref_full.p, dbuf.p, cterm, 1.0 - c->mat.void_scale, c->grad_rho.p, c->stream);
+    backward_elem(c->N, c->X.p, c->bw_u.p, c->kref_full.p, dbuf.p, cterm, 1.0 - c->mat.void_scale, c->grad_rho.p,
+                  c->stream);
   }
   const hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
   PHZ_HIP(hipMemcpyAsync(grad_rho, c->grad_rho.p, c->nn * sizeof(double), kind, c->stream));

@@ -12,6 +12,7 @@
 #include <utility>
 
 #include "common.hpp"
+#include "devutil.hpp"
 
 namespace phz {
 
@@ -687,62 +688,133 @@ __global__ __launch_bounds__(256) void k_reduce_effective(unsigned N, const doub
   }
 }
 
-// dJ/drho_e = factor * ( cterm + <X_e, FW> + sum_{l,l'} <K0[l,l'], (x_l W) x_l'^T> ).
-// Eight threads per element, one per corner l: each forms u = x_l W from its
-// corner's 36 values and sums its row of the K0-weighted cross terms over the
-// eight corners l' (and its part of <X_e, FW>); the element's eight lanes
-// then add their partial sums by shuffles.  K0 and FW sit in LDS.
-__global__ __launch_bounds__(256) void k_backward(unsigned N, const double* __restrict__ X, const double* __restrict__ K0,
-                                                  const double* __restrict__ FW, const double* __restrict__ W,
-                                                  double cterm, double factor, int stride, int off,
-                                                  double* __restrict__ grad) {
-  __shared__ double k0s[32 * 32];
-  __shared__ double fws[32 * 9];
+// U = X W per node: U[(f*9 + L)*nn + n] = sum_L' X[(f*9 + L')*nn + n] W[L'*9 + L]
+__global__ __launch_bounds__(256) void k_mix_cols(unsigned nn, const double* __restrict__ X,
+                                                  const double* __restrict__ W, double* __restrict__ U) {
   __shared__ double ws[81];
-  for (int t = threadIdx.x; t < 32 * 32; t += blockDim.x) k0s[t] = K0[t];
-  for (int t = threadIdx.x; t < 32 * 9; t += blockDim.x) fws[t] = FW[t];
   for (int t = threadIdx.x; t < 81; t += blockDim.x) ws[t] = W[t];
   __syncthreads();
+  const unsigned n = blockIdx.x * blockDim.x + threadIdx.x;
+  const int f = blockIdx.y;
+  if (n >= nn) return;
+  double xv[9];
+  for (int L = 0; L < 9; ++L) xv[L] = X[(size_t)(f * 9 + L) * nn + n];
+  for (int L = 0; L < 9; ++L) {
+    double v = 0.0;
+    for (int Lp = 0; Lp < 9; ++Lp) v += xv[Lp] * ws[Lp * 9 + L];
+    U[(size_t)(f * 9 + L) * nn + n] = v;
+  }
+}
+
+typedef __attribute__((ext_vector_type(4))) double f64x4;
+
+// dJ/drho_e = factor * ( cterm + <X_e, FW> + sum_L U_e[:, L]^T K0 X_e[:, L] ), U = X W
+// (the bilinear term <K0 X_e, X_e W> taken column by column).  X_e[:, L] is
+// the element's 32 inputs of load column L (row 4 c + f: corner c, field f).
+// A workgroup takes a 16 x 4 x 4 block of elements (masked past N on ragged
+// blocks) and, per load column, stages the block's 17 x 5 x 5 nodes of X and U
+// in LDS.  Each wave contracts four rows of 16 elements on the matrix cores:
+// D = K0 X_e for the 16 elements of a row is two row tiles (rows 0..15 and
+// 16..31 of K0) times eight k-steps of v_mfma_f64_16x16x4f64, k-step s being
+// corner s with its four fields; a lane then dots its eight rows of D (one
+// field of eight corners) with the element's U, and the four lanes of an
+// element add their sums at the end.
+__global__ __launch_bounds__(256) void k_backward_mfma(unsigned N, const double* __restrict__ X,
+                                                       const double* __restrict__ U, const double* __restrict__ K0,
+                                                       const double* __restrict__ FW, double cterm, double factor,
+                                                       int stride, int off, double* __restrict__ grad) {
+  constexpr int TX = 16, TY = 4, TZ = 4, NX = TX + 1, NY = TY + 1, NZ = TZ + 1, NB = NX * NY * NZ;
+  constexpr int NS = 4 * NB, PF = (NS + 255) / 256;  // staged values per array, per thread
+  __shared__ double xs[NS];  // [node][field]
+  __shared__ double us[NS];
+  __shared__ double fws[32 * 9];
   const unsigned nn = N * N * N;
-  const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const unsigned e = (unsigned)(gid >> 3);
-  const int l = (int)(gid & 7);
-  // every lane of an element's group takes part in the shuffles below; a
-  // group past the last element (only in the last block) adds zeros
-  const bool live = e < nn;
-  double part = 0.0;
-  if (live) {
-    const Nb q = nbr(e, N);
-    unsigned cn[8];
-    for (int c = 0; c < 8; ++c) cn[c] = corner_node(q, N, c);
-    double xl[36];
-    for (int t = 0; t < 36; ++t) xl[t] = X[(size_t)t * nn + cn[l]];
-    double u[36];  // u = x_l W  (4 x 9)
-    for (int f = 0; f < 4; ++f)
-      for (int L = 0; L < 9; ++L) {
-        double v = 0.0;
-        for (int Kk = 0; Kk < 9; ++Kk) v += xl[f * 9 + Kk] * ws[Kk * 9 + L];
-        u[f * 9 + L] = v;
-      }
-    if (l == 0) part = cterm;
-    for (int f = 0; f < 4; ++f)
-      for (int L = 0; L < 9; ++L) part += xl[f * 9 + L] * fws[(4 * l + f) * 9 + L];
-    for (int lp = 0; lp < 8; ++lp) {
-      for (int fp = 0; fp < 4; ++fp) {
-        double xm[9];
-        for (int L = 0; L < 9; ++L) xm[L] = X[(size_t)(fp * 9 + L) * nn + cn[lp]];
-        for (int f = 0; f < 4; ++f) {
-          double v = 0.0;
-          for (int L = 0; L < 9; ++L) v += u[f * 9 + L] * xm[L];
-          part += k0s[(4 * l + f) * 32 + 4 * lp + fp] * v;
-        }
+  const unsigned ntx = (N + TX - 1) / TX, nty = (N + TY - 1) / TY;
+  const unsigned b = dev::xcd_block(blockIdx.x, gridDim.x);
+  const unsigned x0 = (b % ntx) * TX, y0 = ((b / ntx) % nty) * TY, z0 = (b / (ntx * nty)) * TZ;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  for (int t = tid; t < 32 * 9; t += 256) fws[t] = FW[t];
+  // A operands: K0 rows 16 t + (lane & 15), column 4 s + (lane >> 4)
+  double ak[2][8];
+#pragma unroll
+  for (int t = 0; t < 2; ++t)
+#pragma unroll
+    for (int s8 = 0; s8 < 8; ++s8) ak[t][s8] = K0[(16 * t + (lane & 15)) * 32 + 4 * s8 + (lane >> 4)];
+  // staged values of this thread: slot q = tid + 256 p is field q / NB of
+  // block node q % NB (x fastest); its global offset without the column
+  size_t go[PF];
+#pragma unroll
+  for (int p = 0; p < PF; ++p) {
+    const int q = tid + 256 * p;
+    const int f = q / NB, m = q % NB;
+    const unsigned gx = (x0 + m % NX) % N, gy = (y0 + (m / NX) % NY) % N, gz = (z0 + m / (NX * NY)) % N;
+    go[p] = q < NS ? (size_t)(f * 9) * nn + gx + N * (gy + (size_t)N * gz) : 0;
+  }
+  double px[PF], pu[PF];
+  auto fetch = [&](int L) {
+#pragma unroll
+    for (int p = 0; p < PF; ++p) {
+      px[p] = X[go[p] + (size_t)L * nn];
+      pu[p] = U[go[p] + (size_t)L * nn];
+    }
+  };
+  const int xl = lane & 15, g = lane >> 4;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  fetch(0);
+  for (int L = 0; L < 9; ++L) {
+    __syncthreads();  // the previous column's LDS reads are complete
+#pragma unroll
+    for (int p = 0; p < PF; ++p) {
+      const int q = tid + 256 * p;
+      if (q < NS) {
+        const int f = q / NB, m = q % NB;
+        xs[m * 4 + f] = px[p];
+        us[m * 4 + f] = pu[p];
       }
     }
+    if (L + 1 < 9) fetch(L + 1);  // in flight during this column's products
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int r = wave + 4 * i, ey = r % TY, ez = r / TY;
+      f64x4 d0 = {0.0, 0.0, 0.0, 0.0}, d1 = {0.0, 0.0, 0.0, 0.0};
+      double fw = 0.0;
+#pragma unroll
+      for (int s8 = 0; s8 < 8; ++s8) {
+        const int m = (xl + (s8 & 1)) + NX * ((ey + ((s8 >> 1) & 1)) + NY * (ez + (s8 >> 2)));
+        const double bv = xs[m * 4 + g];  // X_e row 4 s + g (corner s, field g)
+        fw += bv * fws[(4 * s8 + g) * 9 + L];
+        d0 = __builtin_amdgcn_mfma_f64_16x16x4f64(ak[0][s8], bv, d0, 0, 0, 0);
+        d1 = __builtin_amdgcn_mfma_f64_16x16x4f64(ak[1][s8], bv, d1, 0, 0, 0);
+      }
+      // register j of row tile t holds row 16 t + 4 j + g of D (the f64
+      // product's output layout): corner 4 t + j, field g
+      double dot = fw;
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        const f64x4 dd = t == 0 ? d0 : d1;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int c = 4 * t + j;
+          const int m = (xl + (c & 1)) + NX * ((ey + ((c >> 1) & 1)) + NY * (ez + (c >> 2)));
+          const double dj = dd[j];
+          dot += dj * us[m * 4 + g];
+        }
+      }
+      acc[i] += dot;
+    }
   }
-  part += __shfl_xor(part, 1, 8);
-  part += __shfl_xor(part, 2, 8);
-  part += __shfl_xor(part, 4, 8);
-  if (live && l == 0) grad[(size_t)e * stride + off] = factor * part;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    double v = acc[i];
+    v += __shfl_xor(v, 16);
+    v += __shfl_xor(v, 32);
+    const int r = wave + 4 * i;
+    const unsigned ex = x0 + xl, ey = y0 + r % TY, ez = z0 + r / TY;
+    if (g == 0 && ex < N && ey < N && ez < N)
+      grad[(ex + N * (ey + (size_t)N * ez)) * stride + off] = factor * (cterm + v);
+  }
 }
 
 // Chain rule of the point densities rho_ep = 1 - H(phi(x_p)) to the nodes:
@@ -1212,12 +1284,15 @@ void cross_dots(long nn, const double* X, const double* Y, double* out, double* 
   reduce_cols((int)G, 4, 9, 9, 0, 9, work, out, st);
   PHZ_LAUNCH_CHECK();
 }
-void backward_elem(int N, const double* X, const double* K0, const double* FW, double cterm, double factor,
-                   double* grad, hipStream_t st, int stride, int off) {
-  // W (9x9) is stored right after FW (32x9) in the same buffer
-  const size_t nn = (size_t)N * N * N;
-  hipLaunchKernelGGL(k_backward, dim3(blocks_for(nn * 8, 256)), dim3(256), 0, st, (unsigned)N, X, K0, FW, FW + 288,
-                     cterm, factor, stride, off, grad);
+void mix_cols(long nn, const double* X, const double* W, double* U, hipStream_t st) {
+  hipLaunchKernelGGL(k_mix_cols, dim3(blocks_for((size_t)nn, 256), 4), dim3(256), 0, st, (unsigned)nn, X, W, U);
+  PHZ_LAUNCH_CHECK();
+}
+void backward_elem(int N, const double* X, const double* U, const double* K0, const double* FW, double cterm,
+                   double factor, double* grad, hipStream_t st, int stride, int off) {
+  const unsigned nb = ((N + 15) / 16) * ((N + 3) / 4) * ((N + 3) / 4);
+  hipLaunchKernelGGL(k_backward_mfma, dim3(nb), dim3(256), 0, st, (unsigned)N, X, U, K0, FW, cterm, factor, stride,
+                     off, grad);
   PHZ_LAUNCH_CHECK();
 }
 void grad_phi_qp(int N, const double* phi, double eta, const double* g, int stride, double* out, hipStream_t st) {
