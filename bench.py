@@ -81,6 +81,85 @@ def measured_traffic(label, tile=None):
     return k["bytes_per_launch"]
 
 
+def _traffic_label(name, grid):
+    """Timing label of a counted kernel (None for kernels the record does not list) and the element tile."""
+    import re
+    # (the counter files may keep the element kernels' names mangled: their
+    # bf16 operand type defeats the demangler)
+    mm = re.search(r"k_elem_mfmaI((?:L[ib]\d+E)+)E", name)
+    if mm:
+        vals = [("true" if v == "1" else "false") if t == "b" else v for t, v in re.findall(r"L([ib])(\d+)E", mm[1])]
+        name = "k_elem_mfma<" + ", ".join(vals) + ">"
+    m = re.search(r"k_elem_mfma<(\d+), (\d+), 9, (\d+), (true|false), (\d+), (\d+), (\d+)>", name)
+    if m:
+        fo, fi, terms, cheby = int(m[1]), int(m[2]), int(m[3]), m[4] == "true"
+        block = {(4, 4): "full", (3, 3): "A", (1, 3): "B", (1, 1): "S"}[(fo, fi)]
+        tile = {(8, 8, 4): 0, (16, 4, 4): 1, (16, 8, 2): 2}[(int(m[5]), int(m[6]), int(m[7]))]
+        return f"elem_{block}_k9_bf16x{terms}" + ("_cheby" if cheby else ""), tile
+    m = re.search(r"k_stencil_tiled<(\d), (true|false), false, true>", name)
+    if m:
+        n = round(grid ** (1 / 3))
+        return f"coarse_tiledbf_{'A' if m[1] == '3' else 'S'}_f32" + ("_cheby" if m[2] == "true" else "") + f"@{n}", None
+    m = re.search(r"k_fine_tiled<1, 1, 9, (true|false)>", name)
+    if m:
+        return "tiled_S_k9_f32" + ("_cheby" if m[1] == "true" else ""), None
+    m = re.search(r"k_fine_apply<double, (\d), (\d), 1,", name)
+    if m:
+        return {"3": "fine_A_k1_f64", "1": "fine_S_k1_f64"}[m[1]], None
+    return None, None
+
+
+def traffic_summary(fetch_dir, write_dir):
+    """HBM bytes per launch from two rocprofv3 --pmc runs of the bench workload with --copy-calibration
+    (FETCH_SIZE in one, WRITE_SIZE in the other): each counter is scaled by what it reads for the plain copy
+    kernel (y = -x) of known size.  Updates the measured fields and source hashes of the kernels that
+    profiles/hbm_traffic.json lists and prints its table rows."""
+    import csv, glob, hashlib
+    def load(d, counter):
+        rows = []
+        for path in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+            with open(path) as f:
+                rows += [r for r in csv.DictReader(f) if r["Counter_Name"] == counter]
+        return rows
+    fetch, write = load(fetch_dir, "FETCH_SIZE"), load(write_dir, "WRITE_SIZE")
+    path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+    with open(path) as f:
+        rec = json.load(f)
+    cal = rec["calibration"]
+    copy_f = [float(r["Counter_Value"]) for r in fetch if "neg" in r["Kernel_Name"]]
+    copy_w = [float(r["Counter_Value"]) for r in write if "neg" in r["Kernel_Name"]]
+    cal["copy_fetch_kib"], cal["copy_write_kib"] = float(np.mean(copy_f)), float(np.mean(copy_w))
+    cal["fetch_bytes_per_kib"] = cal["copy_bytes_read"] / cal["copy_fetch_kib"]
+    cal["write_bytes_per_kib"] = cal["copy_bytes_written"] / cal["copy_write_kib"]
+    def per_label(rows):
+        acc = {}
+        for r in rows:
+            label, tile = _traffic_label(r["Kernel_Name"], int(r["Grid_Size"]))
+            if label is not None:
+                acc.setdefault((label, tile), []).append(float(r["Counter_Value"]))
+        return acc
+    pf, pw = per_label(fetch), per_label(write)
+    out = []
+    for label, k in rec["kernels"].items():
+        key = (label, k.get("tile"))
+        if key not in pf or key not in pw:
+            continue
+        with open(os.path.join(ROOT, k["source"]), "rb") as f:
+            k["source_sha256"] = hashlib.sha256(f.read()).hexdigest()
+        k["dispatches"] = len(pf[key])
+        k["fetch_kib"], k["write_kib"] = float(np.mean(pf[key])), float(np.mean(pw[key]))
+        k["fetch_bytes"] = round(k["fetch_kib"] * cal["fetch_bytes_per_kib"])
+        k["write_bytes"] = round(k["write_kib"] * cal["write_bytes_per_kib"])
+        k["bytes_per_launch"] = k["fetch_bytes"] + k["write_bytes"]
+        out.append(f"| {label} | `{k['kernel']}` | {k['dispatches']} | {k['fetch_kib']:,.0f} | {k['write_kib']:,.0f} | "
+                   f"{k['bytes_per_launch'] / 1e6:,.1f} MB | {k['algorithmic_bytes'] / 1e6:,.1f} MB | "
+                   f"{k['bytes_per_launch'] / k['algorithmic_bytes']:.2f} |")
+    with open(path, "w") as f:
+        json.dump(rec, f, indent=1)
+        f.write("\n")
+    print("\n".join(out))
+
+
 _CPU_ENV = dict(OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
 
 
@@ -425,7 +504,13 @@ def main():
     ap.add_argument("--coarse-kernel", type=int, default=-1, choices=[-1, 0, 1, 2],
                     help="pin the coarse levels' float kernel (0 direct, 1 LDS-tiled, 2 LDS-tiled on the compact "
                          "bf16 stencils; 1 and 2 where N %% 16 == 0; -1 = timed choice per level)")
+    ap.add_argument("--traffic-summary", nargs=2, default=None, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="no GPU work: update profiles/hbm_traffic.json from the output folders of two rocprofv3 --pmc "
+                         "runs (FETCH_SIZE, WRITE_SIZE) of this benchmark with --copy-calibration, and print the rows")
     args = ap.parse_args()
+    if args.traffic_summary:
+        traffic_summary(*args.traffic_summary)
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU: the solve runs on a single MI355X; "
               "multi-GPU sharding is not part of this build", file=sys.stderr)

@@ -62,7 +62,7 @@ struct ElemTile {
   // the waves per SIMD to ask the register allocator for: three where three
   // workgroups' LDS fits in a CU's 160 KiB (the three-field blocks on the
   // 8x8x4 and 16x4x4 tiles), else two
-  static constexpr int lds_bytes(int fo) { return (NI + 2) * 16 + 8 * NEP * fo * 4 + NEP * 4; }
+  static constexpr int lds_bytes(int fo) { return (NI + 3) * 16 + 8 * NEP * fo * 4 + NEP * 4; }
   static constexpr int waves(int fo) { return fo == 3 && 3 * lds_bytes(fo) <= 160 * 1024 ? 3 : 2; }
 };
 
@@ -103,7 +103,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(ElemTile<TX
   constexpr int NX = TL::NX, NY = TL::NY, NI = TL::NI;
   constexpr int EX = TL::EX, EY = TL::EY, NE = TL::NE, CT = TL::CT, NEP = TL::NEP, MT = TL::MT;
   constexpr int PF = (NI + 255) / 256;  // staged input nodes per thread
-  __shared__ float4 xs[NI + 2];         // input node values, field slots 0..3; two zero pads
+  __shared__ float4 xs[NI + 3];         // input node values, field slots 0..3; two zero pads, a spill slot
   __shared__ float zs[8 * NEP * FO];    // element outputs [corner][element][field]
   __shared__ float se[NEP];
 
@@ -198,19 +198,39 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(ElemTile<TX
     sg[c] = se[(ti + 1 - cx) + EX * ((tj + 1 - cy) + EY * (tk + 1 - cz))];
   }
 
+  // a column's outputs (y; with the Chebyshev step d_new and x; or d1) are
+  // stored once the next column's inputs are staged: the wait for those
+  // loads then does not also wait for the stores
+  float so[3][FO];
+  auto store_outputs = [&](int k) {
+#pragma unroll
+    for (int f = 0; f < FO; ++f) {
+      const size_t o = (size_t)(f * K + k) * nn + n;
+      a.y[o] = so[0][f];
+      if constexpr (CHEBY) {
+        a.dnew[o] = so[1][f];
+        a.x[o] = so[2][f];
+      } else {
+        if (with_d1) a.d1[o] = so[1][f];
+      }
+    }
+  };
+
   for (int k = 0; k < K; ++k) {
     __syncthreads();  // the previous column's LDS reads are complete
 #pragma unroll
     for (int p = 0; p < PF; ++p) {
+      // threads past the staged nodes write the spill slot: the stores need no
+      // branch, so the wait for this column's loads can leave the previous
+      // column's output stores in flight
       const int t = tid + 256 * p;
-      if (t < NI) {
-        float4 v = {0.f, 0.f, 0.f, 0.f};
-        v.x = pv[p][0];
-        if constexpr (FI > 1) { v.y = pv[p][1]; v.z = pv[p][2]; }
-        if constexpr (FI > 3) v.w = pv[p][3];
-        xs[t] = v;
-      }
+      float4 v = {0.f, 0.f, 0.f, 0.f};
+      v.x = pv[p][0];
+      if constexpr (FI > 1) { v.y = pv[p][1]; v.z = pv[p][2]; }
+      if constexpr (FI > 3) v.w = pv[p][3];
+      xs[t < NI ? t : NI + 2] = v;
     }
+    if (k > 0) store_outputs(k - 1);
     // the Chebyshev step's operands of column k (previous correction,
     // iterate) are issued now, in flight during the contraction: fetching
     // them a column ahead too would hold more registers than three waves
@@ -274,25 +294,20 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(ElemTile<TX
       for (int fo = 0; fo < FO; ++fo) acc[fo] += sg[c] * zs[(c * NEP + ee) * FO + fo];
     }
     // y = beta y_in + alpha acc; with the Chebyshev step also
-    // d_new = ca d_old + cb Dinv y and x += d_new
-    float out[FO];
+    // d_new = ca d_old + cb Dinv y and x += d_new; or d1 = ca Dinv y.  Kept
+    // in registers and stored during the next column
+    float* out = so[0];
 #pragma unroll
-    for (int f = 0; f < FO; ++f) {
-      out[f] = has_yin ? a.beta * cyin[f] + a.alpha * acc[f] : a.alpha * acc[f];
-      a.y[(size_t)(f * K + k) * nn + n] = out[f];
-    }
+    for (int f = 0; f < FO; ++f) out[f] = has_yin ? a.beta * cyin[f] + a.alpha * acc[f] : a.alpha * acc[f];
     if constexpr (CHEBY) {
 #pragma unroll
       for (int f = 0; f < FO; ++f) {
         float z = 0.f;
 #pragma unroll
         for (int q = 0; q < FO; ++q) z += Di[f * FO + q] * out[q];
-        const size_t o = (size_t)(f * K + k) * nn + n;
         const float dv = ca * cdold[f] + cb * z;
-        a.dnew[o] = dv;
-        float xo = dv;
-        if (a.fold_dold) xo += cdold[f];
-        a.x[o] = xo + cxit[f];
+        so[1][f] = dv;
+        so[2][f] = (a.fold_dold ? dv + cdold[f] : dv) + cxit[f];
       }
     } else {
       if (with_d1) {
@@ -301,11 +316,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(ElemTile<TX
           float z = 0.f;
 #pragma unroll
           for (int q = 0; q < FO; ++q) z += Di[f * FO + q] * out[q];
-          a.d1[(size_t)(f * K + k) * nn + n] = ca * z;
+          so[1][f] = ca * z;
         }
       }
     }
   }
+  store_outputs(K - 1);
 }
 
 struct TileShape {
