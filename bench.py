@@ -160,6 +160,41 @@ def traffic_summary(fetch_dir, write_dir):
     print("\n".join(out))
 
 
+def measure_peaks(torch, dev):
+    """Achievable rates on this GPU, to read the roofline fractions against (device library kernels, not the
+    solver's): HBM copy, read-only and write-only bandwidth over 4 GiB buffers (far above the 256 MB last-level
+    cache), and dense GEMM throughput in bf16, fp32 and fp64 at n = 8192.  Medians of 10 timed launches after
+    3 warm-ups, timed with HIP events on the current stream."""
+    def timed(fn, reps=10, warm=3):
+        for _ in range(warm):
+            fn()
+        ts = []
+        for _ in range(reps):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(); fn(); b.record(); torch.cuda.synchronize()
+            ts.append(a.elapsed_time(b) * 1e-3)
+        return float(np.median(ts))
+    out = {}
+    nb = 4 << 30
+    src = torch.ones(nb // 4, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    out["copy_GBps"] = 2 * nb / timed(lambda: dst.copy_(src)) / 1e9
+    red = torch.empty((), dtype=torch.float32, device=dev)
+    out["read_GBps"] = nb / timed(lambda: torch.sum(src, dim=0, out=red)) / 1e9
+    out["write_GBps"] = nb / timed(lambda: dst.fill_(1.0)) / 1e9
+    del src, dst
+    n = 8192
+    for dt, name in ((torch.bfloat16, "gemm_bf16_TFLOPs"), (torch.float32, "gemm_fp32_TFLOPs"),
+                     (torch.float64, "gemm_fp64_TFLOPs")):
+        a = torch.randn((n, n), dtype=dt, device=dev)
+        b = torch.randn((n, n), dtype=dt, device=dev).contiguous()
+        c = torch.empty((n, n), dtype=dt, device=dev)
+        out[name] = 2 * n ** 3 / timed(lambda: torch.matmul(a, b, out=c)) / 1e12
+        del a, b, c
+    out["published"] = {"hbm_GBps": 8000, "bf16_TFLOPs": 2500, "fp32_TFLOPs": 157.3, "fp64_TFLOPs": 78.6}
+    return out
+
+
 _CPU_ENV = dict(OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
 
 
@@ -507,6 +542,9 @@ def main():
     ap.add_argument("--traffic-summary", nargs=2, default=None, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="no GPU work: update profiles/hbm_traffic.json from the output folders of two rocprofv3 --pmc "
                          "runs (FETCH_SIZE, WRITE_SIZE) of this benchmark with --copy-calibration, and print the rows")
+    ap.add_argument("--peaks", action="store_true",
+                    help="instead of the step benchmark: the GPU's achievable copy, read and write bandwidth and "
+                         "dense GEMM rates (bf16, fp32, fp64) from device library kernels; prints one JSON line")
     args = ap.parse_args()
     if args.traffic_summary:
         traffic_summary(*args.traffic_summary)
@@ -527,6 +565,9 @@ def main():
     assert torch.cuda.is_available()
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.peaks:
+        print(json.dumps(measure_peaks(torch, dev)))
+        return
     stream = torch.cuda.current_stream()
     n = args.n
     mat = synth.material_workload()
