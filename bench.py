@@ -109,7 +109,7 @@ def _traffic_label(name, grid):
     return None, None
 
 
-def traffic_summary(fetch_dir, write_dir):
+def traffic_summary(fetch_dir, write_dir, path=None):
     """HBM bytes per launch from two rocprofv3 --pmc runs of the bench workload with --copy-calibration
     (FETCH_SIZE in one, WRITE_SIZE in the other): each counter is scaled by what it reads for the plain copy
     kernel (y = -x) of known size.  Updates the measured fields and source hashes of the kernels that
@@ -122,7 +122,7 @@ def traffic_summary(fetch_dir, write_dir):
                 rows += [r for r in csv.DictReader(f) if r["Counter_Name"] == counter]
         return rows
     fetch, write = load(fetch_dir, "FETCH_SIZE"), load(write_dir, "WRITE_SIZE")
-    path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+    path = path or os.path.join(ROOT, "profiles", "hbm_traffic.json")
     with open(path) as f:
         rec = json.load(f)
     cal = rec["calibration"]
@@ -158,6 +158,7 @@ def traffic_summary(fetch_dir, write_dir):
         json.dump(rec, f, indent=1)
         f.write("\n")
     print("\n".join(out))
+    return out
 
 
 def measure_peaks(torch, dev):
