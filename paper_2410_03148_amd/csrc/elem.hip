@@ -220,9 +220,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(ElemTile<TX
     __syncthreads();  // the previous column's LDS reads are complete
 #pragma unroll
     for (int p = 0; p < PF; ++p) {
-      // threads past the staged nodes write the spill slot: the stores need no
-      // branch, so the wait for this column's loads can leave the previous
-      // column's output stores in flight
+      // threads past the staged nodes write the spill slot, so the staging
+      // writes need no branch
       const int t = tid + 256 * p;
       float4 v = {0.f, 0.f, 0.f, 0.f};
       v.x = pv[p][0];
