@@ -552,7 +552,7 @@ def main():
         return
     if args.gpus != 1:
         print("bench.py measures one GPU: the solve runs on a single MI355X; "
-              "multi-GPU sharding is not part of this build", file=sys.stderr)
+              "multi-GPU sharding is not implemented", file=sys.stderr)
         sys.exit(2)
 
     if args.cpu_sweep:
